@@ -1,0 +1,411 @@
+/*
+ * oracle.c -- plain FP64 CPU reference for frontier-based sum-product belief
+ * propagation (LBP, frontier residual BP, randomized BP).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code with the HIP library.
+ *
+ * Written for obviousness, not speed:
+ *   - every message is recomputed with the literal product of Eq. (2), in the
+ *     probability domain, over the neighbours of the source except the target
+ *     (no log-domain aggregate, no cavity division);
+ *   - beliefs follow Eq. (3) literally;
+ *   - the loop is Alg. 1 with the lookahead reading of its three steps:
+ *     evaluate f_BP(m^t) for every message, test convergence, pick the
+ *     frontier, commit (all commits of one iteration read m^t only);
+ *   - the random filter draws from Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+ *     "Parallel random numbers: as easy as 1, 2, 3", SC'11), written here from
+ *     that paper's definition.
+ *
+ * Message ids are canonical: for undirected edge u = (a, b) given in input
+ * order, id 2u is a->b and id 2u+1 is b->a (two messages per edge, Sec. II-A).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_PAIR_ISING 0
+#define OR_PAIR_SHARED 1
+#define OR_PAIR_DENSE 2
+
+#define OR_LBP 0
+#define OR_RBP 1
+#define OR_RNBP 2
+
+typedef struct {
+    int64_t iterations;        /* commits performed (sweeps) */
+    int32_t converged;         /* 1 if some evaluation found n_t == 0 */
+    int32_t pad0;
+    int64_t last_active;       /* n_t of the last evaluation */
+    double last_max_residual;  /* R_t of the last evaluation */
+    int64_t evaluated;         /* Eq. (2) evaluations, all iterations */
+    int64_t committed;         /* messages written, all iterations */
+    int64_t final_t;           /* t of the last evaluation (global clock) */
+    int64_t last_prev_active;  /* n_{t-1} seen by the last evaluation, -1 if none */
+} oracle_stats;
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 (SC'11): 10 rounds of the 4x32 Philox bijection.       */
+/* ------------------------------------------------------------------ */
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                          uint32_t out[4]) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;  /* multipliers */
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;  /* Weyl key bumps */
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform draw for the random filter of Sec. IV-A: key = seed split into two
+ * 32-bit words, counter = (source node, target node, iteration, 0); the top
+ * 24 bits of output word 0 give U in [0, 1). */
+double oracle_uniform(uint64_t seed, uint32_t src, uint32_t dst, uint32_t t) {
+    uint32_t ctr[4] = {src, dst, t, 0u};
+    uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    return (double)(out[0] >> 8) * (1.0 / 16777216.0);
+}
+
+/* ------------------------------------------------------------------ */
+/* Model                                                               */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int N, K;
+    int64_t M, E;
+    const int32_t* edges;      /* [M][2] */
+    double* unary;             /* psi_i(x) = exp(log_unary), [N][K] */
+    int pair_kind;
+    const double* coupling;    /* Ising J, [M] */
+    const double* shared;      /* [K][K] */
+    const double* edge_scale;  /* [M] */
+    const double* pair;        /* [M][K][K] */
+    int64_t* in_ptr;           /* [N+1]: incoming message ids grouped by target */
+    int64_t* in_ids;           /* [E] */
+} model_t;
+
+static int msg_src(const model_t* g, int64_t e) {
+    int64_t u = e >> 1;
+    return (e & 1) ? g->edges[2 * u + 1] : g->edges[2 * u];
+}
+static int msg_dst(const model_t* g, int64_t e) {
+    int64_t u = e >> 1;
+    return (e & 1) ? g->edges[2 * u] : g->edges[2 * u + 1];
+}
+
+/* Pairwise potential of the undirected edge u, first argument the state of
+ * edges[u][0], second the state of edges[u][1] (Eq. (1)). */
+static double pair_psi(const model_t* g, int64_t u, int xa, int xb) {
+    int K = g->K;
+    switch (g->pair_kind) {
+    case OR_PAIR_ISING: {
+        /* psi = exp(J * s_a * s_b) with spins s = -1 (state 0), +1 (state 1) */
+        double sa = xa ? 1.0 : -1.0, sb = xb ? 1.0 : -1.0;
+        return exp(g->coupling[u] * sa * sb);
+    }
+    case OR_PAIR_SHARED:
+        return g->edge_scale[u] * g->shared[xa * K + xb];
+    default:
+        return g->pair[(u * K + xa) * K + xb];
+    }
+}
+
+/* psi_{i,j}(x_i, x_j) for the directed message e = i -> j. */
+static double msg_psi(const model_t* g, int64_t e, int xi, int xj) {
+    int64_t u = e >> 1;
+    return (e & 1) ? pair_psi(g, u, xj, xi) : pair_psi(g, u, xi, xj);
+}
+
+static int build_model(model_t* g, int N, int K, int64_t M, const int32_t* edges,
+                       const double* log_unary, int pair_kind, const double* coupling,
+                       const double* shared, const double* edge_scale,
+                       const double* pair) {
+    memset(g, 0, sizeof(*g));
+    g->N = N; g->K = K; g->M = M; g->E = 2 * M;
+    g->edges = edges;
+    g->pair_kind = pair_kind;
+    g->coupling = coupling; g->shared = shared; g->edge_scale = edge_scale;
+    g->pair = pair;
+    g->unary = (double*)malloc(sizeof(double) * (size_t)N * (size_t)K + 1);
+    g->in_ptr = (int64_t*)calloc((size_t)N + 1, sizeof(int64_t));
+    g->in_ids = (int64_t*)malloc(sizeof(int64_t) * (size_t)g->E + 1);
+    if (!g->unary || !g->in_ptr || !g->in_ids) return -2;
+    for (int64_t i = 0; i < (int64_t)N * K; ++i) g->unary[i] = exp(log_unary[i]);
+    /* neighbour lists Gamma_i, as incoming message ids, in message-id order */
+    for (int64_t e = 0; e < g->E; ++e) g->in_ptr[msg_dst(g, e) + 1]++;
+    for (int i = 0; i < N; ++i) g->in_ptr[i + 1] += g->in_ptr[i];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * ((size_t)N + 1));
+    if (!fill) return -2;
+    memcpy(fill, g->in_ptr, sizeof(int64_t) * ((size_t)N + 1));
+    for (int64_t e = 0; e < g->E; ++e) g->in_ids[fill[msg_dst(g, e)]++] = e;
+    free(fill);
+    return 0;
+}
+
+static void free_model(model_t* g) {
+    free(g->unary);
+    free(g->in_ptr);
+    free(g->in_ids);
+}
+
+/* Eq. (2) for message e = i -> j, from the message set m (read only):
+ *   c(x_j) = sum_{x_i} psi_ij(x_i, x_j) psi_i(x_i) prod_{k in Gamma_i \ j} m_{k->i}(x_i)
+ * then normalised to sum 1 (Sec. II-A).  work holds K doubles. */
+static void eval_message(const model_t* g, const double* m, int64_t e, double* out,
+                         double* work) {
+    int K = g->K;
+    int i = msg_src(g, e);
+    int64_t back = e ^ 1; /* the message j -> i, excluded from the product */
+    for (int xi = 0; xi < K; ++xi) {
+        double prod = g->unary[(int64_t)i * K + xi];
+        for (int64_t q = g->in_ptr[i]; q < g->in_ptr[i + 1]; ++q) {
+            int64_t f = g->in_ids[q];
+            if (f == back) continue;
+            prod *= m[f * K + xi];
+        }
+        work[xi] = prod;
+    }
+    double z = 0.0;
+    for (int xj = 0; xj < K; ++xj) {
+        double s = 0.0;
+        for (int xi = 0; xi < K; ++xi) s += msg_psi(g, e, xi, xj) * work[xi];
+        out[xj] = s;
+        z += s;
+    }
+    for (int xj = 0; xj < K; ++xj) out[xj] /= z;
+}
+
+/* Eq. (3): b_i(x) proportional to psi_i(x) prod_{k in Gamma_i} m_{k->i}(x). */
+static void beliefs(const model_t* g, const double* m, double* out) {
+    int K = g->K;
+    for (int i = 0; i < g->N; ++i) {
+        double z = 0.0;
+        for (int x = 0; x < K; ++x) {
+            double b = g->unary[(int64_t)i * K + x];
+            for (int64_t q = g->in_ptr[i]; q < g->in_ptr[i + 1]; ++q)
+                b *= m[g->in_ids[q] * K + x];
+            out[(int64_t)i * K + x] = b;
+            z += b;
+        }
+        for (int x = 0; x < K; ++x) out[(int64_t)i * K + x] /= z;
+    }
+}
+
+/* Ordering for the greedy frontier of Sec. III-A: larger residual first; equal
+ * residuals by (target, source) ascending. */
+static const model_t* g_sort_model;
+static const double* g_sort_res;
+static int cmp_topk(const void* pa, const void* pb) {
+    int64_t a = *(const int64_t*)pa, b = *(const int64_t*)pb;
+    double ra = g_sort_res[a], rb = g_sort_res[b];
+    if (ra > rb) return -1;
+    if (ra < rb) return 1;
+    int da = msg_dst(g_sort_model, a), db = msg_dst(g_sort_model, b);
+    if (da != db) return da < db ? -1 : 1;
+    int sa = msg_src(g_sort_model, a), sb = msg_src(g_sort_model, b);
+    if (sa != sb) return sa < sb ? -1 : 1;
+    return 0;
+}
+
+/*
+ * Alg. 1 with one of three frontier rules.
+ *
+ *   schedule  OR_LBP : every message (Sec. II-B, Sec. III-A)
+ *             OR_RBP : the k = max(1, ceil(p * E)) largest residuals (Sec. III-A)
+ *             OR_RNBP: residual > eps, then each survivor kept with
+ *                      probability p_t (Sec. IV-A)
+ *   p_t       dynamic_p: p_t = low_p (= p) when n_t / n_{t-1} > ratio_threshold,
+ *             else high_p; the first iteration with no n_{t-1} uses high_p.
+ *             static: p_t = p.
+ *   init_msgs canonical [E][K] start state or NULL for uniform 1/K (Sec. II-A).
+ *   t0        global iteration number of the first evaluation (RNG counter).
+ *   prev_active n_{t0-1}, or -1 if none.
+ *   max_iters maximum number of commits; the state after the last commit is
+ *             evaluated once more so convergence within max_iters is seen.
+ *   trace_*   optional per-evaluation records, length max_iters + 1:
+ *             n_t, |F_t| (0 on the converged/final evaluation), p_t, R_t.
+ * Returns 0 if converged, 1 if not, negative on bad input.
+ */
+int oracle_bp_run(int N, int K, int64_t M, const int32_t* edges, const double* log_unary,
+                  int pair_kind, const double* coupling, const double* shared,
+                  const double* edge_scale, const double* pair, int schedule, double eps,
+                  double p, double high_p, double ratio_threshold, int dynamic_p,
+                  uint64_t seed, int64_t max_iters, const double* init_msgs, int64_t t0,
+                  int64_t prev_active, double* out_msgs, double* out_marginals,
+                  oracle_stats* stats, int64_t* trace_active, int64_t* trace_frontier,
+                  double* trace_p, double* trace_maxres) {
+    if (N < 0 || K < 2 || M < 0 || max_iters < 0) return -1;
+    if (pair_kind == OR_PAIR_ISING && K != 2) return -1;
+    model_t g;
+    if (build_model(&g, N, K, M, edges, log_unary, pair_kind, coupling, shared, edge_scale,
+                    pair) != 0) {
+        free_model(&g);
+        return -2;
+    }
+    const int64_t E = g.E;
+    size_t msz = sizeof(double) * (size_t)E * (size_t)K + 1;
+    double* m = (double*)malloc(msz);       /* m^t */
+    double* cand = (double*)malloc(msz);    /* f_BP(m^t) */
+    double* res = (double*)malloc(sizeof(double) * (size_t)E + 1);
+    unsigned char* sel = (unsigned char*)malloc((size_t)E + 1);
+    int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)E + 1);
+    double* work = (double*)malloc(sizeof(double) * (size_t)K);
+    if (!m || !cand || !res || !sel || !order || !work) {
+        free(m); free(cand); free(res); free(sel); free(order); free(work);
+        free_model(&g);
+        return -2;
+    }
+    if (init_msgs)
+        memcpy(m, init_msgs, sizeof(double) * (size_t)E * (size_t)K);
+    else
+        for (int64_t q = 0; q < E * K; ++q) m[q] = 1.0 / K;
+
+    oracle_stats st;
+    memset(&st, 0, sizeof(st));
+    st.last_prev_active = prev_active;
+    int64_t n_prev = prev_active;
+    int converged = 0;
+    for (int64_t it = 0;; ++it) {
+        int64_t t = t0 + it;
+        /* f_BP(m^t) and the residual of Eq. (4), L-infinity norm */
+        int64_t n_t = 0;
+        double r_max = 0.0;
+        for (int64_t e = 0; e < E; ++e) {
+            eval_message(&g, m, e, cand + e * K, work);
+            double r = 0.0;
+            for (int x = 0; x < K; ++x) {
+                double d = fabs(cand[e * K + x] - m[e * K + x]);
+                if (d > r) r = d;
+            }
+            res[e] = r;
+            if (r > eps) ++n_t;
+            if (r > r_max) r_max = r;
+        }
+        st.evaluated += E;
+        st.last_active = n_t;
+        st.last_max_residual = r_max;
+        st.final_t = t;
+        st.last_prev_active = n_prev;
+        /* p_t from EdgeRatio = n_t / n_{t-1} (Sec. IV-A) */
+        double p_t = p;
+        if (schedule == OR_RNBP && dynamic_p) {
+            if (n_prev > 0 && (double)n_t / (double)n_prev > ratio_threshold)
+                p_t = p;
+            else
+                p_t = high_p;
+        }
+        if (trace_active) trace_active[it] = n_t;
+        if (trace_p) trace_p[it] = p_t;
+        if (trace_maxres) trace_maxres[it] = r_max;
+        if (trace_frontier) trace_frontier[it] = 0;
+        if (n_t == 0) { /* IsConverged */
+            converged = 1;
+            break;
+        }
+        if (it == max_iters) break;
+
+        /* GenerateFrontier */
+        int64_t nsel = 0;
+        memset(sel, 0, (size_t)E);
+        if (schedule == OR_LBP) {
+            memset(sel, 1, (size_t)E);
+            nsel = E;
+        } else if (schedule == OR_RNBP) {
+            for (int64_t e = 0; e < E; ++e) {
+                if (!(res[e] > eps)) continue;
+                double u = oracle_uniform(seed, (uint32_t)msg_src(&g, e),
+                                          (uint32_t)msg_dst(&g, e), (uint32_t)t);
+                if (u < p_t) {
+                    sel[e] = 1;
+                    ++nsel;
+                }
+            }
+        } else { /* OR_RBP */
+            int64_t k = (int64_t)ceil(p * (double)E);
+            if (k < 1) k = 1;
+            if (k > E) k = E;
+            for (int64_t e = 0; e < E; ++e) order[e] = e;
+            g_sort_model = &g;
+            g_sort_res = res;
+            qsort(order, (size_t)E, sizeof(int64_t), cmp_topk);
+            for (int64_t q = 0; q < k; ++q) sel[order[q]] = 1;
+            nsel = k;
+        }
+        /* Update: synchronous commit, every candidate was computed from m^t */
+        for (int64_t e = 0; e < E; ++e)
+            if (sel[e])
+                for (int x = 0; x < K; ++x) m[e * K + x] = cand[e * K + x];
+        st.committed += nsel;
+        st.iterations += 1;
+        if (trace_frontier) trace_frontier[it] = nsel;
+        n_prev = n_t;
+    }
+    st.converged = converged;
+    if (out_msgs) memcpy(out_msgs, m, sizeof(double) * (size_t)E * (size_t)K);
+    if (out_marginals) beliefs(&g, m, out_marginals);
+    if (stats) *stats = st;
+    free(m); free(cand); free(res); free(sel); free(order); free(work);
+    free_model(&g);
+    return converged ? 0 : 1;
+}
+
+/* One evaluation of f_BP and Eq. (4) for a given message set, nothing
+ * committed: the candidates [E][K] and residuals [E] in canonical order. */
+int oracle_bp_evaluate(int N, int K, int64_t M, const int32_t* edges,
+                       const double* log_unary, int pair_kind, const double* coupling,
+                       const double* shared, const double* edge_scale, const double* pair,
+                       const double* msgs, double* out_cand, double* out_res) {
+    if (N < 0 || K < 2 || M < 0) return -1;
+    model_t g;
+    if (build_model(&g, N, K, M, edges, log_unary, pair_kind, coupling, shared, edge_scale,
+                    pair) != 0) {
+        free_model(&g);
+        return -2;
+    }
+    double* work = (double*)malloc(sizeof(double) * (size_t)K);
+    for (int64_t e = 0; e < g.E; ++e) {
+        eval_message(&g, msgs, e, out_cand + e * K, work);
+        double r = 0.0;
+        for (int x = 0; x < K; ++x) {
+            double d = fabs(out_cand[e * K + x] - msgs[e * K + x]);
+            if (d > r) r = d;
+        }
+        out_res[e] = r;
+    }
+    free(work);
+    free_model(&g);
+    return 0;
+}
+
+/* Eq. (3) for a given message set. */
+int oracle_bp_beliefs(int N, int K, int64_t M, const int32_t* edges, const double* log_unary,
+                      const double* msgs, double* out_marginals) {
+    if (N < 0 || K < 2 || M < 0) return -1;
+    model_t g;
+    /* the pairwise potentials do not enter Eq. (3) */
+    if (build_model(&g, N, K, M, edges, log_unary, OR_PAIR_DENSE, NULL, NULL, NULL, NULL) !=
+        0) {
+        free_model(&g);
+        return -2;
+    }
+    beliefs(&g, msgs, out_marginals);
+    free_model(&g);
+    return 0;
+}

@@ -1,0 +1,163 @@
+"""Seeded synthetic pairwise-MRF generators.
+
+This module draws random problem instances and nothing else: it holds none of
+the belief-propagation arithmetic, so both the HIP path and the FP64 oracle can
+be fed from it.  Every generator uses numpy's PCG64 (``default_rng(seed)``) and
+a fixed draw order, so a (generator, arguments, seed) triple names one problem.
+
+A problem is a plain dict:
+    N, K        number of variables, states per variable
+    edges       int32 [M, 2] undirected edges (a, b), no self-loops, no duplicates
+    log_unary   float64 [N, K]: psi_i(x) = exp(log_unary[i, x])
+    pair_kind   PAIR_ISING  : coupling float64 [M], psi = exp(J * s_a * s_b),
+                              spins s = -1 (state 0) and +1 (state 1)
+                PAIR_SHARED : shared float64 [K, K] > 0, edge_scale float64 [M] > 0,
+                              psi_u = edge_scale[u] * shared
+                PAIR_DENSE  : pair float64 [M, K, K] > 0, first index is the state
+                              of edges[u, 0]
+    name        short description
+
+Grid node ids are r * W + c; undirected grid edges are listed per node in id
+order: (id, id + 1) if c < W - 1, then (id, id + W) if r < H - 1.
+"""
+import numpy as np
+
+PAIR_ISING, PAIR_SHARED, PAIR_DENSE = 0, 1, 2
+
+
+def grid_edges(H: int, W: int) -> np.ndarray:
+    ids = np.arange(H * W, dtype=np.int64).reshape(H, W)
+    out = []
+    for r in range(H):
+        for c in range(W):
+            i = ids[r, c]
+            if c < W - 1:
+                out.append((i, i + 1))
+            if r < H - 1:
+                out.append((i, i + W))
+    return np.asarray(out, dtype=np.int32).reshape(-1, 2)
+
+
+def _grid_edges_fast(H: int, W: int) -> np.ndarray:
+    """Same list as grid_edges, vectorised for large grids."""
+    ids = np.arange(H * W, dtype=np.int64)
+    r, c = ids // W, ids % W
+    right = c < W - 1
+    down = r < H - 1
+    # per node: right edge first, then down edge
+    cnt = right.astype(np.int64) + down.astype(np.int64)
+    start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    M = int(cnt.sum())
+    e = np.empty((M, 2), dtype=np.int64)
+    ri = ids[right]
+    e[start[right], 0] = ri
+    e[start[right], 1] = ri + 1
+    di = ids[down]
+    pos = start[down] + right[down].astype(np.int64)
+    e[pos, 0] = di
+    e[pos, 1] = di + W
+    return e.astype(np.int32)
+
+
+def ising_grid(H: int, W: int, C: float, seed: int) -> dict:
+    """Ising grid: h ~ U[-1, 1]^N, then J ~ U[-C, C]^M; psi_i(x) = exp(h_i s_x),
+    psi_ij = exp(J_ij s_i s_j)."""
+    rng = np.random.default_rng(seed)
+    N = H * W
+    edges = _grid_edges_fast(H, W) if N > 4096 else grid_edges(H, W)
+    h = rng.uniform(-1.0, 1.0, size=N)
+    J = rng.uniform(-C, C, size=edges.shape[0])
+    lu = np.stack([-h, h], axis=1)
+    return dict(N=N, K=2, edges=edges, log_unary=lu, pair_kind=PAIR_ISING, coupling=J,
+                name=f"ising{H}x{W}_C{C}_s{seed}", h=h)
+
+
+def chain(N: int, C: float, seed: int) -> dict:
+    """A chain of N binary variables drawn like the Ising grid (one row)."""
+    p = ising_grid(1, N, C, seed)
+    p["name"] = f"chain{N}_C{C}_s{seed}"
+    return p
+
+
+def paper_ising_grid(H: int, W: int, C: float, seed: int) -> dict:
+    """The paper's Ising parameterisation: one U(0, 1] value per state for psi_i,
+    psi_ij = e^{lambda C} when x_i = x_j else e^{-lambda C}, lambda ~ U[-0.5, 0.5].
+    In spin form this is J = lambda * C."""
+    rng = np.random.default_rng(seed)
+    N = H * W
+    edges = _grid_edges_fast(H, W) if N > 4096 else grid_edges(H, W)
+    u = 1.0 - rng.random(size=(N, 2))  # (0, 1]
+    lam = rng.uniform(-0.5, 0.5, size=edges.shape[0])
+    return dict(N=N, K=2, edges=edges, log_unary=np.log(u), pair_kind=PAIR_ISING,
+                coupling=lam * C, name=f"paper_ising{H}x{W}_C{C}_s{seed}")
+
+
+def er_edges(n: int, M: int, rng) -> np.ndarray:
+    """G(n, M): M distinct undirected edges drawn uniformly, no self-loops.
+    Candidate pairs are drawn in batches; duplicates and self-loops are dropped,
+    first occurrence kept, until M edges exist."""
+    if M > n * (n - 1) // 2:
+        raise ValueError("too many edges")
+    keys = np.empty(0, dtype=np.int64)
+    pairs = np.empty((0, 2), dtype=np.int64)
+    while len(keys) < M:
+        need = M - len(keys)
+        cand = rng.integers(0, n, size=(int(need * 1.2) + 16, 2), dtype=np.int64)
+        cand = cand[cand[:, 0] != cand[:, 1]]
+        a = np.minimum(cand[:, 0], cand[:, 1])
+        b = np.maximum(cand[:, 0], cand[:, 1])
+        k = a * n + b
+        allk = np.concatenate([keys, k])
+        allp = np.concatenate([pairs, np.stack([a, b], 1)])
+        _, first = np.unique(allk, return_index=True)
+        first.sort()
+        keys, pairs = allk[first], allp[first]
+    return pairs[:M].astype(np.int32)
+
+
+def er_graph(n: int, avg_degree: float, C: float, seed: int) -> dict:
+    """Erdos-Renyi G(n, M) with M = n * avg_degree / 2, then h ~ U[-1, 1]^n and
+    J ~ U[-C, C]^M as for the Ising grid."""
+    rng = np.random.default_rng(seed)
+    M = int(round(n * avg_degree / 2))
+    edges = er_edges(n, M, rng)
+    h = rng.uniform(-1.0, 1.0, size=n)
+    J = rng.uniform(-C, C, size=M)
+    lu = np.stack([-h, h], axis=1)
+    return dict(N=n, K=2, edges=edges, log_unary=lu, pair_kind=PAIR_ISING, coupling=J,
+                name=f"er{n}_d{avg_degree}_C{C}_s{seed}", h=h)
+
+
+def potts_grid(H: int, W: int, K: int, beta: float, seed: int) -> dict:
+    """Potts grid: log-unary ~ N(0, 1)^{N x K}; one shared K x K matrix
+    exp(beta [a == b]); per-edge scale ~ U[0.5, 1.5]."""
+    rng = np.random.default_rng(seed)
+    N = H * W
+    edges = _grid_edges_fast(H, W) if N > 4096 else grid_edges(H, W)
+    lu = rng.standard_normal(size=(N, K))
+    scale = rng.uniform(0.5, 1.5, size=edges.shape[0])
+    shared = np.exp(beta * np.eye(K))
+    return dict(N=N, K=K, edges=edges, log_unary=lu, pair_kind=PAIR_SHARED, shared=shared,
+                edge_scale=scale, name=f"potts{H}x{W}_K{K}_b{beta}_s{seed}")
+
+
+def random_tree(n: int, K: int, seed: int, coupling_scale: float = 1.0) -> dict:
+    """A random labelled tree (node i > 0 attaches to a uniform earlier node) with
+    dense positive pairwise tables exp(N(0, coupling_scale)) and N(0, 1) log-unaries."""
+    rng = np.random.default_rng(seed)
+    parent = np.array([rng.integers(0, i) for i in range(1, n)], dtype=np.int64)
+    edges = np.stack([parent, np.arange(1, n)], axis=1).astype(np.int32)
+    lu = rng.standard_normal(size=(n, K))
+    pair = np.exp(coupling_scale * rng.standard_normal(size=(n - 1, K, K)))
+    return dict(N=n, K=K, edges=edges, log_unary=lu, pair_kind=PAIR_DENSE, pair=pair,
+                name=f"tree{n}_K{K}_s{seed}")
+
+
+def random_dense_graph(n: int, m: int, K: int, seed: int, coupling_scale: float = 1.0):
+    """Small loopy graph with dense positive tables (for brute-force checks)."""
+    rng = np.random.default_rng(seed)
+    edges = er_edges(n, m, rng)
+    lu = rng.standard_normal(size=(n, K))
+    pair = np.exp(coupling_scale * rng.standard_normal(size=(m, K, K)))
+    return dict(N=n, K=K, edges=edges, log_unary=lu, pair_kind=PAIR_DENSE, pair=pair,
+                name=f"dense{n}_{m}_K{K}_s{seed}")

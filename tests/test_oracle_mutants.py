@@ -1,0 +1,201 @@
+"""Plausible mistakes planted in a copy of the oracle must be caught by its pins.
+
+Each mutant is a textual edit of ``oracle/oracle.c`` compiled to a temporary
+library on the CPU; the committed oracle is never modified.  The battery below
+re-runs the core pins (exact inference, closed form, invariants, frontier
+definitions, Philox known answers) against a given build.
+"""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_11469_amd import inputs
+from tests import exact_refs
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
+                   "oracle.c")
+
+
+def _compile(text, tmpdir, name):
+    c = os.path.join(tmpdir, name + ".c")
+    so = os.path.join(tmpdir, name + ".so")
+    with open(c, "w") as f:
+        f.write(text)
+    subprocess.run(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-o", so, c, "-lm"],
+                   check=True, capture_output=True)
+    return oracle.load_library(so)
+
+
+def _rand_state(E, K, seed):
+    m = np.random.default_rng(seed).uniform(0.05, 1.0, size=(E, K))
+    return m / m.sum(1, keepdims=True)
+
+
+# ---- the battery: each returns True when the pin holds ----
+def pin_tree(lib):
+    prob = inputs.random_tree(8, 3, 2)
+    r = oracle.run(prob, oracle.LBP, eps=1e-13, max_iters=100, lib=lib)
+    return r["converged"] and np.allclose(r["marginals"],
+                                          exact_refs.brute_force_marginals(prob), atol=1e-10)
+
+
+def pin_chain(lib):
+    prob = inputs.chain(60, 2.5, 3)
+    r = oracle.run(prob, oracle.LBP, eps=1e-13, max_iters=500, lib=lib)
+    return r["converged"] and np.allclose(r["marginals"], exact_refs.chain_marginals(prob),
+                                          atol=1e-10)
+
+
+def pin_closed_form(lib):
+    prob = inputs.ising_grid(3, 4, 2.0, 1)
+    E = 2 * len(prob["edges"])
+    m = _rand_state(E, 2, 5)
+    cand, res = oracle.evaluate(prob, m, lib=lib)
+    src, dst = oracle.canonical_src_dst(prob)
+    field = 0.5 * np.log(m[:, 1] / m[:, 0])
+    for e in range(E):
+        others = [f for f in range(E) if dst[f] == src[e] and src[f] != dst[e]]
+        want = exact_refs.ising_message_closed_form(prob["h"][src[e]], prob["coupling"][e // 2],
+                                                    field[others])
+        if not np.allclose(cand[e], want, atol=1e-12):
+            return False
+        if abs(res[e] - np.max(np.abs(want - m[e]))) > 1e-12:
+            return False
+    return True
+
+
+def pin_normalised(lib):
+    prob = inputs.random_dense_graph(7, 10, 3, 4)
+    r = oracle.run(prob, oracle.LBP, eps=1e-6, max_iters=5, lib=lib)
+    return np.allclose(r["msgs"].sum(1), 1.0, atol=1e-13) and np.allclose(
+        r["marginals"].sum(1), 1.0, atol=1e-13)
+
+
+def pin_two_node_beliefs(lib):
+    prob = inputs.random_tree(2, 3, 11)
+    r = oracle.run(prob, oracle.LBP, eps=1e-14, max_iters=10, lib=lib)
+    pa, pb = np.exp(prob["log_unary"][0]), np.exp(prob["log_unary"][1])
+    ba = pa * (prob["pair"][0] @ pb)
+    return np.allclose(r["marginals"][0], ba / ba.sum(), atol=1e-13)
+
+
+def pin_philox(lib):
+    out = oracle.philox4x32_10([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344],
+                               [0xa4093822, 0x299f31d0], lib=lib)
+    return [int(x) for x in out] == [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]
+
+
+def pin_rnbp_definition(lib):
+    prob = inputs.ising_grid(5, 6, 2.0, 6)
+    E = 2 * len(prob["edges"])
+    m0 = _rand_state(E, 2, 2)
+    cand, res = oracle.evaluate(prob, m0)  # reference build for the candidates
+    src, dst = oracle.canonical_src_dst(prob)
+    eps, p, seed, t = 0.02, 0.35, 77, 13
+    u = np.array([oracle.uniform(seed, src[e], dst[e], t) for e in range(E)])
+    sel = (res > eps) & (u < p)
+    r = oracle.run(prob, oracle.RNBP, eps=eps, p=p, dynamic_p=False, seed=seed, max_iters=1,
+                   init_msgs=m0, t0=t, lib=lib)
+    return np.allclose(r["msgs"], np.where(sel[:, None], cand, m0), atol=1e-14)
+
+
+def pin_rbp_sorted(lib):
+    prob = inputs.random_tree(9, 2, 0)
+    prob["pair"] = np.ones_like(prob["pair"])
+    E = 2 * len(prob["edges"])
+    m0 = np.tile([[0.4, 0.6]], (E, 1))
+    src, dst = oracle.canonical_src_dst(prob)
+    order = sorted(range(E), key=lambda e: (dst[e], src[e]))
+    r = oracle.run(prob, oracle.RBP, eps=1e-12, p=3 / E, max_iters=1, init_msgs=m0, lib=lib)
+    changed = np.where(np.any(r["msgs"] != m0, axis=1))[0]
+    return sorted(changed.tolist()) == sorted(order[:3])
+
+
+def pin_rbp_full_is_lbp(lib):
+    prob = inputs.ising_grid(5, 5, 2.5, 1)
+    a = oracle.run(prob, oracle.LBP, eps=1e-4, max_iters=20, lib=lib)
+    b = oracle.run(prob, oracle.RBP, eps=1e-4, p=1.0, max_iters=20, lib=lib)
+    return np.array_equal(a["msgs"], b["msgs"])
+
+
+def pin_dynamic_p(lib):
+    prob = inputs.ising_grid(10, 10, 1.5, 8)
+    r = oracle.run(prob, oracle.RNBP, eps=1e-4, p=0.3, seed=5, max_iters=100, trace=True,
+                   lib=lib)
+    a, pt = r["trace"]["active"], r["trace"]["p"]
+    if pt[0] != 1.0:
+        return False
+    return all(pt[t] == (0.3 if a[t] / a[t - 1] > 0.9 else 1.0) for t in range(1, len(a)))
+
+
+def pin_weak_coupling_agree(lib):
+    prob = inputs.ising_grid(6, 6, 0.25, 5)
+    ref = oracle.run(prob, oracle.LBP, eps=1e-11, max_iters=2000, lib=lib)
+    r = oracle.run(prob, oracle.RNBP, eps=1e-11, p=0.3, seed=1, max_iters=100000, lib=lib)
+    return np.allclose(ref["marginals"], r["marginals"], atol=1e-9)
+
+
+BATTERY = [pin_tree, pin_chain, pin_closed_form, pin_normalised, pin_two_node_beliefs,
+           pin_philox, pin_rnbp_definition, pin_rbp_sorted, pin_rbp_full_is_lbp,
+           pin_dynamic_p, pin_weak_coupling_agree]
+
+MUTANTS = {
+    "reverse_message_not_excluded": ("if (f == back) continue;", ";"),
+    "unary_dropped_from_update": ("double prod = g->unary[(int64_t)i * K + xi];",
+                                  "double prod = 1.0;"),
+    "pairwise_not_transposed_for_reverse": (
+        "return (e & 1) ? pair_psi(g, u, xj, xi) : pair_psi(g, u, xi, xj);",
+        "return pair_psi(g, u, xi, xj);"),
+    "spin_sign_of_one_end": ("double sa = xa ? 1.0 : -1.0,", "double sa = xa ? -1.0 : 1.0,"),
+    "update_not_normalised": ("for (int xj = 0; xj < K; ++xj) out[xj] /= z;", ";"),
+    "belief_unary_dropped": ("double b = g->unary[(int64_t)i * K + x];", "double b = 1.0;"),
+    "residual_l1_not_linf": ("if (d > r) r = d;\n            }\n            res[e] = r;",
+                             "r += d;\n            }\n            res[e] = r;"),
+    "asynchronous_commit": ("            res[e] = r;\n",
+                            "            res[e] = r;\n            if (schedule == OR_LBP) "
+                            "for (int x = 0; x < K; ++x) m[e * K + x] = cand[e * K + x];\n"),
+    "rng_counter_src_dst_swapped": (
+        "double u = oracle_uniform(seed, (uint32_t)msg_src(&g, e),\n"
+        "                                          (uint32_t)msg_dst(&g, e), (uint32_t)t);",
+        "double u = oracle_uniform(seed, (uint32_t)msg_dst(&g, e),\n"
+        "                                          (uint32_t)msg_src(&g, e), (uint32_t)t);"),
+    "edge_ratio_inverted": ("(double)n_t / (double)n_prev > ratio_threshold",
+                            "(double)n_t / (double)n_prev < ratio_threshold"),
+    "tie_break_descending_target": ("if (da != db) return da < db ? -1 : 1;",
+                                    "if (da != db) return da > db ? -1 : 1;"),
+    "philox_multiplier": ("const uint32_t M0 = 0xD2511F53u", "const uint32_t M0 = 0xD2511F55u"),
+    "eps_filter_dropped": ("if (!(res[e] > eps)) continue;", ";"),
+}
+
+
+@pytest.fixture(scope="module")
+def tmpdir():
+    with tempfile.TemporaryDirectory() as d:
+        yield d
+
+
+def test_unmutated_build_passes_battery(tmpdir):
+    lib = _compile(open(SRC).read(), tmpdir, "base")
+    failed = [f.__name__ for f in BATTERY if not f(lib)]
+    assert failed == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmpdir):
+    text = open(SRC).read()
+    old, new = MUTANTS[name]
+    assert text.count(old) == 1, f"mutation anchor for {name} not unique"
+    lib = _compile(text.replace(old, new), tmpdir, name)
+    caught = []
+    for f in BATTERY:
+        try:
+            ok = f(lib)
+        except Exception:
+            ok = False
+        if not ok:
+            caught.append(f.__name__)
+    assert caught, f"mutant {name} passed every pin"

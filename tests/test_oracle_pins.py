@@ -1,0 +1,380 @@
+"""Pins of the FP64 oracle against facts fixed outside it.
+
+Every check here compares the oracle with something other than itself: exact
+inference (enumeration, forward-backward, row elimination), the closed form of
+Eq. (2) for binary spins, published Philox known-answer vectors, symmetries and
+invariants of the update, and the frontier rules re-derived from their
+definitions in numpy.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_11469_amd import inputs
+from tests import exact_refs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 (random filter of Sec. IV-A)
+# --------------------------------------------------------------------------
+def _kat_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            w = [int(x, 16) for x in line.split()]
+            rows.append((w[0:4], w[4:6], w[6:10]))
+    return rows
+
+
+@pytest.mark.parametrize("ctr,key,out", _kat_rows())
+def test_philox_known_answers(ctr, key, out):
+    got = oracle.philox4x32_10(ctr, key)
+    assert [int(x) for x in got] == out
+
+
+def test_uniform_is_word0_top24_bits():
+    seed = 0x0123456789ABCDEF
+    for (s, d, t) in [(0, 1, 0), (5, 7, 3), (123456, 99, 4095)]:
+        w = oracle.philox4x32_10([s, d, t, 0], [seed & 0xFFFFFFFF, seed >> 32])
+        assert oracle.uniform(seed, s, d, t) == (int(w[0]) >> 8) / float(1 << 24)
+
+
+def test_uniform_fraction_within_binomial_bound():
+    n, p = 20000, 0.3
+    u = np.array([oracle.uniform(7, i, i + 1, 11) for i in range(n)])
+    assert u.min() >= 0.0 and u.max() < 1.0
+    frac = np.mean(u < p)
+    assert abs(frac - p) < 5 * np.sqrt(p * (1 - p) / n)
+
+
+# --------------------------------------------------------------------------
+# Eq. (2)/(3) exact on trees and chains (BP is exact on trees)
+# --------------------------------------------------------------------------
+def _tree_diameter(n, edges):
+    adj = [[] for _ in range(n)]
+    for a, b in edges:
+        adj[a].append(b)
+        adj[b].append(a)
+
+    def far(s):
+        dist = [-1] * n
+        dist[s] = 0
+        st = [s]
+        while st:
+            v = st.pop()
+            for w in adj[v]:
+                if dist[w] < 0:
+                    dist[w] = dist[v] + 1
+                    st.append(w)
+        i = int(np.argmax(dist))
+        return i, dist[i]
+
+    a, _ = far(0)
+    _, d = far(a)
+    return d
+
+
+@pytest.mark.parametrize("n,K,seed", [(2, 2, 0), (5, 2, 1), (9, 3, 2), (11, 2, 3), (7, 4, 4)])
+def test_tree_marginals_equal_enumeration(n, K, seed):
+    prob = inputs.random_tree(n, K, seed)
+    exact = exact_refs.brute_force_marginals(prob)
+    r = oracle.run(prob, oracle.LBP, eps=1e-13, max_iters=200)
+    assert r["converged"]
+    # synchronous BP on a tree is exact after (diameter) sweeps
+    assert r["iterations"] <= _tree_diameter(n, prob["edges"]) + 1
+    np.testing.assert_allclose(r["marginals"], exact, atol=1e-12, rtol=0)
+
+
+def test_chain_marginals_equal_forward_backward():
+    # the paper's chain setting: C = 10 (psi_ij = e^{+-lambda C}, lambda ~ U[-0.5, 0.5])
+    prob = inputs.paper_ising_grid(1, 300, 10.0, 5)
+    exact = exact_refs.chain_marginals(prob)
+    r = oracle.run(prob, oracle.LBP, eps=1e-14, max_iters=1000)
+    assert r["converged"]
+    np.testing.assert_allclose(r["marginals"], exact, atol=1e-10, rtol=0)
+
+
+def test_chain_marginals_rnbp_and_rbp_exact():
+    prob = inputs.chain(200, 2.5, 9)
+    exact = exact_refs.chain_marginals(prob)
+    for sched, p in [(oracle.RNBP, 0.3), (oracle.RBP, 0.25)]:
+        r = oracle.run(prob, sched, eps=1e-13, p=p, seed=4, max_iters=20000)
+        assert r["converged"]
+        np.testing.assert_allclose(r["marginals"], exact, atol=1e-10, rtol=0)
+
+
+def test_two_node_closed_form():
+    # one edge: b_a(x) is proportional to psi_a(x) sum_y psi(x, y) psi_b(y)
+    prob = inputs.random_tree(2, 3, 11)
+    r = oracle.run(prob, oracle.LBP, eps=1e-14, max_iters=10)
+    pa = np.exp(prob["log_unary"][0])
+    pb = np.exp(prob["log_unary"][1])
+    T = prob["pair"][0]
+    ba = pa * (T @ pb)
+    bb = pb * (T.T @ pa)
+    np.testing.assert_allclose(r["marginals"][0], ba / ba.sum(), atol=1e-14)
+    np.testing.assert_allclose(r["marginals"][1], bb / bb.sum(), atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Eq. (2) closed form for binary Ising potentials
+# --------------------------------------------------------------------------
+def _random_state(E, K, rng):
+    m = rng.uniform(0.05, 1.0, size=(E, K))
+    return m / m.sum(axis=1, keepdims=True)
+
+
+@pytest.mark.parametrize("C,seed", [(1.0, 0), (2.5, 1), (4.0, 2)])
+def test_ising_update_matches_closed_form(C, seed):
+    prob = inputs.ising_grid(5, 6, C, seed)
+    rng = np.random.default_rng(seed + 100)
+    E = 2 * len(prob["edges"])
+    m = _random_state(E, 2, rng)
+    cand, res = oracle.evaluate(prob, m)
+    src, dst = oracle.canonical_src_dst(prob)
+    h = prob["h"]
+    J = prob["coupling"]
+    field = 0.5 * np.log(m[:, 1] / m[:, 0])
+    for e in range(E):
+        i, j = src[e], dst[e]
+        others = [f for f in range(E) if dst[f] == i and src[f] != j]
+        want = exact_refs.ising_message_closed_form(h[i], J[e // 2], field[others])
+        np.testing.assert_allclose(cand[e], want, atol=1e-13, rtol=0)
+        assert res[e] == pytest.approx(np.max(np.abs(want - m[e])), abs=1e-13)
+
+
+def test_dense_update_against_explicit_formula_small():
+    # K = 3 loopy graph: Eq. (2) written out with an explicit loop over x_i
+    prob = inputs.random_dense_graph(6, 9, 3, 3)
+    rng = np.random.default_rng(3)
+    E = 2 * len(prob["edges"])
+    m = _random_state(E, 3, rng)
+    cand, _ = oracle.evaluate(prob, m)
+    edges = prob["edges"]
+    psi_i = np.exp(prob["log_unary"])
+    for e in range(E):
+        u = e // 2
+        a, b = int(edges[u, 0]), int(edges[u, 1])
+        i, j = (a, b) if e % 2 == 0 else (b, a)
+        T = prob["pair"][u] if e % 2 == 0 else prob["pair"][u].T  # T[x_i, x_j]
+        incoming = []
+        for f in range(E):
+            fu = f // 2
+            fa, fb = int(edges[fu, 0]), int(edges[fu, 1])
+            fs, fd = (fa, fb) if f % 2 == 0 else (fb, fa)
+            if fd == i and fs != j:
+                incoming.append(m[f])
+        g = psi_i[i].copy()
+        for v in incoming:
+            g = g * v
+        c = np.array([sum(T[xi, xj] * g[xi] for xi in range(3)) for xj in range(3)])
+        np.testing.assert_allclose(cand[e], c / c.sum(), atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# The paper's correctness protocol (Sec. IV-E): 10 x 10 Ising, C = 2,
+# exact marginals by variable elimination, KL(exact || BP)
+# --------------------------------------------------------------------------
+def test_transfer_matrix_matches_enumeration_small_grid():
+    prob = inputs.paper_ising_grid(3, 4, 2.0, 1)
+    np.testing.assert_allclose(exact_refs.grid_marginals_transfer(prob, 3, 4),
+                               exact_refs.brute_force_marginals(prob), atol=1e-12)
+
+
+@pytest.mark.slow
+def test_paper_10x10_kl_protocol():
+    kls = {"lbp": [], "rnbp": [], "rbp": []}
+    for seed in range(4):
+        prob = inputs.paper_ising_grid(10, 10, 2.0, seed)
+        exact = exact_refs.grid_marginals_transfer(prob, 10, 10)
+        r_l = oracle.run(prob, oracle.LBP, eps=1e-8, max_iters=5000)
+        r_n = oracle.run(prob, oracle.RNBP, eps=1e-8, p=0.7, seed=seed, max_iters=20000)
+        r_r = oracle.run(prob, oracle.RBP, eps=1e-8, p=1 / 16, max_iters=50000)
+        assert r_l["converged"] and r_n["converged"] and r_r["converged"]
+        kls["lbp"].append(exact_refs.kl_divergence(exact, r_l["marginals"]))
+        kls["rnbp"].append(exact_refs.kl_divergence(exact, r_n["marginals"]))
+        kls["rbp"].append(exact_refs.kl_divergence(exact, r_r["marginals"]))
+        # at paper C = 2 the fixed point is unique: every schedule lands on it
+        np.testing.assert_allclose(r_n["marginals"], r_l["marginals"], atol=1e-6)
+        np.testing.assert_allclose(r_r["marginals"], r_l["marginals"], atol=1e-6)
+    # loopy BP is approximate but close on this easy family
+    assert max(kls["lbp"]) < 0.02
+    assert max(kls["rnbp"]) < 0.02
+
+
+# --------------------------------------------------------------------------
+# Invariants
+# --------------------------------------------------------------------------
+def test_messages_normalised_and_ising_bounds():
+    prob = inputs.ising_grid(8, 8, 2.5, 3)
+    for sched, p in [(oracle.LBP, 1.0), (oracle.RNBP, 0.3), (oracle.RBP, 0.1)]:
+        r = oracle.run(prob, sched, eps=1e-4, p=p, seed=1, max_iters=37)
+        m = r["msgs"]
+        np.testing.assert_allclose(m.sum(axis=1), 1.0, atol=1e-14)
+        Jabs = np.abs(prob["coupling"])[np.arange(len(m)) // 2]
+        ratio = m[:, 1] / m[:, 0]
+        # m(+1)/m(-1) lies in [e^{-2|J|}, e^{2|J|}] after an update (or 1 if untouched)
+        assert np.all(ratio <= np.exp(2 * Jabs) * (1 + 1e-12))
+        assert np.all(ratio >= np.exp(-2 * Jabs) * (1 - 1e-12))
+
+
+def test_spin_flip_symmetry_all_schedules():
+    prob = inputs.ising_grid(6, 7, 2.0, 4)
+    flip = dict(prob)
+    flip["log_unary"] = prob["log_unary"][:, ::-1].copy()
+    for sched, p in [(oracle.LBP, 1.0), (oracle.RNBP, 0.4), (oracle.RBP, 0.2)]:
+        a = oracle.run(prob, sched, eps=1e-6, p=p, seed=9, max_iters=60, trace=True)
+        b = oracle.run(flip, sched, eps=1e-6, p=p, seed=9, max_iters=60, trace=True)
+        np.testing.assert_allclose(a["marginals"], b["marginals"][:, ::-1], atol=1e-12)
+        np.testing.assert_array_equal(a["trace"]["active"], b["trace"]["active"])
+        np.testing.assert_array_equal(a["trace"]["frontier"], b["trace"]["frontier"])
+
+
+def test_zero_coupling_gives_unaries():
+    prob = inputs.ising_grid(5, 5, 0.0, 2)
+    prob["coupling"] = np.zeros_like(prob["coupling"])
+    r = oracle.run(prob, oracle.LBP, eps=1e-12, max_iters=10)
+    assert r["converged"] and r["iterations"] == 0  # uniform messages stay uniform
+    pu = np.exp(prob["log_unary"])
+    np.testing.assert_allclose(r["marginals"], pu / pu.sum(1, keepdims=True), atol=1e-14)
+
+
+def test_zero_field_uniform_is_fixed_point():
+    prob = inputs.ising_grid(6, 6, 2.5, 7)
+    prob["log_unary"] = np.zeros_like(prob["log_unary"])
+    for sched in (oracle.LBP, oracle.RNBP, oracle.RBP):
+        r = oracle.run(prob, sched, eps=1e-12, p=0.5, max_iters=5)
+        assert r["converged"] and r["iterations"] == 0 and r["last_active"] == 0
+        np.testing.assert_allclose(r["marginals"], 0.5, atol=1e-15)
+
+
+def test_weak_coupling_all_schedules_agree():
+    prob = inputs.ising_grid(9, 9, 0.25, 5)
+    ref = oracle.run(prob, oracle.LBP, eps=1e-11, max_iters=2000)
+    assert ref["converged"]
+    for sched, p, seed in [(oracle.RBP, 0.1, 0), (oracle.RBP, 0.5, 0), (oracle.RNBP, 0.3, 1),
+                           (oracle.RNBP, 0.7, 2), (oracle.RNBP, 0.1, 3)]:
+        r = oracle.run(prob, sched, eps=1e-11, p=p, seed=seed, max_iters=200000)
+        assert r["converged"]
+        np.testing.assert_allclose(r["marginals"], ref["marginals"], atol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Frontier rules re-derived from their definitions
+# --------------------------------------------------------------------------
+def test_rbp_full_fraction_equals_lbp_bitwise():
+    prob = inputs.ising_grid(7, 7, 2.5, 1)
+    a = oracle.run(prob, oracle.LBP, eps=1e-4, max_iters=50)
+    b = oracle.run(prob, oracle.RBP, eps=1e-4, p=1.0, max_iters=50)
+    assert np.array_equal(a["msgs"], b["msgs"])
+    assert a["iterations"] == b["iterations"]
+
+
+def test_static_rnbp_full_fraction_commits_exactly_the_active_set():
+    prob = inputs.ising_grid(6, 6, 2.0, 2)
+    rng = np.random.default_rng(0)
+    m0 = _random_state(2 * len(prob["edges"]), 2, rng)
+    cand, res = oracle.evaluate(prob, m0)
+    eps = 0.05
+    r = oracle.run(prob, oracle.RNBP, eps=eps, p=1.0, dynamic_p=False, max_iters=1,
+                   init_msgs=m0)
+    want = np.where((res > eps)[:, None], cand, m0)
+    assert np.array_equal(r["msgs"], want)
+
+
+@pytest.mark.parametrize("p", [0.01, 0.1, 0.37, 0.9])
+def test_rbp_topk_against_python_sorted(p):
+    prob = inputs.random_dense_graph(8, 14, 3, 5)
+    rng = np.random.default_rng(1)
+    E = 2 * len(prob["edges"])
+    m0 = _random_state(E, 3, rng)
+    cand, res = oracle.evaluate(prob, m0)
+    src, dst = oracle.canonical_src_dst(prob)
+    k = max(1, int(np.ceil(p * E)))
+    order = sorted(range(E), key=lambda e: (-res[e], dst[e], src[e]))
+    sel = np.zeros(E, bool)
+    sel[order[:k]] = True
+    r = oracle.run(prob, oracle.RBP, eps=1e-12, p=p, max_iters=1, init_msgs=m0)
+    want = np.where(sel[:, None], cand, m0)
+    assert np.array_equal(r["msgs"], want)
+
+
+def test_rbp_tie_break_by_target_then_source():
+    # J = 0 makes every candidate uniform, so from a start state whose rows are all
+    # (0.4, 0.6) every residual is 0.1: the frontier is the k smallest (target, source)
+    prob = inputs.random_tree(6, 2, 0)
+    prob["pair"] = np.ones_like(prob["pair"])
+    E = 2 * len(prob["edges"])
+    m0 = np.tile([[0.4, 0.6]], (E, 1))
+    cand, res = oracle.evaluate(prob, m0)
+    assert np.all(res == res[0])
+    src, dst = oracle.canonical_src_dst(prob)
+    for k in (1, 2, 5):
+        order = sorted(range(E), key=lambda e: (dst[e], src[e]))
+        r = oracle.run(prob, oracle.RBP, eps=1e-12, p=k / E, max_iters=1, init_msgs=m0)
+        changed = np.where(np.any(r["msgs"] != m0, axis=1))[0]
+        assert sorted(changed.tolist()) == sorted(order[:k])
+
+
+def test_rnbp_frontier_against_definition():
+    prob = inputs.ising_grid(7, 8, 2.0, 6)
+    rng = np.random.default_rng(2)
+    E = 2 * len(prob["edges"])
+    m0 = _random_state(E, 2, rng)
+    cand, res = oracle.evaluate(prob, m0)
+    src, dst = oracle.canonical_src_dst(prob)
+    eps, p, seed, t = 0.02, 0.35, 77, 13
+    u = np.array([oracle.uniform(seed, src[e], dst[e], t) for e in range(E)])
+    sel = (res > eps) & (u < p)
+    r = oracle.run(prob, oracle.RNBP, eps=eps, p=p, dynamic_p=False, seed=seed, max_iters=1,
+                   init_msgs=m0, t0=t)
+    want = np.where(sel[:, None], cand, m0)
+    assert np.array_equal(r["msgs"], want)
+    assert 0 < sel.sum() < (res > eps).sum()
+
+
+def test_dynamic_p_follows_edge_ratio():
+    prob = inputs.ising_grid(10, 10, 1.5, 8)
+    lowp, highp, thr = 0.3, 1.0, 0.9
+    r = oracle.run(prob, oracle.RNBP, eps=1e-4, p=lowp, high_p=highp, ratio_threshold=thr,
+                   seed=5, max_iters=300, trace=True)
+    a, pt = r["trace"]["active"], r["trace"]["p"]
+    assert pt[0] == highp
+    for t in range(1, len(a)):
+        want = lowp if a[t] / a[t - 1] > thr else highp
+        assert pt[t] == want
+    assert (pt == lowp).any() and (pt[1:] == highp).any()
+
+
+def test_resume_equals_uninterrupted():
+    prob = inputs.ising_grid(8, 8, 1.5, 2)
+    kw = dict(schedule=oracle.RNBP, eps=1e-4, p=0.4, seed=3)
+    full = oracle.run(prob, max_iters=40, trace=True, **kw)
+    first = oracle.run(prob, max_iters=15, trace=True, **kw)
+    # resume from the state after 15 commits at t = 15 with n_14 known
+    second = oracle.run(prob, max_iters=25, init_msgs=first["msgs"], t0=15,
+                        prev_active=int(first["trace"]["active"][14]), trace=True, **kw)
+    assert np.array_equal(full["msgs"], second["msgs"])
+    assert np.array_equal(full["trace"]["active"][15:], second["trace"]["active"])
+
+
+# --------------------------------------------------------------------------
+# Qualitative claims of Sec. III-D / IV-D (sanity, not parity)
+# --------------------------------------------------------------------------
+@pytest.mark.slow
+def test_lower_parallelism_converges_more_often():
+    conv = {"lbp": 0, "rnbp": 0}
+    for s in range(6):
+        prob = inputs.ising_grid(16, 16, 1.5, 100 + s)
+        conv["lbp"] += oracle.run(prob, oracle.LBP, eps=1e-4, max_iters=1500)["converged"]
+        conv["rnbp"] += oracle.run(prob, oracle.RNBP, eps=1e-4, p=0.3, seed=s,
+                                   max_iters=1500)["converged"]
+    assert conv["rnbp"] >= conv["lbp"]
+    assert conv["rnbp"] > 0
