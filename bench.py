@@ -1,0 +1,181 @@
+"""Benchmark: randomized BP (RnBP) on the 1000 x 1000 Ising grid on one MI355X.
+
+A step is one complete solve through the C ABI: bp_run (messages reset to
+uniform, RnBP with the EdgeRatio rule, eps = 1e-4, at most 10000 iterations)
+followed by Eq. (3) beliefs into device memory.  Every iteration of a solve runs
+the whole hot path: node aggregates, Eq. (2) for every directed message, the
+residual of Eq. (4), the count / max reduction, the p schedule, the eps and
+random filters and the commit.  The graph (h ~ U[-1, 1], J ~ U[-C, C]) is built
+and uploaded before the timed region; each step uses a different RNG seed.
+
+Prints one JSON line.  ``value`` is message updates (Eq. (2) evaluations) per
+second over the timed steps.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def eval_kernel_bytes(N, E):
+    """Algorithmic bytes of one launch of the K = 2 evaluation kernel in RnBP
+    mode: per directed message the in-slot log-odds (4), the reverse-slot old
+    value (4), the committed value (4), the reverse index (4), the coupling (4)
+    and the source id for the RNG counter (4); per node the slot offset (4) and
+    the unary log-odds (4)."""
+    return 24 * E + 8 * N
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size", type=int, default=1000)
+    ap.add_argument("--C", type=float, default=2.5)
+    ap.add_argument("--p", type=float, default=0.5)
+    ap.add_argument("--eps", type=float, default=1e-4)
+    ap.add_argument("--max-iters", type=int, default=10000)
+    ap.add_argument("--check-every", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--no-ttc", action="store_true")
+    ap.add_argument("--ttc-seeds", type=int, default=3)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding design); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    lib = os.path.join(ROOT, "paper_1909_11469_amd", "libbp.so")
+    if not os.path.exists(lib):
+        import __graft_entry__
+        __graft_entry__.build()
+
+    import numpy as np
+    import torch
+
+    from paper_1909_11469_amd import bp, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    S = args.size
+    _log(f"bench: building Ising {S}x{S} C={args.C}")
+    prob = inputs.ising_grid(S, S, args.C, 0)
+    N, E = prob["N"], 2 * len(prob["edges"])
+    g = bp.Graph(prob)
+    marg = torch.empty((N, 2), dtype=torch.float32, device="cuda")
+    run_kw = dict(eps=args.eps, p=args.p, max_iters=args.max_iters,
+                  check_every=args.check_every)
+
+    for w in range(args.warmup):
+        r = g.run("rnbp", seed=1000 + w, **run_kw)
+        g.marginals_device(marg)
+        _log(f"bench: warmup {w} iterations={r['iterations']} converged={r['converged']}")
+    torch.cuda.synchronize()
+
+    evaluated = committed = iters = conv = 0
+    kern_ms = 0.0
+    kern_n = 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        r = g.run("rnbp", seed=k, profile=True, **run_kw)
+        g.marginals_device(marg)
+        evaluated += r["evaluated"]
+        committed += r["committed"]
+        iters += r["iterations"]
+        conv += int(r["converged"])
+        kern_ms += r["eval_kernel_ms"]
+        kern_n += r["eval_kernel_launches"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    _log(f"bench: timed {args.steps} steps in {elapsed:.3f} s, {iters} iterations, "
+         f"{conv} converged")
+
+    avg_kernel_s = kern_ms / max(kern_n, 1) / 1e3
+    nbytes = eval_kernel_bytes(N, E)
+    achieved = nbytes / avg_kernel_s if avg_kernel_s > 0 else 0.0
+    roofline = {"bound": "hbm", "kernel": "k_eval_logodds<RnBP>",
+                "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK, "traffic": None,
+                "bytes_per_launch": nbytes, "avg_kernel_us": avg_kernel_s * 1e6,
+                "launches": kern_n}
+
+    out = {
+        "metric": "message updates/s (1000x1000 Ising, RnBP)",
+        "value": evaluated / elapsed,
+        "unit": "message updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"ising_{S}x{S}", "C": args.C, "schedule": "rnbp",
+                   "low_p": args.p, "high_p": 1.0, "eps": args.eps,
+                   "max_iters": args.max_iters, "messages": E, "variables": N,
+                   "iterations_timed": iters, "converged_steps": conv,
+                   "committed_updates_per_s": committed / elapsed},
+        "roofline": roofline,
+    }
+
+    if not args.no_ttc:
+        # time to convergence, RnBP vs LBP, per coupling scale (graph resident)
+        ttc = {}
+        for C in (1.0, 2.5, 4.0):
+            rows = {"lbp": [], "rnbp": []}
+            for s in range(args.ttc_seeds):
+                pr = inputs.ising_grid(S, S, C, 100 + s)
+                with bp.Graph(pr) as gg:
+                    for sched in ("lbp", "rnbp"):
+                        torch.cuda.synchronize()
+                        a = time.perf_counter()
+                        rr = gg.run(sched, seed=s, **run_kw)
+                        torch.cuda.synchronize()
+                        rows[sched].append((rr["converged"], time.perf_counter() - a,
+                                            rr["iterations"]))
+                _log(f"bench: ttc C={C} seed={100 + s} lbp={rows['lbp'][-1]} "
+                     f"rnbp={rows['rnbp'][-1]}")
+            ttc[f"C={C}"] = {
+                k: {"converged": sum(c for c, _, _ in v), "graphs": len(v),
+                    "mean_s_converged": (float(np.mean([t for c, t, _ in v if c]))
+                                         if any(c for c, _, _ in v) else None),
+                    "mean_iterations": float(np.mean([i for _, _, i in v]))}
+                for k, v in rows.items()}
+        out["time_to_convergence"] = ttc
+
+    if not args.no_cpu_baseline:
+        import oracle
+        _log(f"bench: cpu baseline, {args.cpu_iters} oracle iterations")
+        a = time.perf_counter()
+        rr = oracle.run(prob, oracle.RNBP, eps=args.eps, p=args.p, seed=0,
+                        max_iters=args.cpu_iters)
+        dt = time.perf_counter() - a
+        out["cpu_baseline"] = {
+            "value": rr["evaluated"] / dt, "unit": "message updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{args.cpu_iters} RnBP iterations ({rr['evaluated']} Eq. (2) "
+                      f"evaluations) of the same {S}x{S} grid, FP64, single thread, "
+                      f"{dt:.1f} s"}
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

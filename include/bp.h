@@ -1,0 +1,204 @@
+/*
+ * bp.h -- C ABI of libbp: frontier-based sum-product belief propagation on
+ * pairwise Markov random fields, on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Sec. II-A, Eq. (1)): N discrete variables with K states each, a
+ * positive unary potential psi_i per variable and a positive pairwise potential
+ * psi_ij per undirected edge.  Every edge carries two directed messages, so a
+ * graph with M edges has E = 2M messages.  Messages start uniform, are
+ * normalised after every update and are updated with Eq. (2); beliefs follow
+ * Eq. (3).
+ *
+ * Solver (Alg. 1): repeat { evaluate f_BP(m^t) and the residual of Eq. (4) for
+ * every message; stop if no residual exceeds eps; choose a frontier; commit
+ * the frontier's new values }.  Frontier rules:
+ *   BP_LBP   every message (synchronous loopy BP, Sec. II-B);
+ *   BP_RBP   the k = max(1, ceil(p * E)) messages with the largest residuals,
+ *            ties by (target, source) ascending (bulk greedy top-k, Sec. III-A);
+ *   BP_RNBP  messages with residual > eps, each then kept with probability p_t
+ *            (randomized BP, Sec. IV-A); with dynamic p, p_t is the low
+ *            setting p when n_t / n_{t-1} > ratio_threshold, else high_p, where
+ *            n_t counts messages with residual > eps (EdgeRatio, Sec. IV-A).
+ *
+ * Conventions
+ *   - Residual: L-infinity norm of the change of the normalised message.
+ *   - Canonical message order (used by bp_get_state / bp_set_state): for the
+ *     undirected edge u = edges[u] = (a, b), row 2u is the message a -> b and
+ *     row 2u + 1 is b -> a.
+ *   - Random filter: U = (w >> 8) * 2^-24 where w is word 0 of
+ *     Philox4x32-10 (Salmon et al., SC'11) with key (seed & 0xffffffff,
+ *     seed >> 32) and counter (source node, target node, t, 0); a message is
+ *     kept when U < p_t.  Results do not depend on the storage order.
+ *   - Messages are FP32 on the device; parameters are given in FP64 and
+ *     rounded to FP32 when the graph is created.
+ *   - Same inputs on the same device give bitwise identical results.
+ *
+ * Memory and threads
+ *   - Every input array is host memory, read during the call and copied; the
+ *     caller keeps ownership.  Output arrays are caller-owned host memory
+ *     unless a function says device.
+ *   - A graph owns its device memory (allocated at creation, or carved from
+ *     the caller's workspace, see bp_graph_desc.workspace) until
+ *     bp_destroy_graph.  All device work of a graph is ordered on its stream.
+ *   - Calls on one graph must not overlap; different graphs are independent.
+ *   - Errors: functions return a bp_status; bp_last_error() gives a
+ *     thread-local description of the last failure in the calling thread.
+ */
+#ifndef BP_H
+#define BP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BP_ABI_VERSION 1
+
+typedef enum bp_status {
+    BP_OK = 0,              /* success; for bp_run: converged */
+    BP_NOT_CONVERGED = 1,   /* bp_run reached max_iters; state and marginals valid */
+    BP_EINVAL = -1,         /* invalid argument or problem description */
+    BP_ENOMEM = -2,         /* device or host allocation failed, or workspace too small */
+    BP_EDEVICE = -3,        /* HIP runtime error (no device, launch failure, ...) */
+    BP_ESTATE = -4          /* call not valid for the graph's current state */
+} bp_status;
+
+typedef enum bp_pair_kind {
+    /* K = 2, psi_ij(x_a, x_b) = exp(J_u s_a s_b), spin s = -1 for state 0 and +1
+     * for state 1; coupling[u] = J_u (any finite value). */
+    BP_PAIR_ISING = 0,
+    /* psi_u(x_a, x_b) = edge_scale[u] * shared[x_a][x_b]; shared [K][K] > 0 and
+     * edge_scale [M] > 0.  (A per-edge scale cancels in the normalised Eq. (2);
+     * it is validated but does not change any result.) */
+    BP_PAIR_SHARED = 1,
+    /* psi_u(x_a, x_b) = pair[u][x_a][x_b] > 0, [M][K][K]. */
+    BP_PAIR_DENSE = 2
+} bp_pair_kind;
+
+typedef enum bp_schedule { BP_LBP = 0, BP_RBP = 1, BP_RNBP = 2 } bp_schedule;
+
+/* bp_graph_desc.flags */
+#define BP_FLAG_GENERIC_LAYOUT 1u /* K = 2 Ising: keep [E][2] probabilities instead of
+                                    one log-odds value per message */
+
+typedef struct bp_graph bp_graph;
+
+typedef struct bp_graph_desc {
+    int32_t num_vars;         /* N, 1 <= N < 2^31 */
+    int32_t num_states;       /* K, 2 <= K <= 64 */
+    int64_t num_edges;        /* M, 0 <= M, 2M < 2^31 */
+    const int32_t* edges;     /* host [M][2]: 0 <= a, b < N, a != b, no duplicate {a, b} */
+    const double* log_unary;  /* host [N][K]: psi_i(x) = exp(log_unary[i][x]), finite */
+    int32_t pair_kind;        /* bp_pair_kind */
+    uint32_t flags;           /* BP_FLAG_* */
+    const double* coupling;   /* host [M], BP_PAIR_ISING only, finite */
+    const double* shared;     /* host [K][K], BP_PAIR_SHARED only, > 0 and finite */
+    const double* edge_scale; /* host [M], BP_PAIR_SHARED only, > 0 and finite */
+    const double* pair;       /* host [M][K][K], BP_PAIR_DENSE only, > 0 and finite */
+    void* stream;             /* hipStream_t for all device work, NULL = null stream */
+    void* workspace;          /* optional caller-owned device memory, 256-byte aligned,
+                                 at least bp_workspace_bytes(); NULL = library allocates */
+    uint64_t workspace_bytes;
+} bp_graph_desc;
+
+typedef struct bp_run_opts {
+    int64_t max_iters;        /* maximum number of commits (sweeps); default 10000 */
+    int32_t check_every;      /* host polls the device convergence flag every this
+                                 many iterations; default 16; results do not depend on it */
+    int32_t dynamic_p;        /* BP_RNBP: 1 = EdgeRatio rule (default), 0 = p_t = p */
+    double high_p;            /* BP_RNBP dynamic: high setting, default 1.0 */
+    double ratio_threshold;   /* BP_RNBP dynamic: default 0.9 */
+    int32_t warm_start;       /* 0 (default): messages reset to uniform 1/K and t = 0;
+                                 1: continue from the current messages and iteration state */
+    int32_t profile;          /* 1: time the evaluation kernel with HIP events */
+} bp_run_opts;
+
+typedef struct bp_run_stats {
+    int64_t iterations;        /* commits performed by this call */
+    int32_t converged;         /* 1 if an evaluation found no residual > eps */
+    int32_t reserved0;
+    int64_t last_active;       /* n_t of the last evaluation */
+    double last_max_residual;  /* max residual of the last evaluation */
+    int64_t evaluated;         /* Eq. (2) evaluations performed by this call */
+    int64_t committed;         /* messages committed by this call */
+    int64_t final_t;           /* global iteration number of the last evaluation */
+    double device_ms;          /* stream time of the whole call (HIP events) */
+    double eval_kernel_ms;     /* profile: summed duration of the evaluation kernel */
+    int64_t eval_kernel_launches; /* profile: number of evaluation-kernel launches timed */
+} bp_run_stats;
+
+/* Iteration state carried between runs (checkpoint / resume, Alg. 1 loop). */
+typedef struct bp_iter_state {
+    int64_t t;            /* global iteration number of the next evaluation */
+    int64_t prev_active;  /* n_{t-1}, or -1 if none (then p_t = high_p) */
+} bp_iter_state;
+
+typedef struct bp_graph_info {
+    int32_t num_vars;
+    int32_t num_states;
+    int64_t num_edges;
+    int64_t num_messages;     /* E = 2M */
+    int32_t layout;           /* 0 = one log-odds value per message (K = 2 Ising),
+                                 1 = [E][K] probabilities */
+    int32_t num_tiles;        /* node tiles of the evaluation kernel */
+    uint64_t device_bytes;    /* device memory held by the graph */
+} bp_graph_info;
+
+/* Fill *opts with the defaults listed in bp_run_opts. */
+void bp_default_opts(bp_run_opts* opts);
+
+/* Device bytes bp_create_graph needs for this description (for a caller-owned
+ * workspace).  Validates the description; returns BP_OK or BP_EINVAL. */
+int bp_workspace_bytes(const bp_graph_desc* desc, uint64_t* bytes);
+
+/* Validate the problem (ranges, self-loops, duplicate edges, positivity and
+ * finiteness of potentials, K range), build the device layout (directed
+ * messages grouped by target, reverse-message index, node tiles), upload it
+ * and set messages to uniform.  *out receives the handle.
+ * Errors: BP_EINVAL, BP_ENOMEM, BP_EDEVICE; *out is NULL on error. */
+int bp_create_graph(const bp_graph_desc* desc, bp_graph** out);
+
+/* Run Alg. 1 with the given frontier rule (see top of file).
+ *   eps   convergence and filter threshold, >= 0 and finite
+ *   p     BP_RBP: fraction of messages per iteration; BP_RNBP: the low setting
+ *         (static: the probability); in (0, 1]; ignored by BP_LBP
+ *   seed  Philox key for BP_RNBP; ignored otherwise
+ *   opts  NULL = defaults; stats NULL = not returned.
+ * Returns BP_OK if converged, BP_NOT_CONVERGED at max_iters, negative on error.
+ * On return the graph holds the final messages and iteration state. */
+int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed,
+           const bp_run_opts* opts, bp_run_stats* stats);
+
+/* Eq. (3) beliefs from the current messages into host [N][K] FP32; each row
+ * sums to 1 up to rounding. */
+int bp_marginals(bp_graph* g, float* out);
+
+/* Same, into caller-owned device memory [N][K] FP32, ordered on the graph's
+ * stream (no synchronisation). */
+int bp_marginals_device(bp_graph* g, float* out_device);
+
+/* Copy the current messages to host [E][K] FP32 in canonical order and the
+ * iteration state to *st (either may be NULL). */
+int bp_get_state(bp_graph* g, float* msgs, bp_iter_state* st);
+
+/* Replace the messages (host [E][K] FP32, canonical order, each row positive;
+ * rows are renormalised to sum 1) and/or the iteration state (either may be
+ * NULL).  Use with bp_run_opts.warm_start = 1. */
+int bp_set_state(bp_graph* g, const float* msgs, const bp_iter_state* st);
+
+/* Sizes and layout of a graph. */
+int bp_graph_info_get(const bp_graph* g, bp_graph_info* info);
+
+/* Release the graph's device memory (not a caller workspace) and the handle.
+ * NULL is ignored. */
+void bp_destroy_graph(bp_graph* g);
+
+/* Description of the last error in the calling thread ("" if none). */
+const char* bp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BP_H */

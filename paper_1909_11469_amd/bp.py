@@ -1,0 +1,282 @@
+"""ctypes binding of libbp (include/bp.h) with the same entry-point names.
+
+Argument marshalling only: every step of belief propagation runs in the HIP
+library.  When PyTorch with a GPU is present, the graph's device memory is a
+torch tensor (the library's workspace) and its work is ordered on torch's
+current stream; otherwise the library allocates and uses the null stream.
+
+Importing this module loads ``libbp.so`` from the package directory and raises
+if it is missing: there is no fallback implementation.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbp.so")
+
+BP_OK, BP_NOT_CONVERGED = 0, 1
+BP_EINVAL, BP_ENOMEM, BP_EDEVICE, BP_ESTATE = -1, -2, -3, -4
+BP_PAIR_ISING, BP_PAIR_SHARED, BP_PAIR_DENSE = 0, 1, 2
+BP_LBP, BP_RBP, BP_RNBP = 0, 1, 2
+BP_FLAG_GENERIC_LAYOUT = 1
+
+SCHEDULES = {"lbp": BP_LBP, "rbp": BP_RBP, "rnbp": BP_RNBP}
+
+# Every symbol include/bp.h declares.
+EXPORTED = ["bp_default_opts", "bp_workspace_bytes", "bp_create_graph", "bp_run",
+            "bp_marginals", "bp_marginals_device", "bp_get_state", "bp_set_state",
+            "bp_graph_info_get", "bp_destroy_graph", "bp_last_error"]
+
+
+class BpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libbp error {code}: {msg}")
+        self.code = code
+
+
+class bp_graph_desc(ctypes.Structure):
+    _fields_ = [("num_vars", ctypes.c_int32), ("num_states", ctypes.c_int32),
+                ("num_edges", ctypes.c_int64), ("edges", ctypes.c_void_p),
+                ("log_unary", ctypes.c_void_p), ("pair_kind", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("coupling", ctypes.c_void_p),
+                ("shared", ctypes.c_void_p), ("edge_scale", ctypes.c_void_p),
+                ("pair", ctypes.c_void_p), ("stream", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
+
+
+class bp_run_opts(ctypes.Structure):
+    _fields_ = [("max_iters", ctypes.c_int64), ("check_every", ctypes.c_int32),
+                ("dynamic_p", ctypes.c_int32), ("high_p", ctypes.c_double),
+                ("ratio_threshold", ctypes.c_double), ("warm_start", ctypes.c_int32),
+                ("profile", ctypes.c_int32)]
+
+
+class bp_run_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("converged", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("last_active", ctypes.c_int64),
+                ("last_max_residual", ctypes.c_double), ("evaluated", ctypes.c_int64),
+                ("committed", ctypes.c_int64), ("final_t", ctypes.c_int64),
+                ("device_ms", ctypes.c_double), ("eval_kernel_ms", ctypes.c_double),
+                ("eval_kernel_launches", ctypes.c_int64)]
+
+
+class bp_iter_state(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("prev_active", ctypes.c_int64)]
+
+
+class bp_graph_info(ctypes.Structure):
+    _fields_ = [("num_vars", ctypes.c_int32), ("num_states", ctypes.c_int32),
+                ("num_edges", ctypes.c_int64), ("num_messages", ctypes.c_int64),
+                ("layout", ctypes.c_int32), ("num_tiles", ctypes.c_int32),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.bp_default_opts.argtypes = [ctypes.POINTER(bp_run_opts)]
+    lib.bp_default_opts.restype = None
+    lib.bp_workspace_bytes.argtypes = [ctypes.POINTER(bp_graph_desc),
+                                       ctypes.POINTER(ctypes.c_uint64)]
+    lib.bp_workspace_bytes.restype = ctypes.c_int
+    lib.bp_create_graph.argtypes = [ctypes.POINTER(bp_graph_desc), ctypes.POINTER(P)]
+    lib.bp_create_graph.restype = ctypes.c_int
+    lib.bp_run.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                           ctypes.POINTER(bp_run_opts), ctypes.POINTER(bp_run_stats)]
+    lib.bp_run.restype = ctypes.c_int
+    lib.bp_marginals.argtypes = [P, P]
+    lib.bp_marginals.restype = ctypes.c_int
+    lib.bp_marginals_device.argtypes = [P, P]
+    lib.bp_marginals_device.restype = ctypes.c_int
+    lib.bp_get_state.argtypes = [P, P, ctypes.POINTER(bp_iter_state)]
+    lib.bp_get_state.restype = ctypes.c_int
+    lib.bp_set_state.argtypes = [P, P, ctypes.POINTER(bp_iter_state)]
+    lib.bp_set_state.restype = ctypes.c_int
+    lib.bp_graph_info_get.argtypes = [P, ctypes.POINTER(bp_graph_info)]
+    lib.bp_graph_info_get.restype = ctypes.c_int
+    lib.bp_destroy_graph.argtypes = [P]
+    lib.bp_destroy_graph.restype = None
+    lib.bp_last_error.argtypes = []
+    lib.bp_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def bp_last_error():
+    return lib.bp_last_error().decode()
+
+
+def _check(rc):
+    if rc < 0:
+        raise BpError(rc, bp_last_error())
+    return rc
+
+
+def bp_default_opts():
+    o = bp_run_opts()
+    lib.bp_default_opts(ctypes.byref(o))
+    return o
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _make_desc(problem, flags=0):
+    """Host arrays (kept alive in the returned tuple) and the descriptor."""
+    N, K = int(problem["N"]), int(problem["K"])
+    edges = np.ascontiguousarray(problem["edges"], dtype=np.int32).reshape(-1, 2)
+    lu = np.ascontiguousarray(problem["log_unary"], dtype=np.float64).reshape(N, K)
+    keep = [edges, lu]
+
+    def f64(name):
+        v = problem.get(name)
+        if v is None:
+            return None
+        a = np.ascontiguousarray(v, dtype=np.float64)
+        keep.append(a)
+        return a
+
+    d = bp_graph_desc()
+    d.num_vars, d.num_states, d.num_edges = N, K, edges.shape[0]
+    d.edges, d.log_unary = _ptr(edges), _ptr(lu)
+    d.pair_kind = int(problem["pair_kind"])
+    d.flags = int(flags)
+    d.coupling = _ptr(f64("coupling"))
+    d.shared = _ptr(f64("shared"))
+    d.edge_scale = _ptr(f64("edge_scale"))
+    d.pair = _ptr(f64("pair"))
+    return d, keep
+
+
+def bp_workspace_bytes(problem, flags=0):
+    d, _keep = _make_desc(problem, flags)
+    n = ctypes.c_uint64()
+    _check(lib.bp_workspace_bytes(ctypes.byref(d), ctypes.byref(n)))
+    return int(n.value)
+
+
+def _torch_cuda():
+    try:
+        import torch
+    except ImportError:
+        return None
+    return torch if torch.cuda.is_available() else None
+
+
+class Graph:
+    """A problem resident on the GPU (bp_create_graph ... bp_destroy_graph)."""
+
+    def __init__(self, problem, flags=0, use_torch=True):
+        self.N, self.K = int(problem["N"]), int(problem["K"])
+        self.M = int(np.asarray(problem["edges"]).reshape(-1, 2).shape[0])
+        self.E = 2 * self.M
+        d, keep = _make_desc(problem, flags)
+        self._workspace = None
+        torch = _torch_cuda() if use_torch else None
+        if torch is not None:
+            n = ctypes.c_uint64()
+            _check(lib.bp_workspace_bytes(ctypes.byref(d), ctypes.byref(n)))
+            # torch's caching allocator owns the device memory; 256-byte alignment
+            self._workspace = torch.empty(int(n.value) + 256, dtype=torch.uint8, device="cuda")
+            base = self._workspace.data_ptr()
+            d.workspace = base + (-base) % 256
+            d.workspace_bytes = int(n.value)
+            d.stream = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p()
+        _check(lib.bp_create_graph(ctypes.byref(d), ctypes.byref(h)))
+        del keep
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.bp_destroy_graph(self.handle)
+            self.handle = None
+        self._workspace = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def info(self):
+        i = bp_graph_info()
+        _check(lib.bp_graph_info_get(self.handle, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in i._fields_}
+
+    def run(self, schedule="lbp", eps=1e-4, p=1.0, seed=0, max_iters=10000, check_every=16,
+            dynamic_p=True, high_p=1.0, ratio_threshold=0.9, warm_start=False, profile=False):
+        o = bp_default_opts()
+        o.max_iters, o.check_every = int(max_iters), int(check_every)
+        o.dynamic_p, o.high_p, o.ratio_threshold = int(bool(dynamic_p)), float(high_p), \
+            float(ratio_threshold)
+        o.warm_start, o.profile = int(bool(warm_start)), int(bool(profile))
+        s = bp_run_stats()
+        sched = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+        rc = _check(lib.bp_run(self.handle, sched, float(eps), float(p), int(seed),
+                               ctypes.byref(o), ctypes.byref(s)))
+        out = {f: getattr(s, f) for f, _ in s._fields_ if f != "reserved0"}
+        out["converged"] = bool(out["converged"])
+        out["status"] = rc
+        return out
+
+    def marginals(self):
+        out = np.empty((self.N, self.K), dtype=np.float32)
+        _check(lib.bp_marginals(self.handle, _ptr(out)))
+        return out
+
+    def marginals_device(self, out_tensor):
+        """Write [N, K] FP32 beliefs into a caller-owned CUDA tensor."""
+        assert out_tensor.is_cuda and out_tensor.numel() == self.N * self.K
+        _check(lib.bp_marginals_device(self.handle, ctypes.c_void_p(out_tensor.data_ptr())))
+        return out_tensor
+
+    def get_state(self):
+        m = np.empty((self.E, self.K), dtype=np.float32)
+        st = bp_iter_state()
+        _check(lib.bp_get_state(self.handle, _ptr(m), ctypes.byref(st)))
+        return m, {"t": st.t, "prev_active": st.prev_active}
+
+    def set_state(self, msgs=None, t=None, prev_active=-1):
+        m = None
+        if msgs is not None:
+            m = np.ascontiguousarray(msgs, dtype=np.float32).reshape(self.E, self.K)
+        st = None
+        if t is not None:
+            st = bp_iter_state(int(t), int(prev_active))
+        _check(lib.bp_set_state(self.handle, _ptr(m), ctypes.byref(st) if st else None))
+
+
+def bp_create_graph(problem, flags=0, use_torch=True):
+    return Graph(problem, flags=flags, use_torch=use_torch)
+
+
+def bp_run(graph, schedule, eps, p, seed, **opts):
+    return graph.run(schedule, eps=eps, p=p, seed=seed, **opts)
+
+
+def bp_marginals(graph):
+    return graph.marginals()
+
+
+def bp_get_state(graph):
+    return graph.get_state()
+
+
+def bp_set_state(graph, msgs=None, t=None, prev_active=-1):
+    graph.set_state(msgs, t, prev_active)
+
+
+def bp_destroy_graph(graph):
+    graph.close()

@@ -1,0 +1,701 @@
+// C ABI of libbp (include/bp.h): validation, device layout, and the host side of
+// the Alg. 1 loop.  The loop itself runs on the device: each iteration is a
+// fixed sequence of kernel launches whose convergence test and EdgeRatio rule
+// read device counters, so the host only enqueues work and polls a flag every
+// check_every iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/bp.h"
+#include "bp_internal.h"
+
+using namespace bp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(BP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_OK(expr, what)                                  \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) return hip_fail(_e, what);    \
+    } while (0)
+
+int kpad(int K) {
+    int p = 2;
+    while (p < K) p <<= 1;
+    return p;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Host-side description of the device layout, built once per graph.
+struct HostLayout {
+    int N = 0, K = 0, layout = 0, pair = 0, row = 1;
+    long long M = 0, E = 0;
+    std::vector<int> in_ptr;          // [N+1]
+    std::vector<int> src;             // [E] source node of the slot's message
+    std::vector<int> rev;             // [E]
+    std::vector<int> slot_of_canon;   // [E]
+    std::vector<int> tile_start;      // [T+1]
+    std::vector<float> coupling;      // [E] (Ising)
+    std::vector<float> unary;         // [N] log-odds or [N][K] log psi (max-shifted)
+    std::vector<float> pair_tab;      // shared (2KK) or dense [E][K][K]
+    std::vector<unsigned char> orient;// [E] (asymmetric shared)
+};
+
+struct Arena {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+};
+
+struct Offsets {
+    size_t in_ptr, src, rev, tile, coupling, unary, pair, orient, m0, m1, cand, keys, revert,
+        ties, state, marg, total;
+};
+
+Offsets plan(const HostLayout& L) {
+    Arena a;
+    Offsets o;
+    const size_t E = (size_t)L.E;
+    o.in_ptr = a.take(sizeof(int) * (L.N + 1));
+    o.src = a.take(sizeof(int) * E);
+    o.rev = a.take(sizeof(int) * E);
+    o.tile = a.take(sizeof(int) * L.tile_start.size());
+    o.coupling = a.take(sizeof(float) * L.coupling.size());
+    o.unary = a.take(sizeof(float) * L.unary.size());
+    o.pair = a.take(sizeof(float) * L.pair_tab.size());
+    o.orient = a.take(L.orient.size());
+    o.m0 = a.take(sizeof(float) * E * L.row);
+    o.m1 = a.take(sizeof(float) * E * L.row);
+    o.cand = a.take(sizeof(float) * E * L.row);
+    o.keys = a.take(sizeof(unsigned int) * E);
+    o.revert = a.take(sizeof(int) * E);
+    o.ties = a.take(sizeof(unsigned int) * (E / 4096 + 2));
+    o.state = a.take(sizeof(DevState));
+    o.marg = a.take(sizeof(float) * (size_t)L.N * L.K);
+    o.total = a.off;
+    return o;
+}
+
+bool finite_all(const double* p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+bool positive_all(const double* p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!(p[i] > 0.0) || !std::isfinite(p[i])) return false;
+    return true;
+}
+
+// Validate the problem (Eq. (1): finite state sets, positive potentials) and
+// build the device layout: directed messages sorted by (target, source), the
+// reverse-slot index, per-slot parameters and node tiles.
+int build_layout(const bp_graph_desc* d, HostLayout& L) {
+    if (!d) return fail(BP_EINVAL, "desc is NULL");
+    const long long N = d->num_vars, K = d->num_states, M = d->num_edges;
+    if (N < 1 || N > 0x7FFFFFFFLL - 1) return fail(BP_EINVAL, "num_vars %lld out of range", N);
+    if (K < 2 || K > kMaxK) return fail(BP_EINVAL, "num_states %lld not in [2, %d]", K, kMaxK);
+    if (M < 0 || 2 * M > 0x7FFFFFFFLL - 1) return fail(BP_EINVAL, "num_edges %lld out of range", M);
+    if (M > 0 && !d->edges) return fail(BP_EINVAL, "edges is NULL");
+    if (!d->log_unary) return fail(BP_EINVAL, "log_unary is NULL");
+    if (!finite_all(d->log_unary, (size_t)(N * K))) return fail(BP_EINVAL, "log_unary not finite");
+    const int kind = d->pair_kind;
+    if (kind == BP_PAIR_ISING) {
+        if (K != 2) return fail(BP_EINVAL, "BP_PAIR_ISING needs num_states == 2");
+        if (M > 0 && !d->coupling) return fail(BP_EINVAL, "coupling is NULL");
+        if (M > 0 && !finite_all(d->coupling, (size_t)M)) return fail(BP_EINVAL, "coupling not finite");
+    } else if (kind == BP_PAIR_SHARED) {
+        if (!d->shared) return fail(BP_EINVAL, "shared is NULL");
+        if (!positive_all(d->shared, (size_t)(K * K)))
+            return fail(BP_EINVAL, "shared potential must be positive and finite");
+        if (M > 0 && !d->edge_scale) return fail(BP_EINVAL, "edge_scale is NULL");
+        if (M > 0 && !positive_all(d->edge_scale, (size_t)M))
+            return fail(BP_EINVAL, "edge_scale must be positive and finite");
+    } else if (kind == BP_PAIR_DENSE) {
+        if (M > 0 && !d->pair) return fail(BP_EINVAL, "pair is NULL");
+        if (M > 0 && !positive_all(d->pair, (size_t)(M * K * K)))
+            return fail(BP_EINVAL, "pair potential must be positive and finite");
+    } else {
+        return fail(BP_EINVAL, "unknown pair_kind %d", kind);
+    }
+    if (d->flags & ~(uint32_t)BP_FLAG_GENERIC_LAYOUT) return fail(BP_EINVAL, "unknown flags");
+    {
+        std::unordered_set<unsigned long long> seen;
+        seen.reserve((size_t)M * 2 + 1);
+        for (long long u = 0; u < M; ++u) {
+            const long long a = d->edges[2 * u], b = d->edges[2 * u + 1];
+            if (a < 0 || a >= N || b < 0 || b >= N)
+                return fail(BP_EINVAL, "edge %lld = (%lld, %lld) out of range", u, a, b);
+            if (a == b) return fail(BP_EINVAL, "edge %lld is a self-loop", u);
+            const unsigned long long key =
+                (unsigned long long)std::min(a, b) * (unsigned long long)N + std::max(a, b);
+            if (!seen.insert(key).second) return fail(BP_EINVAL, "edge %lld duplicates an earlier edge", u);
+        }
+    }
+
+    L.N = (int)N;
+    L.K = (int)K;
+    L.M = M;
+    L.E = 2 * M;
+    L.layout = (kind == BP_PAIR_ISING && !(d->flags & BP_FLAG_GENERIC_LAYOUT)) ? kLayoutLogOdds
+                                                                               : kLayoutGeneric;
+    L.row = L.layout == kLayoutLogOdds ? 1 : (int)K;
+    const long long E = L.E;
+    auto csrc = [&](long long c) { return d->edges[2 * (c >> 1) + ((c & 1) ? 1 : 0)]; };
+    auto cdst = [&](long long c) { return d->edges[2 * (c >> 1) + ((c & 1) ? 0 : 1)]; };
+
+    // counting sort of directed messages by target, then by source inside a target
+    L.in_ptr.assign((size_t)N + 1, 0);
+    for (long long c = 0; c < E; ++c) L.in_ptr[cdst(c) + 1]++;
+    for (long long i = 0; i < N; ++i) L.in_ptr[i + 1] += L.in_ptr[i];
+    std::vector<int> canon_of_slot((size_t)E);
+    {
+        std::vector<int> fill(L.in_ptr.begin(), L.in_ptr.end() - 1);
+        for (long long c = 0; c < E; ++c) canon_of_slot[fill[cdst(c)]++] = (int)c;
+    }
+    for (long long i = 0; i < N; ++i)
+        std::sort(canon_of_slot.begin() + L.in_ptr[i], canon_of_slot.begin() + L.in_ptr[i + 1],
+                  [&](int x, int y) { return csrc(x) < csrc(y); });
+    L.slot_of_canon.assign((size_t)E, 0);
+    for (long long s = 0; s < E; ++s) L.slot_of_canon[canon_of_slot[s]] = (int)s;
+    L.src.resize((size_t)E);
+    L.rev.resize((size_t)E);
+    for (long long s = 0; s < E; ++s) {
+        const int c = canon_of_slot[s];
+        L.src[s] = csrc(c);
+        L.rev[s] = L.slot_of_canon[c ^ 1];
+    }
+
+    // unary: K = 2 log-odds, or log psi shifted so its max per node is 0
+    if (L.layout == kLayoutLogOdds) {
+        L.unary.resize((size_t)N);
+        for (long long i = 0; i < N; ++i)
+            L.unary[i] = (float)(d->log_unary[2 * i + 1] - d->log_unary[2 * i]);
+    } else {
+        L.unary.resize((size_t)(N * K));
+        for (long long i = 0; i < N; ++i) {
+            double mx = -INFINITY;
+            for (long long x = 0; x < K; ++x) mx = std::max(mx, d->log_unary[i * K + x]);
+            for (long long x = 0; x < K; ++x)
+                L.unary[i * K + x] = (float)(d->log_unary[i * K + x] - mx);
+        }
+    }
+
+    // Slot s holds m_{k->i}; the kernel computes the outgoing m_{i->k} there and
+    // needs psi_{ik}(x_i, x_k).  For the canonical message c of slot s, edge
+    // u = c >> 1 = (a, b): c even means k = a, i = b, so the table is transposed.
+    if (kind == BP_PAIR_ISING) {
+        L.pair = kPairIsing;
+        L.coupling.resize((size_t)E);
+        for (long long s = 0; s < E; ++s) L.coupling[s] = (float)d->coupling[canon_of_slot[s] >> 1];
+    } else if (kind == BP_PAIR_SHARED) {
+        bool sym = true;
+        for (long long x = 0; x < K; ++x)
+            for (long long y = 0; y < K; ++y)
+                if (d->shared[x * K + y] != d->shared[y * K + x]) sym = false;
+        double mx = 0.0;
+        for (long long i = 0; i < K * K; ++i) mx = std::max(mx, d->shared[i]);
+        L.pair_tab.resize((size_t)(K * K));
+        for (long long x = 0; x < K; ++x)
+            for (long long y = 0; y < K; ++y) L.pair_tab[x * K + y] = (float)(d->shared[x * K + y] / mx);
+        L.pair = sym ? kPairShared : kPairSharedAsym;
+        if (!sym) {
+            L.orient.resize((size_t)E);
+            for (long long s = 0; s < E; ++s) L.orient[s] = (canon_of_slot[s] & 1) ? 0 : 1;
+        }
+    } else {
+        L.pair = kPairDense;
+        L.pair_tab.resize((size_t)(E * K * K));
+        for (long long s = 0; s < E; ++s) {
+            const int c = canon_of_slot[s];
+            const double* P = d->pair + (size_t)(c >> 1) * K * K;
+            double mx = 0.0;
+            for (long long i = 0; i < K * K; ++i) mx = std::max(mx, P[i]);
+            float* T = L.pair_tab.data() + (size_t)s * K * K;
+            for (long long xi = 0; xi < K; ++xi)
+                for (long long xk = 0; xk < K; ++xk)
+                    T[xi * K + xk] = (float)(((c & 1) ? P[xi * K + xk] : P[xk * K + xi]) / mx);
+        }
+    }
+
+    // node tiles: greedy runs of target nodes within the slot and node limits;
+    // a node whose in-degree alone exceeds the slot limit gets a tile of its own
+    const int slot_lim = L.layout == kLayoutLogOdds ? kTileSlotsLogOdds
+                                                    : std::max(1, kTileFloatsGeneric / (int)K);
+    const int node_lim = L.layout == kLayoutLogOdds ? kTileNodesMax : std::min(kTileNodesMax, slot_lim);
+    L.tile_start.clear();
+    long long n = 0;
+    while (n < N) {
+        L.tile_start.push_back((int)n);
+        const long long s_begin = L.in_ptr[n];
+        long long m = n;
+        while (m < N && (m - n) < node_lim && (L.in_ptr[m + 1] - s_begin) <= slot_lim) ++m;
+        if (m == n) m = n + 1;  // oversize node
+        n = m;
+    }
+    L.tile_start.push_back((int)N);
+    return BP_OK;
+}
+
+}  // namespace
+
+struct bp_graph {
+    HostLayout L;
+    Offsets off;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char* base = nullptr;
+    bool owns_memory = false;
+    int cur = 0;                 // buffer holding the current messages
+    long long t_next = 0;        // global iteration number of the next evaluation
+    long long prev_active = -1;  // n_{t_next - 1}
+    DevState* host_state = nullptr;  // pinned mirror
+
+    template <typename T>
+    T* at(size_t o) const { return reinterpret_cast<T*>(base + o); }
+    float* msg(int i) const { return at<float>(i ? off.m1 : off.m0); }
+    DevState* st() const { return at<DevState>(off.state); }
+};
+
+extern "C" {
+
+void bp_default_opts(bp_run_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->max_iters = 10000;
+    o->check_every = 16;
+    o->dynamic_p = 1;
+    o->high_p = 1.0;
+    o->ratio_threshold = 0.9;
+    o->warm_start = 0;
+    o->profile = 0;
+}
+
+const char* bp_last_error(void) { return g_last_error.c_str(); }
+
+int bp_workspace_bytes(const bp_graph_desc* desc, uint64_t* bytes) {
+    HostLayout L;
+    int rc = build_layout(desc, L);
+    if (rc != BP_OK) return rc;
+    if (bytes) *bytes = plan(L).total;
+    return BP_OK;
+}
+
+int bp_create_graph(const bp_graph_desc* desc, bp_graph** out) {
+    if (!out) return fail(BP_EINVAL, "out is NULL");
+    *out = nullptr;
+    bp_graph* g = new (std::nothrow) bp_graph();
+    if (!g) return fail(BP_ENOMEM, "host allocation failed");
+    int rc = build_layout(desc, g->L);
+    if (rc != BP_OK) {
+        delete g;
+        return rc;
+    }
+    g->off = plan(g->L);
+    g->stream = (hipStream_t)desc->stream;
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) {
+        delete g;
+        return hip_fail(e, "hipGetDevice");
+    }
+    if (desc->workspace) {
+        if ((uintptr_t)desc->workspace % 256 != 0) {
+            delete g;
+            return fail(BP_EINVAL, "workspace must be 256-byte aligned");
+        }
+        if (desc->workspace_bytes < g->off.total) {
+            delete g;
+            return fail(BP_ENOMEM, "workspace of %llu bytes < %llu needed",
+                        (unsigned long long)desc->workspace_bytes,
+                        (unsigned long long)g->off.total);
+        }
+        g->base = (char*)desc->workspace;
+    } else {
+        e = hipMalloc((void**)&g->base, g->off.total);
+        if (e != hipSuccess) {
+            delete g;
+            (void)hipGetLastError();
+            return fail(e == hipErrorOutOfMemory ? BP_ENOMEM : BP_EDEVICE, "hipMalloc(%zu): %s",
+                        g->off.total, hipGetErrorString(e));
+        }
+        g->owns_memory = true;
+    }
+    e = hipHostMalloc((void**)&g->host_state, sizeof(DevState), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        bp_destroy_graph(g);
+        return hip_fail(e, "hipHostMalloc");
+    }
+    const HostLayout& L = g->L;
+    hipStream_t s = g->stream;
+    auto up = [&](size_t o, const void* p, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpyAsync(g->base + o, p, n, hipMemcpyHostToDevice, s);
+    };
+    hipError_t errs[8] = {
+        up(g->off.in_ptr, L.in_ptr.data(), sizeof(int) * L.in_ptr.size()),
+        up(g->off.src, L.src.data(), sizeof(int) * L.src.size()),
+        up(g->off.rev, L.rev.data(), sizeof(int) * L.rev.size()),
+        up(g->off.tile, L.tile_start.data(), sizeof(int) * L.tile_start.size()),
+        up(g->off.coupling, L.coupling.data(), sizeof(float) * L.coupling.size()),
+        up(g->off.unary, L.unary.data(), sizeof(float) * L.unary.size()),
+        up(g->off.pair, L.pair_tab.data(), sizeof(float) * L.pair_tab.size()),
+        up(g->off.orient, L.orient.data(), L.orient.size())};
+    for (hipError_t x : errs)
+        if (x != hipSuccess) {
+            bp_destroy_graph(g);
+            return hip_fail(x, "upload");
+        }
+    const float uni = L.layout == kLayoutLogOdds ? 0.0f : 1.0f / (float)L.K;
+    e = launch_fill(g->msg(0), uni, L.E * L.row, s);
+    if (e == hipSuccess) e = launch_init_state(g->st(), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        bp_destroy_graph(g);
+        return hip_fail(e, "initialise");
+    }
+    g->cur = 0;
+    *out = g;
+    return BP_OK;
+}
+
+void bp_destroy_graph(bp_graph* g) {
+    if (!g) return;
+    {
+        DeviceGuard dg(g->device);
+        if (g->base) (void)hipStreamSynchronize(g->stream);
+        if (g->owns_memory && g->base) (void)hipFree(g->base);
+        if (g->host_state) (void)hipHostFree(g->host_state);
+    }
+    delete g;
+}
+
+int bp_graph_info_get(const bp_graph* g, bp_graph_info* info) {
+    if (!g || !info) return fail(BP_EINVAL, "NULL argument");
+    info->num_vars = g->L.N;
+    info->num_states = g->L.K;
+    info->num_edges = g->L.M;
+    info->num_messages = g->L.E;
+    info->layout = g->L.layout;
+    info->num_tiles = (int)g->L.tile_start.size() - 1;
+    info->device_bytes = g->off.total;
+    return BP_OK;
+}
+
+static unsigned int keep_threshold(double p) {
+    // U = k * 2^-24 < p  <=>  k < ceil(p * 2^24)  (p * 2^24 is exact in double)
+    double x = std::ceil(p * 16777216.0);
+    if (x < 0.0) x = 0.0;
+    if (x > 16777216.0) x = 16777216.0;
+    return (unsigned int)x;
+}
+
+int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const bp_run_opts* opts,
+           bp_run_stats* stats) {
+    if (!g) return fail(BP_EINVAL, "graph is NULL");
+    if (schedule != BP_LBP && schedule != BP_RBP && schedule != BP_RNBP)
+        return fail(BP_EINVAL, "unknown schedule %d", schedule);
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(BP_EINVAL, "eps must be finite and >= 0");
+    if (schedule != BP_LBP && !(p > 0.0 && p <= 1.0)) return fail(BP_EINVAL, "p must be in (0, 1]");
+    bp_run_opts o;
+    bp_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.max_iters < 0) return fail(BP_EINVAL, "max_iters < 0");
+    if (o.check_every < 1) return fail(BP_EINVAL, "check_every < 1");
+    if (schedule == BP_RNBP && o.dynamic_p && !(o.high_p > 0.0 && o.high_p <= 1.0))
+        return fail(BP_EINVAL, "high_p must be in (0, 1]");
+    if (!std::isfinite(o.ratio_threshold)) return fail(BP_EINVAL, "ratio_threshold not finite");
+    DeviceGuard dg(g->device);
+    const HostLayout& L = g->L;
+    hipStream_t s = g->stream;
+    if (!o.warm_start) {
+        const float uni = L.layout == kLayoutLogOdds ? 0.0f : 1.0f / (float)L.K;
+        HIP_OK(launch_fill(g->msg(g->cur), uni, L.E * L.row, s), "fill");
+        g->t_next = 0;
+        g->prev_active = -1;
+    }
+    HIP_OK(launch_init_state(g->st(), s), "init state");
+
+    const int mode = schedule == BP_LBP ? kModeLBP : schedule == BP_RBP ? kModeRBP : kModeRnBP;
+    const unsigned int thr_lo = keep_threshold(p);
+    const unsigned int thr_hi = keep_threshold(o.high_p);
+    EvalArgs a{};
+    a.tile_start = g->at<int>(g->off.tile);
+    a.num_tiles = (int)L.tile_start.size() - 1;
+    a.tiles_per_xcd = (a.num_tiles + 7) / 8;
+    a.in_ptr = g->at<int>(g->off.in_ptr);
+    a.rev = g->at<int>(g->off.rev);
+    a.src = g->at<int>(g->off.src);
+    a.coupling = g->at<float>(g->off.coupling);
+    a.unary = g->at<float>(g->off.unary);
+    a.pair = g->at<float>(g->off.pair);
+    a.orient = g->at<unsigned char>(g->off.orient);
+    a.cand = g->at<float>(g->off.cand);
+    a.keys = g->at<unsigned int>(g->off.keys);
+    a.revert_list = g->at<int>(g->off.revert);
+    a.st = g->st();
+    a.num_states = L.K;
+    a.pair_kind = L.pair;
+    a.eps = (float)eps;
+    a.key0 = (unsigned int)(seed & 0xFFFFFFFFu);
+    a.key1 = (unsigned int)(seed >> 32);
+    bool low_is_a = true, differ = false;
+    if (mode == kModeRnBP && o.dynamic_p) {
+        a.thr_a = std::max(thr_lo, thr_hi);
+        a.thr_b = std::min(thr_lo, thr_hi);
+        low_is_a = thr_lo >= thr_hi;
+        differ = thr_lo != thr_hi;
+    } else {
+        a.thr_a = a.thr_b = thr_lo;
+    }
+    // The device compares FP32 residuals with an FP32 threshold: take the largest
+    // float <= eps, so that for every float r, r > eps_f exactly when r > eps.
+    if ((double)a.eps > eps) a.eps = std::nextafter(a.eps, -INFINITY);
+
+    long long rbp_k = (long long)std::ceil(p * (double)L.E);
+    if (rbp_k < 1) rbp_k = 1;
+    if (rbp_k > L.E) rbp_k = L.E;
+
+    FinishArgs f{};
+    f.st = g->st();
+    f.mode = mode;
+    f.dynamic_p = o.dynamic_p;
+    f.low_is_a = low_is_a;
+    f.thresholds_differ = differ;
+    f.ratio_threshold = o.ratio_threshold;
+    f.num_messages = (unsigned long long)L.E;
+    f.rbp_k = (unsigned long long)rbp_k;
+    f.revert_list = g->at<int>(g->off.revert);
+    f.row = L.row;
+    f.prev_active_host = g->prev_active;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    HIP_OK(hipEventCreate(&ev0), "event");
+    HIP_OK(hipEventCreate(&ev1), "event");
+    std::vector<hipEvent_t> kev;
+    if (o.profile) {
+        kev.resize(2 * (size_t)o.check_every);
+        for (auto& x : kev) HIP_OK(hipEventCreate(&x), "event");
+    }
+    double kernel_ms = 0.0;
+    long long kernel_launches = 0;
+    HIP_OK(hipEventRecord(ev0, s), "event record");
+
+    const int kp = kpad(L.K);
+    const long long t_start = g->t_next;
+    const int cur0 = g->cur;
+    int in_chunk = 0;
+    int rc = BP_OK;
+    for (long long it = 0;; ++it) {
+        const long long t = t_start + it;
+        const bool final_eval = it == o.max_iters;
+        const int b_in = mode == kModeRBP ? cur0 : (int)((cur0 + it) & 1);
+        a.m_in = g->msg(b_in);
+        a.m_out = g->msg(b_in ^ 1);
+        a.t = (unsigned int)t;
+        a.slot_idx = (int)(t & 3);
+        const int emode = final_eval ? kModeEvalOnly : mode;
+        if (o.profile) HIP_OK(hipEventRecord(kev[2 * in_chunk], s), "event record");
+        HIP_OK(launch_eval(L.layout, kp, emode, a, s), "evaluation kernel");
+        if (o.profile) HIP_OK(hipEventRecord(kev[2 * in_chunk + 1], s), "event record");
+        if (mode == kModeRBP && !final_eval) {
+            unsigned int* ties = g->at<unsigned int>(g->off.ties);
+            const int all = rbp_k >= L.E;
+            if (!all)
+                HIP_OK(launch_rbp_select(g->st(), a.keys, (int)L.E, (unsigned int)rbp_k,
+                                         a.slot_idx, ties, s),
+                       "top-k select");
+            HIP_OK(launch_rbp_commit(g->st(), a.keys, a.cand, g->msg(b_in), (int)L.E, L.row, all,
+                                     a.slot_idx, ties, s),
+                   "top-k commit");
+        }
+        f.slot_idx = (int)(t & 3);
+        f.prev_slot_idx = (int)((t - 1) & 3);
+        f.has_prev_in_run = it > 0;
+        f.t = t;
+        f.final_eval = final_eval;
+        f.m_in = a.m_in;
+        f.m_out = a.m_out;
+        HIP_OK(launch_finish(f, s), "finish kernel");
+        ++in_chunk;
+        if (in_chunk == o.check_every || final_eval) {
+            HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost, s),
+                   "state readback");
+            HIP_OK(hipStreamSynchronize(s), "synchronize");
+            if (o.profile) {
+                for (int i = 0; i < in_chunk; ++i) {
+                    float ms = 0.0f;
+                    HIP_OK(hipEventElapsedTime(&ms, kev[2 * i], kev[2 * i + 1]), "event time");
+                    kernel_ms += ms;
+                    ++kernel_launches;
+                }
+            }
+            in_chunk = 0;
+            if (g->host_state->done || final_eval) break;
+        }
+    }
+    HIP_OK(hipEventRecord(ev1, s), "event record");
+    HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost, s),
+           "state readback");
+    HIP_OK(hipStreamSynchronize(s), "synchronize");
+    float total_ms = 0.0f;
+    HIP_OK(hipEventElapsedTime(&total_ms, ev0, ev1), "event time");
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    for (auto& x : kev) (void)hipEventDestroy(x);
+
+    const DevState& h = *g->host_state;
+    const long long iters = (long long)h.iterations;
+    const bool converged = h.done != 0;
+    if (mode != kModeRBP) g->cur = (int)((cur0 + iters) & 1);
+    g->t_next = h.last_t;
+    g->prev_active = h.last_prev;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->iterations = iters;
+        stats->converged = converged ? 1 : 0;
+        stats->last_active = (long long)h.last_active;
+        float rm;
+        std::memcpy(&rm, &h.last_rmax, sizeof(rm));
+        stats->last_max_residual = rm;
+        stats->evaluated = (long long)h.evaluated;
+        stats->committed = (long long)h.committed;
+        stats->final_t = h.last_t;
+        stats->device_ms = total_ms;
+        stats->eval_kernel_ms = kernel_ms;
+        stats->eval_kernel_launches = kernel_launches;
+    }
+    rc = converged ? BP_OK : BP_NOT_CONVERGED;
+    return rc;
+}
+
+int bp_marginals_device(bp_graph* g, float* out_device) {
+    if (!g || !out_device) return fail(BP_EINVAL, "NULL argument");
+    DeviceGuard dg(g->device);
+    const HostLayout& L = g->L;
+    HIP_OK(launch_marginals(L.layout, kpad(L.K), g->at<int>(g->off.in_ptr),
+                            g->at<float>(g->off.unary), g->msg(g->cur), out_device, L.N, L.K,
+                            g->stream),
+           "marginals kernel");
+    return BP_OK;
+}
+
+int bp_marginals(bp_graph* g, float* out) {
+    if (!g || !out) return fail(BP_EINVAL, "NULL argument");
+    DeviceGuard dg(g->device);
+    float* dev = g->at<float>(g->off.marg);
+    int rc = bp_marginals_device(g, dev);
+    if (rc != BP_OK) return rc;
+    HIP_OK(hipMemcpyAsync(out, dev, sizeof(float) * (size_t)g->L.N * g->L.K, hipMemcpyDeviceToHost,
+                          g->stream),
+           "marginals readback");
+    HIP_OK(hipStreamSynchronize(g->stream), "synchronize");
+    return BP_OK;
+}
+
+int bp_get_state(bp_graph* g, float* msgs, bp_iter_state* st) {
+    if (!g) return fail(BP_EINVAL, "graph is NULL");
+    if (msgs) {
+        DeviceGuard dg(g->device);
+        const HostLayout& L = g->L;
+        std::vector<float> dev((size_t)(L.E * L.row));
+        if (!dev.empty()) {
+            HIP_OK(hipMemcpyAsync(dev.data(), g->msg(g->cur), sizeof(float) * dev.size(),
+                                  hipMemcpyDeviceToHost, g->stream),
+                   "state readback");
+            HIP_OK(hipStreamSynchronize(g->stream), "synchronize");
+        }
+        for (long long c = 0; c < L.E; ++c) {
+            const long long s = L.slot_of_canon[c];
+            if (L.layout == kLayoutLogOdds) {
+                const double lam = dev[s];
+                msgs[2 * c + 1] = (float)(1.0 / (1.0 + std::exp(-lam)));
+                msgs[2 * c + 0] = (float)(1.0 / (1.0 + std::exp(lam)));
+            } else {
+                for (int x = 0; x < L.K; ++x) msgs[c * L.K + x] = dev[s * L.K + x];
+            }
+        }
+    }
+    if (st) {
+        st->t = g->t_next;
+        st->prev_active = g->prev_active;
+    }
+    return BP_OK;
+}
+
+int bp_set_state(bp_graph* g, const float* msgs, const bp_iter_state* st) {
+    if (!g) return fail(BP_EINVAL, "graph is NULL");
+    const HostLayout& L = g->L;
+    if (msgs) {
+        std::vector<float> dev((size_t)(L.E * L.row));
+        for (long long c = 0; c < L.E; ++c) {
+            const long long s = L.slot_of_canon[c];
+            double z = 0.0;
+            for (int x = 0; x < L.K; ++x) {
+                const double v = msgs[c * L.K + x];
+                if (!(v > 0.0) || !std::isfinite(v))
+                    return fail(BP_EINVAL, "message %lld has a non-positive or non-finite entry", c);
+                z += v;
+            }
+            if (L.layout == kLayoutLogOdds) {
+                dev[s] = (float)(std::log((double)msgs[2 * c + 1]) - std::log((double)msgs[2 * c]));
+            } else {
+                for (int x = 0; x < L.K; ++x) dev[s * L.K + x] = (float)(msgs[c * L.K + x] / z);
+            }
+        }
+        DeviceGuard dg(g->device);
+        if (!dev.empty()) {
+            HIP_OK(hipMemcpyAsync(g->msg(g->cur), dev.data(), sizeof(float) * dev.size(),
+                                  hipMemcpyHostToDevice, g->stream),
+                   "state upload");
+            HIP_OK(hipStreamSynchronize(g->stream), "synchronize");
+        }
+    }
+    if (st) {
+        if (st->t < 0 || st->t > 0xFFFFFFFFLL) return fail(BP_EINVAL, "t out of range");
+        g->t_next = st->t;
+        g->prev_active = st->prev_active;
+    }
+    return BP_OK;
+}
+
+}  // extern "C"

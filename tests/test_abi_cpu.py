@@ -1,0 +1,159 @@
+"""Host-side checks of libbp that need no GPU: the library loads, exports every
+symbol include/bp.h declares, and rejects invalid problems before touching a
+device (validation runs inside bp_workspace_bytes and bp_create_graph)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1909_11469_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bp():
+    from paper_1909_11469_amd import bp as mod
+    return mod
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "bp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bp_\w+)\s*\(", text)))
+
+
+def test_header_declarations_match_binding(bp):
+    assert _declared_functions() == sorted(bp.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(bp):
+    raw = ctypes.CDLL(bp.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(raw, name), name
+
+
+def test_default_opts(bp):
+    o = bp.bp_default_opts()
+    assert o.max_iters == 10000 and o.check_every == 16 and o.dynamic_p == 1
+    assert o.high_p == 1.0 and o.ratio_threshold == 0.9 and o.warm_start == 0
+
+
+def test_struct_layouts_match_header(bp, tmp_path):
+    """Compile the header with the host C compiler and compare every field offset
+    and struct size with the ctypes mirrors."""
+    structs = [bp.bp_graph_desc, bp.bp_run_opts, bp.bp_run_stats, bp.bp_iter_state,
+               bp.bp_graph_info]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bp.h"', "int main(void) {"]
+    for S in structs:
+        n = S.__name__
+        lines.append(f'printf("{n} %zu\\n", sizeof({n}));')
+        for f, _ in S._fields_:
+            lines.append(f'printf("{n}.{f} %zu\\n", offsetof({n}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for S in structs:
+        n = S.__name__
+        assert int(out[n]) == ctypes.sizeof(S), n
+        for f, _ in S._fields_:
+            assert int(out[f"{n}.{f}"]) == getattr(S, f).offset, f"{n}.{f}"
+
+
+def test_workspace_bytes_grows_with_graph(bp):
+    a = bp.bp_workspace_bytes(inputs.ising_grid(10, 10, 1.0, 0))
+    b = bp.bp_workspace_bytes(inputs.ising_grid(40, 40, 1.0, 0))
+    g = bp.bp_workspace_bytes(inputs.ising_grid(10, 10, 1.0, 0), flags=bp.BP_FLAG_GENERIC_LAYOUT)
+    assert 0 < a < b and g > a
+
+
+def test_edgeless_graph_is_valid(bp):
+    prob = dict(N=5, K=3, edges=np.zeros((0, 2), np.int32), log_unary=np.zeros((5, 3)),
+                pair_kind=bp.BP_PAIR_DENSE, pair=np.zeros((0, 3, 3)))
+    assert bp.bp_workspace_bytes(prob) > 0
+
+
+def _expect_einval(bp, prob, flags=0, match=None):
+    with pytest.raises(bp.BpError) as ei:
+        bp.bp_workspace_bytes(prob, flags)
+    assert ei.value.code == bp.BP_EINVAL
+    if match:
+        assert re.search(match, str(ei.value)), str(ei.value)
+    assert bp.bp_last_error() != ""
+
+
+def test_rejects_bad_problems(bp):
+    base = inputs.ising_grid(3, 3, 1.0, 0)
+
+    def mod(**kw):
+        p = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in base.items()}
+        p.update(kw)
+        return p
+
+    e = base["edges"].copy()
+    e[1, 1] = e[1, 0]
+    _expect_einval(bp, mod(edges=e), match="self-loop")
+    e = base["edges"].copy()
+    e[2] = e[0][::-1]
+    _expect_einval(bp, mod(edges=e), match="duplicate")
+    e = base["edges"].copy()
+    e[0, 0] = 9
+    _expect_einval(bp, mod(edges=e), match="out of range")
+    e = base["edges"].copy()
+    e[0, 0] = -1
+    _expect_einval(bp, mod(edges=e), match="out of range")
+    lu = base["log_unary"].copy()
+    lu[3, 1] = np.nan
+    _expect_einval(bp, mod(log_unary=lu), match="log_unary")
+    J = base["coupling"].copy()
+    J[0] = np.inf
+    _expect_einval(bp, mod(coupling=J), match="coupling")
+    _expect_einval(bp, mod(pair_kind=7), match="pair_kind")
+    _expect_einval(bp, base, flags=0x10, match="flags")
+    # Ising needs K = 2
+    _expect_einval(bp, mod(K=3, log_unary=np.zeros((9, 3))), match="num_states")
+
+
+def test_rejects_nonpositive_potentials(bp):
+    p = inputs.potts_grid(3, 3, 4, 1.0, 0)
+    sh = p["shared"].copy()
+    sh[1, 2] = 0.0
+    _expect_einval(bp, dict(p, shared=sh), match="positive")
+    sc = p["edge_scale"].copy()
+    sc[0] = -1.0
+    _expect_einval(bp, dict(p, edge_scale=sc), match="positive")
+    t = inputs.random_tree(5, 3, 0)
+    pr = t["pair"].copy()
+    pr[2, 1, 1] = 0.0
+    _expect_einval(bp, dict(t, pair=pr), match="positive")
+    _expect_einval(bp, dict(t, K=65, log_unary=np.zeros((5, 65))), match="num_states")
+    _expect_einval(bp, dict(t, K=1, log_unary=np.zeros((5, 1))), match="num_states")
+
+
+def test_create_without_device_reports_device_error(bp):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    with pytest.raises(bp.BpError) as ei:
+        bp.Graph(inputs.ising_grid(4, 4, 1.0, 0), use_torch=False)
+    assert ei.value.code == bp.BP_EDEVICE
+
+
+def test_invalid_problem_rejected_before_device_use(bp):
+    p = inputs.ising_grid(3, 3, 1.0, 0)
+    e = p["edges"].copy()
+    e[0, 1] = e[0, 0]
+    with pytest.raises(bp.BpError) as ei:
+        bp.Graph(dict(p, edges=e), use_torch=False)
+    assert ei.value.code == bp.BP_EINVAL

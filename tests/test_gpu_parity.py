@@ -1,0 +1,409 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances:
+  * one sweep from the same FP32-rounded state: per message
+    max_x |m_gpu - m_ref| / max_x m_ref <= 1e-6 (FP32 messages vs FP64);
+  * marginals at convergence, on problems with a unique fixed point:
+    max-abs <= 1e-4;
+  * frontier sets of one RnBP / RBP iteration: identical except for messages
+    whose FP64 residual lies within 1e-6 of the decision threshold (eps for
+    RnBP, the k-th largest residual for RBP), where FP32 rounding may decide
+    either way; those are counted and must be rare.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_11469_amd import inputs
+from tests import exact_refs
+
+pytestmark = pytest.mark.gpu
+
+SWEEP_TOL = 1e-6
+MARG_TOL = 1e-4
+BAND = 1e-6
+
+
+@pytest.fixture(scope="module")
+def bp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1909_11469_amd import bp as mod
+    return mod
+
+
+def _rel_err(m_gpu, m_ref):
+    d = np.max(np.abs(m_gpu.astype(np.float64) - m_ref), axis=1)
+    return d / np.max(np.abs(m_ref), axis=1)
+
+
+def _random_state(E, K, seed, lo=0.02):
+    rng = np.random.default_rng(seed)
+    m = rng.uniform(lo, 1.0, size=(E, K))
+    m /= m.sum(1, keepdims=True)
+    return m.astype(np.float32)
+
+
+def _one_sweep_parity(bp, prob, state32, flags=0):
+    """GPU: one LBP commit from state32; oracle: f_BP(state32) in FP64."""
+    with bp.Graph(prob, flags=flags) as g:
+        g.set_state(state32, t=0, prev_active=-1)
+        start, _ = g.get_state()
+        r = g.run("lbp", eps=0.0, max_iters=1, warm_start=True)
+        assert r["iterations"] == 1
+        got, _ = g.get_state()
+    cand, res = oracle.evaluate(prob, start.astype(np.float64))
+    err = _rel_err(got, cand)
+    return err, res
+
+
+# ---------------------------------------------------------------------------
+# one LBP sweep (Eq. (2) + normalisation) from an identical FP32 state
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("t0", [0, 3, 17, 60])
+def test_ising20_single_sweep_from_oracle_state(bp, t0):
+    prob = inputs.ising_grid(20, 20, 2.5, 1)
+    ref = oracle.run(prob, oracle.LBP, eps=0.0, max_iters=t0)
+    err, _ = _one_sweep_parity(bp, prob, ref["msgs"].astype(np.float32))
+    assert err.max() <= SWEEP_TOL, err.max()
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("C,seed", [(1.0, 0), (2.5, 3), (4.0, 5)])
+def test_ising_single_sweep_random_state(bp, flags, C, seed):
+    prob = inputs.ising_grid(23, 37, C, seed)  # ragged tiles, several per grid
+    state = _random_state(2 * len(prob["edges"]), 2, seed)
+    err, _ = _one_sweep_parity(bp, prob, state, flags=flags)
+    assert err.max() <= SWEEP_TOL, err.max()
+
+
+def test_er_single_sweep(bp):
+    prob = inputs.er_graph(3000, 6.0, 2.5, 2)
+    state = _random_state(2 * len(prob["edges"]), 2, 4)
+    err, _ = _one_sweep_parity(bp, prob, state)
+    assert err.max() <= SWEEP_TOL, err.max()
+
+
+@pytest.mark.parametrize("K", [3, 8, 32])
+def test_potts_single_sweep(bp, K):
+    prob = inputs.potts_grid(9, 11, K, 1.0, K)
+    state = _random_state(2 * len(prob["edges"]), K, K)
+    err, _ = _one_sweep_parity(bp, prob, state)
+    assert err.max() <= SWEEP_TOL, err.max()
+
+
+def test_asymmetric_shared_table_single_sweep(bp):
+    prob = inputs.potts_grid(6, 7, 5, 1.0, 1)
+    rng = np.random.default_rng(0)
+    prob["shared"] = np.exp(rng.standard_normal((5, 5)))
+    state = _random_state(2 * len(prob["edges"]), 5, 2)
+    err, _ = _one_sweep_parity(bp, prob, state)
+    assert err.max() <= SWEEP_TOL, err.max()
+
+
+@pytest.mark.parametrize("K", [2, 4, 64])
+def test_dense_tables_single_sweep(bp, K):
+    prob = inputs.random_dense_graph(40, 90, K, K, coupling_scale=0.7)
+    state = _random_state(2 * len(prob["edges"]), K, K)
+    err, _ = _one_sweep_parity(bp, prob, state)
+    assert err.max() <= SWEEP_TOL, err.max()
+
+
+def test_high_degree_node_single_sweep(bp):
+    # a star centre with in-degree above every tile limit plus a ring
+    n = 5001
+    star = [(0, i) for i in range(1, n)]
+    ring = [(i, i + 1) for i in range(1, n - 1)]
+    edges = np.array(star + ring, dtype=np.int32)
+    rng = np.random.default_rng(3)
+    for K, kind in [(2, "ising"), (3, "dense")]:
+        if kind == "ising":
+            h = rng.uniform(-1, 1, n)
+            prob = dict(N=n, K=2, edges=edges, log_unary=np.stack([-h, h], 1),
+                        pair_kind=inputs.PAIR_ISING,
+                        coupling=rng.uniform(-0.3, 0.3, len(edges)))
+        else:
+            prob = dict(N=n, K=3, edges=edges, log_unary=rng.standard_normal((n, 3)),
+                        pair_kind=inputs.PAIR_DENSE,
+                        pair=np.exp(0.3 * rng.standard_normal((len(edges), 3, 3))))
+        state = _random_state(2 * len(edges), K, 9, lo=0.3)
+        err, _ = _one_sweep_parity(bp, prob, state)
+        assert err.max() <= SWEEP_TOL, (K, err.max())
+
+
+# ---------------------------------------------------------------------------
+# full runs: converged marginals on problems with a unique fixed point
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_ising20_lbp_converged_marginals(bp, seed):
+    prob = inputs.ising_grid(20, 20, 1.0, seed)
+    ref = oracle.run(prob, oracle.LBP, eps=1e-4, max_iters=10000)
+    with bp.Graph(prob) as g:
+        r = g.run("lbp", eps=1e-4, max_iters=10000)
+        marg = g.marginals()
+    assert r["converged"] and ref["converged"]
+    assert abs(r["iterations"] - ref["iterations"]) <= 1
+    assert np.max(np.abs(marg - ref["marginals"])) <= MARG_TOL
+    np.testing.assert_allclose(marg.sum(1), 1.0, atol=1e-6)
+
+
+@pytest.mark.parametrize("schedule,p", [("rnbp", 0.3), ("rnbp", 0.7), ("rbp", 0.2),
+                                        ("rbp", 1.0)])
+def test_ising20_schedules_converged_marginals(bp, schedule, p):
+    prob = inputs.ising_grid(20, 20, 1.0, 7)
+    ref = oracle.run(prob, oracle.LBP, eps=1e-7, max_iters=10000)
+    with bp.Graph(prob) as g:
+        r = g.run(schedule, eps=1e-6, p=p, seed=11, max_iters=100000)
+        marg = g.marginals()
+    assert r["converged"]
+    assert np.max(np.abs(marg - ref["marginals"])) <= MARG_TOL
+
+
+def test_chain_marginals_exact(bp):
+    prob = inputs.chain(2000, 2.5, 4)
+    exact = exact_refs.chain_marginals(prob)
+    with bp.Graph(prob) as g:
+        r = g.run("rnbp", eps=1e-6, p=0.7, seed=1, max_iters=100000)
+        marg = g.marginals()
+    assert r["converged"]
+    assert np.max(np.abs(marg - exact)) <= MARG_TOL
+
+
+def test_tree_dense_marginals_exact(bp):
+    prob = inputs.random_tree(11, 3, 5)
+    exact = exact_refs.brute_force_marginals(prob)
+    with bp.Graph(prob) as g:
+        r = g.run("lbp", eps=1e-6, max_iters=1000)
+        marg = g.marginals()
+    assert r["converged"]
+    assert np.max(np.abs(marg - exact)) <= MARG_TOL
+
+
+def test_potts_converged_marginals(bp):
+    prob = inputs.potts_grid(12, 12, 32, 1.0, 0)
+    ref = oracle.run(prob, oracle.LBP, eps=1e-6, max_iters=10000)
+    with bp.Graph(prob) as g:
+        r = g.run("rnbp", eps=1e-6, p=0.5, seed=3, max_iters=100000)
+        marg = g.marginals()
+    assert r["converged"] and ref["converged"]
+    assert np.max(np.abs(marg - ref["marginals"])) <= MARG_TOL
+
+
+def test_er_converged_marginals(bp):
+    prob = inputs.er_graph(2000, 6.0, 0.5, 3)
+    ref = oracle.run(prob, oracle.LBP, eps=1e-7, max_iters=10000)
+    with bp.Graph(prob) as g:
+        r = g.run("rnbp", eps=1e-6, p=0.3, seed=3, max_iters=100000)
+        marg = g.marginals()
+    assert r["converged"] and ref["converged"]
+    assert np.max(np.abs(marg - ref["marginals"])) <= MARG_TOL
+
+
+# ---------------------------------------------------------------------------
+# frontier rules, one iteration from an identical state
+# ---------------------------------------------------------------------------
+def _one_iteration(bp, prob, state32, schedule, p, seed=0, t=0, prev=-1, eps=1e-4,
+                   dynamic_p=True, flags=0):
+    with bp.Graph(prob, flags=flags) as g:
+        g.set_state(state32, t=t, prev_active=prev)
+        start, _ = g.get_state()
+        r = g.run(schedule, eps=eps, p=p, seed=seed, max_iters=1, warm_start=True,
+                  dynamic_p=dynamic_p)
+        got, st = g.get_state()
+    changed = np.any(got != start, axis=1)
+    return start, got, changed, r, st
+
+
+@pytest.mark.parametrize("dynamic_p,prev", [(False, -1), (True, -1), (True, 10), (True, 10 ** 6)])
+def test_rnbp_frontier_one_iteration(bp, dynamic_p, prev):
+    prob = inputs.ising_grid(30, 30, 2.5, 2)
+    E = 2 * len(prob["edges"])
+    state = _random_state(E, 2, 5, lo=0.3)
+    eps, p, seed, t = 0.05, 0.4, 1234, 7
+    start, got, changed, r, st = _one_iteration(bp, prob, state, "rnbp", p, seed, t, prev, eps,
+                                                dynamic_p)
+    cand, res = oracle.evaluate(prob, start.astype(np.float64))
+    src, dst = oracle.canonical_src_dst(prob)
+    u = np.array([oracle.uniform(seed, src[e], dst[e], t) for e in range(E)])
+    n_t = int((res > eps).sum())
+    if not dynamic_p:
+        p_t = p
+    else:
+        p_t = p if (prev > 0 and n_t / prev > 0.9) else 1.0
+    want = (res > eps) & (u < p_t)
+    band = np.abs(res - eps) < BAND
+    assert np.array_equal(changed[~band], want[~band])
+    assert band.sum() <= 3
+    # committed values are Eq. (2) candidates
+    err = _rel_err(got[want & ~band], cand[want & ~band])
+    assert err.max() <= SWEEP_TOL
+    assert r["committed"] == changed.sum()
+    assert st["t"] == t + 1 and abs(st["prev_active"] - n_t) <= band.sum()
+
+
+@pytest.mark.parametrize("p", [1 / 256, 0.05, 0.5])
+def test_rbp_frontier_one_iteration(bp, p):
+    prob = inputs.ising_grid(30, 30, 2.5, 4)
+    E = 2 * len(prob["edges"])
+    state = _random_state(E, 2, 6, lo=0.3)
+    start, got, changed, r, _ = _one_iteration(bp, prob, state, "rbp", p, eps=1e-9)
+    cand, res = oracle.evaluate(prob, start.astype(np.float64))
+    src, dst = oracle.canonical_src_dst(prob)
+    k = max(1, int(np.ceil(p * E)))
+    order = sorted(range(E), key=lambda e: (-res[e], dst[e], src[e]))
+    want = np.zeros(E, bool)
+    want[order[:k]] = True
+    kth = res[order[k - 1]]
+    band = np.abs(res - kth) < BAND
+    assert np.array_equal(changed[~band], want[~band])
+    assert changed.sum() == k and r["committed"] == k
+
+
+def test_rbp_full_fraction_bitwise_equals_lbp(bp):
+    prob = inputs.ising_grid(25, 25, 2.5, 8)
+    outs = []
+    for sched in ("lbp", "rbp"):
+        with bp.Graph(prob) as g:
+            g.run(sched, eps=1e-4, p=1.0, max_iters=40)
+            outs.append(g.get_state()[0])
+    assert np.array_equal(outs[0], outs[1])
+
+
+# ---------------------------------------------------------------------------
+# determinism, resume, symmetry, degenerate inputs
+# ---------------------------------------------------------------------------
+def test_bitwise_determinism(bp):
+    prob = inputs.ising_grid(64, 64, 2.5, 3)
+    outs = []
+    for _ in range(2):
+        with bp.Graph(prob) as g:
+            r = g.run("rnbp", eps=1e-4, p=0.3, seed=5, max_iters=300)
+            outs.append((g.get_state()[0], r["committed"], r["last_active"]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
+
+
+@pytest.mark.parametrize("schedule", ["lbp", "rnbp", "rbp"])
+def test_resume_from_exported_state(bp, schedule):
+    # checkpoint through bp_get_state / bp_set_state (FP32 probabilities) and
+    # resume: equal to the uninterrupted run up to the FP32 round trip
+    prob = inputs.ising_grid(40, 40, 1.0, 6)
+    kw = dict(eps=1e-6, p=0.3, seed=9)
+    with bp.Graph(prob) as g:
+        g.run(schedule, max_iters=60, **kw)
+        full = g.get_state()[0]
+    with bp.Graph(prob) as g:
+        g.run(schedule, max_iters=25, **kw)
+        mid, st = g.get_state()
+    assert st["t"] == 25
+    with bp.Graph(prob) as g:
+        g.set_state(mid, t=st["t"], prev_active=st["prev_active"])
+        g.run(schedule, max_iters=35, warm_start=True, **kw)
+        resumed = g.get_state()[0]
+    np.testing.assert_allclose(resumed, full, atol=1e-5)
+
+
+@pytest.mark.parametrize("schedule", ["lbp", "rnbp", "rbp"])
+def test_warm_start_in_place_continuation_is_bitwise(bp, schedule):
+    prob = inputs.ising_grid(40, 40, 2.5, 6)
+    kw = dict(eps=1e-4, p=0.3, seed=9)
+    with bp.Graph(prob) as g:
+        g.run(schedule, max_iters=60, **kw)
+        full = g.get_state()[0]
+    with bp.Graph(prob) as g:
+        g.run(schedule, max_iters=25, **kw)
+        g.run(schedule, max_iters=35, warm_start=True, **kw)
+        cont = g.get_state()[0]
+    assert np.array_equal(full, cont)
+
+
+def test_spin_flip_symmetry(bp):
+    prob = inputs.ising_grid(30, 30, 1.0, 2)
+    flip = dict(prob, log_unary=prob["log_unary"][:, ::-1].copy())
+    with bp.Graph(prob) as g:
+        g.run("lbp", eps=1e-6, max_iters=5000)
+        a = g.marginals()
+    with bp.Graph(flip) as g:
+        g.run("lbp", eps=1e-6, max_iters=5000)
+        b = g.marginals()
+    np.testing.assert_allclose(a, b[:, ::-1], atol=1e-6)
+
+
+def test_zero_field_converges_at_start(bp):
+    prob = inputs.ising_grid(16, 16, 2.5, 1)
+    prob["log_unary"] = np.zeros_like(prob["log_unary"])
+    with bp.Graph(prob) as g:
+        r = g.run("rnbp", eps=1e-9, p=0.5, max_iters=100)
+        marg = g.marginals()
+    assert r["converged"] and r["iterations"] == 0 and r["last_active"] == 0
+    np.testing.assert_allclose(marg, 0.5, atol=1e-7)
+
+
+def test_edgeless_and_isolated_nodes(bp):
+    prob = dict(N=7, K=3, edges=np.zeros((0, 2), np.int32),
+                log_unary=np.log(np.arange(1, 22, dtype=float).reshape(7, 3)),
+                pair_kind=inputs.PAIR_DENSE, pair=np.zeros((0, 3, 3)))
+    with bp.Graph(prob) as g:
+        r = g.run("lbp", eps=1e-6, max_iters=10)
+        marg = g.marginals()
+    assert r["converged"] and r["iterations"] == 0
+    pu = np.exp(prob["log_unary"])
+    np.testing.assert_allclose(marg, pu / pu.sum(1, keepdims=True), atol=1e-6)
+    er = inputs.er_graph(500, 1.0, 1.0, 0)  # many isolated nodes
+    ref = oracle.run(er, oracle.LBP, eps=1e-7, max_iters=1000)
+    with bp.Graph(er) as g:
+        g.run("lbp", eps=1e-6, max_iters=1000)
+        assert np.max(np.abs(g.marginals() - ref["marginals"])) <= MARG_TOL
+
+
+def test_max_iters_zero_only_evaluates(bp):
+    prob = inputs.ising_grid(10, 10, 1.0, 0)
+    with bp.Graph(prob) as g:
+        r = g.run("lbp", eps=1e-4, max_iters=0)
+        m, st = g.get_state()
+    assert not r["converged"] and r["iterations"] == 0 and r["evaluated"] == 360
+    np.testing.assert_array_equal(m, 0.5)
+    assert st["t"] == 0
+
+
+def test_counts_match_oracle_lbp(bp):
+    # LBP has no random decisions: n_t and R_t of the last evaluation agree with
+    # the oracle up to residuals that FP32 rounding can move across eps
+    prob = inputs.ising_grid(20, 20, 1.0, 0)
+    ref = oracle.run(prob, oracle.LBP, eps=1e-4, max_iters=12)
+    _, res = oracle.evaluate(prob, ref["msgs"])
+    with bp.Graph(prob) as g:
+        r = g.run("lbp", eps=1e-4, max_iters=12)
+    assert r["iterations"] == ref["iterations"] == 12
+    assert abs(r["last_active"] - ref["last_active"]) <= int((np.abs(res - 1e-4) < BAND).sum())
+    assert abs(r["last_max_residual"] - ref["last_max_residual"]) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# the 1000 x 1000 Ising workload in the configuration the benchmark times
+# ---------------------------------------------------------------------------
+def test_ising_1000_single_sweep_full_size(bp):
+    prob = inputs.ising_grid(1000, 1000, 2.5, 0)
+    E = 2 * len(prob["edges"])
+    state = _random_state(E, 2, 1, lo=0.05)
+    err, _ = _one_sweep_parity(bp, prob, state)
+    assert err.max() <= SWEEP_TOL, err.max()
+
+
+def test_ising_1000_rnbp_iteration_full_size(bp):
+    prob = inputs.ising_grid(1000, 1000, 2.5, 0)
+    E = 2 * len(prob["edges"])
+    ref = oracle.run(prob, oracle.LBP, eps=0.0, max_iters=2)
+    state = ref["msgs"].astype(np.float32)
+    eps, p, seed, t = 1e-4, 0.5, 77, 2
+    start, got, changed, r, _ = _one_iteration(bp, prob, state, "rnbp", p, seed, t, -1, eps,
+                                               dynamic_p=False)
+    cand, res = oracle.evaluate(prob, start.astype(np.float64))
+    rng = np.random.default_rng(0)
+    sample = rng.choice(E, 20000, replace=False)
+    src, dst = oracle.canonical_src_dst(prob)
+    u = np.array([oracle.uniform(seed, src[e], dst[e], t) for e in sample])
+    want = (res[sample] > eps) & (u < p)
+    band = np.abs(res[sample] - eps) < BAND
+    assert np.array_equal(changed[sample][~band], want[~band])
+    sel = sample[want & ~band]
+    assert _rel_err(got[sel], cand[sel]).max() <= SWEEP_TOL
