@@ -21,6 +21,7 @@
  * Message ids are canonical: for undirected edge u = (a, b) given in input
  * order, id 2u is a->b and id 2u+1 is b->a (two messages per edge, Sec. II-A).
  */
+#include <limits.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -165,23 +166,49 @@ static void free_model(model_t* g) {
     free(g->in_ids);
 }
 
+/* A product of many factors below 1 leaves the double range once a node has a
+ * few hundred neighbours; products are therefore kept as mant * 2^ex with
+ * mant renormalised by frexp after every factor.  This is the same literal
+ * product (one rounding per factor) with a wider exponent. */
+typedef struct {
+    double mant;
+    long ex;
+} xprod;
+
+static void xmul(xprod* p, double v) {
+    int e;
+    p->mant = frexp(p->mant * v, &e);
+    p->ex += e;
+}
+
+/* Scale the K products by a common power of two so the largest is O(1). */
+static void xprod_to_double(const xprod* p, int K, double* out) {
+    long top = LONG_MIN;
+    for (int x = 0; x < K; ++x)
+        if (p[x].mant != 0.0 && p[x].ex > top) top = p[x].ex;
+    for (int x = 0; x < K; ++x)
+        out[x] = p[x].mant == 0.0 ? 0.0 : ldexp(p[x].mant, (int)(p[x].ex - top));
+}
+
 /* Eq. (2) for message e = i -> j, from the message set m (read only):
  *   c(x_j) = sum_{x_i} psi_ij(x_i, x_j) psi_i(x_i) prod_{k in Gamma_i \ j} m_{k->i}(x_i)
- * then normalised to sum 1 (Sec. II-A).  work holds K doubles. */
+ * then normalised to sum 1 (Sec. II-A).  pw holds K products, work K doubles. */
 static void eval_message(const model_t* g, const double* m, int64_t e, double* out,
-                         double* work) {
+                         double* work, xprod* pw) {
     int K = g->K;
     int i = msg_src(g, e);
     int64_t back = e ^ 1; /* the message j -> i, excluded from the product */
     for (int xi = 0; xi < K; ++xi) {
-        double prod = g->unary[(int64_t)i * K + xi];
+        xprod prod = {1.0, 0};
+        xmul(&prod, g->unary[(int64_t)i * K + xi]);
         for (int64_t q = g->in_ptr[i]; q < g->in_ptr[i + 1]; ++q) {
             int64_t f = g->in_ids[q];
             if (f == back) continue;
-            prod *= m[f * K + xi];
+            xmul(&prod, m[f * K + xi]);
         }
-        work[xi] = prod;
+        pw[xi] = prod;
     }
+    xprod_to_double(pw, K, work);
     double z = 0.0;
     for (int xj = 0; xj < K; ++xj) {
         double s = 0.0;
@@ -193,19 +220,26 @@ static void eval_message(const model_t* g, const double* m, int64_t e, double* o
 }
 
 /* Eq. (3): b_i(x) proportional to psi_i(x) prod_{k in Gamma_i} m_{k->i}(x). */
-static void beliefs(const model_t* g, const double* m, double* out) {
+static int beliefs(const model_t* g, const double* m, double* out) {
     int K = g->K;
+    xprod* pw = (xprod*)malloc(sizeof(xprod) * (size_t)K);
+    if (!pw) return -2;
     for (int i = 0; i < g->N; ++i) {
-        double z = 0.0;
         for (int x = 0; x < K; ++x) {
-            double b = g->unary[(int64_t)i * K + x];
+            xprod b = {1.0, 0};
+            xmul(&b, g->unary[(int64_t)i * K + x]);
             for (int64_t q = g->in_ptr[i]; q < g->in_ptr[i + 1]; ++q)
-                b *= m[g->in_ids[q] * K + x];
-            out[(int64_t)i * K + x] = b;
-            z += b;
+                xmul(&b, m[g->in_ids[q] * K + x]);
+            pw[x] = b;
         }
-        for (int x = 0; x < K; ++x) out[(int64_t)i * K + x] /= z;
+        double* row = out + (int64_t)i * K;
+        xprod_to_double(pw, K, row);
+        double z = 0.0;
+        for (int x = 0; x < K; ++x) z += row[x];
+        for (int x = 0; x < K; ++x) row[x] /= z;
     }
+    free(pw);
+    return 0;
 }
 
 /* Ordering for the greedy frontier of Sec. III-A: larger residual first; equal
@@ -267,8 +301,9 @@ int oracle_bp_run(int N, int K, int64_t M, const int32_t* edges, const double* l
     unsigned char* sel = (unsigned char*)malloc((size_t)E + 1);
     int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)E + 1);
     double* work = (double*)malloc(sizeof(double) * (size_t)K);
-    if (!m || !cand || !res || !sel || !order || !work) {
-        free(m); free(cand); free(res); free(sel); free(order); free(work);
+    xprod* pw = (xprod*)malloc(sizeof(xprod) * (size_t)K);
+    if (!m || !cand || !res || !sel || !order || !work || !pw) {
+        free(m); free(cand); free(res); free(sel); free(order); free(work); free(pw);
         free_model(&g);
         return -2;
     }
@@ -288,7 +323,7 @@ int oracle_bp_run(int N, int K, int64_t M, const int32_t* edges, const double* l
         int64_t n_t = 0;
         double r_max = 0.0;
         for (int64_t e = 0; e < E; ++e) {
-            eval_message(&g, m, e, cand + e * K, work);
+            eval_message(&g, m, e, cand + e * K, work, pw);
             double r = 0.0;
             for (int x = 0; x < K; ++x) {
                 double d = fabs(cand[e * K + x] - m[e * K + x]);
@@ -359,9 +394,13 @@ int oracle_bp_run(int N, int K, int64_t M, const int32_t* edges, const double* l
     }
     st.converged = converged;
     if (out_msgs) memcpy(out_msgs, m, sizeof(double) * (size_t)E * (size_t)K);
-    if (out_marginals) beliefs(&g, m, out_marginals);
+    int brc = out_marginals ? beliefs(&g, m, out_marginals) : 0;
     if (stats) *stats = st;
-    free(m); free(cand); free(res); free(sel); free(order); free(work);
+    free(m); free(cand); free(res); free(sel); free(order); free(work); free(pw);
+    if (brc != 0) {
+        free_model(&g);
+        return brc;
+    }
     free_model(&g);
     return converged ? 0 : 1;
 }
@@ -380,8 +419,14 @@ int oracle_bp_evaluate(int N, int K, int64_t M, const int32_t* edges,
         return -2;
     }
     double* work = (double*)malloc(sizeof(double) * (size_t)K);
+    xprod* pw = (xprod*)malloc(sizeof(xprod) * (size_t)K);
+    if (!work || !pw) {
+        free(work); free(pw);
+        free_model(&g);
+        return -2;
+    }
     for (int64_t e = 0; e < g.E; ++e) {
-        eval_message(&g, msgs, e, out_cand + e * K, work);
+        eval_message(&g, msgs, e, out_cand + e * K, work, pw);
         double r = 0.0;
         for (int x = 0; x < K; ++x) {
             double d = fabs(out_cand[e * K + x] - msgs[e * K + x]);
@@ -390,6 +435,7 @@ int oracle_bp_evaluate(int N, int K, int64_t M, const int32_t* edges,
         out_res[e] = r;
     }
     free(work);
+    free(pw);
     free_model(&g);
     return 0;
 }
@@ -405,7 +451,7 @@ int oracle_bp_beliefs(int N, int K, int64_t M, const int32_t* edges, const doubl
         free_model(&g);
         return -2;
     }
-    beliefs(&g, msgs, out_marginals);
+    int rc = beliefs(&g, msgs, out_marginals);
     free_model(&g);
-    return 0;
+    return rc;
 }

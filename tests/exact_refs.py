@@ -131,6 +131,36 @@ def grid_marginals_transfer(problem, H, W):
     return out
 
 
+def star_marginals(problem, center=0):
+    """Exact marginals of a star (every edge joins ``center`` to a leaf), summed in
+    log space: the centre's marginal is psi_c(x) prod_l sum_y psi(x, y) psi_l(y); a
+    leaf's is psi_l(y) sum_x psi(x, y) psi_c(x) prod_{l' != l} (...)."""
+    N, K = int(problem["N"]), int(problem["K"])
+    edges = np.asarray(problem["edges"]).reshape(-1, 2)
+    lu = np.asarray(problem["log_unary"], float)
+    leaf_terms = np.zeros((len(edges), K))  # log sum_y psi(x_c = x, y) psi_l(y)
+    tabs = []
+    for u, (a, b) in enumerate(edges):
+        T = _pair_table(problem, u)
+        if int(a) == center:
+            leaf, Tcl = int(b), T
+        else:
+            assert int(b) == center
+            leaf, Tcl = int(a), T.T
+        tabs.append((leaf, Tcl))
+        leaf_terms[u] = np.log(Tcl @ np.exp(lu[leaf]))
+    total = lu[center] + leaf_terms.sum(axis=0)
+    out = np.zeros((N, K))
+    w = np.exp(total - total.max())
+    out[center] = w / w.sum()
+    for u, (leaf, Tcl) in enumerate(tabs):
+        lc = total - leaf_terms[u]  # centre without this leaf
+        c = np.exp(lc - lc.max())
+        b = np.exp(lu[leaf]) * (Tcl.T @ c)
+        out[leaf] = b / b.sum()
+    return out
+
+
 def ising_message_closed_form(h_i, J, u_in):
     """Eq. (2) for psi_i = exp(h_i s_i), psi_ij = exp(J s_i s_j), with incoming
     messages written as fields u_k = 0.5 log(m(+1) / m(-1)) over Gamma_i \\ j.

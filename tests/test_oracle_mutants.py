@@ -145,14 +145,14 @@ BATTERY = [pin_tree, pin_chain, pin_closed_form, pin_normalised, pin_two_node_be
 
 MUTANTS = {
     "reverse_message_not_excluded": ("if (f == back) continue;", ";"),
-    "unary_dropped_from_update": ("double prod = g->unary[(int64_t)i * K + xi];",
-                                  "double prod = 1.0;"),
+    "unary_dropped_from_update": ("xmul(&prod, g->unary[(int64_t)i * K + xi]);", ";"),
     "pairwise_not_transposed_for_reverse": (
         "return (e & 1) ? pair_psi(g, u, xj, xi) : pair_psi(g, u, xi, xj);",
         "return pair_psi(g, u, xi, xj);"),
     "spin_sign_of_one_end": ("double sa = xa ? 1.0 : -1.0,", "double sa = xa ? -1.0 : 1.0,"),
     "update_not_normalised": ("for (int xj = 0; xj < K; ++xj) out[xj] /= z;", ";"),
-    "belief_unary_dropped": ("double b = g->unary[(int64_t)i * K + x];", "double b = 1.0;"),
+    "belief_unary_dropped": ("xmul(&b, g->unary[(int64_t)i * K + x]);", ";"),
+    "product_exponent_dropped": ("p->ex += e;", ";"),
     "residual_l1_not_linf": ("if (d > r) r = d;\n            }\n            res[e] = r;",
                              "r += d;\n            }\n            res[e] = r;"),
     "asynchronous_commit": ("            res[e] = r;\n",

@@ -110,6 +110,21 @@ def test_chain_marginals_rnbp_and_rbp_exact():
         np.testing.assert_allclose(r["marginals"], exact, atol=1e-10, rtol=0)
 
 
+@pytest.mark.parametrize("K", [2, 3])
+def test_high_degree_star_exact(K):
+    # the centre's products run over thousands of factors below one
+    n = 3001
+    rng = np.random.default_rng(K)
+    edges = np.array([(0, i) if i % 2 else (i, 0) for i in range(1, n)], dtype=np.int32)
+    prob = dict(N=n, K=K, edges=edges, log_unary=rng.standard_normal((n, K)),
+                pair_kind=inputs.PAIR_DENSE,
+                pair=np.exp(0.5 * rng.standard_normal((n - 1, K, K))))
+    exact = exact_refs.star_marginals(prob)
+    r = oracle.run(prob, oracle.LBP, eps=1e-14, max_iters=10)
+    assert r["converged"]
+    np.testing.assert_allclose(r["marginals"], exact, atol=1e-11, rtol=0)
+
+
 def test_two_node_closed_form():
     # one edge: b_a(x) is proportional to psi_a(x) sum_y psi(x, y) psi_b(y)
     prob = inputs.random_tree(2, 3, 11)
