@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbp.so")
+# BP_LIBRARY selects another build of the same library (tuning builds); the
+# default is the in-tree libbp.so.
+LIB_PATH = os.environ.get("BP_LIBRARY") or os.path.join(_HERE, "libbp.so")
 
 BP_OK, BP_NOT_CONVERGED = 0, 1
 BP_EINVAL, BP_ENOMEM, BP_EDEVICE, BP_ESTATE = -1, -2, -3, -4

@@ -17,22 +17,25 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-I" + os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile and link libbp.so.  ``defines`` (e.g. a tile size) and ``out``
+    produce an alternative build for tuning; the default is the shipped one."""
     objs = []
+    tag = "" if out == LIB else "." + os.path.basename(out)
     for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.basename(src) + ".o")
-        cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ["-c", src, "-o", obj]
+        obj = os.path.join(CSRC, os.path.basename(src) + tag + ".o")
+        cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ["-D" + d for d in defines] + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

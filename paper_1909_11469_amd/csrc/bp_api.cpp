@@ -71,6 +71,7 @@ struct HostLayout {
     std::vector<int> rev;             // [E]
     std::vector<int> slot_of_canon;   // [E]
     std::vector<int> tile_start;      // [T+1]
+    std::vector<int> tile_slot;       // [T+1] in_ptr[tile_start]
     std::vector<float> coupling;      // [E] (Ising)
     std::vector<float> unary;         // [N] log-odds or [N][K] log psi (max-shifted)
     std::vector<float> pair_tab;      // shared (2KK) or dense [E][K][K]
@@ -87,8 +88,8 @@ struct Arena {
 };
 
 struct Offsets {
-    size_t in_ptr, src, rev, tile, coupling, unary, pair, orient, m0, m1, cand, keys, revert,
-        ties, state, marg, total;
+    size_t in_ptr, src, rev, tile, tile_slot, coupling, unary, pair, orient, msg[4], cand, keys, ties, state,
+        ctr, marg, total;
 };
 
 Offsets plan(const HostLayout& L) {
@@ -99,17 +100,17 @@ Offsets plan(const HostLayout& L) {
     o.src = a.take(sizeof(int) * E);
     o.rev = a.take(sizeof(int) * E);
     o.tile = a.take(sizeof(int) * L.tile_start.size());
+    o.tile_slot = a.take(sizeof(int) * L.tile_slot.size());
     o.coupling = a.take(sizeof(float) * L.coupling.size());
     o.unary = a.take(sizeof(float) * L.unary.size());
     o.pair = a.take(sizeof(float) * L.pair_tab.size());
     o.orient = a.take(L.orient.size());
-    o.m0 = a.take(sizeof(float) * E * L.row);
-    o.m1 = a.take(sizeof(float) * E * L.row);
+    for (int i = 0; i < 4; ++i) o.msg[i] = a.take(sizeof(float) * E * L.row);
     o.cand = a.take(sizeof(float) * E * L.row);
     o.keys = a.take(sizeof(unsigned int) * E);
-    o.revert = a.take(sizeof(int) * E);
     o.ties = a.take(sizeof(unsigned int) * (E / 4096 + 2));
     o.state = a.take(sizeof(DevState));
+    o.ctr = a.take(sizeof(CounterLine) * 4 * kCounterCopies);
     o.marg = a.take(sizeof(float) * (size_t)L.N * L.K);
     o.total = a.off;
     return o;
@@ -262,7 +263,8 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
     // a node whose in-degree alone exceeds the slot limit gets a tile of its own
     const int slot_lim = L.layout == kLayoutLogOdds ? kTileSlotsLogOdds
                                                     : std::max(1, kTileFloatsGeneric / (int)K);
-    const int node_lim = L.layout == kLayoutLogOdds ? kTileNodesMax : std::min(kTileNodesMax, slot_lim);
+    const int node_lim = L.layout == kLayoutLogOdds ? kTileNodesLogOdds
+                                                    : std::min(kTileNodesMax, slot_lim);
     L.tile_start.clear();
     long long n = 0;
     while (n < N) {
@@ -274,6 +276,8 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
         n = m;
     }
     L.tile_start.push_back((int)N);
+    L.tile_slot.resize(L.tile_start.size());
+    for (size_t i = 0; i < L.tile_start.size(); ++i) L.tile_slot[i] = L.in_ptr[L.tile_start[i]];
     return BP_OK;
 }
 
@@ -286,15 +290,20 @@ struct bp_graph {
     hipStream_t stream = nullptr;
     char* base = nullptr;
     bool owns_memory = false;
-    int cur = 0;                 // buffer holding the current messages
+    // Message buffers: two pairs; pair p holds m^{t+1} under the larger [p][0]
+    // and the smaller [p][1] keep threshold.  (cur_pair, cur_sel) locates m^t.
+    int cur_pair = 0;
+    int cur_sel = 0;
     long long t_next = 0;        // global iteration number of the next evaluation
     long long prev_active = -1;  // n_{t_next - 1}
     DevState* host_state = nullptr;  // pinned mirror
 
     template <typename T>
     T* at(size_t o) const { return reinterpret_cast<T*>(base + o); }
-    float* msg(int i) const { return at<float>(i ? off.m1 : off.m0); }
+    float* msg(int pair, int sel) const { return at<float>(off.msg[2 * pair + sel]); }
+    float* cur() const { return msg(cur_pair, cur_sel); }
     DevState* st() const { return at<DevState>(off.state); }
+    CounterLine* ctr() const { return at<CounterLine>(off.ctr); }
 };
 
 extern "C" {
@@ -371,7 +380,8 @@ int bp_create_graph(const bp_graph_desc* desc, bp_graph** out) {
         if (n == 0) return hipSuccess;
         return hipMemcpyAsync(g->base + o, p, n, hipMemcpyHostToDevice, s);
     };
-    hipError_t errs[8] = {
+    hipError_t errs[9] = {
+        up(g->off.tile_slot, L.tile_slot.data(), sizeof(int) * L.tile_slot.size()),
         up(g->off.in_ptr, L.in_ptr.data(), sizeof(int) * L.in_ptr.size()),
         up(g->off.src, L.src.data(), sizeof(int) * L.src.size()),
         up(g->off.rev, L.rev.data(), sizeof(int) * L.rev.size()),
@@ -386,14 +396,15 @@ int bp_create_graph(const bp_graph_desc* desc, bp_graph** out) {
             return hip_fail(x, "upload");
         }
     const float uni = L.layout == kLayoutLogOdds ? 0.0f : 1.0f / (float)L.K;
-    e = launch_fill(g->msg(0), uni, L.E * L.row, s);
-    if (e == hipSuccess) e = launch_init_state(g->st(), s);
+    e = launch_fill(g->msg(0, 0), uni, L.E * L.row, s);
+    if (e == hipSuccess) e = launch_init_state(g->st(), g->ctr(), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         bp_destroy_graph(g);
         return hip_fail(e, "initialise");
     }
-    g->cur = 0;
+    g->cur_pair = 0;
+    g->cur_sel = 0;
     *out = g;
     return BP_OK;
 }
@@ -449,17 +460,24 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     hipStream_t s = g->stream;
     if (!o.warm_start) {
         const float uni = L.layout == kLayoutLogOdds ? 0.0f : 1.0f / (float)L.K;
-        HIP_OK(launch_fill(g->msg(g->cur), uni, L.E * L.row, s), "fill");
+        HIP_OK(launch_fill(g->cur(), uni, L.E * L.row, s), "fill");
         g->t_next = 0;
         g->prev_active = -1;
     }
-    HIP_OK(launch_init_state(g->st(), s), "init state");
+    if (g->t_next + o.max_iters + 1 > 0xFFFFFFFFLL)
+        return fail(BP_EINVAL, "iteration counter would pass 2^32");
+    HIP_OK(launch_init_state(g->st(), g->ctr(), s), "init state");
 
     const int mode = schedule == BP_LBP ? kModeLBP : schedule == BP_RBP ? kModeRBP : kModeRnBP;
     const unsigned int thr_lo = keep_threshold(p);
     const unsigned int thr_hi = keep_threshold(o.high_p);
+    long long rbp_k = (long long)std::ceil(p * (double)L.E);
+    if (rbp_k < 1) rbp_k = 1;
+    if (rbp_k > L.E) rbp_k = L.E;
+
     EvalArgs a{};
     a.tile_start = g->at<int>(g->off.tile);
+    a.tile_slot = g->at<int>(g->off.tile_slot);
     a.num_tiles = (int)L.tile_start.size() - 1;
     a.tiles_per_xcd = (a.num_tiles + 7) / 8;
     a.in_ptr = g->at<int>(g->off.in_ptr);
@@ -471,42 +489,33 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     a.orient = g->at<unsigned char>(g->off.orient);
     a.cand = g->at<float>(g->off.cand);
     a.keys = g->at<unsigned int>(g->off.keys);
-    a.revert_list = g->at<int>(g->off.revert);
     a.st = g->st();
+    a.ctr = g->ctr();
     a.num_states = L.K;
     a.pair_kind = L.pair;
+    a.sched = mode;
     a.eps = (float)eps;
-    a.key0 = (unsigned int)(seed & 0xFFFFFFFFu);
-    a.key1 = (unsigned int)(seed >> 32);
-    bool low_is_a = true, differ = false;
-    if (mode == kModeRnBP && o.dynamic_p) {
-        a.thr_a = std::max(thr_lo, thr_hi);
-        a.thr_b = std::min(thr_lo, thr_hi);
-        low_is_a = thr_lo >= thr_hi;
-        differ = thr_lo != thr_hi;
-    } else {
-        a.thr_a = a.thr_b = thr_lo;
-    }
     // The device compares FP32 residuals with an FP32 threshold: take the largest
     // float <= eps, so that for every float r, r > eps_f exactly when r > eps.
     if ((double)a.eps > eps) a.eps = std::nextafter(a.eps, -INFINITY);
-
-    long long rbp_k = (long long)std::ceil(p * (double)L.E);
-    if (rbp_k < 1) rbp_k = 1;
-    if (rbp_k > L.E) rbp_k = L.E;
-
-    FinishArgs f{};
-    f.st = g->st();
-    f.mode = mode;
-    f.dynamic_p = o.dynamic_p;
-    f.low_is_a = low_is_a;
-    f.thresholds_differ = differ;
-    f.ratio_threshold = o.ratio_threshold;
-    f.num_messages = (unsigned long long)L.E;
-    f.rbp_k = (unsigned long long)rbp_k;
-    f.revert_list = g->at<int>(g->off.revert);
-    f.row = L.row;
-    f.prev_active_host = g->prev_active;
+    a.key0 = (unsigned int)(seed & 0xFFFFFFFFu);
+    a.key1 = (unsigned int)(seed >> 32);
+    a.dynamic_p = o.dynamic_p;
+    a.ratio_threshold = o.ratio_threshold;
+    a.prev_active_host = g->prev_active;
+    a.num_messages = (unsigned long long)L.E;
+    a.rbp_k = (unsigned long long)rbp_k;
+    a.sel0 = g->cur_sel;
+    if (mode == kModeRnBP && o.dynamic_p) {
+        a.thr_a = std::max(thr_lo, thr_hi);
+        a.thr_b = std::min(thr_lo, thr_hi);
+        a.low_is_a = thr_lo >= thr_hi;
+        a.two_outputs = thr_lo != thr_hi;
+    } else {
+        a.thr_a = a.thr_b = thr_lo;
+        a.low_is_a = 1;
+        a.two_outputs = 0;
+    }
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     HIP_OK(hipEventCreate(&ev0), "event");
@@ -522,42 +531,50 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
 
     const int kp = kpad(L.K);
     const long long t_start = g->t_next;
-    const int cur0 = g->cur;
+    const int pair0 = g->cur_pair;
+    float* const start_buf = g->cur();
+    unsigned int* ties = g->at<unsigned int>(g->off.ties);
     int in_chunk = 0;
-    int rc = BP_OK;
-    for (long long it = 0;; ++it) {
+    long long it = 0;
+    bool final_launched = false;
+    for (;; ++it) {
         const long long t = t_start + it;
-        const bool final_eval = it == o.max_iters;
-        const int b_in = mode == kModeRBP ? cur0 : (int)((cur0 + it) & 1);
-        a.m_in = g->msg(b_in);
-        a.m_out = g->msg(b_in ^ 1);
+        final_launched = it == o.max_iters;
+        if (mode == kModeRBP) {
+            // frontier residual BP commits in place after the top-k selection
+            a.in_buf[0] = a.in_buf[1] = start_buf;
+            a.out_buf[0] = a.out_buf[1] = nullptr;
+        } else {
+            const int pin = (int)((pair0 + it) & 1);
+            if (it == 0) {
+                a.in_buf[0] = a.in_buf[1] = start_buf;
+            } else {
+                a.in_buf[0] = g->msg(pin, 0);
+                a.in_buf[1] = g->msg(pin, 1);
+            }
+            a.out_buf[0] = g->msg(pin ^ 1, 0);
+            a.out_buf[1] = g->msg(pin ^ 1, 1);
+        }
         a.t = (unsigned int)t;
-        a.slot_idx = (int)(t & 3);
-        const int emode = final_eval ? kModeEvalOnly : mode;
+        a.it = it;
+        a.after_final = 0;
+        const int emode = final_launched ? kModeEvalOnly : mode;
         if (o.profile) HIP_OK(hipEventRecord(kev[2 * in_chunk], s), "event record");
         HIP_OK(launch_eval(L.layout, kp, emode, a, s), "evaluation kernel");
         if (o.profile) HIP_OK(hipEventRecord(kev[2 * in_chunk + 1], s), "event record");
-        if (mode == kModeRBP && !final_eval) {
-            unsigned int* ties = g->at<unsigned int>(g->off.ties);
+        if (mode == kModeRBP && !final_launched) {
             const int all = rbp_k >= L.E;
+            HIP_OK(launch_rbp_gate(g->st(), g->ctr(), (int)(t & 3), s), "top-k gate");
             if (!all)
                 HIP_OK(launch_rbp_select(g->st(), a.keys, (int)L.E, (unsigned int)rbp_k,
-                                         a.slot_idx, ties, s),
+                                         (int)(t & 3), ties, s),
                        "top-k select");
-            HIP_OK(launch_rbp_commit(g->st(), a.keys, a.cand, g->msg(b_in), (int)L.E, L.row, all,
-                                     a.slot_idx, ties, s),
+            HIP_OK(launch_rbp_commit(g->st(), a.keys, a.cand, start_buf, (int)L.E, L.row, all,
+                                     (int)(t & 3), ties, s),
                    "top-k commit");
         }
-        f.slot_idx = (int)(t & 3);
-        f.prev_slot_idx = (int)((t - 1) & 3);
-        f.has_prev_in_run = it > 0;
-        f.t = t;
-        f.final_eval = final_eval;
-        f.m_in = a.m_in;
-        f.m_out = a.m_out;
-        HIP_OK(launch_finish(f, s), "finish kernel");
         ++in_chunk;
-        if (in_chunk == o.check_every || final_eval) {
+        if (in_chunk == o.check_every || final_launched) {
             HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost, s),
                    "state readback");
             HIP_OK(hipStreamSynchronize(s), "synchronize");
@@ -570,9 +587,14 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
                 }
             }
             in_chunk = 0;
-            if (g->host_state->done || final_eval) break;
+            if (g->host_state->done || final_launched) break;
         }
     }
+    // close the last launched evaluation (a no-op if a later prologue already did)
+    a.t = (unsigned int)(t_start + it + 1);
+    a.it = it + 1;
+    a.after_final = final_launched ? 1 : 0;
+    HIP_OK(launch_close_run(a, s), "close run");
     HIP_OK(hipEventRecord(ev1, s), "event record");
     HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost, s),
            "state readback");
@@ -584,14 +606,17 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     for (auto& x : kev) (void)hipEventDestroy(x);
 
     const DevState& h = *g->host_state;
-    const long long iters = (long long)h.iterations;
     const bool converged = h.done != 0;
-    if (mode != kModeRBP) g->cur = (int)((cur0 + iters) & 1);
-    g->t_next = h.last_t;
+    const long long final_t = converged ? h.conv_t : h.last_t;
+    if (mode != kModeRBP) {
+        g->cur_pair = (int)((pair0 + (final_t - t_start)) & 1);
+        g->cur_sel = (int)h.in_sel[final_t & 3];
+    }
+    g->t_next = final_t;
     g->prev_active = h.last_prev;
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
-        stats->iterations = iters;
+        stats->iterations = (long long)h.iterations;
         stats->converged = converged ? 1 : 0;
         stats->last_active = (long long)h.last_active;
         float rm;
@@ -599,13 +624,12 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
         stats->last_max_residual = rm;
         stats->evaluated = (long long)h.evaluated;
         stats->committed = (long long)h.committed;
-        stats->final_t = h.last_t;
+        stats->final_t = final_t;
         stats->device_ms = total_ms;
         stats->eval_kernel_ms = kernel_ms;
         stats->eval_kernel_launches = kernel_launches;
     }
-    rc = converged ? BP_OK : BP_NOT_CONVERGED;
-    return rc;
+    return converged ? BP_OK : BP_NOT_CONVERGED;
 }
 
 int bp_marginals_device(bp_graph* g, float* out_device) {
@@ -613,7 +637,7 @@ int bp_marginals_device(bp_graph* g, float* out_device) {
     DeviceGuard dg(g->device);
     const HostLayout& L = g->L;
     HIP_OK(launch_marginals(L.layout, kpad(L.K), g->at<int>(g->off.in_ptr),
-                            g->at<float>(g->off.unary), g->msg(g->cur), out_device, L.N, L.K,
+                            g->at<float>(g->off.unary), g->cur(), out_device, L.N, L.K,
                             g->stream),
            "marginals kernel");
     return BP_OK;
@@ -639,7 +663,7 @@ int bp_get_state(bp_graph* g, float* msgs, bp_iter_state* st) {
         const HostLayout& L = g->L;
         std::vector<float> dev((size_t)(L.E * L.row));
         if (!dev.empty()) {
-            HIP_OK(hipMemcpyAsync(dev.data(), g->msg(g->cur), sizeof(float) * dev.size(),
+            HIP_OK(hipMemcpyAsync(dev.data(), g->cur(), sizeof(float) * dev.size(),
                                   hipMemcpyDeviceToHost, g->stream),
                    "state readback");
             HIP_OK(hipStreamSynchronize(g->stream), "synchronize");
@@ -684,7 +708,7 @@ int bp_set_state(bp_graph* g, const float* msgs, const bp_iter_state* st) {
         }
         DeviceGuard dg(g->device);
         if (!dev.empty()) {
-            HIP_OK(hipMemcpyAsync(g->msg(g->cur), dev.data(), sizeof(float) * dev.size(),
+            HIP_OK(hipMemcpyAsync(g->cur(), dev.data(), sizeof(float) * dev.size(),
                                   hipMemcpyHostToDevice, g->stream),
                    "state upload");
             HIP_OK(hipStreamSynchronize(g->stream), "synchronize");

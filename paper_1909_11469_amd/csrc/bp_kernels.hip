@@ -1,7 +1,7 @@
 // HIP kernels of libbp for gfx950 (CDNA4, wave64).
 //
-// One iteration of Alg. 1 is one launch of an evaluation kernel followed by one
-// launch of k_finish (plus the top-k selection kernels for frontier residual BP).
+// One iteration of Alg. 1 is one launch of an evaluation kernel (plus the top-k
+// selection kernels for frontier residual BP).
 //
 // Evaluation kernel (Eq. (2) + Eq. (4) + frontier rule + commit, fused):
 // messages are stored grouped by target node (CSR by destination), so the
@@ -18,6 +18,12 @@
 // Every slot of the next buffer is written exactly once per iteration (each
 // message is the outgoing message of exactly one node), so the update is
 // synchronous (Jacobi) with no atomics on message values.
+//
+// Randomized BP chooses p_t from n_t, which is only known once every block of
+// iteration t has counted its residuals.  The kernel therefore writes the
+// committed state under both keep thresholds (two output buffers); the next
+// launch computes p_t from the finished counters in its prologue and reads the
+// matching buffer.  No pass over the messages is needed between iterations.
 #include "bp_internal.h"
 
 namespace bp {
@@ -67,9 +73,10 @@ struct RedScratch {
 };
 
 // Block-wide reduction of the per-thread residual max and counts, then one
-// atomic per quantity per block (integer adds and an ordered max on the
-// FP32 bit pattern of a non-negative float: both order independent).
-__device__ __forceinline__ void block_accumulate(RedScratch* red, DevState* st, int slot,
+// atomic per quantity per block into the block's counter copy (integer adds and
+// an ordered max on the FP32 bit pattern of a non-negative float: both order
+// independent, so the totals are deterministic).
+__device__ __forceinline__ void block_accumulate(RedScratch* red, CounterLine* ctr, unsigned int t,
                                                  float rmax, unsigned int act, unsigned int sa,
                                                  unsigned int sb) {
 #pragma unroll
@@ -97,26 +104,11 @@ __device__ __forceinline__ void block_accumulate(RedScratch* red, DevState* st, 
             SA += red->sa[i];
             SB += red->sb[i];
         }
-        if (A) atomicAdd(&st->active[slot], (unsigned long long)A);
-        if (SA) atomicAdd(&st->sel_a[slot], (unsigned long long)SA);
-        if (SB) atomicAdd(&st->sel_b[slot], (unsigned long long)SB);
-        if (r > 0.0f) atomicMax(&st->rmax[slot], __float_as_uint(r));
-    }
-}
-
-// Append the slots of this wave whose `need` is set to the revert list:
-// ballot + popcount prefix inside the wave, one atomic per wave.
-__device__ __forceinline__ void wave_append(bool need, int value, int* list,
-                                            unsigned int* len) {
-    const unsigned long long mask = __ballot(need);
-    if (mask == 0ull) return;
-    const int lane = threadIdx.x & 63;
-    unsigned int base = 0;
-    if (lane == 0) base = atomicAdd(len, (unsigned int)__popcll(mask));
-    base = __shfl(base, 0, 64);
-    if (need) {
-        const unsigned int pre = (unsigned int)__popcll(mask & ((1ull << lane) - 1ull));
-        list[base + pre] = value;
+        CounterLine* c = ctr + (t & 3u) * kCounterCopies + (blockIdx.x & (kCounterCopies - 1));
+        if (A) atomicAdd(&c->active, (unsigned long long)A);
+        if (SA) atomicAdd(&c->sel_a, (unsigned long long)SA);
+        if (SB) atomicAdd(&c->sel_b, (unsigned long long)SB);
+        if (r > 0.0f) atomicMax(&c->rmax, __float_as_uint(r));
     }
 }
 
@@ -127,6 +119,120 @@ __device__ __forceinline__ int tile_of_block(const EvalArgs& a) {
     return (b & 7) * a.tiles_per_xcd + (b >> 3);
 }
 
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ unsigned int wave_max32(unsigned int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned int)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+// Which of the two committed outcomes iteration t - 1 kept: p_{t-1} is the low
+// setting when EdgeRatio = n_{t-1} / n_{t-2} exceeds the threshold (Sec. IV-A).
+__device__ __forceinline__ int select_outcome(const EvalArgs& a, unsigned long long n1, long long n2) {
+    if (a.sched != kModeRnBP || !a.two_outputs) return 0;
+    const bool p_low = !a.dynamic_p || (n2 > 0 && ((double)n1 / (double)n2 > a.ratio_threshold));
+    return (p_low == (a.low_is_a != 0)) ? 0 : 1;
+}
+
+// Run by the 64 lanes of one wave: sum the counter copies of iteration t - 1
+// (and t - 2), and, when `close` is set, record iteration t - 1 (IsConverged,
+// statistics, the buffer p_{t-1} selects) and clear the copies of t + 1.  The
+// statistics are updated with stores and no-return atomics, so nothing waits.
+// Returns n_{t-1} and n_{t-2} (the host's value when t - 2 precedes the run).
+__device__ void wave_close(const EvalArgs& a, bool close, unsigned long long& n1_out,
+                           long long& n2_out) {
+    const int lane = threadIdx.x & 63;
+    const CounterLine* c1 = a.ctr + ((a.t - 1u) & 3u) * kCounterCopies + lane;
+    unsigned long long n1 = c1->active;
+    unsigned long long n2 = a.it >= 2 ? a.ctr[((a.t - 2u) & 3u) * kCounterCopies + lane].active : 0ull;
+    unsigned long long sa = 0, sb = 0;
+    unsigned int rm = 0;
+    if (close) {
+        sa = c1->sel_a;
+        sb = c1->sel_b;
+        rm = c1->rmax;
+    }
+    n1 = wave_sum64(n1);
+    n2 = wave_sum64(n2);
+    const long long n2s = a.it >= 2 ? (long long)n2 : a.prev_active_host;
+    n1_out = n1;
+    n2_out = n2s;
+    if (!close) return;
+    sa = wave_sum64(sa);
+    sb = wave_sum64(sb);
+    rm = wave_max32(rm);
+    CounterLine* z = a.ctr + ((a.t + 1u) & 3u) * kCounterCopies + lane;
+    z->active = 0ull;
+    z->sel_a = 0ull;
+    z->sel_b = 0ull;
+    z->rmax = 0u;
+    if (lane != 0) return;
+    DevState* st = a.st;
+    const unsigned int tp = a.t - 1u;
+    const int sel = select_outcome(a, n1, n2s);
+    atomicAdd(&st->evaluated, a.num_messages);
+    atomicAdd(&st->evals, 1ull);
+    st->last_t = (long long)tp;
+    st->last_active = n1;
+    st->last_rmax = rm;
+    st->last_prev = n2s;
+    if (n1 == 0ull) {
+        st->done = 1u;
+        st->conv_t = (long long)tp;
+    } else if (!a.after_final) {
+        unsigned long long c;
+        if (a.sched == kModeLBP)
+            c = a.num_messages;
+        else if (a.sched == kModeRBP)
+            c = a.rbp_k;
+        else
+            c = sel ? sb : sa;
+        atomicAdd(&st->committed, c);
+        atomicAdd(&st->iterations, 1ull);
+        st->in_sel[a.t & 3u] = (unsigned int)sel;
+    }
+}
+
+// Start of iteration t (all threads of the block): returns the buffer holding
+// m^t, or nullptr when an earlier evaluation found no residual above eps (the
+// block then exits).  The previous launch wrote the outcome under both keep
+// thresholds, so choosing p_{t-1} is choosing a buffer.  Block 0 also closes
+// iteration t - 1.
+__device__ __forceinline__ const float* iteration_prologue(const EvalArgs& a,
+                                                           unsigned long long* s_red) {
+    const bool lead = blockIdx.x == 0;
+    if (a.it == 0) {
+        if (lead && threadIdx.x < 64) {
+            CounterLine* z = a.ctr + ((a.t + 1u) & 3u) * kCounterCopies + threadIdx.x;
+            z->active = 0ull;
+            z->sel_a = 0ull;
+            z->sel_b = 0ull;
+            z->rmax = 0u;
+            if (threadIdx.x == 0) a.st->in_sel[a.t & 3u] = (unsigned int)a.sel0;
+        }
+        return a.in_buf[0];
+    }
+    if (threadIdx.x < 64) {
+        const unsigned int done = a.st->done;
+        unsigned long long n1;
+        long long n2;
+        wave_close(a, lead && !done, n1, n2);
+        if (threadIdx.x == 0) {
+            s_red[0] = done ? 0ull : n1;
+            s_red[1] = (unsigned long long)n2;
+        }
+    }
+    __syncthreads();
+    const unsigned long long n1 = s_red[0];
+    if (n1 == 0ull) return nullptr;
+    return a.in_buf[select_outcome(a, n1, (long long)s_red[1])];
+}
+
 // ---------------------------------------------------------------------------
 // K = 2 Ising, one log-odds value per message: lambda = log(m(1) / m(0)).
 // Aggregate L_i = u_i + sum_k lambda_{k->i} with u_i = log psi_i(1) - log psi_i(0).
@@ -135,20 +241,61 @@ __device__ __forceinline__ int tile_of_block(const EvalArgs& a) {
 // ---------------------------------------------------------------------------
 constexpr int kPerThreadLO = kTileSlotsLogOdds / kBlock;
 
+// Eq. (2), Eq. (4) and the frontier rule for one slot; returns the residual.
+template <int MODE>
+__device__ __forceinline__ float logodds_slot(const EvalArgs& a, float L, float lam_q, float J,
+                                              float lam_old, int e, int src, int node,
+                                              unsigned int& act, unsigned int& sa,
+                                              unsigned int& sb) {
+    const float H = 0.5f * (L - lam_q);
+    const float lam_new = logcosh_shift(J + H) - logcosh_shift(J - H);
+    const float r = fabsf(sigmoid_fast(lam_new) - sigmoid_fast(lam_old));
+    const bool active = r > a.eps;
+    act += active;
+    if (MODE == kModeLBP) {
+        a.out_buf[0][e] = lam_new;
+    } else if (MODE == kModeRnBP) {
+        bool ka = false, kb = false;
+        if (active) {
+            const unsigned int u24 =
+                philox_word0((unsigned int)node, (unsigned int)src, a.t, a.key0, a.key1) >> 8;
+            ka = u24 < a.thr_a;
+            kb = u24 < a.thr_b;
+        }
+        sa += ka;
+        sb += kb;
+        a.out_buf[0][e] = ka ? lam_new : lam_old;
+        if (a.two_outputs) a.out_buf[1][e] = kb ? lam_new : lam_old;
+    } else if (MODE == kModeRBP) {
+        a.cand[e] = lam_new;
+        a.keys[e] = __float_as_uint(r);
+    }
+    return r;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
+    constexpr int TN = kTileNodesLogOdds;
     __shared__ float s_lam[kTileSlotsLogOdds];
     __shared__ unsigned short s_owner[kTileSlotsLogOdds];
-    __shared__ float s_L[kTileNodesMax];
+    __shared__ unsigned short s_ptr[TN + 1];
+    __shared__ float s_L[TN];
     __shared__ RedScratch red;
     __shared__ float s_part[kBlock / 64];
+    __shared__ unsigned long long s_red[2];
 
-    DevState* st = a.st;
-    if (st->done) return;
+    // tile bounds first: they do not depend on the prologue's counters
     const int tile = tile_of_block(a);
-    if (tile >= a.num_tiles) return;
-    const int n0 = a.tile_start[tile], n1 = a.tile_start[tile + 1];
-    const int s0 = a.in_ptr[n0], s1 = a.in_ptr[n1];
+    const bool in_range = tile < a.num_tiles;
+    int n0 = 0, n1 = 0, s0 = 0, s1 = 0;
+    if (in_range) {
+        n0 = a.tile_start[tile];
+        n1 = a.tile_start[tile + 1];
+        s0 = a.tile_slot[tile];
+        s1 = a.tile_slot[tile + 1];
+    }
+    const float* __restrict__ m_in = iteration_prologue(a, s_red);
+    if (!m_in || !in_range) return;
     const int ns = s1 - s0, nn = n1 - n0;
     const int tid = threadIdx.x;
 
@@ -156,21 +303,49 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
     unsigned int act = 0, sa = 0, sb = 0;
 
     if (ns <= kTileSlotsLogOdds) {
-        float lam[kPerThreadLO];
+        // Phase 1: every independent global load of this thread, then the
+        // reverse-slot gathers; the LDS work of phase 2 overlaps the gathers.
+        // Indices are clamped into the tile instead of predicated so that the
+        // compiler issues all loads before the first wait.
+        constexpr int JN = TN / kBlock + 1;
+        int ptrv[JN];
+        float uv[JN];
+#pragma unroll
+        for (int j = 0; j < JN; ++j) {
+            const int v = tid + j * kBlock;
+            ptrv[j] = a.in_ptr[n0 + min(v, nn)];
+            uv[j] = a.unary[n0 + min(v, nn - 1)];
+        }
+        float lam[kPerThreadLO], J[kPerThreadLO], old[kPerThreadLO];
+        int e[kPerThreadLO], src[kPerThreadLO];
+        if (ns > 0) {
+#pragma unroll
+            for (int k = 0; k < kPerThreadLO; ++k) {
+                const int s = s0 + min(tid + k * kBlock, ns - 1);
+                lam[k] = m_in[s];
+                e[k] = a.rev[s];
+                J[k] = a.coupling[s];
+                src[k] = MODE == kModeRnBP ? a.src[s] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kPerThreadLO; ++k) old[k] = m_in[e[k]];
+        }
+#pragma unroll
+        for (int j = 0; j < JN; ++j) {
+            const int v = tid + j * kBlock;
+            if (v <= nn) s_ptr[v] = (unsigned short)(ptrv[j] - s0);
+            if (v < nn) s_L[v] = uv[j];
+        }
 #pragma unroll
         for (int k = 0; k < kPerThreadLO; ++k) {
             const int q = tid + k * kBlock;
-            lam[k] = 0.0f;
-            if (q < ns) {
-                lam[k] = a.m_in[s0 + q];
-                s_lam[q] = lam[k];
-            }
+            if (q < ns) s_lam[q] = lam[k];
         }
         __syncthreads();
+        // Phase 2: node aggregates in slot order
         for (int v = tid; v < nn; v += kBlock) {
-            const int n = n0 + v;
-            const int q0 = a.in_ptr[n] - s0, q1 = a.in_ptr[n + 1] - s0;
-            float L = a.unary[n];
+            const int q0 = s_ptr[v], q1 = s_ptr[v + 1];
+            float L = s_L[v];
             for (int q = q0; q < q1; ++q) {
                 L += s_lam[q];
                 s_owner[q] = (unsigned short)v;
@@ -178,50 +353,22 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
             s_L[v] = L;
         }
         __syncthreads();
+        // Phase 3: one outgoing message per slot
 #pragma unroll
         for (int k = 0; k < kPerThreadLO; ++k) {
             const int q = tid + k * kBlock;
-            bool need = false;
-            int e = 0;
             if (q < ns) {
-                const int s = s0 + q;
                 const int v = s_owner[q];
-                const float H = 0.5f * (s_L[v] - lam[k]);
-                const float J = a.coupling[s];
-                const float lam_new = logcosh_shift(J + H) - logcosh_shift(J - H);
-                e = a.rev[s];
-                const float lam_old = a.m_in[e];
-                const float r = fabsf(sigmoid_fast(lam_new) - sigmoid_fast(lam_old));
-                const bool active = r > a.eps;
+                const float r = logodds_slot<MODE>(a, s_L[v], lam[k], J[k], old[k], e[k], src[k],
+                                                   n0 + v, act, sa, sb);
                 rmax = fmaxf(rmax, r);
-                act += active;
-                if (MODE == kModeLBP) {
-                    a.m_out[e] = lam_new;
-                } else if (MODE == kModeRnBP) {
-                    bool ka = false, kb = false;
-                    if (active) {
-                        const unsigned int u24 =
-                            philox_word0((unsigned int)(n0 + v), (unsigned int)a.src[s], a.t,
-                                         a.key0, a.key1) >> 8;
-                        ka = u24 < a.thr_a;
-                        kb = u24 < a.thr_b;
-                    }
-                    sa += ka;
-                    sb += kb;
-                    need = ka && !kb;
-                    a.m_out[e] = ka ? lam_new : lam_old;
-                } else if (MODE == kModeRBP) {
-                    a.cand[e] = lam_new;
-                    a.keys[e] = __float_as_uint(r);
-                }
             }
-            if (MODE == kModeRnBP) wave_append(need, e, a.revert_list, &st->revert_len[a.slot_idx]);
         }
     } else {
         // A single node whose in-degree exceeds the tile: aggregate by a block
         // reduction, then stream the slots.
         float part = 0.0f;
-        for (int q = tid; q < ns; q += kBlock) part += a.m_in[s0 + q];
+        for (int q = tid; q < ns; q += kBlock) part += m_in[s0 + q];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
         if ((tid & 63) == 0) s_part[tid >> 6] = part;
@@ -229,46 +376,16 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
         float L = a.unary[n0];
 #pragma unroll
         for (int i = 0; i < kBlock / 64; ++i) L += s_part[i];
-        for (int base = 0; base < ns; base += kBlock) {
-            const int q = base + tid;
-            bool need = false;
-            int e = 0;
-            if (q < ns) {
-                const int s = s0 + q;
-                const float lam_q = a.m_in[s];
-                const float H = 0.5f * (L - lam_q);
-                const float J = a.coupling[s];
-                const float lam_new = logcosh_shift(J + H) - logcosh_shift(J - H);
-                e = a.rev[s];
-                const float lam_old = a.m_in[e];
-                const float r = fabsf(sigmoid_fast(lam_new) - sigmoid_fast(lam_old));
-                const bool active = r > a.eps;
-                rmax = fmaxf(rmax, r);
-                act += active;
-                if (MODE == kModeLBP) {
-                    a.m_out[e] = lam_new;
-                } else if (MODE == kModeRnBP) {
-                    bool ka = false, kb = false;
-                    if (active) {
-                        const unsigned int u24 =
-                            philox_word0((unsigned int)n0, (unsigned int)a.src[s], a.t, a.key0,
-                                         a.key1) >> 8;
-                        ka = u24 < a.thr_a;
-                        kb = u24 < a.thr_b;
-                    }
-                    sa += ka;
-                    sb += kb;
-                    need = ka && !kb;
-                    a.m_out[e] = ka ? lam_new : lam_old;
-                } else if (MODE == kModeRBP) {
-                    a.cand[e] = lam_new;
-                    a.keys[e] = __float_as_uint(r);
-                }
-            }
-            if (MODE == kModeRnBP) wave_append(need, e, a.revert_list, &st->revert_len[a.slot_idx]);
+        for (int q = tid; q < ns; q += kBlock) {
+            const int s = s0 + q;
+            const int e = a.rev[s];
+            const int src = MODE == kModeRnBP ? a.src[s] : 0;
+            const float r = logodds_slot<MODE>(a, L, m_in[s], a.coupling[s], m_in[e], e, src, n0,
+                                               act, sa, sb);
+            rmax = fmaxf(rmax, r);
         }
     }
-    block_accumulate(&red, st, a.slot_idx, rmax, act, sa, sb);
+    block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
 }
 
 // ---------------------------------------------------------------------------
@@ -278,8 +395,9 @@ template <int KP, int MODE>
 __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
     extern __shared__ float smem[];
     __shared__ RedScratch red;
-    DevState* st = a.st;
-    if (st->done) return;
+    __shared__ unsigned long long s_red[2];
+    const float* __restrict__ m_in = iteration_prologue(a, s_red);
+    if (!m_in) return;
     const int tile = tile_of_block(a);
     if (tile >= a.num_tiles) return;
     const int K = a.num_states;
@@ -290,16 +408,20 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
     unsigned short* s_owner = (unsigned short*)(s_psi + K * K);
 
     const int n0 = a.tile_start[tile], n1 = a.tile_start[tile + 1];
-    const int s0 = a.in_ptr[n0], s1 = a.in_ptr[n1];
+    const int s0 = a.tile_slot[tile], s1 = a.tile_slot[tile + 1];
     const int ns = s1 - s0, nn = n1 - n0;
     const int tid = threadIdx.x;
     const bool big = ns > TS;
+    // Logs are taken of K * m: the constant cancels in the cavity and the
+    // normalisation, and it keeps the node aggregate near zero for messages
+    // near uniform, where FP32 rounding of a large aggregate would dominate.
+    const float fK = (float)K;
 
     if (a.pair_kind == kPairShared || a.pair_kind == kPairSharedAsym)
         for (int i = tid; i < K * K; i += kBlock) s_psi[i] = a.pair[i];
     if (!big) {
         const long long base = (long long)s0 * K;
-        for (int i = tid; i < ns * K; i += kBlock) s_logm[i] = __logf(a.m_in[base + i]);
+        for (int i = tid; i < ns * K; i += kBlock) s_logm[i] = logf(fK * m_in[base + i]);
         __syncthreads();
         for (int i = tid; i < nn * K; i += kBlock) {
             const int v = i / K, x = i - v * K;
@@ -315,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
         // single node with in-degree > TS: aggregate each state with a strided sum
         for (int x = 0; x < K; ++x) {
             float part = 0.0f;
-            for (int q = tid; q < ns; q += kBlock) part += __logf(a.m_in[(long long)(s0 + q) * K + x]);
+            for (int q = tid; q < ns; q += kBlock) part += logf(fK * m_in[(long long)(s0 + q) * K + x]);
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
             if ((tid & 63) == 0) red.rmax[tid >> 6] = part;
@@ -332,188 +454,129 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
 
     float rmax = 0.0f;
     unsigned int act = 0, sa = 0, sb = 0;
-    for (int base = 0; base < ns; base += kBlock) {
-        const int q = base + tid;
-        bool need = false;
-        int e = 0;
-        if (q < ns) {
-            const int s = s0 + q;
-            const int v = big ? 0 : s_owner[q];
-            const int node = n0 + v;
-            float g[KP];
-            float mx = -3.402823466e38f;
+    for (int q = tid; q < ns; q += kBlock) {
+        const int s = s0 + q;
+        const int v = big ? 0 : s_owner[q];
+        const int node = n0 + v;
+        float g[KP];
+        float mx = -3.402823466e38f;
+#pragma unroll
+        for (int x = 0; x < KP; ++x) {
+            if (x < K) {
+                const float lm = big ? logf(fK * m_in[(long long)s * K + x]) : s_logm[q * K + x];
+                g[x] = s_A[v * K + x] - lm;
+                mx = fmaxf(mx, g[x]);
+            }
+        }
+#pragma unroll
+        for (int x = 0; x < KP; ++x)
+            if (x < K) g[x] = expf(g[x] - mx);
+        float c[KP];
+#pragma unroll
+        for (int y = 0; y < KP; ++y) c[y] = 0.0f;
+        if (a.pair_kind == kPairIsing) {
+            // exp(J s_i s_k) scaled by exp(-|J|): one entry is 1, the other exp(-2|J|)
+            const float J = a.coupling[s];
+            const float ep = expf(J - fabsf(J)), em = expf(-J - fabsf(J));
+            c[0] = ep * g[0] + em * g[1];
+            c[1] = em * g[0] + ep * g[1];
+        } else {
+            // c(y) = sum_x psi(x, y) g(x): element (x, y) of the table at
+            // P[x * sx + y * sy] (the transpose for the other direction)
+            const float* P;
+            int sx = K, sy = 1;
+            if (a.pair_kind == kPairDense) {
+                P = a.pair + (long long)s * K * K;
+            } else {
+                P = s_psi;
+                if (a.pair_kind == kPairSharedAsym && a.orient[s]) {
+                    sx = 1;
+                    sy = K;
+                }
+            }
 #pragma unroll
             for (int x = 0; x < KP; ++x) {
                 if (x < K) {
-                    const float lm = big ? __logf(a.m_in[(long long)s * K + x]) : s_logm[q * K + x];
-                    g[x] = s_A[v * K + x] - lm;
-                    mx = fmaxf(mx, g[x]);
+                    const float gx = g[x];
+#pragma unroll
+                    for (int y = 0; y < KP; ++y)
+                        if (y < K) c[y] = fmaf(P[x * sx + y * sy], gx, c[y]);
                 }
             }
+        }
+        float z = 0.0f;
 #pragma unroll
-            for (int x = 0; x < KP; ++x)
-                if (x < K) g[x] = __expf(g[x] - mx);
-            float c[KP];
+        for (int y = 0; y < KP; ++y)
+            if (y < K) z += c[y];
+        const float inv = 1.0f / z;
+        const int e = a.rev[s];
+        const long long eo = (long long)e * K;
+        float r = 0.0f;
+        float old[KP];
 #pragma unroll
-            for (int y = 0; y < KP; ++y) c[y] = 0.0f;
-            if (a.pair_kind == kPairIsing) {
-                const float J = a.coupling[s];
-                const float ep = __expf(J), em = __expf(-J);
-                c[0] = ep * g[0] + em * g[1];
-                c[1] = em * g[0] + ep * g[1];
-            } else {
-                // c(y) = sum_x psi(x, y) g(x): element (x, y) of the table at
-                // P[x * sx + y * sy] (the transpose for the other direction)
-                const float* P;
-                int sx = K, sy = 1;
-                if (a.pair_kind == kPairDense) {
-                    P = a.pair + (long long)s * K * K;
-                } else {
-                    P = s_psi;
-                    if (a.pair_kind == kPairSharedAsym && a.orient[s]) {
-                        sx = 1;
-                        sy = K;
-                    }
-                }
-#pragma unroll
-                for (int x = 0; x < KP; ++x) {
-                    if (x < K) {
-                        const float gx = g[x];
-#pragma unroll
-                        for (int y = 0; y < KP; ++y)
-                            if (y < K) c[y] = fmaf(P[x * sx + y * sy], gx, c[y]);
-                    }
-                }
+        for (int y = 0; y < KP; ++y) {
+            if (y < K) {
+                c[y] *= inv;
+                old[y] = m_in[eo + y];
+                r = fmaxf(r, fabsf(c[y] - old[y]));
             }
-            float z = 0.0f;
+        }
+        const bool active = r > a.eps;
+        rmax = fmaxf(rmax, r);
+        act += active;
+        if (MODE == kModeLBP) {
 #pragma unroll
             for (int y = 0; y < KP; ++y)
-                if (y < K) z += c[y];
-            const float inv = 1.0f / z;
-            e = a.rev[s];
-            const long long eo = (long long)e * K;
-            float r = 0.0f;
-            float old[KP];
-#pragma unroll
-            for (int y = 0; y < KP; ++y) {
-                if (y < K) {
-                    c[y] *= inv;
-                    old[y] = a.m_in[eo + y];
-                    r = fmaxf(r, fabsf(c[y] - old[y]));
-                }
+                if (y < K) a.out_buf[0][eo + y] = c[y];
+        } else if (MODE == kModeRnBP) {
+            bool ka = false, kb = false;
+            if (active) {
+                const unsigned int u24 = philox_word0((unsigned int)node, (unsigned int)a.src[s],
+                                                      a.t, a.key0, a.key1) >> 8;
+                ka = u24 < a.thr_a;
+                kb = u24 < a.thr_b;
             }
-            const bool active = r > a.eps;
-            rmax = fmaxf(rmax, r);
-            act += active;
-            if (MODE == kModeLBP) {
+            sa += ka;
+            sb += kb;
+#pragma unroll
+            for (int y = 0; y < KP; ++y)
+                if (y < K) a.out_buf[0][eo + y] = ka ? c[y] : old[y];
+            if (a.two_outputs) {
 #pragma unroll
                 for (int y = 0; y < KP; ++y)
-                    if (y < K) a.m_out[eo + y] = c[y];
-            } else if (MODE == kModeRnBP) {
-                bool ka = false, kb = false;
-                if (active) {
-                    const unsigned int u24 = philox_word0((unsigned int)node, (unsigned int)a.src[s],
-                                                          a.t, a.key0, a.key1) >> 8;
-                    ka = u24 < a.thr_a;
-                    kb = u24 < a.thr_b;
-                }
-                sa += ka;
-                sb += kb;
-                need = ka && !kb;
-#pragma unroll
-                for (int y = 0; y < KP; ++y)
-                    if (y < K) a.m_out[eo + y] = ka ? c[y] : old[y];
-            } else if (MODE == kModeRBP) {
-#pragma unroll
-                for (int y = 0; y < KP; ++y)
-                    if (y < K) a.cand[eo + y] = c[y];
-                a.keys[e] = __float_as_uint(r);
+                    if (y < K) a.out_buf[1][eo + y] = kb ? c[y] : old[y];
             }
+        } else if (MODE == kModeRBP) {
+#pragma unroll
+            for (int y = 0; y < KP; ++y)
+                if (y < K) a.cand[eo + y] = c[y];
+            a.keys[e] = __float_as_uint(r);
         }
-        if (MODE == kModeRnBP) wave_append(need, e, a.revert_list, &st->revert_len[a.slot_idx]);
     }
-    block_accumulate(&red, st, a.slot_idx, rmax, act, sa, sb);
+    block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
 }
 
-// ---------------------------------------------------------------------------
-// End of iteration t: IsConverged, p_t from EdgeRatio, the revert of messages
-// kept only under the larger threshold when p_t takes the smaller one, and the
-// scalar bookkeeping.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_finish(FinishArgs a) {
-    DevState* st = a.st;
-    if (st->done) return;
-    const unsigned long long n_t = st->active[a.slot_idx];
-    const bool converged = n_t == 0ull;
-    bool p_low = false;
-    if (a.mode == kModeRnBP) {
-        if (a.dynamic_p) {
-            const long long np = a.has_prev_in_run ? (long long)st->active[a.prev_slot_idx]
-                                                   : a.prev_active_host;
-            p_low = np > 0 && ((double)n_t / (double)np > a.ratio_threshold);
-        } else {
-            p_low = true;
-        }
-    }
-    const bool use_a = !a.thresholds_differ || (p_low == (a.low_is_a != 0));
-    if (a.mode == kModeRnBP && !converged && !a.final_eval && !use_a) {
-        const unsigned int len = st->revert_len[a.slot_idx];
-        const int row = a.row;
-        for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < len;
-             i += gridDim.x * blockDim.x) {
-            const long long e = a.revert_list[i];
-            for (int x = 0; x < row; ++x) a.m_out[e * row + x] = a.m_in[e * row + x];
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        unsigned long long committed = 0;
-        if (!converged && !a.final_eval) {
-            if (a.mode == kModeLBP)
-                committed = a.num_messages;
-            else if (a.mode == kModeRBP)
-                committed = a.rbp_k;
-            else
-                committed = use_a ? st->sel_a[a.slot_idx] : st->sel_b[a.slot_idx];
-            st->committed += committed;
-            st->iterations += 1;
-        }
-        st->last_t = a.t;
-        st->last_active = n_t;
-        st->last_rmax = st->rmax[a.slot_idx];
-        st->evaluated += a.num_messages;
-        const long long np_seen = a.has_prev_in_run ? (long long)st->active[a.prev_slot_idx]
-                                                    : a.prev_active_host;
-        st->last_prev = np_seen;
-        if (a.trace) {
-            const long long i = a.trace_base + (long long)st->evals;
-            if (i >= 0 && i < a.trace_cap) {
-                long long* row = a.trace + 4 * i;
-                row[0] = (long long)n_t;
-                row[1] = (long long)committed;
-                row[2] = (long long)(p_low ? 1 : 0);
-                row[3] = (long long)st->rmax[a.slot_idx];
-            }
-        }
-        st->evals += 1ull;
-        if (converged) {
-            st->done = 1u;
-            st->conv_t = a.t;
-        }
-        const int z = (a.slot_idx + 2) & 3;
-        st->active[z] = 0ull;
-        st->sel_a[z] = 0ull;
-        st->sel_b[z] = 0ull;
-        st->rmax[z] = 0u;
-        st->revert_len[z] = 0u;
-    }
+// Closes the last evaluation of a run (one wave): the same bookkeeping the
+// next evaluation's prologue would do.
+__global__ void k_close_run(EvalArgs a) {
+    if (a.st->done) return;
+    unsigned long long n1;
+    long long n2;
+    wave_close(a, true, n1, n2);
 }
 
-__global__ void k_init_state(DevState* st) {
+__global__ void k_init_state(DevState* st, CounterLine* ctr) {
     unsigned int* w = (unsigned int*)st;
     const int nw = (int)(sizeof(DevState) / sizeof(unsigned int));
     for (int i = threadIdx.x; i < nw; i += blockDim.x) w[i] = 0u;
+    unsigned int* c = (unsigned int*)ctr;
+    const int nc = (int)(4 * kCounterCopies * sizeof(CounterLine) / sizeof(unsigned int));
+    for (int i = threadIdx.x; i < nc; i += blockDim.x) c[i] = 0u;
     __syncthreads();
-    if (threadIdx.x == 0) st->conv_t = -1;
+    if (threadIdx.x == 0) {
+        st->conv_t = -1;
+        st->last_prev = -1;
+    }
 }
 
 __global__ void k_fill(float* p, float v, long long n) {
@@ -543,7 +606,7 @@ __global__ void k_marginals_generic(const int* in_ptr, const float* unary, const
     float mx = -3.402823466e38f;
     for (int x = 0; x < K; ++x) {
         float acc = unary[(long long)n * K + x];
-        for (int s = in_ptr[n]; s < in_ptr[n + 1]; ++s) acc += logf(m[(long long)s * K + x]);
+        for (int s = in_ptr[n]; s < in_ptr[n + 1]; ++s) acc += logf((float)K * m[(long long)s * K + x]);
         A[x] = acc;
         mx = fmaxf(mx, acc);
     }
@@ -564,10 +627,17 @@ __global__ void k_marginals_generic(const int* in_ptr, const float* unary, const
 constexpr int kSelBlock = 256;
 constexpr int kCommitChunk = 4096;
 
+// IsConverged for the top-k step: nothing is selected or committed when the
+// evaluation of iteration t found no residual above eps.
+__global__ void k_rbp_gate(DevState* st, const CounterLine* ctr, int slot) {
+    const unsigned long long n = wave_sum64(ctr[slot * kCounterCopies + threadIdx.x].active);
+    if (threadIdx.x == 0) st->rbp_skip = (st->done || n == 0ull) ? 1u : 0u;
+}
+
 __global__ __launch_bounds__(kSelBlock) void k_rbp_hist(DevState* st, const unsigned int* keys,
                                                         int E, int pass, int slot) {
     __shared__ unsigned int h[256];
-    if (st->done || st->active[slot] == 0ull) return;
+    if (st->rbp_skip) return;
     for (int i = threadIdx.x; i < 256; i += kSelBlock) h[i] = 0u;
     __syncthreads();
     const unsigned int prefix = pass ? st->sel_prefix : 0u;
@@ -585,7 +655,7 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_hist(DevState* st, const unsi
 __global__ __launch_bounds__(kSelBlock) void k_rbp_scan(DevState* st, int pass, unsigned int k,
                                                         int slot) {
     __shared__ unsigned int h[256];
-    if (st->done || st->active[slot] == 0ull) return;
+    if (st->rbp_skip) return;
     const int i = threadIdx.x;
     h[i] = st->hist[pass][i];
     st->hist[pass][i] = 0u;
@@ -618,7 +688,7 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_tiecount(DevState* st, const 
                                                             int E, int slot,
                                                             unsigned int* block_ties) {
     __shared__ unsigned int part[kSelBlock / 64];
-    if (st->done || st->active[slot] == 0ull || !st->sel_rank_ties) return;
+    if (st->rbp_skip || !st->sel_rank_ties) return;
     const unsigned int T = st->sel_prefix;
     const int beg = blockIdx.x * kCommitChunk;
     const int end = min(E, beg + kCommitChunk);
@@ -637,7 +707,7 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_tiecount(DevState* st, const 
 
 __global__ __launch_bounds__(kSelBlock) void k_rbp_tiescan(DevState* st, int slot,
                                                            unsigned int* block_ties, int nb) {
-    if (st->done || st->active[slot] == 0ull || !st->sel_rank_ties) return;
+    if (st->rbp_skip || !st->sel_rank_ties) return;
     if (threadIdx.x == 0) {
         unsigned int run = 0;
         for (int b = 0; b < nb; ++b) {
@@ -653,7 +723,7 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_commit(DevState* st, const un
                                                           int row, int all, int slot,
                                                           const unsigned int* block_ties) {
     __shared__ unsigned int wsum[kSelBlock / 64];
-    if (st->done || st->active[slot] == 0ull) return;
+    if (st->rbp_skip) return;
     const int beg = blockIdx.x * kCommitChunk;
     const int end = min(E, beg + kCommitChunk);
     const unsigned int T = st->sel_prefix;
@@ -697,8 +767,8 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_commit(DevState* st, const un
 // ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
-hipError_t launch_init_state(DevState* st, hipStream_t s) {
-    k_init_state<<<1, 256, 0, s>>>(st);
+hipError_t launch_init_state(DevState* st, CounterLine* ctr, hipStream_t s) {
+    k_init_state<<<1, 256, 0, s>>>(st, ctr);
     return hipGetLastError();
 }
 
@@ -749,8 +819,8 @@ hipError_t launch_eval(int layout, int kp, int mode, const EvalArgs& a, hipStrea
     }
 }
 
-hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
-    k_finish<<<256, kBlock, 0, s>>>(a);
+hipError_t launch_close_run(const EvalArgs& a, hipStream_t s) {
+    k_close_run<<<1, 64, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -763,6 +833,11 @@ hipError_t launch_marginals(int layout, int kp, const int* in_ptr, const float* 
         k_marginals_logodds<<<grid, 256, 0, s>>>(in_ptr, unary, m, out, N);
     else
         k_marginals_generic<<<grid, 256, 0, s>>>(in_ptr, unary, m, out, N, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_rbp_gate(DevState* st, const CounterLine* ctr, int slot_idx, hipStream_t s) {
+    k_rbp_gate<<<1, 64, 0, s>>>(st, ctr, slot_idx);
     return hipGetLastError();
 }
 
