@@ -28,13 +28,13 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def eval_kernel_bytes(N, E):
+def eval_kernel_bytes(N, E, two_outputs=True):
     """Algorithmic bytes of one launch of the K = 2 evaluation kernel in RnBP
-    mode: per directed message the in-slot log-odds (4), the reverse-slot old
-    value (4), the committed value (4), the reverse index (4), the coupling (4)
-    and the source id for the RNG counter (4); per node the slot offset (4) and
-    the unary log-odds (4)."""
-    return 24 * E + 8 * N
+    mode, each array element moved once: per directed message the in-slot
+    log-odds (4), the reverse index (4), the coupling (4), the source id for the
+    RNG counter (4) and the committed value under each keep threshold (4 + 4);
+    per node the slot offset (4) and the unary log-odds (4)."""
+    return (20 + (4 if two_outputs else 0)) * E + 8 * N
 
 
 def main():
@@ -48,9 +48,14 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--max-iters", type=int, default=10000)
     ap.add_argument("--check-every", type=int, default=64)
+    ap.add_argument("--profile-every", type=int, default=16,
+                    help="time one evaluation launch in this many with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-ttc", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 256 MiB device-to-device copy kernel first (a known-size "
+                         "reference for hardware byte counters)")
     ap.add_argument("--ttc-seeds", type=int, default=3)
     args = ap.parse_args()
 
@@ -80,6 +85,13 @@ def main():
     run_kw = dict(eps=args.eps, p=args.p, max_iters=args.max_iters,
                   check_every=args.check_every)
 
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     for w in range(args.warmup):
         r = g.run("rnbp", seed=1000 + w, **run_kw)
         g.marginals_device(marg)
@@ -91,7 +103,7 @@ def main():
     kern_n = 0
     t0 = time.perf_counter()
     for k in range(args.steps):
-        r = g.run("rnbp", seed=k, profile=True, **run_kw)
+        r = g.run("rnbp", seed=k, profile=args.profile_every, **run_kw)
         g.marginals_device(marg)
         evaluated += r["evaluated"]
         committed += r["committed"]

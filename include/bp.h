@@ -112,7 +112,8 @@ typedef struct bp_run_opts {
     double ratio_threshold;   /* BP_RNBP dynamic: default 0.9 */
     int32_t warm_start;       /* 0 (default): messages reset to uniform 1/K and t = 0;
                                  1: continue from the current messages and iteration state */
-    int32_t profile;          /* 1: time the evaluation kernel with HIP events */
+    int32_t profile;          /* k > 0: time every k-th launch of the evaluation kernel
+                                 with a pair of HIP events on the graph's stream */
 } bp_run_opts;
 
 typedef struct bp_run_stats {
@@ -125,8 +126,8 @@ typedef struct bp_run_stats {
     int64_t committed;         /* messages committed by this call */
     int64_t final_t;           /* global iteration number of the last evaluation */
     double device_ms;          /* stream time of the whole call (HIP events) */
-    double eval_kernel_ms;     /* profile: summed duration of the evaluation kernel */
-    int64_t eval_kernel_launches; /* profile: number of evaluation-kernel launches timed */
+    double eval_kernel_ms;     /* profile: summed duration of the timed evaluation launches */
+    int64_t eval_kernel_launches; /* profile: number of evaluation launches timed */
 } bp_run_stats;
 
 /* Iteration state carried between runs (checkpoint / resume, Alg. 1 loop). */

@@ -223,7 +223,7 @@ class Graph:
         o.max_iters, o.check_every = int(max_iters), int(check_every)
         o.dynamic_p, o.high_p, o.ratio_threshold = int(bool(dynamic_p)), float(high_p), \
             float(ratio_threshold)
-        o.warm_start, o.profile = int(bool(warm_start)), int(bool(profile))
+        o.warm_start, o.profile = int(bool(warm_start)), int(profile)
         s = bp_run_stats()
         sched = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
         rc = _check(lib.bp_run(self.handle, sched, float(eps), float(p), int(seed),

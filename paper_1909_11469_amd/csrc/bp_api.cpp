@@ -66,12 +66,14 @@ struct DeviceGuard {
 struct HostLayout {
     int N = 0, K = 0, layout = 0, pair = 0, row = 1;
     long long M = 0, E = 0;
-    std::vector<int> in_ptr;          // [N+1]
-    std::vector<int> src;             // [E] source node of the slot's message
+    std::vector<int> node_ptr;        // [N+1] slot range of each source node
+    std::vector<int> dst;             // [E] target node of the slot's message
     std::vector<int> rev;             // [E]
     std::vector<int> slot_of_canon;   // [E]
     std::vector<int> tile_start;      // [T+1]
-    std::vector<int> tile_slot;       // [T+1] in_ptr[tile_start]
+    std::vector<int> tile_slot;       // [T+1] node_ptr[tile_start]
+    std::vector<int> tiles4;          // log-odds layout: regular tiles {n0, n1, s0, s1}
+    std::vector<int> big4;            // log-odds layout: single-node tiles over the slot limit
     std::vector<float> coupling;      // [E] (Ising)
     std::vector<float> unary;         // [N] log-odds or [N][K] log psi (max-shifted)
     std::vector<float> pair_tab;      // shared (2KK) or dense [E][K][K]
@@ -88,7 +90,7 @@ struct Arena {
 };
 
 struct Offsets {
-    size_t in_ptr, src, rev, tile, tile_slot, coupling, unary, pair, orient, msg[4], cand, keys, ties, state,
+    size_t node_ptr, dst, rev, tile, tile_slot, tiles4, big4, coupling, unary, pair, orient, msg[4], cand, keys, ties, state,
         ctr, marg, total;
 };
 
@@ -96,11 +98,13 @@ Offsets plan(const HostLayout& L) {
     Arena a;
     Offsets o;
     const size_t E = (size_t)L.E;
-    o.in_ptr = a.take(sizeof(int) * (L.N + 1));
-    o.src = a.take(sizeof(int) * E);
+    o.node_ptr = a.take(sizeof(int) * (L.N + 1));
+    o.dst = a.take(sizeof(int) * E);
     o.rev = a.take(sizeof(int) * E);
     o.tile = a.take(sizeof(int) * L.tile_start.size());
     o.tile_slot = a.take(sizeof(int) * L.tile_slot.size());
+    o.tiles4 = a.take(sizeof(int) * L.tiles4.size());
+    o.big4 = a.take(sizeof(int) * L.big4.size());
     o.coupling = a.take(sizeof(float) * L.coupling.size());
     o.unary = a.take(sizeof(float) * L.unary.size());
     o.pair = a.take(sizeof(float) * L.pair_tab.size());
@@ -129,7 +133,7 @@ bool positive_all(const double* p, size_t n) {
 }
 
 // Validate the problem (Eq. (1): finite state sets, positive potentials) and
-// build the device layout: directed messages sorted by (target, source), the
+// build the device layout: directed messages sorted by (source, target), the
 // reverse-slot index, per-slot parameters and node tiles.
 int build_layout(const bp_graph_desc* d, HostLayout& L) {
     if (!d) return fail(BP_EINVAL, "desc is NULL");
@@ -185,25 +189,28 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
     auto csrc = [&](long long c) { return d->edges[2 * (c >> 1) + ((c & 1) ? 1 : 0)]; };
     auto cdst = [&](long long c) { return d->edges[2 * (c >> 1) + ((c & 1) ? 0 : 1)]; };
 
-    // counting sort of directed messages by target, then by source inside a target
-    L.in_ptr.assign((size_t)N + 1, 0);
-    for (long long c = 0; c < E; ++c) L.in_ptr[cdst(c) + 1]++;
-    for (long long i = 0; i < N; ++i) L.in_ptr[i + 1] += L.in_ptr[i];
+    // Counting sort of directed messages by source, then by target inside a
+    // source: slot e holds m_{i->k}, the message its thread computes, so the
+    // old value, the outputs and the per-slot constants are read and written
+    // contiguously; the one gather is the incoming m_{k->i} at rev[e].
+    L.node_ptr.assign((size_t)N + 1, 0);
+    for (long long c = 0; c < E; ++c) L.node_ptr[csrc(c) + 1]++;
+    for (long long i = 0; i < N; ++i) L.node_ptr[i + 1] += L.node_ptr[i];
     std::vector<int> canon_of_slot((size_t)E);
     {
-        std::vector<int> fill(L.in_ptr.begin(), L.in_ptr.end() - 1);
-        for (long long c = 0; c < E; ++c) canon_of_slot[fill[cdst(c)]++] = (int)c;
+        std::vector<int> fill(L.node_ptr.begin(), L.node_ptr.end() - 1);
+        for (long long c = 0; c < E; ++c) canon_of_slot[fill[csrc(c)]++] = (int)c;
     }
     for (long long i = 0; i < N; ++i)
-        std::sort(canon_of_slot.begin() + L.in_ptr[i], canon_of_slot.begin() + L.in_ptr[i + 1],
-                  [&](int x, int y) { return csrc(x) < csrc(y); });
+        std::sort(canon_of_slot.begin() + L.node_ptr[i], canon_of_slot.begin() + L.node_ptr[i + 1],
+                  [&](int x, int y) { return cdst(x) < cdst(y); });
     L.slot_of_canon.assign((size_t)E, 0);
     for (long long s = 0; s < E; ++s) L.slot_of_canon[canon_of_slot[s]] = (int)s;
-    L.src.resize((size_t)E);
+    L.dst.resize((size_t)E);
     L.rev.resize((size_t)E);
     for (long long s = 0; s < E; ++s) {
         const int c = canon_of_slot[s];
-        L.src[s] = csrc(c);
+        L.dst[s] = cdst(c);
         L.rev[s] = L.slot_of_canon[c ^ 1];
     }
 
@@ -222,9 +229,9 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
         }
     }
 
-    // Slot s holds m_{k->i}; the kernel computes the outgoing m_{i->k} there and
-    // needs psi_{ik}(x_i, x_k).  For the canonical message c of slot s, edge
-    // u = c >> 1 = (a, b): c even means k = a, i = b, so the table is transposed.
+    // Slot s holds m_{i->k}, whose update needs psi_{ik}(x_i, x_k).  For the
+    // canonical message c of slot s and edge u = c >> 1 = (a, b): c even means
+    // i = a, k = b (the table as given); c odd means i = b, so it is transposed.
     if (kind == BP_PAIR_ISING) {
         L.pair = kPairIsing;
         L.coupling.resize((size_t)E);
@@ -242,7 +249,7 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
         L.pair = sym ? kPairShared : kPairSharedAsym;
         if (!sym) {
             L.orient.resize((size_t)E);
-            for (long long s = 0; s < E; ++s) L.orient[s] = (canon_of_slot[s] & 1) ? 0 : 1;
+            for (long long s = 0; s < E; ++s) L.orient[s] = (canon_of_slot[s] & 1) ? 1 : 0;
         }
     } else {
         L.pair = kPairDense;
@@ -255,7 +262,7 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
             float* T = L.pair_tab.data() + (size_t)s * K * K;
             for (long long xi = 0; xi < K; ++xi)
                 for (long long xk = 0; xk < K; ++xk)
-                    T[xi * K + xk] = (float)(((c & 1) ? P[xi * K + xk] : P[xk * K + xi]) / mx);
+                    T[xi * K + xk] = (float)(((c & 1) ? P[xk * K + xi] : P[xi * K + xk]) / mx);
         }
     }
 
@@ -269,15 +276,22 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
     long long n = 0;
     while (n < N) {
         L.tile_start.push_back((int)n);
-        const long long s_begin = L.in_ptr[n];
+        const long long s_begin = L.node_ptr[n];
         long long m = n;
-        while (m < N && (m - n) < node_lim && (L.in_ptr[m + 1] - s_begin) <= slot_lim) ++m;
+        while (m < N && (m - n) < node_lim && (L.node_ptr[m + 1] - s_begin) <= slot_lim) ++m;
         if (m == n) m = n + 1;  // oversize node
         n = m;
     }
     L.tile_start.push_back((int)N);
     L.tile_slot.resize(L.tile_start.size());
-    for (size_t i = 0; i < L.tile_start.size(); ++i) L.tile_slot[i] = L.in_ptr[L.tile_start[i]];
+    for (size_t i = 0; i < L.tile_start.size(); ++i) L.tile_slot[i] = L.node_ptr[L.tile_start[i]];
+    L.tiles4.clear();
+    L.big4.clear();
+    for (size_t i = 0; i + 1 < L.tile_start.size(); ++i) {
+        const int q[4] = {L.tile_start[i], L.tile_start[i + 1], L.tile_slot[i], L.tile_slot[i + 1]};
+        std::vector<int>& dstv = (q[3] - q[2] > slot_lim) ? L.big4 : L.tiles4;
+        dstv.insert(dstv.end(), q, q + 4);
+    }
     return BP_OK;
 }
 
@@ -297,6 +311,8 @@ struct bp_graph {
     long long t_next = 0;        // global iteration number of the next evaluation
     long long prev_active = -1;  // n_{t_next - 1}
     DevState* host_state = nullptr;  // pinned mirror
+    int num_cus = 0;                 // compute units of the device
+    int resident[4] = {0, 0, 0, 0};  // log-odds eval blocks resident per CU, by mode
 
     template <typename T>
     T* at(size_t o) const { return reinterpret_cast<T*>(base + o); }
@@ -380,10 +396,12 @@ int bp_create_graph(const bp_graph_desc* desc, bp_graph** out) {
         if (n == 0) return hipSuccess;
         return hipMemcpyAsync(g->base + o, p, n, hipMemcpyHostToDevice, s);
     };
-    hipError_t errs[9] = {
+    hipError_t errs[11] = {
         up(g->off.tile_slot, L.tile_slot.data(), sizeof(int) * L.tile_slot.size()),
-        up(g->off.in_ptr, L.in_ptr.data(), sizeof(int) * L.in_ptr.size()),
-        up(g->off.src, L.src.data(), sizeof(int) * L.src.size()),
+        up(g->off.tiles4, L.tiles4.data(), sizeof(int) * L.tiles4.size()),
+        up(g->off.big4, L.big4.data(), sizeof(int) * L.big4.size()),
+        up(g->off.node_ptr, L.node_ptr.data(), sizeof(int) * L.node_ptr.size()),
+        up(g->off.dst, L.dst.data(), sizeof(int) * L.dst.size()),
         up(g->off.rev, L.rev.data(), sizeof(int) * L.rev.size()),
         up(g->off.tile, L.tile_start.data(), sizeof(int) * L.tile_start.size()),
         up(g->off.coupling, L.coupling.data(), sizeof(float) * L.coupling.size()),
@@ -405,6 +423,12 @@ int bp_create_graph(const bp_graph_desc* desc, bp_graph** out) {
     }
     g->cur_pair = 0;
     g->cur_sel = 0;
+    e = hipDeviceGetAttribute(&g->num_cus, hipDeviceAttributeMultiprocessorCount, g->device);
+    if (e != hipSuccess) {
+        bp_destroy_graph(g);
+        return hip_fail(e, "hipDeviceGetAttribute");
+    }
+    for (int m = 0; m < 4; ++m) g->resident[m] = logodds_blocks_per_cu(m);
     *out = g;
     return BP_OK;
 }
@@ -478,11 +502,24 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     EvalArgs a{};
     a.tile_start = g->at<int>(g->off.tile);
     a.tile_slot = g->at<int>(g->off.tile_slot);
-    a.num_tiles = (int)L.tile_start.size() - 1;
+    a.tiles4 = g->at<int>(g->off.tiles4);
+    a.big4 = g->at<int>(g->off.big4);
+    a.num_tiles = L.layout == kLayoutLogOdds ? (int)(L.tiles4.size() / 4) : (int)L.tile_start.size() - 1;
+    a.num_big = L.layout == kLayoutLogOdds ? (int)(L.big4.size() / 4) : 0;
     a.tiles_per_xcd = (a.num_tiles + 7) / 8;
-    a.in_ptr = g->at<int>(g->off.in_ptr);
+    {
+        // one persistent block per resident slot (the least occupancy over the
+        // modes this run launches), never more than the tiles need
+        const int mode_now = schedule == BP_LBP ? kModeLBP : schedule == BP_RBP ? kModeRBP : kModeRnBP;
+        int per_cu = std::min(g->resident[mode_now], g->resident[kModeEvalOnly]);
+        if (per_cu < 1) per_cu = 1;
+        long long cap = (long long)per_cu * std::max(g->num_cus, 1);
+        cap = std::max<long long>(8, cap / 8 * 8);
+        a.pipe_grid = (int)std::min<long long>(cap, std::max(8, 8 * a.tiles_per_xcd));
+    }
+    a.node_ptr = g->at<int>(g->off.node_ptr);
     a.rev = g->at<int>(g->off.rev);
-    a.src = g->at<int>(g->off.src);
+    a.dst = g->at<int>(g->off.dst);
     a.coupling = g->at<float>(g->off.coupling);
     a.unary = g->at<float>(g->off.unary);
     a.pair = g->at<float>(g->off.pair);
@@ -520,9 +557,13 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     HIP_OK(hipEventCreate(&ev0), "event");
     HIP_OK(hipEventCreate(&ev1), "event");
+    // profile = k > 0: bracket every k-th evaluation launch with a pair of events
     std::vector<hipEvent_t> kev;
-    if (o.profile) {
+    std::vector<int> kev_used;
+    const long long prof_every = o.profile > 0 ? o.profile : 0;
+    if (prof_every) {
         kev.resize(2 * (size_t)o.check_every);
+        kev_used.assign((size_t)o.check_every, 0);
         for (auto& x : kev) HIP_OK(hipEventCreate(&x), "event");
     }
     double kernel_ms = 0.0;
@@ -559,9 +600,11 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
         a.it = it;
         a.after_final = 0;
         const int emode = final_launched ? kModeEvalOnly : mode;
-        if (o.profile) HIP_OK(hipEventRecord(kev[2 * in_chunk], s), "event record");
+        const bool timed = prof_every && (it % prof_every) == 0;
+        if (timed) HIP_OK(hipEventRecord(kev[2 * in_chunk], s), "event record");
         HIP_OK(launch_eval(L.layout, kp, emode, a, s), "evaluation kernel");
-        if (o.profile) HIP_OK(hipEventRecord(kev[2 * in_chunk + 1], s), "event record");
+        if (timed) HIP_OK(hipEventRecord(kev[2 * in_chunk + 1], s), "event record");
+        if (prof_every) kev_used[in_chunk] = timed ? 1 : 0;
         if (mode == kModeRBP && !final_launched) {
             const int all = rbp_k >= L.E;
             HIP_OK(launch_rbp_gate(g->st(), g->ctr(), (int)(t & 3), s), "top-k gate");
@@ -578,8 +621,9 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
             HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost, s),
                    "state readback");
             HIP_OK(hipStreamSynchronize(s), "synchronize");
-            if (o.profile) {
+            if (prof_every) {
                 for (int i = 0; i < in_chunk; ++i) {
+                    if (!kev_used[i]) continue;
                     float ms = 0.0f;
                     HIP_OK(hipEventElapsedTime(&ms, kev[2 * i], kev[2 * i + 1]), "event time");
                     kernel_ms += ms;
@@ -636,7 +680,7 @@ int bp_marginals_device(bp_graph* g, float* out_device) {
     if (!g || !out_device) return fail(BP_EINVAL, "NULL argument");
     DeviceGuard dg(g->device);
     const HostLayout& L = g->L;
-    HIP_OK(launch_marginals(L.layout, kpad(L.K), g->at<int>(g->off.in_ptr),
+    HIP_OK(launch_marginals(L.layout, kpad(L.K), g->at<int>(g->off.node_ptr), g->at<int>(g->off.rev),
                             g->at<float>(g->off.unary), g->cur(), out_device, L.N, L.K,
                             g->stream),
            "marginals kernel");

@@ -7,15 +7,15 @@
 
 namespace bp {
 
-// Tile limits of the evaluation kernel.  A tile is a run of consecutive target
-// nodes whose incoming messages (a contiguous slot range) are processed by one
-// 256-thread block; the slot limit depends on the message layout.
+// Tile limits of the evaluation kernel.  A tile is a run of consecutive source
+// nodes whose outgoing messages (a contiguous slot range) are processed by one
+// block; the slot limit depends on the message layout.
 #ifndef BP_BLOCK
 #define BP_BLOCK 256
 #endif
 constexpr int kBlock = BP_BLOCK;
 #ifndef BP_TILE_SLOTS_LOGODDS
-#define BP_TILE_SLOTS_LOGODDS 2048
+#define BP_TILE_SLOTS_LOGODDS 512
 #endif
 constexpr int kTileSlotsLogOdds = BP_TILE_SLOTS_LOGODDS;  // K = 2 log-odds layout
 constexpr int kTileNodesLogOdds = kTileSlotsLogOdds / 2;  // nodes per log-odds tile
@@ -68,13 +68,17 @@ struct DevState {
 };
 
 struct EvalArgs {
-    const int* tile_start;      // [T+1] first node of each tile
-    const int* tile_slot;       // [T+1] first slot of each tile
+    const int* tile_start;      // [T+1] first node of each tile ([E][K] layout)
+    const int* tile_slot;       // [T+1] first slot of each tile ([E][K] layout)
+    const int* tiles4;          // log-odds layout: [T][4] {n0, n1, s0, s1} of the regular tiles
+    const int* big4;            // log-odds layout: [num_big][4] single-node tiles over the limit
     int num_tiles;
     int tiles_per_xcd;          // ceil(T / 8): block -> tile remap for XCD locality
-    const int* in_ptr;          // [N+1] slot range of each target node
+    int num_big;
+    int pipe_grid;              // blocks of the persistent log-odds kernel (multiple of 8)
+    const int* node_ptr;        // [N+1] slot range of each source node
     const int* rev;             // [E] slot of the reverse message
-    const int* src;             // [E] source node of the message in each slot
+    const int* dst;             // [E] target node of the message in each slot
     const float* coupling;      // [E] Ising J per slot
     const float* unary;         // log-odds [N] (K = 2 log-odds layout) or log psi [N][K]
     const float* pair;          // shared [K][K] or dense [E][K][K]
@@ -110,8 +114,10 @@ hipError_t launch_init_state(DevState* st, CounterLine* ctr, hipStream_t s);
 hipError_t launch_fill(float* p, float v, long long n, hipStream_t s);
 hipError_t launch_eval(int layout, int kp, int mode, const EvalArgs& a, hipStream_t s);
 hipError_t launch_close_run(const EvalArgs& a, hipStream_t s);
-hipError_t launch_marginals(int layout, int kp, const int* in_ptr, const float* unary,
-                            const float* m, float* out, int N, int K, hipStream_t s);
+int logodds_blocks_per_cu(int mode);
+hipError_t launch_marginals(int layout, int kp, const int* node_ptr, const int* rev,
+                            const float* unary, const float* m, float* out, int N, int K,
+                            hipStream_t s);
 // frontier residual BP selection
 hipError_t launch_rbp_gate(DevState* st, const CounterLine* ctr, int slot_idx, hipStream_t s);
 hipError_t launch_rbp_select(DevState* st, const unsigned int* keys, int E, unsigned int k,

@@ -4,20 +4,22 @@
 // selection kernels for frontier residual BP).
 //
 // Evaluation kernel (Eq. (2) + Eq. (4) + frontier rule + commit, fused):
-// messages are stored grouped by target node (CSR by destination), so the
-// incoming messages of a run of target nodes form one contiguous slot range.
-// A 256-thread block owns such a tile of nodes:
-//   phase 1  coalesced load of the tile's incoming messages into LDS (as logs);
-//   phase 2  one thread per node (per node-state for K > 2) sums them with the
-//            log unary into the node aggregate A_i = log psi_i + sum_k log m_{k->i};
-//   phase 3  one thread per slot: the slot holds m_{k->i}, so the thread computes
-//            the outgoing message m_{i->k} from the cavity A_i - log m_{k->i}
-//            (Eq. (2) excludes exactly that message), normalises it, reads the
-//            old m_{i->k} at the reverse slot, forms the L-infinity residual, applies
-//            the frontier rule and writes the committed value to the next buffer.
-// Every slot of the next buffer is written exactly once per iteration (each
-// message is the outgoing message of exactly one node), so the update is
-// synchronous (Jacobi) with no atomics on message values.
+// messages are stored grouped by source node (CSR by source), so slot e holds
+// m_{i->k}, the message the thread of slot e recomputes, and the outgoing
+// messages of a run of source nodes form one contiguous slot range.  A block
+// owns such a tile of nodes:
+//   phase 1  coalesced loads of the tile's own slots (old value, reverse index,
+//            coupling, target id) and of the incoming messages m_{k->i} at the
+//            reverse slots (the one gather per message);
+//   phase 2  one thread per node (per node-state for K > 2) sums the incoming
+//            logs with the log unary into A_i = log psi_i + sum_k log m_{k->i};
+//   phase 3  one thread per slot computes m_{i->k} from the cavity
+//            A_i - log m_{k->i} (Eq. (2) excludes exactly that message),
+//            normalises it, forms the L-infinity residual against the old value,
+//            applies the frontier rule and writes the next buffer at its own
+//            slot (coalesced).
+// Every slot of the next buffer is written exactly once per iteration, so the
+// update is synchronous (Jacobi) with no atomics on message values.
 //
 // Randomized BP chooses p_t from n_t, which is only known once every block of
 // iteration t has counted its residuals.  The kernel therefore writes the
@@ -42,14 +44,15 @@ __device__ __forceinline__ unsigned int philox_word0(unsigned int c0, unsigned i
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const unsigned int hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-        const unsigned int hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-        const unsigned int n0 = hi1 ^ c1 ^ k0;
-        const unsigned int n2 = hi0 ^ c3 ^ k1;
+        // full 64-bit products: one v_mad_u64_u32 each instead of a hi/lo pair
+        const unsigned long long p0 = (unsigned long long)0xD2511F53u * c0;
+        const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c2;
+        const unsigned int n0 = (unsigned int)(p1 >> 32) ^ c1 ^ k0;
+        const unsigned int n2 = (unsigned int)(p0 >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = lo1;
+        c1 = (unsigned int)p1;
         c2 = n2;
-        c3 = lo0;
+        c3 = (unsigned int)p0;
     }
     return c0;
 }
@@ -63,6 +66,15 @@ __device__ __forceinline__ float sigmoid_fast(float x) {
 __device__ __forceinline__ float logcosh_shift(float x) {
     const float a = fabsf(x);
     return a + __logf(1.0f + __expf(-2.0f * a));
+}
+
+// Workgroup barrier for LDS hand-offs only: waits for this wave's LDS
+// operations and meets the other waves, without the release/acquire fences of
+// __syncthreads(), which would also wait for every outstanding global load
+// (the prefetched next tile).  No global memory written in a launch is read
+// back by another wave of the same block.
+__device__ __forceinline__ void lds_barrier() {
+    __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 struct RedScratch {
@@ -204,8 +216,9 @@ __device__ void wave_close(const EvalArgs& a, bool close, unsigned long long& n1
 // thresholds, so choosing p_{t-1} is choosing a buffer.  Block 0 also closes
 // iteration t - 1.
 __device__ __forceinline__ const float* iteration_prologue(const EvalArgs& a,
-                                                           unsigned long long* s_red) {
-    const bool lead = blockIdx.x == 0;
+                                                           unsigned long long* s_red,
+                                                           bool may_close = true) {
+    const bool lead = may_close && blockIdx.x == 0;
     if (a.it == 0) {
         if (lead && threadIdx.x < 64) {
             CounterLine* z = a.ctr + ((a.t + 1u) & 3u) * kCounterCopies + threadIdx.x;
@@ -227,7 +240,7 @@ __device__ __forceinline__ const float* iteration_prologue(const EvalArgs& a,
             s_red[1] = (unsigned long long)n2;
         }
     }
-    __syncthreads();
+    lds_barrier();
     const unsigned long long n1 = s_red[0];
     if (n1 == 0ull) return nullptr;
     return a.in_buf[select_outcome(a, n1, (long long)s_red[1])];
@@ -238,16 +251,16 @@ __device__ __forceinline__ const float* iteration_prologue(const EvalArgs& a,
 // Aggregate L_i = u_i + sum_k lambda_{k->i} with u_i = log psi_i(1) - log psi_i(0).
 // With H = (L_i - lambda_{k->i}) / 2 the outgoing message of Eq. (2) for
 // psi = exp(J s_i s_k) has log-odds log cosh(J + H) - log cosh(J - H).
+// The slot e of m_{i->k} gives e as the output index, its own old value, and
+// lambda_{k->i} at rev[e].
 // ---------------------------------------------------------------------------
-constexpr int kPerThreadLO = kTileSlotsLogOdds / kBlock;
-
 // Eq. (2), Eq. (4) and the frontier rule for one slot; returns the residual.
 template <int MODE>
-__device__ __forceinline__ float logodds_slot(const EvalArgs& a, float L, float lam_q, float J,
-                                              float lam_old, int e, int src, int node,
+__device__ __forceinline__ float logodds_slot(const EvalArgs& a, float L, float lam_in, float J,
+                                              float lam_old, int e, int dst, int node,
                                               unsigned int& act, unsigned int& sa,
                                               unsigned int& sb) {
-    const float H = 0.5f * (L - lam_q);
+    const float H = 0.5f * (L - lam_in);
     const float lam_new = logcosh_shift(J + H) - logcosh_shift(J - H);
     const float r = fabsf(sigmoid_fast(lam_new) - sigmoid_fast(lam_old));
     const bool active = r > a.eps;
@@ -258,7 +271,7 @@ __device__ __forceinline__ float logodds_slot(const EvalArgs& a, float L, float 
         bool ka = false, kb = false;
         if (active) {
             const unsigned int u24 =
-                philox_word0((unsigned int)node, (unsigned int)src, a.t, a.key0, a.key1) >> 8;
+                philox_word0((unsigned int)node, (unsigned int)dst, a.t, a.key0, a.key1) >> 8;
             ka = u24 < a.thr_a;
             kb = u24 < a.thr_b;
         }
@@ -273,117 +286,193 @@ __device__ __forceinline__ float logodds_slot(const EvalArgs& a, float L, float 
     return r;
 }
 
+constexpr int kPP = kTileSlotsLogOdds / kBlock;              // slots per thread per tile
+constexpr int kPJ = (kTileNodesLogOdds + kBlock) / kBlock;    // node entries (TN + 1) per thread
+
+// The per-thread share of one tile: node bounds and unaries, and the slots'
+// own old values, reverse indices, couplings and target ids.
+struct TileRegs {
+    int n0, nn, s0, ns;
+    int ptr[kPJ];
+    float u[kPJ];
+    float old[kPP];
+    int rev[kPP];
+    float J[kPP];
+    int dst[kPP];
+};
+
+// Issue every load of a tile (indices clamped into the tile, so there is no
+// per-lane branch and the loads are not ordered behind one another).
+template <int MODE>
+__device__ __forceinline__ void tile_load(TileRegs& d, const EvalArgs& a, const float* m_in,
+                                          int4 b) {
+    const int tid = threadIdx.x;
+    d.n0 = b.x;
+    d.nn = b.y - b.x;
+    d.s0 = b.z;
+    d.ns = b.w - b.z;
+#pragma unroll
+    for (int j = 0; j < kPJ; ++j) {
+        const int v = tid + j * kBlock;
+        d.ptr[j] = a.node_ptr[d.n0 + min(v, d.nn)];
+        d.u[j] = a.unary[d.n0 + min(v, d.nn - 1)];
+    }
+    if (d.ns > 0) {
+#pragma unroll
+        for (int k = 0; k < kPP; ++k) {
+            const int s = d.s0 + min(tid + k * kBlock, d.ns - 1);
+            d.old[k] = m_in[s];
+            d.rev[k] = a.rev[s];
+            d.J[k] = a.coupling[s];
+            d.dst[k] = MODE == kModeRnBP ? a.dst[s] : 0;
+        }
+    }
+}
+
+// Tile w + j * W of this block's XCD range (tiles are dealt to XCDs in
+// contiguous ranges so that neighbouring tiles share an L2), or -1.
+__device__ __forceinline__ int block_tile(const EvalArgs& a, int j) {
+    const int w = (int)(blockIdx.x >> 3) + j * (int)(gridDim.x >> 3);
+    if (w >= a.tiles_per_xcd) return -1;
+    const int t = (int)(blockIdx.x & 7) * a.tiles_per_xcd + w;
+    return t < a.num_tiles ? t : -1;
+}
+
+// K = 2 evaluation kernel.  A persistent grid (as many blocks as are resident)
+// walks the tiles; while a block computes tile j, the loads of tile j + 1 are
+// in flight, so the math of Eq. (2), the residual and the random filter
+// overlaps the memory traffic instead of following it.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
+    constexpr int TS = kTileSlotsLogOdds;
     constexpr int TN = kTileNodesLogOdds;
-    __shared__ float s_lam[kTileSlotsLogOdds];
-    __shared__ unsigned short s_owner[kTileSlotsLogOdds];
+    __shared__ float s_lam[TS];
+    __shared__ unsigned short s_owner[TS];
     __shared__ unsigned short s_ptr[TN + 1];
     __shared__ float s_L[TN];
     __shared__ RedScratch red;
-    __shared__ float s_part[kBlock / 64];
     __shared__ unsigned long long s_red[2];
 
-    // tile bounds first: they do not depend on the prologue's counters
-    const int tile = tile_of_block(a);
-    const bool in_range = tile < a.num_tiles;
-    int n0 = 0, n1 = 0, s0 = 0, s1 = 0;
-    if (in_range) {
-        n0 = a.tile_start[tile];
-        n1 = a.tile_start[tile + 1];
-        s0 = a.tile_slot[tile];
-        s1 = a.tile_slot[tile + 1];
-    }
+    const int4* __restrict__ tiles = (const int4*)a.tiles4;
+    const int t0 = block_tile(a, 0), t1 = block_tile(a, 1);
+    int4 bcur = t0 >= 0 ? tiles[t0] : make_int4(0, 0, 0, 0);
+    int4 bnext = t1 >= 0 ? tiles[t1] : make_int4(0, 0, 0, 0);
     const float* __restrict__ m_in = iteration_prologue(a, s_red);
-    if (!m_in || !in_range) return;
-    const int ns = s1 - s0, nn = n1 - n0;
+    if (!m_in) return;
     const int tid = threadIdx.x;
-
     float rmax = 0.0f;
     unsigned int act = 0, sa = 0, sb = 0;
 
-    if (ns <= kTileSlotsLogOdds) {
-        // Phase 1: every independent global load of this thread, then the
-        // reverse-slot gathers; the LDS work of phase 2 overlaps the gathers.
-        // Indices are clamped into the tile instead of predicated so that the
-        // compiler issues all loads before the first wait.
-        constexpr int JN = TN / kBlock + 1;
-        int ptrv[JN];
-        float uv[JN];
+    if (t0 >= 0) {
+        // Software pipeline over this block's tiles.  Iteration j: issue the
+        // loads of tile j+1, aggregate tile j (LDS), issue the gathers of tile
+        // j+1, compute and store tile j, then stage tile j+1 into LDS.  Every
+        // wait therefore falls on loads that had a whole phase to complete.
+        TileRegs cur, nxt;
+        float lin[kPP];
+        tile_load<MODE>(cur, a, m_in, bcur);
+        if (cur.ns > 0) {
 #pragma unroll
-        for (int j = 0; j < JN; ++j) {
-            const int v = tid + j * kBlock;
-            ptrv[j] = a.in_ptr[n0 + min(v, nn)];
-            uv[j] = a.unary[n0 + min(v, nn - 1)];
+            for (int k = 0; k < kPP; ++k) lin[k] = m_in[cur.rev[k]];
         }
-        float lam[kPerThreadLO], J[kPerThreadLO], old[kPerThreadLO];
-        int e[kPerThreadLO], src[kPerThreadLO];
-        if (ns > 0) {
+        // stage tile 0
 #pragma unroll
-            for (int k = 0; k < kPerThreadLO; ++k) {
-                const int s = s0 + min(tid + k * kBlock, ns - 1);
-                lam[k] = m_in[s];
-                e[k] = a.rev[s];
-                J[k] = a.coupling[s];
-                src[k] = MODE == kModeRnBP ? a.src[s] : 0;
-            }
-#pragma unroll
-            for (int k = 0; k < kPerThreadLO; ++k) old[k] = m_in[e[k]];
+        for (int jj = 0; jj < kPJ; ++jj) {
+            const int v = tid + jj * kBlock;
+            if (v <= cur.nn) s_ptr[v] = (unsigned short)(cur.ptr[jj] - cur.s0);
+            if (v < cur.nn) s_L[v] = cur.u[jj];
         }
 #pragma unroll
-        for (int j = 0; j < JN; ++j) {
-            const int v = tid + j * kBlock;
-            if (v <= nn) s_ptr[v] = (unsigned short)(ptrv[j] - s0);
-            if (v < nn) s_L[v] = uv[j];
-        }
-#pragma unroll
-        for (int k = 0; k < kPerThreadLO; ++k) {
+        for (int k = 0; k < kPP; ++k) {
             const int q = tid + k * kBlock;
-            if (q < ns) s_lam[q] = lam[k];
+            if (q < cur.ns) s_lam[q] = lin[k];
         }
-        __syncthreads();
-        // Phase 2: node aggregates in slot order
-        for (int v = tid; v < nn; v += kBlock) {
-            const int q0 = s_ptr[v], q1 = s_ptr[v + 1];
-            float L = s_L[v];
-            for (int q = q0; q < q1; ++q) {
-                L += s_lam[q];
-                s_owner[q] = (unsigned short)v;
+        for (int j = 0;; ++j) {
+            const bool has_next = block_tile(a, j + 1) >= 0;
+            const int t2 = block_tile(a, j + 2);
+            const int4 bnext2 = t2 >= 0 ? tiles[t2] : make_int4(0, 0, 0, 0);
+            if (has_next) tile_load<MODE>(nxt, a, m_in, bnext);
+            lds_barrier();
+            // node aggregates of tile j, incoming messages in slot order
+            for (int v = tid; v < cur.nn; v += kBlock) {
+                const int q0 = s_ptr[v], q1 = s_ptr[v + 1];
+                float L = s_L[v];
+                for (int q = q0; q < q1; ++q) {
+                    L += s_lam[q];
+                    s_owner[q] = (unsigned short)v;
+                }
+                s_L[v] = L;
             }
-            s_L[v] = L;
-        }
-        __syncthreads();
-        // Phase 3: one outgoing message per slot
+            lds_barrier();
+            float lin_n[kPP];
+            if (has_next && nxt.ns > 0) {
 #pragma unroll
-        for (int k = 0; k < kPerThreadLO; ++k) {
-            const int q = tid + k * kBlock;
-            if (q < ns) {
-                const int v = s_owner[q];
-                const float r = logodds_slot<MODE>(a, s_L[v], lam[k], J[k], old[k], e[k], src[k],
-                                                   n0 + v, act, sa, sb);
-                rmax = fmaxf(rmax, r);
+                for (int k = 0; k < kPP; ++k) lin_n[k] = m_in[nxt.rev[k]];
             }
-        }
-    } else {
-        // A single node whose in-degree exceeds the tile: aggregate by a block
-        // reduction, then stream the slots.
-        float part = 0.0f;
-        for (int q = tid; q < ns; q += kBlock) part += m_in[s0 + q];
+            // outgoing messages of tile j, written at their own slots
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-        if ((tid & 63) == 0) s_part[tid >> 6] = part;
-        __syncthreads();
-        float L = a.unary[n0];
+            for (int k = 0; k < kPP; ++k) {
+                const int q = tid + k * kBlock;
+                if (q < cur.ns) {
+                    const int v = s_owner[q];
+                    const float r = logodds_slot<MODE>(a, s_L[v], lin[k], cur.J[k], cur.old[k],
+                                                       cur.s0 + q, cur.dst[k], cur.n0 + v, act, sa,
+                                                       sb);
+                    rmax = fmaxf(rmax, r);
+                }
+            }
+            if (!has_next) break;
+            lds_barrier();  // tile j's LDS reads are done
+            cur = nxt;
 #pragma unroll
-        for (int i = 0; i < kBlock / 64; ++i) L += s_part[i];
-        for (int q = tid; q < ns; q += kBlock) {
-            const int s = s0 + q;
-            const int e = a.rev[s];
-            const int src = MODE == kModeRnBP ? a.src[s] : 0;
-            const float r = logodds_slot<MODE>(a, L, m_in[s], a.coupling[s], m_in[e], e, src, n0,
-                                               act, sa, sb);
-            rmax = fmaxf(rmax, r);
+            for (int k = 0; k < kPP; ++k) lin[k] = lin_n[k];
+#pragma unroll
+            for (int jj = 0; jj < kPJ; ++jj) {
+                const int v = tid + jj * kBlock;
+                if (v <= cur.nn) s_ptr[v] = (unsigned short)(cur.ptr[jj] - cur.s0);
+                if (v < cur.nn) s_L[v] = cur.u[jj];
+            }
+#pragma unroll
+            for (int k = 0; k < kPP; ++k) {
+                const int q = tid + k * kBlock;
+                if (q < cur.ns) s_lam[q] = lin[k];
+            }
+            bnext = bnext2;
         }
+    }
+    block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
+}
+
+// Nodes whose degree exceeds a tile: one block per node, aggregate by a block
+// reduction of the gathered incoming messages, then stream the slots.  Runs
+// after k_eval_logodds in the same iteration (same prologue, no bookkeeping).
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_eval_logodds_big(EvalArgs a) {
+    __shared__ RedScratch red;
+    __shared__ float s_part[kBlock / 64];
+    __shared__ unsigned long long s_red[2];
+    const int4 b = ((const int4*)a.big4)[blockIdx.x];
+    const float* __restrict__ m_in = iteration_prologue(a, s_red, false);
+    if (!m_in) return;
+    const int tid = threadIdx.x;
+    const int n0 = b.x, s0 = b.z, ns = b.w - b.z;
+    float rmax = 0.0f;
+    unsigned int act = 0, sa = 0, sb = 0;
+    float part = 0.0f;
+    for (int q = tid; q < ns; q += kBlock) part += m_in[a.rev[s0 + q]];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    if ((tid & 63) == 0) s_part[tid >> 6] = part;
+    __syncthreads();
+    float L = a.unary[n0];
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) L += s_part[i];
+    for (int q = tid; q < ns; q += kBlock) {
+        const int s = s0 + q;
+        const int dst = MODE == kModeRnBP ? a.dst[s] : 0;
+        const float r = logodds_slot<MODE>(a, L, m_in[a.rev[s]], a.coupling[s], m_in[s], s, dst, n0,
+                                           act, sa, sb);
+        rmax = fmaxf(rmax, r);
     }
     block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
 }
@@ -402,10 +491,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
     if (tile >= a.num_tiles) return;
     const int K = a.num_states;
     const int TS = kTileFloatsGeneric / K;  // slots (and nodes) per tile
-    float* s_logm = smem;                   // [TS][K]
+    float* s_logm = smem;                   // [TS][K] logs of the incoming messages
     float* s_A = s_logm + TS * K;           // [TS][K]
     float* s_psi = s_A + TS * K;            // [K][K] shared table
-    unsigned short* s_owner = (unsigned short*)(s_psi + K * K);
+    int* s_rev = (int*)(s_psi + K * K);     // [TS]
+    unsigned short* s_owner = (unsigned short*)(s_rev + TS);
 
     const int n0 = a.tile_start[tile], n1 = a.tile_start[tile + 1];
     const int s0 = a.tile_slot[tile], s1 = a.tile_slot[tile + 1];
@@ -420,13 +510,18 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
     if (a.pair_kind == kPairShared || a.pair_kind == kPairSharedAsym)
         for (int i = tid; i < K * K; i += kBlock) s_psi[i] = a.pair[i];
     if (!big) {
-        const long long base = (long long)s0 * K;
-        for (int i = tid; i < ns * K; i += kBlock) s_logm[i] = logf(fK * m_in[base + i]);
+        for (int q = tid; q < ns; q += kBlock) s_rev[q] = a.rev[s0 + q];
+        __syncthreads();
+        // incoming rows m_{k->i}, gathered row by row (K consecutive threads per row)
+        for (int i = tid; i < ns * K; i += kBlock) {
+            const int q = i / K, x = i - q * K;
+            s_logm[i] = logf(fK * m_in[(long long)s_rev[q] * K + x]);
+        }
         __syncthreads();
         for (int i = tid; i < nn * K; i += kBlock) {
             const int v = i / K, x = i - v * K;
             const int n = n0 + v;
-            const int q0 = a.in_ptr[n] - s0, q1 = a.in_ptr[n + 1] - s0;
+            const int q0 = a.node_ptr[n] - s0, q1 = a.node_ptr[n + 1] - s0;
             float acc = a.unary[(long long)n * K + x];
             for (int q = q0; q < q1; ++q) acc += s_logm[q * K + x];
             s_A[i] = acc;
@@ -434,10 +529,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
                 for (int q = q0; q < q1; ++q) s_owner[q] = (unsigned short)v;
         }
     } else {
-        // single node with in-degree > TS: aggregate each state with a strided sum
+        // single node with degree > TS: aggregate each state with a strided sum
         for (int x = 0; x < K; ++x) {
             float part = 0.0f;
-            for (int q = tid; q < ns; q += kBlock) part += logf(fK * m_in[(long long)(s0 + q) * K + x]);
+            for (int q = tid; q < ns; q += kBlock)
+                part += logf(fK * m_in[(long long)a.rev[s0 + q] * K + x]);
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
             if ((tid & 63) == 0) red.rmax[tid >> 6] = part;
@@ -458,12 +554,13 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
         const int s = s0 + q;
         const int v = big ? 0 : s_owner[q];
         const int node = n0 + v;
+        const long long rin = big ? (long long)a.rev[s] * K : 0;
         float g[KP];
         float mx = -3.402823466e38f;
 #pragma unroll
         for (int x = 0; x < KP; ++x) {
             if (x < K) {
-                const float lm = big ? logf(fK * m_in[(long long)s * K + x]) : s_logm[q * K + x];
+                const float lm = big ? logf(fK * m_in[rin + x]) : s_logm[q * K + x];
                 g[x] = s_A[v * K + x] - lm;
                 mx = fmaxf(mx, g[x]);
             }
@@ -509,8 +606,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
         for (int y = 0; y < KP; ++y)
             if (y < K) z += c[y];
         const float inv = 1.0f / z;
-        const int e = a.rev[s];
-        const long long eo = (long long)e * K;
+        const long long eo = (long long)s * K;
         float r = 0.0f;
         float old[KP];
 #pragma unroll
@@ -531,7 +627,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
         } else if (MODE == kModeRnBP) {
             bool ka = false, kb = false;
             if (active) {
-                const unsigned int u24 = philox_word0((unsigned int)node, (unsigned int)a.src[s],
+                const unsigned int u24 = philox_word0((unsigned int)node, (unsigned int)a.dst[s],
                                                       a.t, a.key0, a.key1) >> 8;
                 ka = u24 < a.thr_a;
                 kb = u24 < a.thr_b;
@@ -550,7 +646,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
 #pragma unroll
             for (int y = 0; y < KP; ++y)
                 if (y < K) a.cand[eo + y] = c[y];
-            a.keys[e] = __float_as_uint(r);
+            a.keys[s] = __float_as_uint(r);
         }
     }
     block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
@@ -588,25 +684,26 @@ __global__ void k_fill(float* p, float v, long long n) {
 // ---------------------------------------------------------------------------
 // Eq. (3): beliefs from the node aggregate.
 // ---------------------------------------------------------------------------
-__global__ void k_marginals_logodds(const int* in_ptr, const float* unary, const float* lam,
-                                    float* out, int N) {
+__global__ void k_marginals_logodds(const int* node_ptr, const int* rev, const float* unary,
+                                    const float* lam, float* out, int N) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     float L = unary[n];
-    for (int s = in_ptr[n]; s < in_ptr[n + 1]; ++s) L += lam[s];
+    for (int s = node_ptr[n]; s < node_ptr[n + 1]; ++s) L += lam[rev[s]];
     out[2 * (long long)n + 1] = 1.0f / (1.0f + expf(-L));
     out[2 * (long long)n + 0] = 1.0f / (1.0f + expf(L));
 }
 
-__global__ void k_marginals_generic(const int* in_ptr, const float* unary, const float* m,
-                                    float* out, int N, int K) {
+__global__ void k_marginals_generic(const int* node_ptr, const int* rev, const float* unary,
+                                    const float* m, float* out, int N, int K) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     float A[kMaxK];
     float mx = -3.402823466e38f;
     for (int x = 0; x < K; ++x) {
         float acc = unary[(long long)n * K + x];
-        for (int s = in_ptr[n]; s < in_ptr[n + 1]; ++s) acc += logf((float)K * m[(long long)s * K + x]);
+        for (int s = node_ptr[n]; s < node_ptr[n + 1]; ++s)
+            acc += logf((float)K * m[(long long)rev[s] * K + x]);
         A[x] = acc;
         mx = fmaxf(mx, acc);
     }
@@ -796,17 +893,26 @@ hipError_t launch_eval(int layout, int kp, int mode, const EvalArgs& a, hipStrea
     const int grid = 8 * a.tiles_per_xcd;
     if (grid <= 0) return hipSuccess;
     if (layout == kLayoutLogOdds) {
+        const int g = a.pipe_grid;
         switch (mode) {
-        case kModeLBP: k_eval_logodds<kModeLBP><<<grid, kBlock, 0, s>>>(a); break;
-        case kModeRnBP: k_eval_logodds<kModeRnBP><<<grid, kBlock, 0, s>>>(a); break;
-        case kModeRBP: k_eval_logodds<kModeRBP><<<grid, kBlock, 0, s>>>(a); break;
-        default: k_eval_logodds<kModeEvalOnly><<<grid, kBlock, 0, s>>>(a); break;
+        case kModeLBP: k_eval_logodds<kModeLBP><<<g, kBlock, 0, s>>>(a); break;
+        case kModeRnBP: k_eval_logodds<kModeRnBP><<<g, kBlock, 0, s>>>(a); break;
+        case kModeRBP: k_eval_logodds<kModeRBP><<<g, kBlock, 0, s>>>(a); break;
+        default: k_eval_logodds<kModeEvalOnly><<<g, kBlock, 0, s>>>(a); break;
+        }
+        if (a.num_big > 0) {
+            switch (mode) {
+            case kModeLBP: k_eval_logodds_big<kModeLBP><<<a.num_big, kBlock, 0, s>>>(a); break;
+            case kModeRnBP: k_eval_logodds_big<kModeRnBP><<<a.num_big, kBlock, 0, s>>>(a); break;
+            case kModeRBP: k_eval_logodds_big<kModeRBP><<<a.num_big, kBlock, 0, s>>>(a); break;
+            default: k_eval_logodds_big<kModeEvalOnly><<<a.num_big, kBlock, 0, s>>>(a); break;
+            }
         }
         return hipGetLastError();
     }
     const int K = a.num_states;
     const int TS = kTileFloatsGeneric / K;
-    const size_t shm = sizeof(float) * (size_t)(2 * TS * K + K * K) +
+    const size_t shm = sizeof(float) * (size_t)(2 * TS * K + K * K) + sizeof(int) * (size_t)TS +
                        sizeof(unsigned short) * (size_t)TS;
     switch (kp) {
     case 2: return launch_generic_kp<2>(mode, a, grid, shm, s);
@@ -819,20 +925,41 @@ hipError_t launch_eval(int layout, int kp, int mode, const EvalArgs& a, hipStrea
     }
 }
 
+int logodds_blocks_per_cu(int mode) {
+    int n = 0;
+    hipError_t e;
+    switch (mode) {
+    case kModeLBP:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeLBP>, kBlock, 0);
+        break;
+    case kModeRnBP:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeRnBP>, kBlock, 0);
+        break;
+    case kModeRBP:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeRBP>, kBlock, 0);
+        break;
+    default:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeEvalOnly>, kBlock, 0);
+        break;
+    }
+    return e == hipSuccess ? n : 0;
+}
+
 hipError_t launch_close_run(const EvalArgs& a, hipStream_t s) {
     k_close_run<<<1, 64, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_marginals(int layout, int kp, const int* in_ptr, const float* unary,
-                            const float* m, float* out, int N, int K, hipStream_t s) {
+hipError_t launch_marginals(int layout, int kp, const int* node_ptr, const int* rev,
+                            const float* unary, const float* m, float* out, int N, int K,
+                            hipStream_t s) {
     (void)kp;
     if (N <= 0) return hipSuccess;
     const int grid = (N + 255) / 256;
     if (layout == kLayoutLogOdds)
-        k_marginals_logodds<<<grid, 256, 0, s>>>(in_ptr, unary, m, out, N);
+        k_marginals_logodds<<<grid, 256, 0, s>>>(node_ptr, rev, unary, m, out, N);
     else
-        k_marginals_generic<<<grid, 256, 0, s>>>(in_ptr, unary, m, out, N, K);
+        k_marginals_generic<<<grid, 256, 0, s>>>(node_ptr, rev, unary, m, out, N, K);
     return hipGetLastError();
 }
 
