@@ -37,6 +37,21 @@ def eval_kernel_bytes(N, E, two_outputs=True):
     return (20 + (4 if two_outputs else 0)) * E + 8 * N
 
 
+def counter_traffic(path, kernel_src):
+    """Bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary, or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = dict(line.strip().split("=", 1) for line in open(path)
+                  if "=" in line and not line.startswith("#"))
+        sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if kv.get("kernel_source_sha256") != sha:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +68,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-ttc", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device-to-device copy kernel first (a known-size "
                          "reference for hardware byte counters)")
@@ -120,9 +136,12 @@ def main():
     avg_kernel_s = kern_ms / max(kern_n, 1) / 1e3
     nbytes = eval_kernel_bytes(N, E)
     achieved = nbytes / avg_kernel_s if avg_kernel_s > 0 else 0.0
+    traffic = counter_traffic(
+        os.path.join(ROOT, "profiles", "k_eval_logodds_rnbp_ising1000_counters.txt"),
+        os.path.join(ROOT, "paper_1909_11469_amd", "csrc", "bp_kernels.hip"))
     roofline = {"bound": "hbm", "kernel": "k_eval_logodds<RnBP>",
                 "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": None,
+                "frac": achieved / HBM_PEAK, "traffic": traffic,
                 "bytes_per_launch": nbytes, "avg_kernel_us": avg_kernel_s * 1e6,
                 "launches": kern_n}
 
@@ -171,6 +190,36 @@ def main():
                     "mean_iterations": float(np.mean([i for _, _, i in v]))}
                 for k, v in rows.items()}
         out["time_to_convergence"] = ttc
+
+    if not args.no_extra:
+        extra = {}
+        # frontier residual BP on the same graph: share of the iteration spent
+        # outside the evaluation kernel (top-k selection and commit)
+        for p_rbp in (1 / 256, 1 / 16):
+            r = g.run("rbp", eps=args.eps, p=p_rbp, max_iters=200, check_every=args.check_every,
+                      profile=1)
+            it_us = r["device_ms"] * 1e3 / (r["iterations"] + 1)
+            ev_us = r["eval_kernel_ms"] * 1e3 / max(r["eval_kernel_launches"], 1)
+            extra[f"rbp_p={p_rbp:.6g}"] = {
+                "iteration_us": it_us, "eval_kernel_us": ev_us,
+                "selection_share": max(0.0, 1.0 - ev_us / it_us),
+                "committed_per_iteration": r["committed"] / max(r["iterations"], 1)}
+            _log(f"bench: rbp p={p_rbp:.6g} {extra[f'rbp_p={p_rbp:.6g}']}")
+        # the irregular and the K = 32 workloads (parity-tested; throughput only)
+        for name, pr, sched, p_, iters in (
+                ("er_200k_deg6_C2.5", inputs.er_graph(200000, 6.0, 2.5, 0), "rnbp", 0.3, 1000),
+                ("potts_500x500_K32", inputs.potts_grid(500, 500, 32, 1.0, 0), "rnbp", 0.5, 100)):
+            with bp.Graph(pr) as gg:
+                gg.run(sched, eps=args.eps, p=p_, seed=1, max_iters=10)
+                rr = gg.run(sched, eps=args.eps, p=p_, seed=2, max_iters=iters,
+                            check_every=args.check_every, profile=args.profile_every)
+            extra[name] = {
+                "schedule": sched, "p": p_, "messages": 2 * len(pr["edges"]),
+                "iterations": rr["iterations"], "converged": rr["converged"],
+                "message_updates_per_s": rr["evaluated"] / (rr["device_ms"] / 1e3),
+                "eval_kernel_us": rr["eval_kernel_ms"] * 1e3 / max(rr["eval_kernel_launches"], 1)}
+            _log(f"bench: {name} {extra[name]}")
+        out["extra"] = extra
 
     if not args.no_cpu_baseline:
         import oracle

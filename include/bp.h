@@ -112,8 +112,10 @@ typedef struct bp_run_opts {
     double ratio_threshold;   /* BP_RNBP dynamic: default 0.9 */
     int32_t warm_start;       /* 0 (default): messages reset to uniform 1/K and t = 0;
                                  1: continue from the current messages and iteration state */
-    int32_t profile;          /* k > 0: time every k-th launch of the evaluation kernel
-                                 with a pair of HIP events on the graph's stream */
+    int32_t profile;          /* k > 0: time the evaluation kernel with HIP events on the
+                                 graph's stream: whole chunks of back-to-back launches when
+                                 it is the only kernel of an iteration, else every k-th
+                                 launch */
 } bp_run_opts;
 
 typedef struct bp_run_stats {

@@ -557,10 +557,15 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     HIP_OK(hipEventCreate(&ev0), "event");
     HIP_OK(hipEventCreate(&ev1), "event");
-    // profile = k > 0: bracket every k-th evaluation launch with a pair of events
+    // profile = k > 0.  When the evaluation kernel is the only launch of an
+    // iteration (LBP / RnBP without oversized nodes), a pair of events brackets
+    // each chunk of back-to-back launches: chunk time / launches is the kernel's
+    // average duration (gaps between dispatches included).  Otherwise every
+    // k-th evaluation launch gets its own pair of events.
     std::vector<hipEvent_t> kev;
     std::vector<int> kev_used;
     const long long prof_every = o.profile > 0 ? o.profile : 0;
+    const bool prof_window = prof_every && mode != kModeRBP && a.num_big == 0;
     if (prof_every) {
         kev.resize(2 * (size_t)o.check_every);
         kev_used.assign((size_t)o.check_every, 0);
@@ -600,11 +605,12 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
         a.it = it;
         a.after_final = 0;
         const int emode = final_launched ? kModeEvalOnly : mode;
-        const bool timed = prof_every && (it % prof_every) == 0;
+        const bool timed = prof_every && !prof_window && (it % prof_every) == 0;
+        if (prof_window && in_chunk == 0) HIP_OK(hipEventRecord(kev[0], s), "event record");
         if (timed) HIP_OK(hipEventRecord(kev[2 * in_chunk], s), "event record");
         HIP_OK(launch_eval(L.layout, kp, emode, a, s), "evaluation kernel");
         if (timed) HIP_OK(hipEventRecord(kev[2 * in_chunk + 1], s), "event record");
-        if (prof_every) kev_used[in_chunk] = timed ? 1 : 0;
+        if (prof_every && !prof_window) kev_used[in_chunk] = timed ? 1 : 0;
         if (mode == kModeRBP && !final_launched) {
             const int all = rbp_k >= L.E;
             HIP_OK(launch_rbp_gate(g->st(), g->ctr(), (int)(t & 3), s), "top-k gate");
@@ -618,10 +624,16 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
         }
         ++in_chunk;
         if (in_chunk == o.check_every || final_launched) {
+            if (prof_window) HIP_OK(hipEventRecord(kev[1], s), "event record");
             HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost, s),
                    "state readback");
             HIP_OK(hipStreamSynchronize(s), "synchronize");
-            if (prof_every) {
+            if (prof_window) {
+                float ms = 0.0f;
+                HIP_OK(hipEventElapsedTime(&ms, kev[0], kev[1]), "event time");
+                kernel_ms += ms;
+                kernel_launches += in_chunk;
+            } else if (prof_every) {
                 for (int i = 0; i < in_chunk; ++i) {
                     if (!kev_used[i]) continue;
                     float ms = 0.0f;

@@ -57,15 +57,25 @@ __device__ __forceinline__ unsigned int philox_word0(unsigned int c0, unsigned i
     return c0;
 }
 
+// Hardware exp2 / log2 (v_exp_f32, v_log_f32) where the argument range needs
+// none of the library's fix-ups: exp2 of a non-positive argument may flush to
+// zero, which is harmless below; log2 is only taken of values in [1, 2].
+__device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// 1 / (1 + e^{-x}); e^{-x} overflows to +inf for x < -88 and gives 0.
 __device__ __forceinline__ float sigmoid_fast(float x) {
-    return __frcp_rn(1.0f + __expf(-x));
+    return __frcp_rn(1.0f + exp2_hw(-kLog2e * x));
 }
 
 // log cosh(x) + log 2, i.e. |x| + log(1 + exp(-2|x|)); the constant cancels in
 // the differences it is used in.
 __device__ __forceinline__ float logcosh_shift(float x) {
     const float a = fabsf(x);
-    return a + __logf(1.0f + __expf(-2.0f * a));
+    return a + kLn2 * log2_hw(1.0f + exp2_hw(-2.0f * kLog2e * a));
 }
 
 // Workgroup barrier for LDS hand-offs only: waits for this wave's LDS
