@@ -29,12 +29,13 @@ def _log(msg):
 
 
 def eval_kernel_bytes(N, E, two_outputs=True):
-    """Algorithmic bytes of one launch of the K = 2 evaluation kernel in RnBP
-    mode, each array element moved once: per directed message the in-slot
-    log-odds (4), the reverse index (4), the coupling (4), the source id for the
-    RNG counter (4) and the committed value under each keep threshold (4 + 4);
-    per node the slot offset (4) and the unary log-odds (4)."""
-    return (20 + (4 if two_outputs else 0)) * E + 8 * N
+    """Algorithmic bytes of one launch of the K = 2 evaluation kernel, each
+    array element moved once: per directed message the in-slot log-odds (4),
+    the reverse index (4), the coupling (4) and the committed value (4), and in
+    RnBP mode the target id for the RNG counter (4) and the committed value
+    under the second keep threshold (4); per node the slot offset (4) and the
+    unary log-odds (4)."""
+    return (24 if two_outputs else 16) * E + 8 * N
 
 
 def counter_traffic(path, kernel_src):
@@ -219,6 +220,23 @@ def main():
                 "message_updates_per_s": rr["evaluated"] / (rr["device_ms"] / 1e3),
                 "eval_kernel_us": rr["eval_kernel_ms"] * 1e3 / max(rr["eval_kernel_launches"], 1)}
             _log(f"bench: {name} {extra[name]}")
+        # a working set far beyond the 256 MB Infinity Cache: every byte of a
+        # sweep comes from HBM (16M variables, 64M messages)
+        pr = inputs.ising_grid(4000, 4000, args.C, 0)
+        N4, E4 = pr["N"], 2 * len(pr["edges"])
+        with bp.Graph(pr) as gg:
+            del pr
+            row = {"messages": E4}
+            for sched in ("lbp", "rnbp"):
+                rr = gg.run(sched, eps=args.eps, p=args.p, seed=1, max_iters=60,
+                            check_every=args.check_every, profile=args.profile_every)
+                us = rr["eval_kernel_ms"] * 1e3 / max(rr["eval_kernel_launches"], 1)
+                nb = eval_kernel_bytes(N4, E4, two_outputs=sched == "rnbp")
+                row[sched] = {"eval_kernel_us": us, "bytes_per_launch": nb,
+                              "hbm_frac": nb / (us * 1e-6) / HBM_PEAK if us > 0 else None,
+                              "message_updates_per_s": rr["evaluated"] / (rr["device_ms"] / 1e3)}
+        extra["ising_4000x4000_C%g" % args.C] = row
+        _log(f"bench: ising 4000x4000 {row}")
         out["extra"] = extra
 
     if not args.no_cpu_baseline:

@@ -62,20 +62,15 @@ __device__ __forceinline__ unsigned int philox_word0(unsigned int c0, unsigned i
 // zero, which is harmless below; log2 is only taken of values in [1, 2].
 __device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
+// v_rcp_f32 (1 ulp); the arguments below are in [1, 2] or are normal floats
+__device__ __forceinline__ float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
 
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 
 // 1 / (1 + e^{-x}); e^{-x} overflows to +inf for x < -88 and gives 0.
 __device__ __forceinline__ float sigmoid_fast(float x) {
-    return __frcp_rn(1.0f + exp2_hw(-kLog2e * x));
-}
-
-// log cosh(x) + log 2, i.e. |x| + log(1 + exp(-2|x|)); the constant cancels in
-// the differences it is used in.
-__device__ __forceinline__ float logcosh_shift(float x) {
-    const float a = fabsf(x);
-    return a + kLn2 * log2_hw(1.0f + exp2_hw(-2.0f * kLog2e * a));
+    return rcp_hw(1.0f + exp2_hw(-kLog2e * x));
 }
 
 // Workgroup barrier for LDS hand-offs only: waits for this wave's LDS
@@ -260,19 +255,31 @@ __device__ __forceinline__ const float* iteration_prologue(const EvalArgs& a,
 // K = 2 Ising, one log-odds value per message: lambda = log(m(1) / m(0)).
 // Aggregate L_i = u_i + sum_k lambda_{k->i} with u_i = log psi_i(1) - log psi_i(0).
 // With H = (L_i - lambda_{k->i}) / 2 the outgoing message of Eq. (2) for
-// psi = exp(J s_i s_k) has log-odds log cosh(J + H) - log cosh(J - H).
+// psi = exp(J s_i s_k) has m(1) - m(0) = tanh J tanh H (sum over x_i in closed
+// form; normalisation included).
 // The slot e of m_{i->k} gives e as the output index, its own old value, and
 // lambda_{k->i} at rev[e].
 // ---------------------------------------------------------------------------
 // Eq. (2), Eq. (4) and the frontier rule for one slot; returns the residual.
+// With tJ = tanh J (stored per slot) and tau = tanh H, Eq. (2) gives the new
+// message's probability of state 1 directly, m(1) = (1 + tJ tau) / 2, and its
+// log-odds log((1 + tJ tau) / (1 - tJ tau)).  The log-odds loses relative
+// accuracy when tJ tau is near +-1, but only where sigma' = m(1) m(0) is as small,
+// so the message itself keeps an absolute error of a few FP32 ulps.
 template <int MODE>
-__device__ __forceinline__ float logodds_slot(const EvalArgs& a, float L, float lam_in, float J,
+__device__ __forceinline__ float logodds_slot(const EvalArgs& a, float L, float lam_in, float tJ,
                                               float lam_old, int e, int dst, int node,
                                               unsigned int& act, unsigned int& sa,
                                               unsigned int& sb) {
     const float H = 0.5f * (L - lam_in);
-    const float lam_new = logcosh_shift(J + H) - logcosh_shift(J - H);
-    const float r = fabsf(sigmoid_fast(lam_new) - sigmoid_fast(lam_old));
+    // tanh H = sign(H) (1 - e^{-2|H|}) / (1 + e^{-2|H|})
+    const float eh = exp2_hw(-2.0f * kLog2e * fabsf(H));
+    const float tau = copysignf((1.0f - eh) * rcp_hw(1.0f + eh), H);
+    const float x = tJ * tau;
+    const float p1 = 0.5f + 0.5f * x;   // m_new(1)
+    const float p0 = 0.5f - 0.5f * x;   // m_new(0)
+    const float lam_new = kLn2 * log2_hw(p1 * rcp_hw(p0));
+    const float r = fabsf(p1 - sigmoid_fast(lam_old));
     const bool active = r > a.eps;
     act += active;
     if (MODE == kModeLBP) {

@@ -39,24 +39,18 @@ def grid_edges(H: int, W: int) -> np.ndarray:
 
 
 def _grid_edges_fast(H: int, W: int) -> np.ndarray:
-    """Same list as grid_edges, vectorised for large grids."""
-    ids = np.arange(H * W, dtype=np.int64)
-    r, c = ids // W, ids % W
-    right = c < W - 1
-    down = r < H - 1
-    # per node: right edge first, then down edge
-    cnt = right.astype(np.int64) + down.astype(np.int64)
-    start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
-    M = int(cnt.sum())
-    e = np.empty((M, 2), dtype=np.int64)
-    ri = ids[right]
-    e[start[right], 0] = ri
-    e[start[right], 1] = ri + 1
-    di = ids[down]
-    pos = start[down] + right[down].astype(np.int64)
-    e[pos, 0] = di
-    e[pos, 1] = di + W
-    return e.astype(np.int32)
+    """Same list as grid_edges, vectorised for large grids: every node has a
+    (right, down) pair of candidate edges, masked at the last column and row."""
+    ids = np.arange(H * W, dtype=np.int32).reshape(H, W)
+    e = np.empty((H, W, 2, 2), dtype=np.int32)
+    e[:, :, 0, 0] = ids
+    e[:, :, 0, 1] = ids + 1
+    e[:, :, 1, 0] = ids
+    e[:, :, 1, 1] = ids + W
+    keep = np.empty((H, W, 2), dtype=bool)
+    keep[:, :, 0] = np.arange(W) < W - 1
+    keep[:, :, 1] = (np.arange(H) < H - 1)[:, None]
+    return e[keep]
 
 
 def ising_grid(H: int, W: int, C: float, seed: int) -> dict:
