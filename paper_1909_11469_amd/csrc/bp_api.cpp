@@ -233,13 +233,9 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
     // canonical message c of slot s and edge u = c >> 1 = (a, b): c even means
     // i = a, k = b (the table as given); c odd means i = b, so it is transposed.
     if (kind == BP_PAIR_ISING) {
-        // the log-odds kernel takes tanh J, the [E][K] kernel J
         L.pair = kPairIsing;
         L.coupling.resize((size_t)E);
-        for (long long s = 0; s < E; ++s) {
-            const double J = d->coupling[canon_of_slot[s] >> 1];
-            L.coupling[s] = (float)(L.layout == kLayoutLogOdds ? std::tanh(J) : J);
-        }
+        for (long long s = 0; s < E; ++s) L.coupling[s] = (float)d->coupling[canon_of_slot[s] >> 1];
     } else if (kind == BP_PAIR_SHARED) {
         bool sym = true;
         for (long long x = 0; x < K; ++x)

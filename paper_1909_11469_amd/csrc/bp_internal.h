@@ -79,7 +79,7 @@ struct EvalArgs {
     const int* node_ptr;        // [N+1] slot range of each source node
     const int* rev;             // [E] slot of the reverse message
     const int* dst;             // [E] target node of the message in each slot
-    const float* coupling;      // [E] Ising coupling per slot: tanh J (log-odds layout) or J
+    const float* coupling;      // [E] Ising J per slot
     const float* unary;         // log-odds [N] (K = 2 log-odds layout) or log psi [N][K]
     const float* pair;          // shared [K][K] or dense [E][K][K]
     const unsigned char* orient;// [E] 1 if the shared table must be transposed for the slot

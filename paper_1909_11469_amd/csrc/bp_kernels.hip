@@ -57,12 +57,12 @@ __device__ __forceinline__ unsigned int philox_word0(unsigned int c0, unsigned i
     return c0;
 }
 
-// Hardware exp2 / log2 (v_exp_f32, v_log_f32) where the argument range needs
-// none of the library's fix-ups: exp2 of a non-positive argument may flush to
-// zero, which is harmless below; log2 is only taken of values in [1, 2].
+// Hardware exp2 / log2 / reciprocal (v_exp_f32, v_log_f32, v_rcp_f32, about 1 ulp)
+// where the argument range needs none of the library's fix-ups: exp2 may
+// underflow to zero or overflow to +inf, both harmless where it is used below;
+// log2 is only taken of values in [1, 2]; rcp only of values in [1, +inf].
 __device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
-// v_rcp_f32 (1 ulp); the arguments below are in [1, 2] or are normal floats
 __device__ __forceinline__ float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
 
 constexpr float kLog2e = 1.4426950408889634f;
@@ -255,31 +255,31 @@ __device__ __forceinline__ const float* iteration_prologue(const EvalArgs& a,
 // K = 2 Ising, one log-odds value per message: lambda = log(m(1) / m(0)).
 // Aggregate L_i = u_i + sum_k lambda_{k->i} with u_i = log psi_i(1) - log psi_i(0).
 // With H = (L_i - lambda_{k->i}) / 2 the outgoing message of Eq. (2) for
-// psi = exp(J s_i s_k) has m(1) - m(0) = tanh J tanh H (sum over x_i in closed
-// form; normalisation included).
+// psi = exp(J s_i s_k) has log-odds log cosh(J + H) - log cosh(J - H) (the sum
+// over x_i in closed form; normalisation included).
 // The slot e of m_{i->k} gives e as the output index, its own old value, and
 // lambda_{k->i} at rev[e].
 // ---------------------------------------------------------------------------
+// log(1 + e^{-2|x|}), in (0, log 2]: log2 is taken of a value in (1, 2].
+__device__ __forceinline__ float logcosh_tail(float x) {
+    return kLn2 * log2_hw(1.0f + exp2_hw(-2.0f * kLog2e * fabsf(x)));
+}
+
 // Eq. (2), Eq. (4) and the frontier rule for one slot; returns the residual.
-// With tJ = tanh J (stored per slot) and tau = tanh H, Eq. (2) gives the new
-// message's probability of state 1 directly, m(1) = (1 + tJ tau) / 2, and its
-// log-odds log((1 + tJ tau) / (1 - tJ tau)).  The log-odds loses relative
-// accuracy when tJ tau is near +-1, but only where sigma' = m(1) m(0) is as small,
-// so the message itself keeps an absolute error of a few FP32 ulps.
+// log cosh(J + H) - log cosh(J - H) is evaluated as
+// 2 sgn(J H) min(|J|, |H|) + tail(J + H) - tail(J - H): the identity
+// |J + H| - |J - H| = 2 sgn(J H) min(|J|, |H|) keeps it exact in the leading term
+// for any finite J and H (no cancellation of two large magnitudes, no overflow),
+// and the tails are bounded by log 2.
 template <int MODE>
-__device__ __forceinline__ float logodds_slot(const EvalArgs& a, float L, float lam_in, float tJ,
+__device__ __forceinline__ float logodds_slot(const EvalArgs& a, float L, float lam_in, float J,
                                               float lam_old, int e, int dst, int node,
                                               unsigned int& act, unsigned int& sa,
                                               unsigned int& sb) {
     const float H = 0.5f * (L - lam_in);
-    // tanh H = sign(H) (1 - e^{-2|H|}) / (1 + e^{-2|H|})
-    const float eh = exp2_hw(-2.0f * kLog2e * fabsf(H));
-    const float tau = copysignf((1.0f - eh) * rcp_hw(1.0f + eh), H);
-    const float x = tJ * tau;
-    const float p1 = 0.5f + 0.5f * x;   // m_new(1)
-    const float p0 = 0.5f - 0.5f * x;   // m_new(0)
-    const float lam_new = kLn2 * log2_hw(p1 * rcp_hw(p0));
-    const float r = fabsf(p1 - sigmoid_fast(lam_old));
+    const float lead = copysignf(2.0f * fminf(fabsf(J), fabsf(H)), J * H);
+    const float lam_new = lead + logcosh_tail(J + H) - logcosh_tail(J - H);
+    const float r = fabsf(sigmoid_fast(lam_new) - sigmoid_fast(lam_old));
     const bool active = r > a.eps;
     act += active;
     if (MODE == kModeLBP) {

@@ -131,6 +131,28 @@ def test_high_degree_node_single_sweep(bp):
         assert err.max() <= SWEEP_TOL, (K, err.max())
 
 
+@pytest.mark.parametrize("C", [12.0, 40.0])
+def test_strong_coupling_single_sweep_and_finite(bp, C):
+    # |J| up to 40: message log-odds reach 2|J| = 80 (m(0) ~ 1e-35).  FP32
+    # log-odds of magnitude up to Lam = 2 max|J| carry a rounding error of
+    # 2^-24 Lam each; the aggregate of a degree-4 node sums 5 such terms, which
+    # moves H by at most 2.5 * 2^-24 Lam and the message by half of that.
+    prob = inputs.ising_grid(23, 37, C, 7)
+    lam_max = 2.0 * np.max(np.abs(prob["coupling"]))
+    tol = SWEEP_TOL + 5 * 2.0 ** -24 * lam_max / 2
+    for t0 in (0, 5, 40):
+        ref = oracle.run(prob, oracle.LBP, eps=0.0, max_iters=t0)
+        err, _ = _one_sweep_parity(bp, prob, ref["msgs"].astype(np.float32))
+        assert err.max() <= tol, (t0, err.max(), tol)
+    with bp.Graph(prob) as g:
+        g.run("lbp", eps=0.0, max_iters=300)
+        m, _ = g.get_state()
+        b = g.marginals()
+    assert np.all(np.isfinite(m)) and np.all(m >= 0.0)
+    assert np.all(np.isfinite(b))
+    np.testing.assert_allclose(b.sum(1), 1.0, atol=1e-6)
+
+
 # ---------------------------------------------------------------------------
 # full runs: converged marginals on problems with a unique fixed point
 # ---------------------------------------------------------------------------
