@@ -143,8 +143,9 @@ typedef struct bp_graph_info {
     int32_t num_states;
     int64_t num_edges;
     int64_t num_messages;     /* E = 2M */
-    int32_t layout;           /* 0 = one log-odds value per message (K = 2 Ising),
-                                 1 = [E][K] probabilities */
+    int32_t layout;           /* 0 = one log-odds value per message (K = 2 Ising with
+                                 fewer than 2^30 - 512 messages and variables),
+                                 1 = [E][K] probabilities (everything else) */
     int32_t num_tiles;        /* node tiles of the evaluation kernel */
     uint64_t device_bytes;    /* device memory held by the graph */
 } bp_graph_info;

@@ -182,8 +182,13 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
     L.K = (int)K;
     L.M = M;
     L.E = 2 * M;
-    L.layout = (kind == BP_PAIR_ISING && !(d->flags & BP_FLAG_GENERIC_LAYOUT)) ? kLayoutLogOdds
-                                                                               : kLayoutGeneric;
+    // The log-odds kernel addresses its arrays with 32-bit byte offsets, so it
+    // takes graphs with fewer than 2^30 messages and nodes; larger K = 2 graphs
+    // use the [E][K] layout.
+    const bool small = 2 * M < (1ll << 30) - kTileSlotsLogOdds && N < (1ll << 30) - kTileSlotsLogOdds;
+    L.layout = (kind == BP_PAIR_ISING && !(d->flags & BP_FLAG_GENERIC_LAYOUT) && small)
+                   ? kLayoutLogOdds
+                   : kLayoutGeneric;
     L.row = L.layout == kLayoutLogOdds ? 1 : (int)K;
     const long long E = L.E;
     auto csrc = [&](long long c) { return d->edges[2 * (c >> 1) + ((c & 1) ? 1 : 0)]; };
@@ -541,6 +546,7 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     a.ratio_threshold = o.ratio_threshold;
     a.prev_active_host = g->prev_active;
     a.num_messages = (unsigned long long)L.E;
+    a.num_nodes = L.N;
     a.rbp_k = (unsigned long long)rbp_k;
     a.sel0 = g->cur_sel;
     if (mode == kModeRnBP && o.dynamic_p) {
@@ -615,10 +621,10 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
             const int all = rbp_k >= L.E;
             HIP_OK(launch_rbp_gate(g->st(), g->ctr(), (int)(t & 3), s), "top-k gate");
             if (!all)
-                HIP_OK(launch_rbp_select(g->st(), a.keys, (int)L.E, (unsigned int)rbp_k,
+                HIP_OK(launch_rbp_select(g->st(), a.keys, a.rev, (int)L.E, (unsigned int)rbp_k,
                                          (int)(t & 3), ties, s),
                        "top-k select");
-            HIP_OK(launch_rbp_commit(g->st(), a.keys, a.cand, start_buf, (int)L.E, L.row, all,
+            HIP_OK(launch_rbp_commit(g->st(), a.keys, a.rev, a.cand, start_buf, (int)L.E, L.row, all,
                                      (int)(t & 3), ties, s),
                    "top-k commit");
         }

@@ -106,6 +106,7 @@ struct EvalArgs {
     double ratio_threshold;
     long long prev_active_host; // n_{t-1} from the iteration state (second launch)
     unsigned long long num_messages;
+    int num_nodes;
     unsigned long long rbp_k;   // RBP frontier size
 };
 
@@ -120,10 +121,11 @@ hipError_t launch_marginals(int layout, int kp, const int* node_ptr, const int* 
                             hipStream_t s);
 // frontier residual BP selection
 hipError_t launch_rbp_gate(DevState* st, const CounterLine* ctr, int slot_idx, hipStream_t s);
-hipError_t launch_rbp_select(DevState* st, const unsigned int* keys, int E, unsigned int k,
-                             int slot_idx, unsigned int* block_ties, hipStream_t s);
-hipError_t launch_rbp_commit(DevState* st, const unsigned int* keys, const float* cand,
-                             float* m, int E, int row, int all, int slot_idx,
+hipError_t launch_rbp_select(DevState* st, const unsigned int* keys, const int* rev, int E,
+                             unsigned int k, int slot_idx, unsigned int* block_ties,
+                             hipStream_t s);
+hipError_t launch_rbp_commit(DevState* st, const unsigned int* keys, const int* rev,
+                             const float* cand, float* m, int E, int row, int all, int slot_idx,
                              const unsigned int* block_ties, hipStream_t s);
 
 }  // namespace bp

@@ -265,16 +265,57 @@ __device__ __forceinline__ float logcosh_tail(float x) {
     return kLn2 * log2_hw(1.0f + exp2_hw(-2.0f * kLog2e * fabsf(x)));
 }
 
+// Array access with a 32-bit byte offset from a wave-uniform base: the
+// compiler emits the global_load/store form that adds a 32-bit VGPR offset to a
+// 64-bit SGPR base, so per-lane accesses need no 64-bit address arithmetic.
+// Every array the K = 2 kernel touches holds fewer than 2^30 four-byte elements
+// (checked at graph creation).
+template <class T>
+__device__ __forceinline__ T ld32(const T* base, int i) {
+    return *(const T*)((const char*)base + (unsigned int)i * 4u);
+}
+template <class T>
+__device__ __forceinline__ void st32(T* base, int i, T v) {
+    *(T*)((char*)base + (unsigned int)i * 4u) = v;
+}
+// A pointer the compiler cannot prove uniform (chosen from LDS data), made uniform.
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)v);
+    const unsigned int hi = __builtin_amdgcn_readfirstlane((unsigned int)(v >> 32));
+    return (T*)(((unsigned long long)hi << 32) | lo);
+}
+
+// Where one slot's results go: plain pointers, or buffer resources.
+struct OutPtr {
+    const EvalArgs& a;
+    __device__ void out0(int e, float v) const { a.out_buf[0][e] = v; }
+    __device__ void out1(int e, float v) const { a.out_buf[1][e] = v; }
+    __device__ void cand(int e, float v) const { a.cand[e] = v; }
+    __device__ void key(int e, float r) const { a.keys[e] = __float_as_uint(r); }
+};
+struct OutOff {
+    float* o0;
+    float* o1;
+    float* c;
+    unsigned int* k;
+    __device__ void out0(int e, float v) const { st32(o0, e, v); }
+    __device__ void out1(int e, float v) const { st32(o1, e, v); }
+    __device__ void cand(int e, float v) const { st32(c, e, v); }
+    __device__ void key(int e, float r) const { st32(k, e, __float_as_uint(r)); }
+};
+
 // Eq. (2), Eq. (4) and the frontier rule for one slot; returns the residual.
 // log cosh(J + H) - log cosh(J - H) is evaluated as
 // 2 sgn(J H) min(|J|, |H|) + tail(J + H) - tail(J - H): the identity
 // |J + H| - |J - H| = 2 sgn(J H) min(|J|, |H|) keeps it exact in the leading term
 // for any finite J and H (no cancellation of two large magnitudes, no overflow),
 // and the tails are bounded by log 2.
-template <int MODE>
-__device__ __forceinline__ float logodds_slot(const EvalArgs& a, float L, float lam_in, float J,
-                                              float lam_old, int e, int dst, int node,
-                                              unsigned int& act, unsigned int& sa,
+template <int MODE, class Out>
+__device__ __forceinline__ float logodds_slot(const EvalArgs& a, const Out& out, float L,
+                                              float lam_in, float J, float lam_old, int e, int dst,
+                                              int node, unsigned int& act, unsigned int& sa,
                                               unsigned int& sb) {
     const float H = 0.5f * (L - lam_in);
     const float lead = copysignf(2.0f * fminf(fabsf(J), fabsf(H)), J * H);
@@ -283,7 +324,7 @@ __device__ __forceinline__ float logodds_slot(const EvalArgs& a, float L, float 
     const bool active = r > a.eps;
     act += active;
     if (MODE == kModeLBP) {
-        a.out_buf[0][e] = lam_new;
+        out.out0(e, lam_new);
     } else if (MODE == kModeRnBP) {
         bool ka = false, kb = false;
         if (active) {
@@ -294,11 +335,11 @@ __device__ __forceinline__ float logodds_slot(const EvalArgs& a, float L, float 
         }
         sa += ka;
         sb += kb;
-        a.out_buf[0][e] = ka ? lam_new : lam_old;
-        if (a.two_outputs) a.out_buf[1][e] = kb ? lam_new : lam_old;
+        out.out0(e, ka ? lam_new : lam_old);
+        if (a.two_outputs) out.out1(e, kb ? lam_new : lam_old);
     } else if (MODE == kModeRBP) {
-        a.cand[e] = lam_new;
-        a.keys[e] = __float_as_uint(r);
+        out.cand(e, lam_new);
+        out.key(e, r);
     }
     return r;
 }
@@ -331,17 +372,17 @@ __device__ __forceinline__ void tile_load(TileRegs& d, const EvalArgs& a, const 
 #pragma unroll
     for (int j = 0; j < kPJ; ++j) {
         const int v = tid + j * kBlock;
-        d.ptr[j] = a.node_ptr[d.n0 + min(v, d.nn)];
-        d.u[j] = a.unary[d.n0 + min(v, d.nn - 1)];
+        d.ptr[j] = ld32(a.node_ptr, d.n0 + min(v, d.nn));
+        d.u[j] = ld32(a.unary, d.n0 + min(v, d.nn - 1));
     }
     if (d.ns > 0) {
 #pragma unroll
         for (int k = 0; k < kPP; ++k) {
             const int s = d.s0 + min(tid + k * kBlock, d.ns - 1);
-            d.old[k] = m_in[s];
-            d.rev[k] = a.rev[s];
-            d.J[k] = a.coupling[s];
-            d.dst[k] = MODE == kModeRnBP ? a.dst[s] : 0;
+            d.old[k] = ld32(m_in, s);
+            d.rev[k] = ld32(a.rev, s);
+            d.J[k] = ld32(a.coupling, s);
+            d.dst[k] = MODE == kModeRnBP ? ld32(a.dst, s) : 0;
         }
     }
 }
@@ -374,8 +415,10 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
     const int t0 = block_tile(a, 0), t1 = block_tile(a, 1);
     int4 bcur = t0 >= 0 ? tiles[t0] : make_int4(0, 0, 0, 0);
     int4 bnext = t1 >= 0 ? tiles[t1] : make_int4(0, 0, 0, 0);
-    const float* __restrict__ m_in = iteration_prologue(a, s_red);
-    if (!m_in) return;
+    const float* m_sel = iteration_prologue(a, s_red);
+    if (!m_sel) return;
+    const float* __restrict__ m_in = uniform_ptr(m_sel);
+    const OutOff out{a.out_buf[0], a.out_buf[1], a.cand, a.keys};
     const int tid = threadIdx.x;
     float rmax = 0.0f;
     unsigned int act = 0, sa = 0, sb = 0;
@@ -390,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
         tile_load<MODE>(cur, a, m_in, bcur);
         if (cur.ns > 0) {
 #pragma unroll
-            for (int k = 0; k < kPP; ++k) lin[k] = m_in[cur.rev[k]];
+            for (int k = 0; k < kPP; ++k) lin[k] = ld32(m_in, cur.rev[k]);
         }
         // stage tile 0
 #pragma unroll
@@ -424,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
             float lin_n[kPP];
             if (has_next && nxt.ns > 0) {
 #pragma unroll
-                for (int k = 0; k < kPP; ++k) lin_n[k] = m_in[nxt.rev[k]];
+                for (int k = 0; k < kPP; ++k) lin_n[k] = ld32(m_in, nxt.rev[k]);
             }
             // outgoing messages of tile j, written at their own slots
 #pragma unroll
@@ -432,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
                 const int q = tid + k * kBlock;
                 if (q < cur.ns) {
                     const int v = s_owner[q];
-                    const float r = logodds_slot<MODE>(a, s_L[v], lin[k], cur.J[k], cur.old[k],
+                    const float r = logodds_slot<MODE>(a, out, s_L[v], lin[k], cur.J[k], cur.old[k],
                                                        cur.s0 + q, cur.dst[k], cur.n0 + v, act, sa,
                                                        sb);
                     rmax = fmaxf(rmax, r);
@@ -487,7 +530,8 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds_big(EvalArgs a) {
     for (int q = tid; q < ns; q += kBlock) {
         const int s = s0 + q;
         const int dst = MODE == kModeRnBP ? a.dst[s] : 0;
-        const float r = logodds_slot<MODE>(a, L, m_in[a.rev[s]], a.coupling[s], m_in[s], s, dst, n0,
+        const float r = logodds_slot<MODE>(a, OutPtr{a}, L, m_in[a.rev[s]], a.coupling[s], m_in[s], s,
+                                           dst, n0,
                                            act, sa, sb);
         rmax = fmaxf(rmax, r);
     }
@@ -798,8 +842,12 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_scan(DevState* st, int pass, 
     }
 }
 
+// Ties at the threshold key are taken in (target, source) order.  Slots are
+// ordered by (source, target), so position p visits the message in slot rev[p],
+// whose (target, source) is the (source, target) of slot p: walking positions
+// in order walks tied messages in (target, source) order.
 __global__ __launch_bounds__(kSelBlock) void k_rbp_tiecount(DevState* st, const unsigned int* keys,
-                                                            int E, int slot,
+                                                            const int* rev, int E, int slot,
                                                             unsigned int* block_ties) {
     __shared__ unsigned int part[kSelBlock / 64];
     if (st->rbp_skip || !st->sel_rank_ties) return;
@@ -807,7 +855,7 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_tiecount(DevState* st, const 
     const int beg = blockIdx.x * kCommitChunk;
     const int end = min(E, beg + kCommitChunk);
     unsigned int c = 0;
-    for (int e = beg + threadIdx.x; e < end; e += kSelBlock) c += keys[e] == T;
+    for (int q = beg + threadIdx.x; q < end; q += kSelBlock) c += keys[rev[q]] == T;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
@@ -833,8 +881,9 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_tiescan(DevState* st, int slo
 }
 
 __global__ __launch_bounds__(kSelBlock) void k_rbp_commit(DevState* st, const unsigned int* keys,
-                                                          const float* cand, float* m, int E,
-                                                          int row, int all, int slot,
+                                                          const int* rev, const float* cand,
+                                                          float* m, int E, int row, int all,
+                                                          int slot,
                                                           const unsigned int* block_ties) {
     __shared__ unsigned int wsum[kSelBlock / 64];
     if (st->rbp_skip) return;
@@ -845,9 +894,11 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_commit(DevState* st, const un
     const unsigned int krem = st->sel_krem;
     unsigned int offset = rank ? block_ties[blockIdx.x] : 0u;
     for (int base = beg; base < end; base += kSelBlock) {
-        const int e = base + threadIdx.x;
+        const int q = base + threadIdx.x;
+        // with ranked ties, position q holds the message in slot rev[q]
+        const int e = (rank && q < end) ? rev[q] : q;
         bool take = false, tie = false;
-        if (e < end) {
+        if (q < end) {
             if (all) {
                 take = true;
             } else {
@@ -985,8 +1036,9 @@ hipError_t launch_rbp_gate(DevState* st, const CounterLine* ctr, int slot_idx, h
     return hipGetLastError();
 }
 
-hipError_t launch_rbp_select(DevState* st, const unsigned int* keys, int E, unsigned int k,
-                             int slot_idx, unsigned int* block_ties, hipStream_t s) {
+hipError_t launch_rbp_select(DevState* st, const unsigned int* keys, const int* rev, int E,
+                             unsigned int k, int slot_idx, unsigned int* block_ties,
+                             hipStream_t s) {
     int grid = (E + kSelBlock * 16 - 1) / (kSelBlock * 16);
     if (grid < 1) grid = 1;
     if (grid > 4096) grid = 4096;
@@ -995,17 +1047,18 @@ hipError_t launch_rbp_select(DevState* st, const unsigned int* keys, int E, unsi
         k_rbp_scan<<<1, kSelBlock, 0, s>>>(st, pass, k, slot_idx);
     }
     const int nb = (E + kCommitChunk - 1) / kCommitChunk;
-    k_rbp_tiecount<<<nb > 0 ? nb : 1, kSelBlock, 0, s>>>(st, keys, E, slot_idx, block_ties);
+    k_rbp_tiecount<<<nb > 0 ? nb : 1, kSelBlock, 0, s>>>(st, keys, rev, E, slot_idx, block_ties);
     k_rbp_tiescan<<<1, kSelBlock, 0, s>>>(st, slot_idx, block_ties, nb);
     return hipGetLastError();
 }
 
-hipError_t launch_rbp_commit(DevState* st, const unsigned int* keys, const float* cand, float* m,
-                             int E, int row, int all, int slot_idx,
+hipError_t launch_rbp_commit(DevState* st, const unsigned int* keys, const int* rev,
+                             const float* cand, float* m, int E, int row, int all, int slot_idx,
                              const unsigned int* block_ties, hipStream_t s) {
     const int nb = (E + kCommitChunk - 1) / kCommitChunk;
     if (nb <= 0) return hipSuccess;
-    k_rbp_commit<<<nb, kSelBlock, 0, s>>>(st, keys, cand, m, E, row, all, slot_idx, block_ties);
+    k_rbp_commit<<<nb, kSelBlock, 0, s>>>(st, keys, rev, cand, m, E, row, all, slot_idx,
+                                          block_ties);
     return hipGetLastError();
 }
 

@@ -281,6 +281,31 @@ def test_rbp_frontier_one_iteration(bp, p):
     assert changed.sum() == k and r["committed"] == k
 
 
+@pytest.mark.parametrize("p", [0.05, 0.3, 0.77])
+def test_rbp_exact_ties_taken_in_target_source_order(bp, p):
+    # equal fields and couplings: from uniform messages every residual is
+    # bitwise the same (on both sides), so the whole top-k is decided by the
+    # tie order, (target, source) ascending
+    H, W = 6, 7
+    edges = inputs.grid_edges(H, W)
+    N = H * W
+    prob = dict(N=N, K=2, edges=edges, log_unary=np.tile([-0.5, 0.5], (N, 1)),
+                pair_kind=inputs.PAIR_ISING, coupling=np.full(len(edges), 0.3))
+    E = 2 * len(edges)
+    state = np.full((E, 2), 0.5, dtype=np.float32)
+    start, got, changed, r, _ = _one_iteration(bp, prob, state, "rbp", p, eps=1e-9)
+    _, res = oracle.evaluate(prob, start.astype(np.float64))
+    assert np.all(res == res[0]) and res[0] > 0
+    src, dst = oracle.canonical_src_dst(prob)
+    k = max(1, int(np.ceil(p * E)))
+    order = sorted(range(E), key=lambda e: (dst[e], src[e]))
+    want = np.zeros(E, bool)
+    want[order[:k]] = True
+    assert np.array_equal(changed, want)
+    ref = oracle.run(prob, oracle.RBP, eps=1e-9, p=p, max_iters=1, init_msgs=start)
+    assert np.array_equal(ref["msgs"] != start, np.repeat(want[:, None], 2, 1))
+
+
 def test_rbp_full_fraction_bitwise_equals_lbp(bp):
     prob = inputs.ising_grid(25, 25, 2.5, 8)
     outs = []
