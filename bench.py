@@ -32,10 +32,9 @@ def eval_kernel_bytes(N, E, two_outputs=True):
     """Algorithmic bytes of one launch of the K = 2 evaluation kernel, each
     array element moved once: per directed message the in-slot log-odds (4),
     the reverse index (4), the coupling (4) and the committed value (4), and in
-    RnBP mode the target id for the RNG counter (4) and the committed value
-    under the second keep threshold (4); per node the slot offset (4) and the
-    unary log-odds (4)."""
-    return (24 if two_outputs else 16) * E + 8 * N
+    RnBP mode the committed value under the second keep threshold (4); per node
+    the slot offset (4) and the unary log-odds (4)."""
+    return (20 if two_outputs else 16) * E + 8 * N
 
 
 def counter_traffic(path, kernel_src):

@@ -25,10 +25,13 @@
  *   - Canonical message order (used by bp_get_state / bp_set_state): for the
  *     undirected edge u = edges[u] = (a, b), row 2u is the message a -> b and
  *     row 2u + 1 is b -> a.
- *   - Random filter: U = (w >> 8) * 2^-24 where w is word 0 of
- *     Philox4x32-10 (Salmon et al., SC'11) with key (seed & 0xffffffff,
- *     seed >> 32) and counter (source node, target node, t, 0); a message is
- *     kept when U < p_t.  Results do not depend on the storage order.
+ *   - Random filter: for the message i -> j, where j is the neighbour of rank r
+ *     of i (the neighbours of i in ascending id order, r = 0, 1, ...),
+ *     U = (w >> 8) * 2^-24 where w is word r mod 4 of Philox4x32-10 (Salmon et
+ *     al., SC'11) with key (seed & 0xffffffff, seed >> 32) and counter
+ *     (i, r div 4, t, 0); a message is kept when U < p_t.  One Philox call
+ *     serves four messages of a source.  Results do not depend on the storage
+ *     order.
  *   - Messages are FP32 on the device; parameters are given in FP64 and
  *     rounded to FP32 when the graph is created.
  *   - Same inputs on the same device give bitwise identical results.

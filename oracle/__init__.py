@@ -116,9 +116,22 @@ def philox4x32_10(ctr, key, lib=None):
     return out
 
 
-def uniform(seed, src, dst, t, lib=None):
-    """U(seed, src, dst, t) in [0, 1) of the random frontier filter."""
-    return _load(lib).oracle_uniform(int(seed), int(src), int(dst), int(t))
+def uniform(seed, src, rank, t, lib=None):
+    """U in [0, 1) of the random frontier filter for the message src -> j at
+    iteration t, where j is the neighbour of rank `rank` of src (neighbours in
+    ascending id order)."""
+    return _load(lib).oracle_uniform(int(seed), int(src), int(rank), int(t))
+
+
+def neighbour_rank(problem):
+    """Rank of the target among the source's neighbours (ascending ids) for
+    every canonical message id."""
+    src, dst = canonical_src_dst(problem)
+    order = np.lexsort((dst, src))
+    rank = np.empty(len(src), np.int64)
+    first = np.searchsorted(src[order], src[order], side="left")
+    rank[order] = np.arange(len(src)) - first
+    return rank
 
 
 def run(problem, schedule=LBP, eps=1e-4, p=1.0, high_p=1.0, ratio_threshold=0.9,

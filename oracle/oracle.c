@@ -74,15 +74,17 @@ void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* Uniform draw for the random filter of Sec. IV-A: key = seed split into two
- * 32-bit words, counter = (source node, target node, iteration, 0); the top
- * 24 bits of output word 0 give U in [0, 1). */
-double oracle_uniform(uint64_t seed, uint32_t src, uint32_t dst, uint32_t t) {
-    uint32_t ctr[4] = {src, dst, t, 0u};
+/* Uniform draw for the random filter of Sec. IV-A.  The message i -> j, where j
+ * is the neighbour of rank r of i (neighbours of i in ascending id order,
+ * r = 0, 1, ...), takes word r mod 4 of Philox4x32-10 with key = seed split into
+ * two 32-bit words and counter = (i, r div 4, t, 0); the top 24 bits of that
+ * word give U in [0, 1).  One call serves four messages of one source. */
+double oracle_uniform(uint64_t seed, uint32_t src, uint32_t rank, uint32_t t) {
+    uint32_t ctr[4] = {src, rank / 4u, t, 0u};
     uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
     uint32_t out[4];
     oracle_philox4x32_10(ctr, key, out);
-    return (double)(out[0] >> 8) * (1.0 / 16777216.0);
+    return (double)(out[rank % 4u] >> 8) * (1.0 / 16777216.0);
 }
 
 /* ------------------------------------------------------------------ */
@@ -100,6 +102,7 @@ typedef struct {
     const double* pair;        /* [M][K][K] */
     int64_t* in_ptr;           /* [N+1]: incoming message ids grouped by target */
     int64_t* in_ids;           /* [E] */
+    int32_t* rank;             /* [E]: rank of the target among the source's neighbours */
 } model_t;
 
 static int msg_src(const model_t* g, int64_t e) {
@@ -157,6 +160,20 @@ static int build_model(model_t* g, int N, int K, int64_t M, const int32_t* edges
     memcpy(fill, g->in_ptr, sizeof(int64_t) * ((size_t)N + 1));
     for (int64_t e = 0; e < g->E; ++e) g->in_ids[fill[msg_dst(g, e)]++] = e;
     free(fill);
+    /* rank of j among the neighbours of i for every message i -> j: the
+     * incoming list of i holds the messages k -> i, one per neighbour k, and the
+     * message i -> k is the other direction (id ^ 1) of the same edge */
+    g->rank = (int32_t*)malloc(sizeof(int32_t) * (size_t)g->E + 1);
+    if (!g->rank) return -2;
+    for (int i = 0; i < N; ++i) {
+        for (int64_t a = g->in_ptr[i]; a < g->in_ptr[i + 1]; ++a) {
+            int k = msg_src(g, g->in_ids[a]);
+            int32_t r = 0;
+            for (int64_t b = g->in_ptr[i]; b < g->in_ptr[i + 1]; ++b)
+                if (msg_src(g, g->in_ids[b]) < k) ++r;
+            g->rank[g->in_ids[a] ^ 1] = r;
+        }
+    }
     return 0;
 }
 
@@ -164,6 +181,7 @@ static void free_model(model_t* g) {
     free(g->unary);
     free(g->in_ptr);
     free(g->in_ids);
+    free(g->rank);
 }
 
 /* A product of many factors below 1 leaves the double range once a node has a
@@ -366,7 +384,7 @@ int oracle_bp_run(int N, int K, int64_t M, const int32_t* edges, const double* l
             for (int64_t e = 0; e < E; ++e) {
                 if (!(res[e] > eps)) continue;
                 double u = oracle_uniform(seed, (uint32_t)msg_src(&g, e),
-                                          (uint32_t)msg_dst(&g, e), (uint32_t)t);
+                                          (uint32_t)g.rank[e], (uint32_t)t);
                 if (u < p_t) {
                     sel[e] = 1;
                     ++nsel;

@@ -67,7 +67,6 @@ struct HostLayout {
     int N = 0, K = 0, layout = 0, pair = 0, row = 1;
     long long M = 0, E = 0;
     std::vector<int> node_ptr;        // [N+1] slot range of each source node
-    std::vector<int> dst;             // [E] target node of the slot's message
     std::vector<int> rev;             // [E]
     std::vector<int> slot_of_canon;   // [E]
     std::vector<int> tile_start;      // [T+1]
@@ -90,7 +89,7 @@ struct Arena {
 };
 
 struct Offsets {
-    size_t node_ptr, dst, rev, tile, tile_slot, tiles4, big4, coupling, unary, pair, orient, msg[4], cand, keys, ties, state,
+    size_t node_ptr, rev, tile, tile_slot, tiles4, big4, coupling, unary, pair, orient, msg[4], cand, keys, ties, state,
         ctr, marg, total;
 };
 
@@ -99,7 +98,6 @@ Offsets plan(const HostLayout& L) {
     Offsets o;
     const size_t E = (size_t)L.E;
     o.node_ptr = a.take(sizeof(int) * (L.N + 1));
-    o.dst = a.take(sizeof(int) * E);
     o.rev = a.take(sizeof(int) * E);
     o.tile = a.take(sizeof(int) * L.tile_start.size());
     o.tile_slot = a.take(sizeof(int) * L.tile_slot.size());
@@ -211,13 +209,8 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
                   [&](int x, int y) { return cdst(x) < cdst(y); });
     L.slot_of_canon.assign((size_t)E, 0);
     for (long long s = 0; s < E; ++s) L.slot_of_canon[canon_of_slot[s]] = (int)s;
-    L.dst.resize((size_t)E);
     L.rev.resize((size_t)E);
-    for (long long s = 0; s < E; ++s) {
-        const int c = canon_of_slot[s];
-        L.dst[s] = cdst(c);
-        L.rev[s] = L.slot_of_canon[c ^ 1];
-    }
+    for (long long s = 0; s < E; ++s) L.rev[s] = L.slot_of_canon[canon_of_slot[s] ^ 1];
 
     // unary: K = 2 log-odds, or log psi shifted so its max per node is 0
     if (L.layout == kLayoutLogOdds) {
@@ -406,7 +399,6 @@ int bp_create_graph(const bp_graph_desc* desc, bp_graph** out) {
         up(g->off.tiles4, L.tiles4.data(), sizeof(int) * L.tiles4.size()),
         up(g->off.big4, L.big4.data(), sizeof(int) * L.big4.size()),
         up(g->off.node_ptr, L.node_ptr.data(), sizeof(int) * L.node_ptr.size()),
-        up(g->off.dst, L.dst.data(), sizeof(int) * L.dst.size()),
         up(g->off.rev, L.rev.data(), sizeof(int) * L.rev.size()),
         up(g->off.tile, L.tile_start.data(), sizeof(int) * L.tile_start.size()),
         up(g->off.coupling, L.coupling.data(), sizeof(float) * L.coupling.size()),
@@ -524,7 +516,6 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     }
     a.node_ptr = g->at<int>(g->off.node_ptr);
     a.rev = g->at<int>(g->off.rev);
-    a.dst = g->at<int>(g->off.dst);
     a.coupling = g->at<float>(g->off.coupling);
     a.unary = g->at<float>(g->off.unary);
     a.pair = g->at<float>(g->off.pair);

@@ -78,7 +78,6 @@ struct EvalArgs {
     int pipe_grid;              // blocks of the persistent log-odds kernel (multiple of 8)
     const int* node_ptr;        // [N+1] slot range of each source node
     const int* rev;             // [E] slot of the reverse message
-    const int* dst;             // [E] target node of the message in each slot
     const float* coupling;      // [E] Ising J per slot
     const float* unary;         // log-odds [N] (K = 2 log-odds layout) or log psi [N][K]
     const float* pair;          // shared [K][K] or dense [E][K][K]

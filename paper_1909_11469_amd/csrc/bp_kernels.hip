@@ -32,11 +32,14 @@ namespace bp {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), output word 0 only.
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The random filter of
+// Sec. IV-A for the message i -> j, j the neighbour of rank r of i (slots of a
+// source are ordered by target, so r is the slot's offset in the source's
+// range), uses word r mod 4 of the output for counter (i, r div 4, t, 0): one
+// call serves four messages of one source.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned int philox_word0(unsigned int c0, unsigned int c1,
-                                                     unsigned int c2, unsigned int k0,
-                                                     unsigned int k1) {
+__device__ __forceinline__ uint4 philox4(unsigned int c0, unsigned int c1, unsigned int c2,
+                                         unsigned int k0, unsigned int k1) {
     unsigned int c3 = 0u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
@@ -54,7 +57,15 @@ __device__ __forceinline__ unsigned int philox_word0(unsigned int c0, unsigned i
         c2 = n2;
         c3 = (unsigned int)p0;
     }
-    return c0;
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// The 24-bit uniform of the message of rank r of source i at iteration t.
+__device__ __forceinline__ unsigned int draw24(const EvalArgs& a, int i, int r) {
+    const uint4 w = philox4((unsigned int)i, (unsigned int)r >> 2, a.t, a.key0, a.key1);
+    const int k = r & 3;
+    const unsigned int x = k == 0 ? w.x : k == 1 ? w.y : k == 2 ? w.z : w.w;
+    return x >> 8;
 }
 
 // Hardware exp2 / log2 / reciprocal (v_exp_f32, v_log_f32, v_rcp_f32, about 1 ulp)
@@ -314,9 +325,9 @@ struct OutOff {
 // and the tails are bounded by log 2.
 template <int MODE, class Out>
 __device__ __forceinline__ float logodds_slot(const EvalArgs& a, const Out& out, float L,
-                                              float lam_in, float J, float lam_old, int e, int dst,
-                                              int node, unsigned int& act, unsigned int& sa,
-                                              unsigned int& sb) {
+                                              float lam_in, float J, float lam_old, int e,
+                                              unsigned int u24, unsigned int& act,
+                                              unsigned int& sa, unsigned int& sb) {
     const float H = 0.5f * (L - lam_in);
     const float lead = copysignf(2.0f * fminf(fabsf(J), fabsf(H)), J * H);
     const float lam_new = lead + logcosh_tail(J + H) - logcosh_tail(J - H);
@@ -328,8 +339,6 @@ __device__ __forceinline__ float logodds_slot(const EvalArgs& a, const Out& out,
     } else if (MODE == kModeRnBP) {
         bool ka = false, kb = false;
         if (active) {
-            const unsigned int u24 =
-                philox_word0((unsigned int)node, (unsigned int)dst, a.t, a.key0, a.key1) >> 8;
             ka = u24 < a.thr_a;
             kb = u24 < a.thr_b;
         }
@@ -348,7 +357,7 @@ constexpr int kPP = kTileSlotsLogOdds / kBlock;              // slots per thread
 constexpr int kPJ = (kTileNodesLogOdds + kBlock) / kBlock;    // node entries (TN + 1) per thread
 
 // The per-thread share of one tile: node bounds and unaries, and the slots'
-// own old values, reverse indices, couplings and target ids.
+// own old values, reverse indices and couplings.
 struct TileRegs {
     int n0, nn, s0, ns;
     int ptr[kPJ];
@@ -356,7 +365,6 @@ struct TileRegs {
     float old[kPP];
     int rev[kPP];
     float J[kPP];
-    int dst[kPP];
 };
 
 // Issue every load of a tile (indices clamped into the tile, so there is no
@@ -382,7 +390,6 @@ __device__ __forceinline__ void tile_load(TileRegs& d, const EvalArgs& a, const 
             d.old[k] = ld32(m_in, s);
             d.rev[k] = ld32(a.rev, s);
             d.J[k] = ld32(a.coupling, s);
-            d.dst[k] = MODE == kModeRnBP ? ld32(a.dst, s) : 0;
         }
     }
 }
@@ -406,6 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
     constexpr int TN = kTileNodesLogOdds;
     __shared__ float s_lam[TS];
     __shared__ unsigned short s_owner[TS];
+    __shared__ unsigned int s_u[MODE == kModeRnBP ? TS : 1];  // 24-bit uniforms of the slots
     __shared__ unsigned short s_ptr[TN + 1];
     __shared__ float s_L[TN];
     __shared__ RedScratch red;
@@ -453,7 +461,8 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
             const int4 bnext2 = t2 >= 0 ? tiles[t2] : make_int4(0, 0, 0, 0);
             if (has_next) tile_load<MODE>(nxt, a, m_in, bnext);
             lds_barrier();
-            // node aggregates of tile j, incoming messages in slot order
+            // node aggregates of tile j, incoming messages in slot order; for
+            // RnBP also the draws of the node's messages, four per Philox call
             for (int v = tid; v < cur.nn; v += kBlock) {
                 const int q0 = s_ptr[v], q1 = s_ptr[v + 1];
                 float L = s_L[v];
@@ -462,6 +471,16 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
                     s_owner[q] = (unsigned short)v;
                 }
                 s_L[v] = L;
+                if (MODE == kModeRnBP) {
+                    for (int q = q0; q < q1; q += 4) {
+                        const uint4 w = philox4((unsigned int)(cur.n0 + v), (unsigned int)(q - q0) >> 2,
+                                                a.t, a.key0, a.key1);
+                        s_u[q] = w.x >> 8;
+                        if (q + 1 < q1) s_u[q + 1] = w.y >> 8;
+                        if (q + 2 < q1) s_u[q + 2] = w.z >> 8;
+                        if (q + 3 < q1) s_u[q + 3] = w.w >> 8;
+                    }
+                }
             }
             lds_barrier();
             float lin_n[kPP];
@@ -475,9 +494,9 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
                 const int q = tid + k * kBlock;
                 if (q < cur.ns) {
                     const int v = s_owner[q];
+                    const unsigned int u24 = MODE == kModeRnBP ? s_u[q] : 0u;
                     const float r = logodds_slot<MODE>(a, out, s_L[v], lin[k], cur.J[k], cur.old[k],
-                                                       cur.s0 + q, cur.dst[k], cur.n0 + v, act, sa,
-                                                       sb);
+                                                       cur.s0 + q, u24, act, sa, sb);
                     rmax = fmaxf(rmax, r);
                 }
             }
@@ -529,10 +548,9 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds_big(EvalArgs a) {
     for (int i = 0; i < kBlock / 64; ++i) L += s_part[i];
     for (int q = tid; q < ns; q += kBlock) {
         const int s = s0 + q;
-        const int dst = MODE == kModeRnBP ? a.dst[s] : 0;
+        const unsigned int u24 = MODE == kModeRnBP ? draw24(a, n0, q) : 0u;
         const float r = logodds_slot<MODE>(a, OutPtr{a}, L, m_in[a.rev[s]], a.coupling[s], m_in[s], s,
-                                           dst, n0,
-                                           act, sa, sb);
+                                           u24, act, sa, sb);
         rmax = fmaxf(rmax, r);
     }
     block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
@@ -688,8 +706,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
         } else if (MODE == kModeRnBP) {
             bool ka = false, kb = false;
             if (active) {
-                const unsigned int u24 = philox_word0((unsigned int)node, (unsigned int)a.dst[s],
-                                                      a.t, a.key0, a.key1) >> 8;
+                const unsigned int u24 = draw24(a, node, s - a.node_ptr[node]);
                 ka = u24 < a.thr_a;
                 kb = u24 < a.thr_b;
             }

@@ -245,8 +245,9 @@ def test_rnbp_frontier_one_iteration(bp, dynamic_p, prev):
     start, got, changed, r, st = _one_iteration(bp, prob, state, "rnbp", p, seed, t, prev, eps,
                                                 dynamic_p)
     cand, res = oracle.evaluate(prob, start.astype(np.float64))
-    src, dst = oracle.canonical_src_dst(prob)
-    u = np.array([oracle.uniform(seed, src[e], dst[e], t) for e in range(E)])
+    src, _ = oracle.canonical_src_dst(prob)
+    rank = oracle.neighbour_rank(prob)
+    u = np.array([oracle.uniform(seed, src[e], rank[e], t) for e in range(E)])
     n_t = int((res > eps).sum())
     if not dynamic_p:
         p_t = p
@@ -447,8 +448,9 @@ def test_ising_1000_rnbp_iteration_full_size(bp):
     cand, res = oracle.evaluate(prob, start.astype(np.float64))
     rng = np.random.default_rng(0)
     sample = rng.choice(E, 20000, replace=False)
-    src, dst = oracle.canonical_src_dst(prob)
-    u = np.array([oracle.uniform(seed, src[e], dst[e], t) for e in sample])
+    src, _ = oracle.canonical_src_dst(prob)
+    rank = oracle.neighbour_rank(prob)
+    u = np.array([oracle.uniform(seed, src[e], rank[e], t) for e in sample])
     want = (res[sample] > eps) & (u < p)
     band = np.abs(res[sample] - eps) < BAND
     assert np.array_equal(changed[sample][~band], want[~band])

@@ -90,13 +90,16 @@ def pin_philox(lib):
 
 
 def pin_rnbp_definition(lib):
-    prob = inputs.ising_grid(5, 6, 2.0, 6)
+    # degrees above 4, so that both the block (r div 4) and the word (r mod 4)
+    # of the draw matter
+    prob = inputs.er_graph(40, 9.0, 1.0, 6)
     E = 2 * len(prob["edges"])
     m0 = _rand_state(E, 2, 2)
     cand, res = oracle.evaluate(prob, m0)  # reference build for the candidates
     src, dst = oracle.canonical_src_dst(prob)
+    rank = oracle.neighbour_rank(prob)
     eps, p, seed, t = 0.02, 0.35, 77, 13
-    u = np.array([oracle.uniform(seed, src[e], dst[e], t) for e in range(E)])
+    u = np.array([oracle.uniform(seed, src[e], rank[e], t) for e in range(E)])
     sel = (res > eps) & (u < p)
     r = oracle.run(prob, oracle.RNBP, eps=eps, p=p, dynamic_p=False, seed=seed, max_iters=1,
                    init_msgs=m0, t0=t, lib=lib)
@@ -158,11 +161,12 @@ MUTANTS = {
     "asynchronous_commit": ("            res[e] = r;\n",
                             "            res[e] = r;\n            if (schedule == OR_LBP) "
                             "for (int x = 0; x < K; ++x) m[e * K + x] = cand[e * K + x];\n"),
-    "rng_counter_src_dst_swapped": (
-        "double u = oracle_uniform(seed, (uint32_t)msg_src(&g, e),\n"
-        "                                          (uint32_t)msg_dst(&g, e), (uint32_t)t);",
-        "double u = oracle_uniform(seed, (uint32_t)msg_dst(&g, e),\n"
-        "                                          (uint32_t)msg_src(&g, e), (uint32_t)t);"),
+    "rng_counter_source_is_target": (
+        "double u = oracle_uniform(seed, (uint32_t)msg_src(&g, e),",
+        "double u = oracle_uniform(seed, (uint32_t)msg_dst(&g, e),"),
+    "rng_word_always_zero": ("return (double)(out[rank % 4u] >> 8)", "return (double)(out[0] >> 8)"),
+    "rng_block_dropped": ("uint32_t ctr[4] = {src, rank / 4u, t, 0u};", "uint32_t ctr[4] = {src, 0u, t, 0u};"),
+    "rank_descending": ("if (msg_src(g, g->in_ids[b]) < k) ++r;", "if (msg_src(g, g->in_ids[b]) > k) ++r;"),
     "edge_ratio_inverted": ("(double)n_t / (double)n_prev > ratio_threshold",
                             "(double)n_t / (double)n_prev < ratio_threshold"),
     "tie_break_descending_target": ("if (da != db) return da < db ? -1 : 1;",

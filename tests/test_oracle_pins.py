@@ -39,19 +39,34 @@ def test_philox_known_answers(ctr, key, out):
     assert [int(x) for x in got] == out
 
 
-def test_uniform_is_word0_top24_bits():
+def test_uniform_is_rank_word_top24_bits():
+    # message src -> (neighbour of rank r): word r mod 4 of counter (src, r div 4, t, 0)
     seed = 0x0123456789ABCDEF
-    for (s, d, t) in [(0, 1, 0), (5, 7, 3), (123456, 99, 4095)]:
-        w = oracle.philox4x32_10([s, d, t, 0], [seed & 0xFFFFFFFF, seed >> 32])
-        assert oracle.uniform(seed, s, d, t) == (int(w[0]) >> 8) / float(1 << 24)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for (s, r, t) in [(0, 0, 0), (5, 1, 3), (5, 3, 3), (123456, 6, 4095), (7, 13, 2)]:
+        w = oracle.philox4x32_10([s, r // 4, t, 0], key)
+        assert oracle.uniform(seed, s, r, t) == (int(w[r % 4]) >> 8) / float(1 << 24)
 
 
 def test_uniform_fraction_within_binomial_bound():
     n, p = 20000, 0.3
-    u = np.array([oracle.uniform(7, i, i + 1, 11) for i in range(n)])
+    u = np.array([oracle.uniform(7, i // 8, i % 8, 11) for i in range(n)])
     assert u.min() >= 0.0 and u.max() < 1.0
     frac = np.mean(u < p)
     assert abs(frac - p) < 5 * np.sqrt(p * (1 - p) / n)
+    # the four words of one call are not correlated with one another
+    w = u.reshape(-1, 4)
+    c = np.corrcoef(w.T)
+    assert np.max(np.abs(c - np.eye(4))) < 5 / np.sqrt(len(w))
+
+
+def test_neighbour_rank_brute_force():
+    prob = inputs.er_graph(60, 9.0, 1.0, 3)
+    src, dst = oracle.canonical_src_dst(prob)
+    rank = oracle.neighbour_rank(prob)
+    for e in range(len(src)):
+        nb = sorted(dst[src == src[e]])
+        assert rank[e] == nb.index(dst[e])
 
 
 # --------------------------------------------------------------------------
@@ -338,15 +353,19 @@ def test_rbp_tie_break_by_target_then_source():
         assert sorted(changed.tolist()) == sorted(order[:k])
 
 
-def test_rnbp_frontier_against_definition():
-    prob = inputs.ising_grid(7, 8, 2.0, 6)
+@pytest.mark.parametrize("which", ["grid", "er"])
+def test_rnbp_frontier_against_definition(which):
+    # the ER graph has nodes of degree above 4 (more than one draw per source)
+    prob = inputs.ising_grid(7, 8, 2.0, 6) if which == "grid" else inputs.er_graph(80, 9.0, 1.0, 4)
+    assert which == "grid" or np.bincount(np.asarray(prob["edges"]).ravel()).max() > 8
     rng = np.random.default_rng(2)
     E = 2 * len(prob["edges"])
     m0 = _random_state(E, 2, rng)
     cand, res = oracle.evaluate(prob, m0)
     src, dst = oracle.canonical_src_dst(prob)
+    rank = oracle.neighbour_rank(prob)
     eps, p, seed, t = 0.02, 0.35, 77, 13
-    u = np.array([oracle.uniform(seed, src[e], dst[e], t) for e in range(E)])
+    u = np.array([oracle.uniform(seed, src[e], rank[e], t) for e in range(E)])
     sel = (res > eps) & (u < p)
     r = oracle.run(prob, oracle.RNBP, eps=eps, p=p, dynamic_p=False, seed=seed, max_iters=1,
                    init_msgs=m0, t0=t)
