@@ -98,7 +98,7 @@ Offsets plan(const HostLayout& L) {
     Offsets o;
     const size_t E = (size_t)L.E;
     o.node_ptr = a.take(sizeof(int) * (L.N + 1));
-    o.rev = a.take(sizeof(int) * E);
+    o.rev = a.take(sizeof(int) * L.rev.size());
     o.tile = a.take(sizeof(int) * L.tile_start.size());
     o.tile_slot = a.take(sizeof(int) * L.tile_slot.size());
     o.tiles4 = a.take(sizeof(int) * L.tiles4.size());
@@ -211,6 +211,8 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
     for (long long s = 0; s < E; ++s) L.slot_of_canon[canon_of_slot[s]] = (int)s;
     L.rev.resize((size_t)E);
     for (long long s = 0; s < E; ++s) L.rev[s] = L.slot_of_canon[canon_of_slot[s] ^ 1];
+    // the K = 2 kernel reads slot 0 of a tile without slots: keep one valid entry
+    if (E == 0) L.rev.assign(1, 0);
 
     // unary: K = 2 log-odds, or log psi shifted so its max per node is 0
     if (L.layout == kLayoutLogOdds) {
@@ -232,7 +234,7 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
     // i = a, k = b (the table as given); c odd means i = b, so it is transposed.
     if (kind == BP_PAIR_ISING) {
         L.pair = kPairIsing;
-        L.coupling.resize((size_t)E);
+        L.coupling.resize((size_t)std::max(E, 1ll));  // one entry for a graph without edges
         for (long long s = 0; s < E; ++s) L.coupling[s] = (float)d->coupling[canon_of_slot[s] >> 1];
     } else if (kind == BP_PAIR_SHARED) {
         bool sym = true;
@@ -290,6 +292,9 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
         std::vector<int>& dstv = (q[3] - q[2] > slot_lim) ? L.big4 : L.tiles4;
         dstv.insert(dstv.end(), q, q + 4);
     }
+    // The regular-tile kernel also runs the iteration bookkeeping, so it must
+    // launch even when every node is oversized: give it one empty tile.
+    if (L.tiles4.empty()) L.tiles4.insert(L.tiles4.end(), {0, 0, 0, 0});
     return BP_OK;
 }
 

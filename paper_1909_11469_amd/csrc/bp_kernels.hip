@@ -167,33 +167,43 @@ __device__ __forceinline__ int select_outcome(const EvalArgs& a, unsigned long l
     return (p_low == (a.low_is_a != 0)) ? 0 : 1;
 }
 
-// Run by the 64 lanes of one wave: sum the counter copies of iteration t - 1
-// (and t - 2), and, when `close` is set, record iteration t - 1 (IsConverged,
-// statistics, the buffer p_{t-1} selects) and clear the copies of t + 1.  The
-// statistics are updated with stores and no-return atomics, so nothing waits.
-// Returns n_{t-1} and n_{t-2} (the host's value when t - 2 precedes the run).
-__device__ void wave_close(const EvalArgs& a, bool close, unsigned long long& n1_out,
-                           long long& n2_out) {
+// The counter lines the prologue needs, loaded by the 64 lanes of one wave
+// (lane c reads copy c): n of iterations t - 1 and t - 2, and for the block that
+// closes iteration t - 1 also its frontier sizes and max residual.
+struct CtrLoad {
+    unsigned long long n1, n2, sa, sb;
+    unsigned int rm, done;
+};
+
+__device__ __forceinline__ void ctr_load(const EvalArgs& a, bool lead, CtrLoad& c) {
     const int lane = threadIdx.x & 63;
     const CounterLine* c1 = a.ctr + ((a.t - 1u) & 3u) * kCounterCopies + lane;
-    unsigned long long n1 = c1->active;
-    unsigned long long n2 = a.it >= 2 ? a.ctr[((a.t - 2u) & 3u) * kCounterCopies + lane].active : 0ull;
-    unsigned long long sa = 0, sb = 0;
-    unsigned int rm = 0;
-    if (close) {
-        sa = c1->sel_a;
-        sb = c1->sel_b;
-        rm = c1->rmax;
-    }
-    n1 = wave_sum64(n1);
-    n2 = wave_sum64(n2);
+    c.done = a.st->done;
+    c.n1 = c1->active;
+    c.n2 = a.it >= 2 ? a.ctr[((a.t - 2u) & 3u) * kCounterCopies + lane].active : 0ull;
+    c.sa = lead ? c1->sel_a : 0ull;
+    c.sb = lead ? c1->sel_b : 0ull;
+    c.rm = lead ? c1->rmax : 0u;
+}
+
+// Run by the 64 lanes of one wave after ctr_load: sum the counter copies of
+// iteration t - 1 (and t - 2), and, when `close` is set, record iteration
+// t - 1 (IsConverged, statistics, the buffer p_{t-1} selects) and clear the
+// copies of t + 1.  The statistics are updated with stores and no-return
+// atomics, so nothing waits.  Returns n_{t-1} and n_{t-2} (the host's value
+// when t - 2 precedes the run).
+__device__ void wave_close(const EvalArgs& a, bool close, const CtrLoad& c,
+                           unsigned long long& n1_out, long long& n2_out) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long n1 = wave_sum64(c.n1);
+    const unsigned long long n2 = wave_sum64(c.n2);
     const long long n2s = a.it >= 2 ? (long long)n2 : a.prev_active_host;
     n1_out = n1;
     n2_out = n2s;
     if (!close) return;
-    sa = wave_sum64(sa);
-    sb = wave_sum64(sb);
-    rm = wave_max32(rm);
+    const unsigned long long sa = wave_sum64(c.sa);
+    const unsigned long long sb = wave_sum64(c.sb);
+    const unsigned int rm = wave_max32(c.rm);
     CounterLine* z = a.ctr + ((a.t + 1u) & 3u) * kCounterCopies + lane;
     z->active = 0ull;
     z->sel_a = 0ull;
@@ -213,27 +223,32 @@ __device__ void wave_close(const EvalArgs& a, bool close, unsigned long long& n1
         st->done = 1u;
         st->conv_t = (long long)tp;
     } else if (!a.after_final) {
-        unsigned long long c;
+        unsigned long long cm;
         if (a.sched == kModeLBP)
-            c = a.num_messages;
+            cm = a.num_messages;
         else if (a.sched == kModeRBP)
-            c = a.rbp_k;
+            cm = a.rbp_k;
         else
-            c = sel ? sb : sa;
-        atomicAdd(&st->committed, c);
+            cm = sel ? sb : sa;
+        atomicAdd(&st->committed, cm);
         atomicAdd(&st->iterations, 1ull);
         st->in_sel[a.t & 3u] = (unsigned int)sel;
     }
 }
 
-// Start of iteration t (all threads of the block): returns the buffer holding
-// m^t, or nullptr when an earlier evaluation found no residual above eps (the
-// block then exits).  The previous launch wrote the outcome under both keep
-// thresholds, so choosing p_{t-1} is choosing a buffer.  Block 0 also closes
-// iteration t - 1.
-__device__ __forceinline__ const float* iteration_prologue(const EvalArgs& a,
-                                                           unsigned long long* s_red,
-                                                           bool may_close = true) {
+// Start of iteration t, in two parts so that a kernel can issue other loads
+// between them: prologue_issue loads the counters (wave 0), prologue_finish
+// (all threads of the block) returns the buffer holding m^t, or nullptr when
+// an earlier evaluation found no residual above eps (the block then exits).
+// The previous launch wrote the outcome under both keep thresholds, so
+// choosing p_{t-1} is choosing a buffer.  Block 0 also closes iteration t - 1.
+__device__ __forceinline__ void prologue_issue(const EvalArgs& a, CtrLoad& c, bool may_close) {
+    if (a.it != 0 && threadIdx.x < 64) ctr_load(a, may_close && blockIdx.x == 0, c);
+}
+
+__device__ __forceinline__ const float* prologue_finish(const EvalArgs& a, const CtrLoad& c,
+                                                        unsigned long long* s_red,
+                                                        bool may_close) {
     const bool lead = may_close && blockIdx.x == 0;
     if (a.it == 0) {
         if (lead && threadIdx.x < 64) {
@@ -247,12 +262,11 @@ __device__ __forceinline__ const float* iteration_prologue(const EvalArgs& a,
         return a.in_buf[0];
     }
     if (threadIdx.x < 64) {
-        const unsigned int done = a.st->done;
         unsigned long long n1;
         long long n2;
-        wave_close(a, lead && !done, n1, n2);
+        wave_close(a, lead && !c.done, c, n1, n2);
         if (threadIdx.x == 0) {
-            s_red[0] = done ? 0ull : n1;
+            s_red[0] = c.done ? 0ull : n1;
             s_red[1] = (unsigned long long)n2;
         }
     }
@@ -260,6 +274,14 @@ __device__ __forceinline__ const float* iteration_prologue(const EvalArgs& a,
     const unsigned long long n1 = s_red[0];
     if (n1 == 0ull) return nullptr;
     return a.in_buf[select_outcome(a, n1, (long long)s_red[1])];
+}
+
+__device__ __forceinline__ const float* iteration_prologue(const EvalArgs& a,
+                                                           unsigned long long* s_red,
+                                                           bool may_close = true) {
+    CtrLoad c;
+    prologue_issue(a, c, may_close);
+    return prologue_finish(a, c, s_red, may_close);
 }
 
 // ---------------------------------------------------------------------------
@@ -368,10 +390,10 @@ struct TileRegs {
 };
 
 // Issue every load of a tile (indices clamped into the tile, so there is no
-// per-lane branch and the loads are not ordered behind one another).
+// per-lane branch and the loads are not ordered behind one another): the graph
+// constants, then the tile's own old messages.
 template <int MODE>
-__device__ __forceinline__ void tile_load(TileRegs& d, const EvalArgs& a, const float* m_in,
-                                          int4 b) {
+__device__ __forceinline__ void tile_load_const(TileRegs& d, const EvalArgs& a, int4 b) {
     const int tid = threadIdx.x;
     d.n0 = b.x;
     d.nn = b.y - b.x;
@@ -381,17 +403,29 @@ __device__ __forceinline__ void tile_load(TileRegs& d, const EvalArgs& a, const 
     for (int j = 0; j < kPJ; ++j) {
         const int v = tid + j * kBlock;
         d.ptr[j] = ld32(a.node_ptr, d.n0 + min(v, d.nn));
-        d.u[j] = ld32(a.unary, d.n0 + min(v, d.nn - 1));
+        d.u[j] = ld32(a.unary, d.n0 + min(v, max(d.nn - 1, 0)));
     }
-    if (d.ns > 0) {
+    // a tile without slots reads slot s0, which lies inside the graph's
+    // device arena (the arrays are carved from one allocation in sequence)
 #pragma unroll
-        for (int k = 0; k < kPP; ++k) {
-            const int s = d.s0 + min(tid + k * kBlock, d.ns - 1);
-            d.old[k] = ld32(m_in, s);
-            d.rev[k] = ld32(a.rev, s);
-            d.J[k] = ld32(a.coupling, s);
-        }
+    for (int k = 0; k < kPP; ++k) {
+        const int s = d.s0 + min(tid + k * kBlock, max(d.ns - 1, 0));
+        d.rev[k] = ld32(a.rev, s);
+        d.J[k] = ld32(a.coupling, s);
     }
+}
+
+__device__ __forceinline__ void tile_load_msgs(TileRegs& d, const float* m_in) {
+#pragma unroll
+    for (int k = 0; k < kPP; ++k)
+        d.old[k] = ld32(m_in, d.s0 + min((int)threadIdx.x + k * kBlock, max(d.ns - 1, 0)));
+}
+
+template <int MODE>
+__device__ __forceinline__ void tile_load(TileRegs& d, const EvalArgs& a, const float* m_in,
+                                          int4 b) {
+    tile_load_const<MODE>(d, a, b);
+    tile_load_msgs(d, m_in);
 }
 
 // Tile w + j * W of this block's XCD range (tiles are dealt to XCDs in
@@ -421,9 +455,18 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
 
     const int4* __restrict__ tiles = (const int4*)a.tiles4;
     const int t0 = block_tile(a, 0), t1 = block_tile(a, 1);
-    int4 bcur = t0 >= 0 ? tiles[t0] : make_int4(0, 0, 0, 0);
+    // a block without tiles loads tile 0 and computes nothing, so that the
+    // first loads are unconditional
+    int4 bcur = tiles[t0 >= 0 ? t0 : 0];
     int4 bnext = t1 >= 0 ? tiles[t1] : make_int4(0, 0, 0, 0);
-    const float* m_sel = iteration_prologue(a, s_red);
+    // the counters are loaded first and the first tile's graph constants next,
+    // so that the two latencies overlap (loads complete in issue order)
+    CtrLoad cl;
+    prologue_issue(a, cl, true);
+    TileRegs cur, nxt;
+    tile_load_const<MODE>(cur, a, bcur);
+    __builtin_amdgcn_sched_barrier(0);
+    const float* m_sel = prologue_finish(a, cl, s_red, true);
     if (!m_sel) return;
     const float* __restrict__ m_in = uniform_ptr(m_sel);
     const OutOff out{a.out_buf[0], a.out_buf[1], a.cand, a.keys};
@@ -436,13 +479,10 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
         // loads of tile j+1, aggregate tile j (LDS), issue the gathers of tile
         // j+1, compute and store tile j, then stage tile j+1 into LDS.  Every
         // wait therefore falls on loads that had a whole phase to complete.
-        TileRegs cur, nxt;
         float lin[kPP];
-        tile_load<MODE>(cur, a, m_in, bcur);
-        if (cur.ns > 0) {
+        tile_load_msgs(cur, m_in);
 #pragma unroll
-            for (int k = 0; k < kPP; ++k) lin[k] = ld32(m_in, cur.rev[k]);
-        }
+        for (int k = 0; k < kPP; ++k) lin[k] = ld32(m_in, cur.rev[k]);
         // stage tile 0
 #pragma unroll
         for (int jj = 0; jj < kPJ; ++jj) {
@@ -484,7 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
             }
             lds_barrier();
             float lin_n[kPP];
-            if (has_next && nxt.ns > 0) {
+            if (has_next) {
 #pragma unroll
                 for (int k = 0; k < kPP; ++k) lin_n[k] = ld32(m_in, nxt.rev[k]);
             }
@@ -734,9 +774,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
 // next evaluation's prologue would do.
 __global__ void k_close_run(EvalArgs a) {
     if (a.st->done) return;
+    CtrLoad c;
+    ctr_load(a, true, c);
     unsigned long long n1;
     long long n2;
-    wave_close(a, true, n1, n2);
+    wave_close(a, true, c, n1, n2);
 }
 
 __global__ void k_init_state(DevState* st, CounterLine* ctr) {
