@@ -131,6 +131,29 @@ def test_high_degree_node_single_sweep(bp):
         assert err.max() <= SWEEP_TOL, (K, err.max())
 
 
+def test_every_node_oversized(bp):
+    # complete graph on 530 nodes: every degree (529) exceeds a K = 2 tile, so
+    # all nodes go to the single-node kernel and the regular kernel only keeps
+    # the iteration bookkeeping
+    n = 530
+    a, b = np.triu_indices(n, 1)
+    edges = np.stack([a, b], 1).astype(np.int32)
+    rng = np.random.default_rng(5)
+    h = rng.uniform(-1, 1, n)
+    prob = dict(N=n, K=2, edges=edges, log_unary=np.stack([-h, h], 1),
+                pair_kind=inputs.PAIR_ISING, coupling=rng.uniform(-0.02, 0.02, len(edges)))
+    state = _random_state(2 * len(edges), 2, 3, lo=0.3)
+    err, _ = _one_sweep_parity(bp, prob, state)
+    assert err.max() <= SWEEP_TOL, err.max()
+    ref = oracle.run(prob, oracle.LBP, eps=1e-5, max_iters=200)
+    with bp.Graph(prob) as g:
+        r = g.run("lbp", eps=1e-5, max_iters=200)
+        marg = g.marginals()
+    assert r["converged"] and ref["converged"]
+    assert abs(r["iterations"] - ref["iterations"]) <= 1
+    assert np.max(np.abs(marg - ref["marginals"])) <= MARG_TOL
+
+
 @pytest.mark.parametrize("C", [12.0, 40.0])
 def test_strong_coupling_single_sweep_and_finite(bp, C):
     # |J| up to 40: message log-odds reach 2|J| = 80 (m(0) ~ 1e-35).  FP32
