@@ -71,6 +71,8 @@ struct HostLayout {
     std::vector<int> slot_of_canon;   // [E]
     std::vector<int> tile_start;      // [T+1]
     std::vector<int> tile_slot;       // [T+1] node_ptr[tile_start]
+    int tile_nodes_max = 1;           // most nodes in one regular tile
+    int tile_big = 0;                 // 1 if some node's slots exceed the tile limit
     std::vector<int> tiles4;          // log-odds layout: regular tiles {n0, n1, s0, s1}
     std::vector<int> big4;            // log-odds layout: single-node tiles over the slot limit
     std::vector<float> coupling;      // [E] (Ising)
@@ -287,6 +289,14 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
     for (size_t i = 0; i < L.tile_start.size(); ++i) L.tile_slot[i] = L.node_ptr[L.tile_start[i]];
     L.tiles4.clear();
     L.big4.clear();
+    L.tile_nodes_max = 1;
+    L.tile_big = 0;
+    for (size_t i = 0; i + 1 < L.tile_start.size(); ++i) {
+        if (L.tile_slot[i + 1] - L.tile_slot[i] > slot_lim)
+            L.tile_big = 1;
+        else
+            L.tile_nodes_max = std::max(L.tile_nodes_max, L.tile_start[i + 1] - L.tile_start[i]);
+    }
     for (size_t i = 0; i + 1 < L.tile_start.size(); ++i) {
         const int q[4] = {L.tile_start[i], L.tile_start[i + 1], L.tile_slot[i], L.tile_slot[i + 1]};
         std::vector<int>& dstv = (q[3] - q[2] > slot_lim) ? L.big4 : L.tiles4;
@@ -543,6 +553,8 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     a.prev_active_host = g->prev_active;
     a.num_messages = (unsigned long long)L.E;
     a.num_nodes = L.N;
+    a.tile_nodes_max = L.tile_nodes_max;
+    a.tile_big = L.tile_big;
     a.rbp_k = (unsigned long long)rbp_k;
     a.sel0 = g->cur_sel;
     if (mode == kModeRnBP && o.dynamic_p) {

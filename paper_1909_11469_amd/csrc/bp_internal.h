@@ -106,6 +106,8 @@ struct EvalArgs {
     long long prev_active_host; // n_{t-1} from the iteration state (second launch)
     unsigned long long num_messages;
     int num_nodes;
+    int tile_nodes_max;         // [E][K] layout: most nodes in one regular tile
+    int tile_big;               // [E][K] layout: 1 if some node's slots exceed a tile
     unsigned long long rbp_k;   // RBP frontier size
 };
 

@@ -599,7 +599,416 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds_big(EvalArgs a) {
 // ---------------------------------------------------------------------------
 // Generic layout: [E][K] normalised FP32 probabilities, K <= KP.
 // ---------------------------------------------------------------------------
-template <int KP, int MODE>
+// Lanes of one group of R = 2 or 4 consecutive lanes (R aligned) exchanging
+// values with DPP quad permutations (no LDS).
+__device__ __forceinline__ float dpp_xor1(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float dpp_xor2(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float dpp_xor3(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x1B, 0xF, 0xF, false));
+}
+template <int R>
+__device__ __forceinline__ float group_max(float v) {
+    v = fmaxf(v, dpp_xor1(v));
+    if (R == 4) v = fmaxf(v, dpp_xor2(v));
+    return v;
+}
+// Sum over the group in a fixed order (part 0 + part 1 [+ part 2 + part 3]),
+// the same in every lane of the group.
+template <int R>
+__device__ __forceinline__ float group_sum(float v, int h) {
+    if (R == 2) {
+        const float o = dpp_xor1(v);
+        return h == 0 ? v + o : o + v;
+    }
+    const float o1 = dpp_xor1(v), o2 = dpp_xor2(v), o3 = dpp_xor3(v);
+    float p[4];
+    p[0] = h == 0 ? v : h == 1 ? o1 : h == 2 ? o2 : o3;
+    p[1] = h == 1 ? v : h == 0 ? o1 : h == 3 ? o2 : o3;
+    p[2] = h == 2 ? v : h == 3 ? o1 : h == 0 ? o2 : o3;
+    p[3] = h == 3 ? v : h == 2 ? o1 : h == 1 ? o2 : o3;
+    return (p[0] + p[1]) + (p[2] + p[3]);
+}
+
+// Eq. (2) for one slot split over a group of R lanes (KP = K states, each lane
+// owns KR = K / R of them): the lane computes its part of the cavity
+// distribution g, the group exchanges the parts, and each lane forms its KR
+// outputs c(y) = sum_x psi(x, y) g(x) from the shared table in LDS.  The
+// normalisation and the residual are reduced over the group.
+template <int KP, int R, int MODE>
+__device__ __forceinline__ void slot_update_split(const EvalArgs& a, const float* __restrict__ m_in,
+                                                  const float* s_logm, const float* s_A,
+                                                  const float* s_psi,
+                                                  const unsigned short* s_owner, int s0, int n0,
+                                                  int ns, float& rmax, unsigned int& act,
+                                                  unsigned int& sa, unsigned int& sb) {
+    constexpr int KR = KP / R;
+    constexpr int KS = KP + 1;
+    const int tid = threadIdx.x;
+    const int q = tid / R, h = tid % R;
+    if (q >= ns) return;  // the R lanes of a slot leave together
+    const int s = s0 + q;
+    const int v = s_owner[q];
+    float gp[KR];
+    float mx = -3.402823466e38f;
+#pragma unroll
+    for (int i = 0; i < KR; ++i) {
+        const int x = h * KR + i;
+        gp[i] = s_A[v * KS + x] - s_logm[q * KS + x];
+        mx = fmaxf(mx, gp[i]);
+    }
+    mx = group_max<R>(mx);
+#pragma unroll
+    for (int i = 0; i < KR; ++i) gp[i] = expf(gp[i] - mx);
+    // g(x) for all x: part p comes from the lane with h' = p, i.e. partner h ^ p
+    float g[KP];
+#pragma unroll
+    for (int i = 0; i < KR; ++i) {
+        const float o1 = dpp_xor1(gp[i]);
+        if (R == 2) {
+            g[i] = h == 0 ? gp[i] : o1;
+            g[KR + i] = h == 0 ? o1 : gp[i];
+        } else {
+            const float o2 = dpp_xor2(gp[i]), o3 = dpp_xor3(gp[i]);
+#pragma unroll
+            for (int pp = 0; pp < R; ++pp) {
+                const int k = pp ^ h;
+                g[pp * KR + i] = k == 0 ? gp[i] : k == 1 ? o1 : k == 2 ? o2 : o3;
+            }
+        }
+    }
+    float c[KR];
+#pragma unroll
+    for (int j = 0; j < KR; ++j) c[j] = 0.0f;
+    if (a.pair_kind == kPairSharedAsym && a.orient[s]) {
+        // transposed table: c(y) = sum_x psi(y, x) g(x)
+#pragma unroll
+        for (int j = 0; j < KR; ++j) {
+            const float4* row = (const float4*)(s_psi + (h * KR + j) * KP);
+            float acc = 0.0f;
+#pragma unroll
+            for (int x4 = 0; x4 < KP / 4; ++x4) {
+                const float4 p4 = row[x4];
+                acc = fmaf(p4.x, g[4 * x4], acc);
+                acc = fmaf(p4.y, g[4 * x4 + 1], acc);
+                acc = fmaf(p4.z, g[4 * x4 + 2], acc);
+                acc = fmaf(p4.w, g[4 * x4 + 3], acc);
+            }
+            c[j] = acc;
+        }
+    } else {
+#pragma unroll
+        for (int x = 0; x < KP; ++x) {
+            const float4* row = (const float4*)(s_psi + x * KP + h * KR);
+            const float gx = g[x];
+#pragma unroll
+            for (int j4 = 0; j4 < KR / 4; ++j4) {
+                const float4 p4 = row[j4];
+                c[4 * j4] = fmaf(p4.x, gx, c[4 * j4]);
+                c[4 * j4 + 1] = fmaf(p4.y, gx, c[4 * j4 + 1]);
+                c[4 * j4 + 2] = fmaf(p4.z, gx, c[4 * j4 + 2]);
+                c[4 * j4 + 3] = fmaf(p4.w, gx, c[4 * j4 + 3]);
+            }
+        }
+    }
+    float z = 0.0f;
+#pragma unroll
+    for (int j = 0; j < KR; ++j) z += c[j];
+    z = group_sum<R>(z, h);
+    const float inv = 1.0f / z;
+    const long long eo = (long long)s * KP + h * KR;
+    float old[KR];
+    float r = 0.0f;
+#pragma unroll
+    for (int j4 = 0; j4 < KR / 4; ++j4) {
+        const float4 o4 = *(const float4*)(m_in + eo + 4 * j4);
+        old[4 * j4] = o4.x;
+        old[4 * j4 + 1] = o4.y;
+        old[4 * j4 + 2] = o4.z;
+        old[4 * j4 + 3] = o4.w;
+    }
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        c[j] *= inv;
+        r = fmaxf(r, fabsf(c[j] - old[j]));
+    }
+    r = group_max<R>(r);
+    const bool active = r > a.eps;
+    const bool lead = h == 0;  // counts once per slot
+    rmax = fmaxf(rmax, r);
+    act += active && lead;
+    if (MODE == kModeLBP) {
+#pragma unroll
+        for (int j = 0; j < KR; ++j) a.out_buf[0][eo + j] = c[j];
+    } else if (MODE == kModeRnBP) {
+        bool ka = false, kb = false;
+        if (active) {
+            const int node = n0 + v;
+            const unsigned int u24 = draw24(a, node, s - a.node_ptr[node]);
+            ka = u24 < a.thr_a;
+            kb = u24 < a.thr_b;
+        }
+        sa += ka && lead;
+        sb += kb && lead;
+#pragma unroll
+        for (int j = 0; j < KR; ++j) a.out_buf[0][eo + j] = ka ? c[j] : old[j];
+        if (a.two_outputs) {
+#pragma unroll
+            for (int j = 0; j < KR; ++j) a.out_buf[1][eo + j] = kb ? c[j] : old[j];
+        }
+    } else if (MODE == kModeRBP) {
+#pragma unroll
+        for (int j = 0; j < KR; ++j) a.cand[eo + j] = c[j];
+        if (lead) a.keys[s] = __float_as_uint(r);
+    }
+}
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Eq. (2) for K = 32 with one symmetric shared table on the matrix cores.  Each
+// wave takes 32 slots of the tile; the products c = g P of its slots are one
+// 32 x 32 x 32 matrix product, 16 v_mfma_f32_32x32x2f32 steps with FP32 inputs
+// and FP32 accumulation.  Operand layout of that instruction: lane l supplies
+// A[l % 32][l / 32] and B[l / 32][l % 32] of each 32 x 2 / 2 x 32 step, and
+// holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32] in accumulator r = 0..15.
+// So lane (m = l % 32, h = l / 32) computes the cavity values g(x) of slot m
+// for the states x = 2 s + h, holds column m of the table for those states,
+// and after the product the tile goes through LDS (rows of 33 floats) back to
+// one slot per lane pair, each lane with 16 consecutive states of its slot.
+template <int MODE>
+__device__ __forceinline__ void slot_update_mfma32(const EvalArgs& a, const float* __restrict__ m_in,
+                                                   float* s_logm, const float* s_A,
+                                                   const unsigned short* s_owner, int s0,
+                                                   int n0, int ns, float& rmax,
+                                                   unsigned int& act, unsigned int& sa,
+                                                   unsigned int& sb) {
+    constexpr int K = 32, KS = 33;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = lane & 31, h = lane >> 5;
+    const int q = 32 * w + m;  // slot of the tile
+    const bool valid = q < ns;
+    // B operand: P[2 s + h][m]
+    float pb[16];
+#pragma unroll
+    for (int st = 0; st < 16; ++st) pb[st] = a.pair[(2 * st + h) * K + m];
+    // A operand: the cavity distribution of slot q at the states 2 s + h
+    const int v = valid ? s_owner[q] : 0;
+    float gv[16];
+    float mx = -3.402823466e38f;
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+        const int x = 2 * st + h;
+        gv[st] = valid ? s_A[v * KS + x] - s_logm[q * KS + x] : 0.0f;
+        mx = fmaxf(mx, gv[st]);
+    }
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+#pragma unroll
+    for (int st = 0; st < 16; ++st) gv[st] = expf(gv[st] - mx);
+    floatx16 d;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) d[r] = 0.0f;
+#pragma unroll
+    for (int st = 0; st < 16; ++st) d = __builtin_amdgcn_mfma_f32_32x32x2f32(gv[st], pb[st], d, 0, 0, 0);
+    // D[i][m] -> LDS row 32 w + i (the wave's own rows of the log buffer, which
+    // its lanes have finished reading: LDS operations of a wave run in order)
+    float* rows = s_logm + (32 * w) * KS;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) rows[(8 * (r >> 2) + 4 * h + (r & 3)) * KS + m] = d[r];
+    // back as slot m, states 16 h .. 16 h + 15
+    float c[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) c[t] = rows[m * KS + 16 * h + t];
+    if (!valid) return;
+    float z = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) z += c[t];
+    const float zo = __shfl_xor(z, 32, 64);
+    z = h == 0 ? z + zo : zo + z;
+    const float inv = 1.0f / z;
+    const int sl = s0 + q;
+    const long long eo = (long long)sl * K + 16 * h;
+    float old[16];
+#pragma unroll
+    for (int t4 = 0; t4 < 4; ++t4) {
+        const float4 o4 = *(const float4*)(m_in + eo + 4 * t4);
+        old[4 * t4] = o4.x;
+        old[4 * t4 + 1] = o4.y;
+        old[4 * t4 + 2] = o4.z;
+        old[4 * t4 + 3] = o4.w;
+    }
+    float r = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        c[t] *= inv;
+        r = fmaxf(r, fabsf(c[t] - old[t]));
+    }
+    r = fmaxf(r, __shfl_xor(r, 32, 64));
+    const bool active = r > a.eps;
+    const bool lead = h == 0;  // counts once per slot
+    rmax = fmaxf(rmax, r);
+    act += active && lead;
+    float4* o0 = (float4*)(a.out_buf[0] + eo);
+    if (MODE == kModeLBP) {
+#pragma unroll
+        for (int t4 = 0; t4 < 4; ++t4)
+            o0[t4] = make_float4(c[4 * t4], c[4 * t4 + 1], c[4 * t4 + 2], c[4 * t4 + 3]);
+    } else if (MODE == kModeRnBP) {
+        bool ka = false, kb = false;
+        if (active) {
+            const int node = n0 + v;
+            const unsigned int u24 = draw24(a, node, sl - a.node_ptr[node]);
+            ka = u24 < a.thr_a;
+            kb = u24 < a.thr_b;
+        }
+        sa += ka && lead;
+        sb += kb && lead;
+#pragma unroll
+        for (int t4 = 0; t4 < 4; ++t4)
+            o0[t4] = ka ? make_float4(c[4 * t4], c[4 * t4 + 1], c[4 * t4 + 2], c[4 * t4 + 3])
+                        : make_float4(old[4 * t4], old[4 * t4 + 1], old[4 * t4 + 2], old[4 * t4 + 3]);
+        if (a.two_outputs) {
+            float4* o1 = (float4*)(a.out_buf[1] + eo);
+#pragma unroll
+            for (int t4 = 0; t4 < 4; ++t4)
+                o1[t4] = kb ? make_float4(c[4 * t4], c[4 * t4 + 1], c[4 * t4 + 2], c[4 * t4 + 3])
+                            : make_float4(old[4 * t4], old[4 * t4 + 1], old[4 * t4 + 2], old[4 * t4 + 3]);
+        }
+    } else if (MODE == kModeRBP) {
+        float4* oc = (float4*)(a.cand + eo);
+#pragma unroll
+        for (int t4 = 0; t4 < 4; ++t4)
+            oc[t4] = make_float4(c[4 * t4], c[4 * t4 + 1], c[4 * t4 + 2], c[4 * t4 + 3]);
+        if (lead) a.keys[sl] = __float_as_uint(r);
+    }
+}
+
+// A shared K x K table seen through the constant address space: with K known
+// at compile time its entries are wave-uniform scalar loads (s_load into SGPRs
+// that the multiply-adds read directly), not one LDS read per multiply-add.
+typedef const __attribute__((address_space(4))) float* ConstF;
+
+// c(y) += sum_x P[x][y] g(x) (T: P[y][x]) for a uniform table P.
+template <int K, bool T>
+__device__ __forceinline__ void matvec_uniform(ConstF P, const float* g, float* c) {
+#pragma unroll
+    for (int x = 0; x < K; ++x) {
+        const float gx = g[x];
+#pragma unroll
+        for (int y = 0; y < K; ++y) c[y] = fmaf(T ? P[y * K + x] : P[x * K + y], gx, c[y]);
+    }
+}
+
+// EXACT: K == KP, so K is a compile-time constant (shifts instead of
+// divisions, scalar loads of a shared table).
+// LDS of the [E][K] kernels: rows of K + 1 floats (a thread per slot reads its
+// own row, and an odd stride puts the rows of neighbouring lanes in different
+// banks).  Node rows are sized by the largest node count of a tile.
+struct GenericLds {
+    float* logm;             // [TS][KS] logs of the incoming messages
+    float* A;                // [TN][KS] node aggregates
+    float* psi;              // [K][K] shared table (paths that read it from LDS)
+    int* rev;                // [TS]
+    int* ptr;                // [TN + 1] local slot offsets of the nodes
+    unsigned short* owner;   // [TS]
+};
+
+// with_psi: reserve the K x K table (the launch sizes the LDS the same way)
+__device__ __forceinline__ GenericLds generic_lds(float* smem, int K, int TS, int TN,
+                                                  bool with_psi) {
+    GenericLds l;
+    const int KS = K + 1;
+    l.logm = smem;
+    l.A = l.logm + TS * KS;
+    l.psi = l.A + ((TN * KS + 3) & ~3);  // 16-byte aligned: read as float4 rows
+    l.rev = (int*)(l.psi + (with_psi ? K * K : 0));
+    l.ptr = l.rev + TS;
+    l.owner = (unsigned short*)(l.ptr + TN + 1);
+    return l;
+}
+
+// Phase 1 of a tile whose slots fit (ns <= TS): gather the incoming rows
+// m_{k->i} (K consecutive threads per row; a tile holds at most
+// kTileFloatsGeneric values, kPer per thread, and a thread issues all of its
+// loads before using the first), take logs of K * m (the constant cancels in
+// the cavity and the normalisation, and it keeps the node aggregate near zero
+// for messages near uniform, where FP32 rounding of a large aggregate would
+// dominate), and sum them per node with the unary: A_i(x) of Eq. (2)/(3).
+// Ends with a barrier.
+__device__ __forceinline__ void generic_phase1(const EvalArgs& a, const float* __restrict__ m_in,
+                                               const GenericLds& l, int K, int n0, int nn,
+                                               int s0, int ns) {
+    const int tid = threadIdx.x;
+    const int KS = K + 1;
+    const float fK = (float)K;
+    for (int q = tid; q < ns; q += kBlock) l.rev[q] = a.rev[s0 + q];
+    for (int v = tid; v <= nn; v += kBlock) l.ptr[v] = a.node_ptr[n0 + v] - s0;
+    __syncthreads();
+    constexpr int kPer = kTileFloatsGeneric / kBlock;
+    float gat[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = tid + j * kBlock;
+        const int q = i / K, x = i - q * K;
+        gat[j] = q < ns ? m_in[(long long)l.rev[q] * K + x] : 1.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = tid + j * kBlock;
+        const int q = i / K, x = i - q * K;
+        if (q < ns) l.logm[q * KS + x] = logf(fK * gat[j]);
+    }
+    // the nodes' unaries (loads first), then the aggregates
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = tid + j * kBlock;
+        const int v = i / K, x = i - v * K;
+        gat[j] = v < nn ? a.unary[(long long)(n0 + v) * K + x] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = tid + j * kBlock;
+        const int v = i / K, x = i - v * K;
+        if (v < nn) {
+            const int q0 = l.ptr[v], q1 = l.ptr[v + 1];
+            float acc = gat[j];
+            for (int q = q0; q < q1; ++q) acc += l.logm[q * KS + x];
+            l.A[v * KS + x] = acc;
+            if (x == 0)
+                for (int q = q0; q < q1; ++q) l.owner[q] = (unsigned short)v;
+        }
+    }
+    __syncthreads();
+}
+
+// K = 32 with a symmetric shared table and no oversized node: Eq. (2) on the
+// matrix cores (slot_update_mfma32).  A kernel of its own, so that its register
+// count (and hence its occupancy) is not set by the paths it does not take.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_eval_mfma32(EvalArgs a) {
+    extern __shared__ float smem[];
+    __shared__ RedScratch red;
+    __shared__ unsigned long long s_red[2];
+    const float* __restrict__ m_in = iteration_prologue(a, s_red);
+    if (!m_in) return;
+    const int tile = tile_of_block(a);
+    if (tile >= a.num_tiles) return;
+    constexpr int K = 32;
+    constexpr int TS = kTileFloatsGeneric / K;
+    const GenericLds l = generic_lds(smem, K, TS, a.tile_nodes_max, false);
+    const int n0 = a.tile_start[tile], n1 = a.tile_start[tile + 1];
+    const int s0 = a.tile_slot[tile], s1 = a.tile_slot[tile + 1];
+    generic_phase1(a, m_in, l, K, n0, n1 - n0, s0, s1 - s0);
+    float rmax = 0.0f;
+    unsigned int act = 0, sa = 0, sb = 0;
+    slot_update_mfma32<MODE>(a, m_in, l.logm, l.A, l.owner, s0, n0, s1 - s0, rmax, act, sa, sb);
+    block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
+}
+
+template <int KP, int MODE, bool EXACT>
 __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
     extern __shared__ float smem[];
     __shared__ RedScratch red;
@@ -608,45 +1017,30 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
     if (!m_in) return;
     const int tile = tile_of_block(a);
     if (tile >= a.num_tiles) return;
-    const int K = a.num_states;
-    const int TS = kTileFloatsGeneric / K;  // slots (and nodes) per tile
-    float* s_logm = smem;                   // [TS][K] logs of the incoming messages
-    float* s_A = s_logm + TS * K;           // [TS][K]
-    float* s_psi = s_A + TS * K;            // [K][K] shared table
-    int* s_rev = (int*)(s_psi + K * K);     // [TS]
-    unsigned short* s_owner = (unsigned short*)(s_rev + TS);
+    const int K = EXACT ? KP : a.num_states;
+    const int TS = kTileFloatsGeneric / K;  // slots per tile
+    const int KS = K + 1;
+    const GenericLds l = generic_lds(smem, K, TS, a.tile_nodes_max, true);
+    float* s_logm = l.logm;
+    float* s_A = l.A;
+    float* s_psi = l.psi;
+    unsigned short* s_owner = l.owner;
 
     const int n0 = a.tile_start[tile], n1 = a.tile_start[tile + 1];
     const int s0 = a.tile_slot[tile], s1 = a.tile_slot[tile + 1];
     const int ns = s1 - s0, nn = n1 - n0;
     const int tid = threadIdx.x;
     const bool big = ns > TS;
-    // Logs are taken of K * m: the constant cancels in the cavity and the
-    // normalisation, and it keeps the node aggregate near zero for messages
-    // near uniform, where FP32 rounding of a large aggregate would dominate.
     const float fK = (float)K;
 
-    if (a.pair_kind == kPairShared || a.pair_kind == kPairSharedAsym)
+    // K > 16 with a shared table: each slot is split over R lanes, which read
+    // the table from LDS (the lanes of a wave need different columns)
+    constexpr int R = (EXACT && KP * kBlock > kTileFloatsGeneric) ? KP * kBlock / kTileFloatsGeneric : 1;
+    const bool shared = a.pair_kind == kPairShared || a.pair_kind == kPairSharedAsym;
+    if (shared && (!EXACT || R > 1))
         for (int i = tid; i < K * K; i += kBlock) s_psi[i] = a.pair[i];
     if (!big) {
-        for (int q = tid; q < ns; q += kBlock) s_rev[q] = a.rev[s0 + q];
-        __syncthreads();
-        // incoming rows m_{k->i}, gathered row by row (K consecutive threads per row)
-        for (int i = tid; i < ns * K; i += kBlock) {
-            const int q = i / K, x = i - q * K;
-            s_logm[i] = logf(fK * m_in[(long long)s_rev[q] * K + x]);
-        }
-        __syncthreads();
-        for (int i = tid; i < nn * K; i += kBlock) {
-            const int v = i / K, x = i - v * K;
-            const int n = n0 + v;
-            const int q0 = a.node_ptr[n] - s0, q1 = a.node_ptr[n + 1] - s0;
-            float acc = a.unary[(long long)n * K + x];
-            for (int q = q0; q < q1; ++q) acc += s_logm[q * K + x];
-            s_A[i] = acc;
-            if (x == 0)
-                for (int q = q0; q < q1; ++q) s_owner[q] = (unsigned short)v;
-        }
+        generic_phase1(a, m_in, l, K, n0, nn, s0, ns);
     } else {
         // single node with degree > TS: aggregate each state with a strided sum
         for (int x = 0; x < K; ++x) {
@@ -669,6 +1063,12 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
 
     float rmax = 0.0f;
     unsigned int act = 0, sa = 0, sb = 0;
+    if (R > 1 && shared && !big) {
+        slot_update_split<KP, R, MODE>(a, m_in, s_logm, s_A, s_psi, s_owner, s0, n0, ns, rmax, act,
+                                       sa, sb);
+        block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
+        return;
+    }
     for (int q = tid; q < ns; q += kBlock) {
         const int s = s0 + q;
         const int v = big ? 0 : s_owner[q];
@@ -679,8 +1079,8 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
 #pragma unroll
         for (int x = 0; x < KP; ++x) {
             if (x < K) {
-                const float lm = big ? logf(fK * m_in[rin + x]) : s_logm[q * K + x];
-                g[x] = s_A[v * K + x] - lm;
+                const float lm = big ? logf(fK * m_in[rin + x]) : s_logm[q * KS + x];
+                g[x] = s_A[v * KS + x] - lm;
                 mx = fmaxf(mx, g[x]);
             }
         }
@@ -696,6 +1096,12 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
             const float ep = expf(J - fabsf(J)), em = expf(-J - fabsf(J));
             c[0] = ep * g[0] + em * g[1];
             c[1] = em * g[0] + ep * g[1];
+        } else if (EXACT && a.pair_kind != kPairDense) {
+            const ConstF P4 = (ConstF)(uintptr_t)a.pair;
+            if (a.pair_kind == kPairSharedAsym && a.orient[s])
+                matvec_uniform<KP, true>(P4, g, c);
+            else
+                matvec_uniform<KP, false>(P4, g, c);
         } else {
             // c(y) = sum_x psi(x, y) g(x): element (x, y) of the table at
             // P[x * sx + y * sy] (the transpose for the other direction)
@@ -1004,16 +1410,23 @@ hipError_t launch_fill(float* p, float v, long long n, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int KP>
+template <int KP, bool EXACT>
 static hipError_t launch_generic_kp(int mode, const EvalArgs& a, int grid, size_t shm,
                                     hipStream_t s) {
     switch (mode) {
-    case kModeLBP: k_eval_generic<KP, kModeLBP><<<grid, kBlock, shm, s>>>(a); break;
-    case kModeRnBP: k_eval_generic<KP, kModeRnBP><<<grid, kBlock, shm, s>>>(a); break;
-    case kModeRBP: k_eval_generic<KP, kModeRBP><<<grid, kBlock, shm, s>>>(a); break;
-    default: k_eval_generic<KP, kModeEvalOnly><<<grid, kBlock, shm, s>>>(a); break;
+    case kModeLBP: k_eval_generic<KP, kModeLBP, EXACT><<<grid, kBlock, shm, s>>>(a); break;
+    case kModeRnBP: k_eval_generic<KP, kModeRnBP, EXACT><<<grid, kBlock, shm, s>>>(a); break;
+    case kModeRBP: k_eval_generic<KP, kModeRBP, EXACT><<<grid, kBlock, shm, s>>>(a); break;
+    default: k_eval_generic<KP, kModeEvalOnly, EXACT><<<grid, kBlock, shm, s>>>(a); break;
     }
     return hipGetLastError();
+}
+
+template <int KP>
+static hipError_t launch_generic_k(int mode, const EvalArgs& a, int grid, size_t shm,
+                                   hipStream_t s) {
+    return a.num_states == KP ? launch_generic_kp<KP, true>(mode, a, grid, shm, s)
+                              : launch_generic_kp<KP, false>(mode, a, grid, shm, s);
 }
 
 hipError_t launch_eval(int layout, int kp, int mode, const EvalArgs& a, hipStream_t s) {
@@ -1039,15 +1452,28 @@ hipError_t launch_eval(int layout, int kp, int mode, const EvalArgs& a, hipStrea
     }
     const int K = a.num_states;
     const int TS = kTileFloatsGeneric / K;
-    const size_t shm = sizeof(float) * (size_t)(2 * TS * K + K * K) + sizeof(int) * (size_t)TS +
-                       sizeof(unsigned short) * (size_t)TS;
+    const int TN = a.tile_nodes_max;
+    if (K == 32 && a.pair_kind == kPairShared && !a.tile_big) {
+        // no shared table in LDS
+        const size_t shm = sizeof(float) * (size_t)(TS * (K + 1) + ((TN * (K + 1) + 3) & ~3)) +
+                           sizeof(int) * (size_t)(TS + TN + 1) + sizeof(unsigned short) * (size_t)TS;
+        switch (mode) {
+        case kModeLBP: k_eval_mfma32<kModeLBP><<<grid, kBlock, shm, s>>>(a); break;
+        case kModeRnBP: k_eval_mfma32<kModeRnBP><<<grid, kBlock, shm, s>>>(a); break;
+        case kModeRBP: k_eval_mfma32<kModeRBP><<<grid, kBlock, shm, s>>>(a); break;
+        default: k_eval_mfma32<kModeEvalOnly><<<grid, kBlock, shm, s>>>(a); break;
+        }
+        return hipGetLastError();
+    }
+    const size_t shm = sizeof(float) * (size_t)(TS * (K + 1) + ((TN * (K + 1) + 3) & ~3) + K * K) +
+                       sizeof(int) * (size_t)(TS + TN + 1) + sizeof(unsigned short) * (size_t)TS;
     switch (kp) {
-    case 2: return launch_generic_kp<2>(mode, a, grid, shm, s);
-    case 4: return launch_generic_kp<4>(mode, a, grid, shm, s);
-    case 8: return launch_generic_kp<8>(mode, a, grid, shm, s);
-    case 16: return launch_generic_kp<16>(mode, a, grid, shm, s);
-    case 32: return launch_generic_kp<32>(mode, a, grid, shm, s);
-    case 64: return launch_generic_kp<64>(mode, a, grid, shm, s);
+    case 2: return launch_generic_k<2>(mode, a, grid, shm, s);
+    case 4: return launch_generic_k<4>(mode, a, grid, shm, s);
+    case 8: return launch_generic_k<8>(mode, a, grid, shm, s);
+    case 16: return launch_generic_k<16>(mode, a, grid, shm, s);
+    case 32: return launch_generic_k<32>(mode, a, grid, shm, s);
+    case 64: return launch_generic_k<64>(mode, a, grid, shm, s);
     default: return hipErrorInvalidValue;
     }
 }

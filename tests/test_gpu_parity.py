@@ -84,7 +84,7 @@ def test_er_single_sweep(bp):
     assert err.max() <= SWEEP_TOL, err.max()
 
 
-@pytest.mark.parametrize("K", [3, 8, 32])
+@pytest.mark.parametrize("K", [3, 8, 16, 32, 64])
 def test_potts_single_sweep(bp, K):
     prob = inputs.potts_grid(9, 11, K, 1.0, K)
     state = _random_state(2 * len(prob["edges"]), K, K)
@@ -92,11 +92,14 @@ def test_potts_single_sweep(bp, K):
     assert err.max() <= SWEEP_TOL, err.max()
 
 
-def test_asymmetric_shared_table_single_sweep(bp):
-    prob = inputs.potts_grid(6, 7, 5, 1.0, 1)
+@pytest.mark.parametrize("K", [5, 32, 64])
+def test_asymmetric_shared_table_single_sweep(bp, K):
+    # K = 32 and 64 take the lane-group path with the transposed table for
+    # half of the messages
+    prob = inputs.potts_grid(6, 7, K, 1.0, 1)
     rng = np.random.default_rng(0)
-    prob["shared"] = np.exp(rng.standard_normal((5, 5)))
-    state = _random_state(2 * len(prob["edges"]), 5, 2)
+    prob["shared"] = np.exp(0.5 * rng.standard_normal((K, K)))
+    state = _random_state(2 * len(prob["edges"]), K, 2)
     err, _ = _one_sweep_parity(bp, prob, state)
     assert err.max() <= SWEEP_TOL, err.max()
 
@@ -285,6 +288,30 @@ def test_rnbp_frontier_one_iteration(bp, dynamic_p, prev):
     assert err.max() <= SWEEP_TOL
     assert r["committed"] == changed.sum()
     assert st["t"] == t + 1 and abs(st["prev_active"] - n_t) <= band.sum()
+
+
+@pytest.mark.parametrize("K", [8, 32, 64])
+def test_rnbp_frontier_one_iteration_potts(bp, K):
+    # the [E][K] kernels: each lane path counts a message once and keeps or
+    # reverts all K entries of it together
+    prob = inputs.potts_grid(9, 10, K, 1.0, 3)
+    E = 2 * len(prob["edges"])
+    state = _random_state(E, K, 7, lo=0.3)
+    # eps at the median residual: about half of the messages pass the filter
+    eps = float(np.median(oracle.evaluate(prob, state.astype(np.float64))[1]))
+    p, seed, t = 0.4, 99, 5
+    start, got, changed, r, _ = _one_iteration(bp, prob, state, "rnbp", p, seed, t, -1, eps,
+                                                dynamic_p=False)
+    cand, res = oracle.evaluate(prob, start.astype(np.float64))
+    src, _ = oracle.canonical_src_dst(prob)
+    rank = oracle.neighbour_rank(prob)
+    u = np.array([oracle.uniform(seed, src[e], rank[e], t) for e in range(E)])
+    want = (res > eps) & (u < p)
+    band = np.abs(res - eps) < BAND
+    assert np.array_equal(changed[~band], want[~band])
+    assert 0 < want.sum() < E
+    assert _rel_err(got[want & ~band], cand[want & ~band]).max() <= SWEEP_TOL
+    assert r["committed"] == changed.sum()
 
 
 @pytest.mark.parametrize("p", [1 / 256, 0.05, 0.5])
