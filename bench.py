@@ -52,6 +52,63 @@ def counter_traffic(path, kernel_src):
     return float(kv["traffic_bytes_per_launch"])
 
 
+def serving_mix(inputs, np, n, seed=0):
+    """The serving workload: Ising grids with side ~ U{32..256} and Erdos-Renyi
+    graphs with n ~ U[1k, 20k], average degree ~ U{4..8}; C ~ U[1, 3]."""
+    rng = np.random.default_rng(seed)
+    mix = []
+    for i in range(n):
+        C = float(rng.uniform(1.0, 3.0))
+        if rng.random() < 0.5:
+            side = int(rng.integers(32, 257))
+            mix.append(inputs.ising_grid(side, side, C, 1000 + i))
+        else:
+            mix.append(inputs.er_graph(int(rng.integers(1000, 20001)), float(rng.integers(4, 9)), C,
+                                       1000 + i))
+    return mix
+
+
+def serving_bench(bp, inputs, np, torch, args, n=48, max_iters=2000, p=0.5):
+    """Batched serving (one launch per iteration for every resident graph) vs one
+    graph per bp_run, on the same requests: RnBP, eps = 1e-4, at most 2000
+    iterations per request.  All requests arrive at time 0; latency is each
+    request's completion time."""
+    mix = serving_mix(inputs, np, n)
+    msgs = sum(2 * len(pr["edges"]) for pr in mix)
+    torch.cuda.synchronize()
+    # batched
+    with bp.Server(2 << 30, max_graphs=64) as srv:
+        t0 = time.perf_counter()
+        ids = [srv.submit(pr, "rnbp", eps=args.eps, p=p, seed=i, max_iters=max_iters)
+               for i, pr in enumerate(mix)]
+        done = {}
+        while len(done) < n:
+            srv.step(16)
+            now = time.perf_counter() - t0
+            for i in ids:
+                if i not in done and srv.result(i) is not None:
+                    done[i] = now
+        t_batch = time.perf_counter() - t0
+    lat_b = np.array(sorted(done.values()))
+    # one graph at a time
+    t0 = time.perf_counter()
+    lat_s = []
+    for i, pr in enumerate(mix):
+        with bp.Graph(pr) as g:
+            g.run("rnbp", eps=args.eps, p=p, seed=i, max_iters=max_iters, check_every=64)
+            g.marginals()
+        lat_s.append(time.perf_counter() - t0)
+    t_seq = time.perf_counter() - t0
+    lat_s = np.array(lat_s)
+    return {"requests": n, "messages_total": msgs, "max_iters": max_iters,
+            "batched": {"graphs_per_s": n / t_batch, "p50_ms": float(np.percentile(lat_b, 50) * 1e3),
+                        "p99_ms": float(np.percentile(lat_b, 99) * 1e3), "makespan_s": t_batch},
+            "one_graph_per_run": {"graphs_per_s": n / t_seq,
+                                  "p50_ms": float(np.percentile(lat_s, 50) * 1e3),
+                                  "p99_ms": float(np.percentile(lat_s, 99) * 1e3),
+                                  "makespan_s": t_seq}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +293,8 @@ def main():
                               "message_updates_per_s": rr["evaluated"] / (rr["device_ms"] / 1e3)}
         extra["ising_4000x4000_C%g" % args.C] = row
         _log(f"bench: ising 4000x4000 {row}")
+        extra["serving"] = serving_bench(bp, inputs, np, torch, args)
+        _log(f"bench: serving {extra['serving']}")
         out["extra"] = extra
 
     if not args.no_cpu_baseline:

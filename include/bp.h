@@ -205,6 +205,73 @@ void bp_destroy_graph(bp_graph* g);
 /* Description of the last error in the calling thread ("" if none). */
 const char* bp_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Serving: many independent graphs solved together.
+ *
+ * A server keeps up to max_graphs graphs resident in one device arena and
+ * evaluates one iteration of every resident graph per kernel launch (each
+ * block takes one tile of one graph), so small graphs share the GPU instead
+ * of each paying for whole-GPU launches.  Requests wait in FIFO order until
+ * the arena has room, join the batch at the next step, and leave it when
+ * they converge or reach max_iters.  Every graph advances exactly as bp_run
+ * would advance it alone (same tiles, arithmetic, counters and random keys),
+ * so a result does not depend on which other graphs shared its launches:
+ * it is bitwise identical to bp_run with the same arguments on a fresh graph.
+ * Requests must use BP_PAIR_ISING with the one-log-odds-per-message layout
+ * (no BP_FLAG_GENERIC_LAYOUT, fewer than 2^30 - 512 messages) and the
+ * BP_LBP or BP_RNBP schedule.
+ * ------------------------------------------------------------------------ */
+typedef struct bp_server bp_server;
+
+typedef struct bp_server_desc {
+    uint64_t arena_bytes;   /* device memory for resident graphs (> 0) */
+    void* arena;            /* optional caller-owned device memory, 256-byte aligned,
+                               at least arena_bytes; NULL = library allocates */
+    void* stream;           /* hipStream_t for all device work, NULL = null stream */
+    int32_t max_graphs;     /* most graphs resident at once, 1 ... 65536 */
+    int32_t reserved;
+} bp_server_desc;
+
+typedef struct bp_request {
+    int32_t schedule;       /* BP_LBP or BP_RNBP */
+    int32_t reserved;
+    double eps;             /* as bp_run */
+    double p;               /* as bp_run (RnBP low setting) */
+    uint64_t seed;          /* as bp_run */
+    bp_run_opts opts;       /* max_iters, dynamic_p, high_p, ratio_threshold as bp_run;
+                               check_every, warm_start and profile are ignored */
+} bp_request;
+
+/* Create a server.  Errors: BP_EINVAL, BP_ENOMEM, BP_EDEVICE; *out NULL on error. */
+int bp_server_create(const bp_server_desc* desc, bp_server** out);
+
+/* Validate and copy a request (the caller keeps ownership of every array in
+ * *graph; graph->stream and graph->workspace are ignored).  *id receives the
+ * request's id (> 0).  A graph that needs more than the whole arena is
+ * rejected with BP_ENOMEM.  Errors: BP_EINVAL, BP_ENOMEM. */
+int bp_server_submit(bp_server* s, const bp_graph_desc* graph, const bp_request* req,
+                     int64_t* id);
+
+/* Admit queued requests that fit, run `launches` batched iterations, then
+ * retire the graphs that converged or reached max_iters (their results become
+ * available to bp_server_result).  *finished (may be NULL) receives the number
+ * retired by this call.  Synchronises the server's stream. */
+int bp_server_step(bp_server* s, int32_t launches, int32_t* finished);
+
+/* Result of a retired request: Eq. (3) beliefs into host [N][2] FP32 and the
+ * run statistics as bp_run reports them (device_ms and the profile fields are
+ * 0).  Returns BP_OK and forgets the request, BP_ESTATE if the request is
+ * still queued or resident, BP_EINVAL for an unknown id. */
+int bp_server_result(bp_server* s, int64_t id, float* marginals, bp_run_stats* stats);
+
+/* Requests waiting for room, resident in the batch, and retired but not yet
+ * fetched (any pointer may be NULL). */
+int bp_server_counts(const bp_server* s, int64_t* queued, int64_t* resident, int64_t* retired);
+
+/* Release the server's device memory (not a caller arena) and every request.
+ * NULL is ignored. */
+void bp_server_destroy(bp_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,9 @@ SCHEDULES = {"lbp": BP_LBP, "rbp": BP_RBP, "rnbp": BP_RNBP}
 # Every symbol include/bp.h declares.
 EXPORTED = ["bp_default_opts", "bp_workspace_bytes", "bp_create_graph", "bp_run",
             "bp_marginals", "bp_marginals_device", "bp_get_state", "bp_set_state",
-            "bp_graph_info_get", "bp_destroy_graph", "bp_last_error"]
+            "bp_graph_info_get", "bp_destroy_graph", "bp_last_error",
+            "bp_server_create", "bp_server_submit", "bp_server_step", "bp_server_result",
+            "bp_server_counts", "bp_server_destroy"]
 
 
 class BpError(RuntimeError):
@@ -75,6 +77,18 @@ class bp_graph_info(ctypes.Structure):
                 ("device_bytes", ctypes.c_uint64)]
 
 
+class bp_server_desc(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_uint64), ("arena", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p), ("max_graphs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class bp_request(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("p", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("opts", bp_run_opts)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -105,6 +119,20 @@ def _load():
     lib.bp_destroy_graph.restype = None
     lib.bp_last_error.argtypes = []
     lib.bp_last_error.restype = ctypes.c_char_p
+    I64P = ctypes.POINTER(ctypes.c_int64)
+    lib.bp_server_create.argtypes = [ctypes.POINTER(bp_server_desc), ctypes.POINTER(P)]
+    lib.bp_server_create.restype = ctypes.c_int
+    lib.bp_server_submit.argtypes = [P, ctypes.POINTER(bp_graph_desc), ctypes.POINTER(bp_request),
+                                     I64P]
+    lib.bp_server_submit.restype = ctypes.c_int
+    lib.bp_server_step.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.bp_server_step.restype = ctypes.c_int
+    lib.bp_server_result.argtypes = [P, ctypes.c_int64, P, ctypes.POINTER(bp_run_stats)]
+    lib.bp_server_result.restype = ctypes.c_int
+    lib.bp_server_counts.argtypes = [P, I64P, I64P, I64P]
+    lib.bp_server_counts.restype = ctypes.c_int
+    lib.bp_server_destroy.argtypes = [P]
+    lib.bp_server_destroy.restype = None
     return lib
 
 
@@ -282,3 +310,79 @@ def bp_set_state(graph, msgs=None, t=None, prev_active=-1):
 
 def bp_destroy_graph(graph):
     graph.close()
+
+
+class Server:
+    """Batched serving of many K = 2 Ising graphs (bp_server_* in include/bp.h).
+
+    submit() copies a problem and returns a request id; step(n) admits what fits,
+    runs n batched iterations and retires finished graphs; result(id) returns
+    (marginals, stats) once the request is retired, else None."""
+
+    def __init__(self, arena_bytes, max_graphs=256, use_torch=True):
+        d = bp_server_desc()
+        d.arena_bytes, d.max_graphs = int(arena_bytes), int(max_graphs)
+        self._arena = None
+        torch = _torch_cuda() if use_torch else None
+        if torch is not None:
+            self._arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device="cuda")
+            base = self._arena.data_ptr()
+            d.arena = base + (-base) % 256
+            d.stream = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p()
+        _check(lib.bp_server_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        self._shapes = {}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.bp_server_destroy(self.handle)
+            self.handle = None
+        self._arena = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, problem, schedule="rnbp", eps=1e-4, p=0.5, seed=0, max_iters=10000,
+               dynamic_p=True, high_p=1.0, ratio_threshold=0.9):
+        d, keep = _make_desc(problem)
+        r = bp_request()
+        r.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+        r.eps, r.p, r.seed = float(eps), float(p), int(seed)
+        r.opts = bp_default_opts()
+        r.opts.max_iters = int(max_iters)
+        r.opts.dynamic_p, r.opts.high_p = int(bool(dynamic_p)), float(high_p)
+        r.opts.ratio_threshold = float(ratio_threshold)
+        i = ctypes.c_int64()
+        _check(lib.bp_server_submit(self.handle, ctypes.byref(d), ctypes.byref(r), ctypes.byref(i)))
+        del keep
+        self._shapes[i.value] = int(problem["N"])
+        return i.value
+
+    def step(self, launches=16):
+        n = ctypes.c_int32()
+        _check(lib.bp_server_step(self.handle, int(launches), ctypes.byref(n)))
+        return n.value
+
+    def result(self, rid):
+        m = np.empty((self._shapes[rid], 2), dtype=np.float32)
+        s = bp_run_stats()
+        rc = lib.bp_server_result(self.handle, int(rid), _ptr(m), ctypes.byref(s))
+        if rc == BP_ESTATE:
+            return None
+        _check(rc)
+        del self._shapes[rid]
+        out = {f: getattr(s, f) for f, _ in s._fields_ if f != "reserved0"}
+        out["converged"] = bool(out["converged"])
+        return m, out
+
+    def counts(self):
+        q, a, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.bp_server_counts(self.handle, ctypes.byref(q), ctypes.byref(a), ctypes.byref(d)))
+        return q.value, a.value, d.value

@@ -10,8 +10,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <numeric>
 #include <string>
+#include <unordered_map>
 #include <unordered_set>
 #include <vector>
 
@@ -476,34 +479,11 @@ static unsigned int keep_threshold(double p) {
     return (unsigned int)x;
 }
 
-int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const bp_run_opts* opts,
-           bp_run_stats* stats) {
-    if (!g) return fail(BP_EINVAL, "graph is NULL");
-    if (schedule != BP_LBP && schedule != BP_RBP && schedule != BP_RNBP)
-        return fail(BP_EINVAL, "unknown schedule %d", schedule);
-    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(BP_EINVAL, "eps must be finite and >= 0");
-    if (schedule != BP_LBP && !(p > 0.0 && p <= 1.0)) return fail(BP_EINVAL, "p must be in (0, 1]");
-    bp_run_opts o;
-    bp_default_opts(&o);
-    if (opts) o = *opts;
-    if (o.max_iters < 0) return fail(BP_EINVAL, "max_iters < 0");
-    if (o.check_every < 1) return fail(BP_EINVAL, "check_every < 1");
-    if (schedule == BP_RNBP && o.dynamic_p && !(o.high_p > 0.0 && o.high_p <= 1.0))
-        return fail(BP_EINVAL, "high_p must be in (0, 1]");
-    if (!std::isfinite(o.ratio_threshold)) return fail(BP_EINVAL, "ratio_threshold not finite");
-    DeviceGuard dg(g->device);
+// The evaluation arguments of a run of `schedule` on g (everything but the
+// per-launch fields t, it, in_buf, out_buf, after_final).
+static EvalArgs run_args(const bp_graph* g, int schedule, double eps, double p, uint64_t seed,
+                         const bp_run_opts& o, long long& rbp_k_out) {
     const HostLayout& L = g->L;
-    hipStream_t s = g->stream;
-    if (!o.warm_start) {
-        const float uni = L.layout == kLayoutLogOdds ? 0.0f : 1.0f / (float)L.K;
-        HIP_OK(launch_fill(g->cur(), uni, L.E * L.row, s), "fill");
-        g->t_next = 0;
-        g->prev_active = -1;
-    }
-    if (g->t_next + o.max_iters + 1 > 0xFFFFFFFFLL)
-        return fail(BP_EINVAL, "iteration counter would pass 2^32");
-    HIP_OK(launch_init_state(g->st(), g->ctr(), s), "init state");
-
     const int mode = schedule == BP_LBP ? kModeLBP : schedule == BP_RBP ? kModeRBP : kModeRnBP;
     const unsigned int thr_lo = keep_threshold(p);
     const unsigned int thr_hi = keep_threshold(o.high_p);
@@ -567,6 +547,42 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
         a.low_is_a = 1;
         a.two_outputs = 0;
     }
+
+    rbp_k_out = rbp_k;
+    return a;
+}
+
+int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const bp_run_opts* opts,
+           bp_run_stats* stats) {
+    if (!g) return fail(BP_EINVAL, "graph is NULL");
+    if (schedule != BP_LBP && schedule != BP_RBP && schedule != BP_RNBP)
+        return fail(BP_EINVAL, "unknown schedule %d", schedule);
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(BP_EINVAL, "eps must be finite and >= 0");
+    if (schedule != BP_LBP && !(p > 0.0 && p <= 1.0)) return fail(BP_EINVAL, "p must be in (0, 1]");
+    bp_run_opts o;
+    bp_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.max_iters < 0) return fail(BP_EINVAL, "max_iters < 0");
+    if (o.check_every < 1) return fail(BP_EINVAL, "check_every < 1");
+    if (schedule == BP_RNBP && o.dynamic_p && !(o.high_p > 0.0 && o.high_p <= 1.0))
+        return fail(BP_EINVAL, "high_p must be in (0, 1]");
+    if (!std::isfinite(o.ratio_threshold)) return fail(BP_EINVAL, "ratio_threshold not finite");
+    DeviceGuard dg(g->device);
+    const HostLayout& L = g->L;
+    hipStream_t s = g->stream;
+    if (!o.warm_start) {
+        const float uni = L.layout == kLayoutLogOdds ? 0.0f : 1.0f / (float)L.K;
+        HIP_OK(launch_fill(g->cur(), uni, L.E * L.row, s), "fill");
+        g->t_next = 0;
+        g->prev_active = -1;
+    }
+    if (g->t_next + o.max_iters + 1 > 0xFFFFFFFFLL)
+        return fail(BP_EINVAL, "iteration counter would pass 2^32");
+    HIP_OK(launch_init_state(g->st(), g->ctr(), s), "init state");
+
+    const int mode = schedule == BP_LBP ? kModeLBP : schedule == BP_RBP ? kModeRBP : kModeRnBP;
+    long long rbp_k = 0;
+    EvalArgs a = run_args(g, schedule, eps, p, seed, o, rbp_k);
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     HIP_OK(hipEventCreate(&ev0), "event");
@@ -790,6 +806,404 @@ int bp_set_state(bp_graph* g, const float* msgs, const bp_iter_state* st) {
         g->prev_active = st->prev_active;
     }
     return BP_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Serving: batched evaluation of many resident graphs (bp_server_*).
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+struct Request {
+    int64_t id = 0;
+    // host copies of the caller's arrays
+    std::vector<int32_t> edges;
+    std::vector<double> log_unary, coupling;
+    bp_graph_desc desc{};
+    bp_request req{};
+    uint64_t bytes = 0;
+    enum State { kQueued, kResident, kRetired } state = kQueued;
+    bp_graph* g = nullptr;
+    uint64_t off = 0;  // arena offset
+    int slot = -1;
+    std::vector<float> marg;
+    bp_run_stats stats{};
+};
+
+// First-fit allocator over the arena, 256-byte granules.
+struct ArenaAlloc {
+    std::map<uint64_t, uint64_t> free_;  // offset -> size
+    void init(uint64_t bytes) {
+        free_.clear();
+        free_[0] = bytes & ~uint64_t(255);
+    }
+    bool take(uint64_t bytes, uint64_t* off) {
+        bytes = (bytes + 255) & ~uint64_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const uint64_t rest = it->second - bytes, at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void give(uint64_t off, uint64_t bytes) {
+        bytes = (bytes + 255) & ~uint64_t(255);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+}  // namespace
+
+struct bp_server {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char* base = nullptr;
+    uint64_t bytes = 0;
+    bool owns = false;
+    int max_graphs = 0;
+    ArenaAlloc alloc;
+    uint64_t graphs_off = 0;               // BatchGraph [max_graphs]
+    uint64_t list_off = 0, list_cap = 0;   // int4 tile list (entries)
+    std::vector<BatchGraph> rec;           // host mirror of the records
+    std::vector<Request*> slots;           // resident request per slot
+    std::vector<int> h_list;               // {graph, tile, oversized, 0}
+    bool list_dirty = false;
+    std::deque<Request*> queue;
+    std::unordered_map<int64_t, Request*> reqs;
+    long long launch = 0;
+    int64_t next_id = 1;
+    uint64_t done_off = 0;                 // unsigned [max_graphs]: gathered done flags
+    unsigned int* h_done = nullptr;        // pinned mirror
+};
+
+namespace {
+
+int server_admit(bp_server* s) {
+    while (!s->queue.empty()) {
+        int slot = -1;
+        for (int i = 0; i < s->max_graphs; ++i)
+            if (!s->slots[i]) {
+                slot = i;
+                break;
+            }
+        if (slot < 0) return BP_OK;
+        Request* r = s->queue.front();
+        uint64_t off = 0;
+        if (!s->alloc.take(r->bytes, &off)) return BP_OK;  // FIFO: wait for room
+        bp_graph_desc d = r->desc;
+        d.edges = r->edges.data();
+        d.log_unary = r->log_unary.data();
+        d.coupling = r->coupling.data();
+        d.stream = (void*)s->stream;
+        d.workspace = s->base + off;
+        d.workspace_bytes = r->bytes;
+        bp_graph* g = nullptr;
+        const int rc = bp_create_graph(&d, &g);
+        if (rc != BP_OK) {
+            s->alloc.give(off, r->bytes);
+            return rc;
+        }
+        s->queue.pop_front();
+        r->g = g;
+        r->off = off;
+        r->slot = slot;
+        r->state = Request::kResident;
+        s->slots[slot] = r;
+        bp_run_opts o = r->req.opts;
+        long long rbp_k = 0;
+        BatchGraph& b = s->rec[slot];
+        std::memset(&b, 0, sizeof(b));
+        b.a = run_args(g, r->req.schedule, r->req.eps, r->req.p, r->req.seed, o, rbp_k);
+        b.a.prev_active_host = -1;
+        b.a.sel0 = 0;
+        for (int i = 0; i < 4; ++i) b.msg[i] = g->msg(i >> 1, i & 1);
+        b.first = s->launch;
+        b.max_iters = o.max_iters;
+        b.mode = r->req.schedule == BP_LBP ? kModeLBP : kModeRnBP;
+        HIP_OK(hipMemcpyAsync(s->base + s->graphs_off + sizeof(BatchGraph) * (size_t)slot, &b,
+                              sizeof(BatchGraph), hipMemcpyHostToDevice, s->stream),
+               "batch record upload");
+        const HostLayout& L = g->L;
+        for (int t = 0; t < (int)(L.tiles4.size() / 4); ++t)
+            s->h_list.insert(s->h_list.end(), {slot, t, 0, 0});
+        for (int t = 0; t < (int)(L.big4.size() / 4); ++t)
+            s->h_list.insert(s->h_list.end(), {slot, t, 1, 0});
+        s->list_dirty = true;
+    }
+    return BP_OK;
+}
+
+int server_upload_list(bp_server* s) {
+    if (!s->list_dirty) return BP_OK;
+    const uint64_t entries = s->h_list.size() / 4;
+    if (entries > s->list_cap) {
+        uint64_t cap = std::max<uint64_t>(entries, 2 * s->list_cap);
+        uint64_t off = 0;
+        if (!s->alloc.take(cap * 16, &off)) {
+            cap = entries;
+            if (!s->alloc.take(cap * 16, &off)) return fail(BP_ENOMEM, "arena full: tile list");
+        }
+        HIP_OK(hipStreamSynchronize(s->stream), "synchronize");  // the old list is no longer read
+        if (s->list_cap) s->alloc.give(s->list_off, s->list_cap * 16);
+        s->list_off = off;
+        s->list_cap = cap;
+    }
+    if (entries)
+        HIP_OK(hipMemcpyAsync(s->base + s->list_off, s->h_list.data(), entries * 16,
+                              hipMemcpyHostToDevice, s->stream),
+               "tile list upload");
+    s->list_dirty = false;
+    return BP_OK;
+}
+
+// Close the run of a finished graph exactly as bp_run closes its own, take its
+// beliefs and statistics, and return its memory.
+int server_retire(bp_server* s, Request* r, const DevState& h) {
+    bp_graph* g = r->g;
+    BatchGraph& b = s->rec[r->slot];
+    const long long last_it = std::min(s->launch - 1 - b.first, b.max_iters);
+    EvalArgs a = b.a;
+    a.t = (unsigned int)(last_it + 1);
+    a.it = last_it + 1;
+    a.after_final = last_it == b.max_iters ? 1 : 0;
+    HIP_OK(launch_close_run(a, s->stream), "close run");
+    HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost, s->stream),
+           "state readback");
+    HIP_OK(hipStreamSynchronize(s->stream), "synchronize");
+    (void)h;
+    const DevState& st = *g->host_state;
+    const bool converged = st.done != 0;
+    const long long final_t = converged ? st.conv_t : st.last_t;
+    g->cur_pair = (int)(final_t & 1);
+    g->cur_sel = (int)st.in_sel[final_t & 3];
+    r->marg.resize((size_t)g->L.N * g->L.K);
+    int rc = bp_marginals(g, r->marg.data());
+    if (rc != BP_OK) return rc;
+    std::memset(&r->stats, 0, sizeof(r->stats));
+    r->stats.iterations = (long long)st.iterations;
+    r->stats.converged = converged ? 1 : 0;
+    r->stats.last_active = (long long)st.last_active;
+    float rm;
+    std::memcpy(&rm, &st.last_rmax, sizeof(rm));
+    r->stats.last_max_residual = rm;
+    r->stats.evaluated = (long long)st.evaluated;
+    r->stats.committed = (long long)st.committed;
+    r->stats.final_t = final_t;
+    bp_destroy_graph(g);
+    r->g = nullptr;
+    s->alloc.give(r->off, r->bytes);
+    s->slots[r->slot] = nullptr;
+    r->slot = -1;
+    r->state = Request::kRetired;
+    return BP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bp_server_create(const bp_server_desc* d, bp_server** out) {
+    if (!out) return fail(BP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(BP_EINVAL, "desc is NULL");
+    if (d->max_graphs < 1 || d->max_graphs > 65536)
+        return fail(BP_EINVAL, "max_graphs %d not in [1, 65536]", d->max_graphs);
+    const uint64_t rec_bytes = ((sizeof(BatchGraph) * (uint64_t)d->max_graphs) + 255) & ~uint64_t(255);
+    if (d->arena_bytes <= rec_bytes) return fail(BP_EINVAL, "arena_bytes too small");
+    if (d->arena && (uintptr_t)d->arena % 256 != 0)
+        return fail(BP_EINVAL, "arena must be 256-byte aligned");
+    bp_server* s = new (std::nothrow) bp_server();
+    if (!s) return fail(BP_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) {
+        delete s;
+        return hip_fail(e, "hipGetDevice");
+    }
+    s->stream = (hipStream_t)d->stream;
+    s->bytes = d->arena_bytes;
+    s->max_graphs = d->max_graphs;
+    if (d->arena) {
+        s->base = (char*)d->arena;
+    } else {
+        e = hipMalloc((void**)&s->base, d->arena_bytes);
+        if (e != hipSuccess) {
+            delete s;
+            (void)hipGetLastError();
+            return fail(e == hipErrorOutOfMemory ? BP_ENOMEM : BP_EDEVICE, "hipMalloc(%llu): %s",
+                        (unsigned long long)d->arena_bytes, hipGetErrorString(e));
+        }
+        s->owns = true;
+    }
+    s->alloc.init(s->bytes);
+    s->alloc.take(rec_bytes, &s->graphs_off);
+    if (!s->alloc.take(sizeof(unsigned int) * (uint64_t)s->max_graphs, &s->done_off)) {
+        bp_server_destroy(s);
+        return fail(BP_EINVAL, "arena_bytes too small");
+    }
+    e = hipHostMalloc((void**)&s->h_done, sizeof(unsigned int) * (size_t)s->max_graphs,
+                      hipHostMallocDefault);
+    if (e != hipSuccess) {
+        bp_server_destroy(s);
+        return hip_fail(e, "hipHostMalloc");
+    }
+    // empty slots: null state pointers (the status kernel reads every slot)
+    e = hipMemsetAsync(s->base + s->graphs_off, 0, rec_bytes, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        bp_server_destroy(s);
+        return hip_fail(e, "initialise");
+    }
+    s->rec.resize((size_t)s->max_graphs);
+    s->slots.assign((size_t)s->max_graphs, nullptr);
+    *out = s;
+    return BP_OK;
+}
+
+int bp_server_submit(bp_server* s, const bp_graph_desc* graph, const bp_request* req, int64_t* id) {
+    if (!s || !graph || !req) return fail(BP_EINVAL, "NULL argument");
+    if (graph->pair_kind != BP_PAIR_ISING || graph->num_states != 2 || graph->flags != 0)
+        return fail(BP_EINVAL, "serving takes K = 2 Ising graphs in the log-odds layout");
+    if (req->schedule != BP_LBP && req->schedule != BP_RNBP)
+        return fail(BP_EINVAL, "serving takes BP_LBP or BP_RNBP");
+    if (!(req->eps >= 0.0) || !std::isfinite(req->eps)) return fail(BP_EINVAL, "eps must be finite and >= 0");
+    if (req->schedule == BP_RNBP && !(req->p > 0.0 && req->p <= 1.0)) return fail(BP_EINVAL, "p must be in (0, 1]");
+    const bp_run_opts& o = req->opts;
+    if (o.max_iters < 0) return fail(BP_EINVAL, "max_iters < 0");
+    if (o.max_iters + 1 > 0xFFFFFFFFLL) return fail(BP_EINVAL, "max_iters too large");
+    if (req->schedule == BP_RNBP && o.dynamic_p && !(o.high_p > 0.0 && o.high_p <= 1.0))
+        return fail(BP_EINVAL, "high_p must be in (0, 1]");
+    if (!std::isfinite(o.ratio_threshold)) return fail(BP_EINVAL, "ratio_threshold not finite");
+    HostLayout L;
+    int rc = build_layout(graph, L);  // full validation
+    if (rc != BP_OK) return rc;
+    if (L.layout != kLayoutLogOdds) return fail(BP_EINVAL, "graph too large for the log-odds layout");
+    const uint64_t need = plan(L).total;
+    if (need + 256 > s->bytes) return fail(BP_ENOMEM, "graph needs %llu bytes, arena has %llu",
+                                           (unsigned long long)need, (unsigned long long)s->bytes);
+    Request* r = new (std::nothrow) Request();
+    if (!r) return fail(BP_ENOMEM, "host allocation failed");
+    const size_t M = (size_t)graph->num_edges, N = (size_t)graph->num_vars;
+    r->edges.assign(graph->edges, graph->edges + 2 * M);
+    r->log_unary.assign(graph->log_unary, graph->log_unary + 2 * N);
+    if (M) r->coupling.assign(graph->coupling, graph->coupling + M);
+    r->desc = *graph;
+    r->req = *req;
+    r->bytes = need;
+    r->id = s->next_id++;
+    s->queue.push_back(r);
+    s->reqs[r->id] = r;
+    if (id) *id = r->id;
+    return BP_OK;
+}
+
+int bp_server_step(bp_server* s, int32_t launches, int32_t* finished) {
+    if (finished) *finished = 0;
+    if (!s) return fail(BP_EINVAL, "server is NULL");
+    if (launches < 0) return fail(BP_EINVAL, "launches < 0");
+    DeviceGuard dg(s->device);
+    int rc = server_admit(s);
+    if (rc != BP_OK) return rc;
+    rc = server_upload_list(s);
+    if (rc != BP_OK) return rc;
+    const int blocks = (int)(s->h_list.size() / 4);
+    BatchGraph* graphs = (BatchGraph*)(s->base + s->graphs_off);
+    const int* list = (const int*)(s->base + s->list_off);
+    for (int k = 0; k < launches; ++k) {
+        HIP_OK(launch_eval_batch(graphs, s->max_graphs, list, blocks, s->launch, s->stream),
+               "batch evaluation");
+        ++s->launch;
+    }
+    // poll every resident graph (one gathered readback of the done flags),
+    // retire the finished ones
+    int n = 0;
+    unsigned int* d_done = (unsigned int*)(s->base + s->done_off);
+    HIP_OK(launch_batch_status(graphs, s->max_graphs, d_done, s->stream), "batch status");
+    HIP_OK(hipMemcpyAsync(s->h_done, d_done, sizeof(unsigned int) * (size_t)s->max_graphs,
+                          hipMemcpyDeviceToHost, s->stream),
+           "status readback");
+    HIP_OK(hipStreamSynchronize(s->stream), "synchronize");
+    bool removed = false;
+    for (Request* r : s->slots) {
+        if (!r || !r->g) continue;
+        const BatchGraph& b = s->rec[r->slot];
+        const long long last_it = s->launch - 1 - b.first;
+        if (s->h_done[r->slot] || last_it >= b.max_iters) {
+            rc = server_retire(s, r, *r->g->host_state);
+            if (rc != BP_OK) return rc;
+            ++n;
+            removed = true;
+        }
+    }
+    if (removed) {
+        std::vector<int> keep;
+        keep.reserve(s->h_list.size());
+        for (size_t i = 0; i < s->h_list.size(); i += 4)
+            if (s->slots[s->h_list[i]])
+                keep.insert(keep.end(), s->h_list.begin() + i, s->h_list.begin() + i + 4);
+        s->h_list.swap(keep);
+        s->list_dirty = true;
+    }
+    if (finished) *finished = n;
+    return BP_OK;
+}
+
+int bp_server_result(bp_server* s, int64_t id, float* marginals, bp_run_stats* stats) {
+    if (!s) return fail(BP_EINVAL, "server is NULL");
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return fail(BP_EINVAL, "unknown request %lld", (long long)id);
+    Request* r = it->second;
+    if (r->state != Request::kRetired) return BP_ESTATE;
+    if (marginals) std::memcpy(marginals, r->marg.data(), sizeof(float) * r->marg.size());
+    if (stats) *stats = r->stats;
+    s->reqs.erase(it);
+    delete r;
+    return BP_OK;
+}
+
+int bp_server_counts(const bp_server* s, int64_t* queued, int64_t* resident, int64_t* retired) {
+    if (!s) return fail(BP_EINVAL, "server is NULL");
+    int64_t q = 0, a = 0, d = 0;
+    for (const auto& kv : s->reqs) {
+        if (kv.second->state == Request::kQueued) ++q;
+        else if (kv.second->state == Request::kResident) ++a;
+        else ++d;
+    }
+    if (queued) *queued = q;
+    if (resident) *resident = a;
+    if (retired) *retired = d;
+    return BP_OK;
+}
+
+void bp_server_destroy(bp_server* s) {
+    if (!s) return;
+    {
+        DeviceGuard dg(s->device);
+        (void)hipStreamSynchronize(s->stream);
+        for (auto& kv : s->reqs) {
+            if (kv.second->g) bp_destroy_graph(kv.second->g);
+            delete kv.second;
+        }
+        if (s->owns && s->base) (void)hipFree(s->base);
+        if (s->h_done) (void)hipHostFree(s->h_done);
+    }
+    delete s;
 }
 
 }  // extern "C"

@@ -111,7 +111,26 @@ struct EvalArgs {
     unsigned long long rbp_k;   // RBP frontier size
 };
 
+// One graph of a serving batch (device memory).  `a` holds the graph's
+// arguments as bp_run would set them; before every batched launch a small
+// kernel sets the per-launch fields (t, it, in_buf, out_buf, the mode of the
+// final evaluation) from the launch index.
+struct BatchGraph {
+    EvalArgs a;
+    float* msg[4];          // message buffer b of pair p at msg[2 p + b]
+    long long first;        // global launch index of the graph's first evaluation
+    long long max_iters;    // commits allowed; launch max_iters evaluates only
+    int mode;               // kModeLBP or kModeRnBP
+    int mode_now;           // this launch: mode, or kModeEvalOnly for the final evaluation
+    int skip;               // this launch: 1 if the graph is not evaluated
+    int pad;
+};
+
 // Launch wrappers (bp_kernels.hip).  All return the hipError_t of the launch.
+hipError_t launch_eval_batch(BatchGraph* graphs, int num_graphs, const int* list, int num_blocks,
+                             long long launch, hipStream_t s);
+hipError_t launch_batch_status(const BatchGraph* graphs, int num_graphs, unsigned int* done,
+                               hipStream_t s);
 hipError_t launch_init_state(DevState* st, CounterLine* ctr, hipStream_t s);
 hipError_t launch_fill(float* p, float v, long long n, hipStream_t s);
 hipError_t launch_eval(int layout, int kp, int mode, const EvalArgs& a, hipStream_t s);

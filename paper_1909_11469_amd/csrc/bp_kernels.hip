@@ -241,15 +241,15 @@ __device__ void wave_close(const EvalArgs& a, bool close, const CtrLoad& c,
 // (all threads of the block) returns the buffer holding m^t, or nullptr when
 // an earlier evaluation found no residual above eps (the block then exits).
 // The previous launch wrote the outcome under both keep thresholds, so
-// choosing p_{t-1} is choosing a buffer.  Block 0 also closes iteration t - 1.
-__device__ __forceinline__ void prologue_issue(const EvalArgs& a, CtrLoad& c, bool may_close) {
-    if (a.it != 0 && threadIdx.x < 64) ctr_load(a, may_close && blockIdx.x == 0, c);
+// choosing p_{t-1} is choosing a buffer.  The lead block (one per graph and
+// launch) also closes iteration t - 1.
+__device__ __forceinline__ void prologue_issue(const EvalArgs& a, CtrLoad& c, bool lead) {
+    if (a.it != 0 && threadIdx.x < 64) ctr_load(a, lead, c);
 }
 
 __device__ __forceinline__ const float* prologue_finish(const EvalArgs& a, const CtrLoad& c,
                                                         unsigned long long* s_red,
-                                                        bool may_close) {
-    const bool lead = may_close && blockIdx.x == 0;
+                                                        bool lead) {
     if (a.it == 0) {
         if (lead && threadIdx.x < 64) {
             CounterLine* z = a.ctr + ((a.t + 1u) & 3u) * kCounterCopies + threadIdx.x;
@@ -277,11 +277,10 @@ __device__ __forceinline__ const float* prologue_finish(const EvalArgs& a, const
 }
 
 __device__ __forceinline__ const float* iteration_prologue(const EvalArgs& a,
-                                                           unsigned long long* s_red,
-                                                           bool may_close = true) {
+                                                           unsigned long long* s_red, bool lead) {
     CtrLoad c;
-    prologue_issue(a, c, may_close);
-    return prologue_finish(a, c, s_red, may_close);
+    prologue_issue(a, c, lead);
+    return prologue_finish(a, c, s_red, lead);
 }
 
 // ---------------------------------------------------------------------------
@@ -462,11 +461,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
     // the counters are loaded first and the first tile's graph constants next,
     // so that the two latencies overlap (loads complete in issue order)
     CtrLoad cl;
-    prologue_issue(a, cl, true);
+    prologue_issue(a, cl, blockIdx.x == 0);
     TileRegs cur, nxt;
     tile_load_const<MODE>(cur, a, bcur);
     __builtin_amdgcn_sched_barrier(0);
-    const float* m_sel = prologue_finish(a, cl, s_red, true);
+    const float* m_sel = prologue_finish(a, cl, s_red, blockIdx.x == 0);
     if (!m_sel) return;
     const float* __restrict__ m_in = uniform_ptr(m_sel);
     const OutOff out{a.out_buf[0], a.out_buf[1], a.cand, a.keys};
@@ -562,21 +561,15 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
     block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
 }
 
-// Nodes whose degree exceeds a tile: one block per node, aggregate by a block
-// reduction of the gathered incoming messages, then stream the slots.  Runs
-// after k_eval_logodds in the same iteration (same prologue, no bookkeeping).
+// A node whose degree exceeds a tile: one block, aggregate by a block
+// reduction of the gathered incoming messages, then stream the slots.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_eval_logodds_big(EvalArgs a) {
-    __shared__ RedScratch red;
-    __shared__ float s_part[kBlock / 64];
-    __shared__ unsigned long long s_red[2];
-    const int4 b = ((const int4*)a.big4)[blockIdx.x];
-    const float* __restrict__ m_in = iteration_prologue(a, s_red, false);
-    if (!m_in) return;
+__device__ __forceinline__ void logodds_big_node(const EvalArgs& a, const float* __restrict__ m_in,
+                                                 int4 b, float* s_part, float& rmax,
+                                                 unsigned int& act, unsigned int& sa,
+                                                 unsigned int& sb) {
     const int tid = threadIdx.x;
     const int n0 = b.x, s0 = b.z, ns = b.w - b.z;
-    float rmax = 0.0f;
-    unsigned int act = 0, sa = 0, sb = 0;
     float part = 0.0f;
     for (int q = tid; q < ns; q += kBlock) part += m_in[a.rev[s0 + q]];
 #pragma unroll
@@ -592,6 +585,152 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds_big(EvalArgs a) {
         const float r = logodds_slot<MODE>(a, OutPtr{a}, L, m_in[a.rev[s]], a.coupling[s], m_in[s], s,
                                            u24, act, sa, sb);
         rmax = fmaxf(rmax, r);
+    }
+}
+
+// Nodes whose degree exceeds a tile, one block each.  Runs after k_eval_logodds
+// in the same iteration (same prologue, no bookkeeping).
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_eval_logodds_big(EvalArgs a) {
+    __shared__ RedScratch red;
+    __shared__ float s_part[kBlock / 64];
+    __shared__ unsigned long long s_red[2];
+    const int4 b = ((const int4*)a.big4)[blockIdx.x];
+    const float* __restrict__ m_in = iteration_prologue(a, s_red, false);
+    if (!m_in) return;
+    float rmax = 0.0f;
+    unsigned int act = 0, sa = 0, sb = 0;
+    logodds_big_node<MODE>(a, m_in, b, s_part, rmax, act, sa, sb);
+    block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
+}
+
+// ---------------------------------------------------------------------------
+// Batched evaluation for serving: one launch evaluates one iteration of every
+// graph of a batch.  Each block takes one tile (or one oversized node) of one
+// graph; the graph's arguments live in device memory and its iteration number
+// is the launch index minus the launch of its first evaluation, so graphs
+// admitted at different times advance independently, each exactly as bp_run
+// would advance it alone (same tiles, same per-slot arithmetic, per-graph
+// counters and random keys).
+// ---------------------------------------------------------------------------
+template <int MODE>
+__device__ __forceinline__ void logodds_tile_once(const EvalArgs& a, const float* __restrict__ m_in,
+                                                  int4 b, float* s_lam, unsigned short* s_owner,
+                                                  unsigned int* s_u, unsigned short* s_ptr,
+                                                  float* s_L, float& rmax, unsigned int& act,
+                                                  unsigned int& sa, unsigned int& sb) {
+    const int tid = threadIdx.x;
+    const OutOff out{a.out_buf[0], a.out_buf[1], a.cand, a.keys};
+    TileRegs cur;
+    tile_load<MODE>(cur, a, m_in, b);
+    float lin[kPP];
+#pragma unroll
+    for (int k = 0; k < kPP; ++k) lin[k] = ld32(m_in, cur.rev[k]);
+#pragma unroll
+    for (int jj = 0; jj < kPJ; ++jj) {
+        const int v = tid + jj * kBlock;
+        if (v <= cur.nn) s_ptr[v] = (unsigned short)(cur.ptr[jj] - cur.s0);
+        if (v < cur.nn) s_L[v] = cur.u[jj];
+    }
+#pragma unroll
+    for (int k = 0; k < kPP; ++k) {
+        const int q = tid + k * kBlock;
+        if (q < cur.ns) s_lam[q] = lin[k];
+    }
+    lds_barrier();
+    for (int v = tid; v < cur.nn; v += kBlock) {
+        const int q0 = s_ptr[v], q1 = s_ptr[v + 1];
+        float L = s_L[v];
+        for (int q = q0; q < q1; ++q) {
+            L += s_lam[q];
+            s_owner[q] = (unsigned short)v;
+        }
+        s_L[v] = L;
+        if (MODE == kModeRnBP) {
+            for (int q = q0; q < q1; q += 4) {
+                const uint4 w = philox4((unsigned int)(cur.n0 + v), (unsigned int)(q - q0) >> 2, a.t,
+                                        a.key0, a.key1);
+                s_u[q] = w.x >> 8;
+                if (q + 1 < q1) s_u[q + 1] = w.y >> 8;
+                if (q + 2 < q1) s_u[q + 2] = w.z >> 8;
+                if (q + 3 < q1) s_u[q + 3] = w.w >> 8;
+            }
+        }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < kPP; ++k) {
+        const int q = tid + k * kBlock;
+        if (q < cur.ns) {
+            const int v = s_owner[q];
+            const unsigned int u24 = MODE == kModeRnBP ? s_u[q] : 0u;
+            const float r = logodds_slot<MODE>(a, out, s_L[v], lin[k], cur.J[k], cur.old[k],
+                                               cur.s0 + q, u24, act, sa, sb);
+            rmax = fmaxf(rmax, r);
+        }
+    }
+}
+
+// Before each batched launch: the per-launch fields of every graph's
+// arguments, as bp_run sets them for its iteration `it`.
+__global__ void k_batch_advance(BatchGraph* graphs, int num_graphs, long long launch) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= num_graphs) return;
+    BatchGraph& G = graphs[g];
+    const long long it = launch - G.first;
+    G.skip = (it < 0 || it > G.max_iters) ? 1 : 0;
+    if (G.skip) return;
+    EvalArgs& a = G.a;
+    a.it = it;
+    a.t = (unsigned int)it;
+    a.after_final = 0;
+    const int pin = (int)(it & 1);
+    a.in_buf[0] = it == 0 ? G.msg[0] : G.msg[2 * pin];
+    a.in_buf[1] = it == 0 ? G.msg[0] : G.msg[2 * pin + 1];
+    a.out_buf[0] = G.msg[2 * (pin ^ 1)];
+    a.out_buf[1] = G.msg[2 * (pin ^ 1) + 1];
+    G.mode_now = it == G.max_iters ? kModeEvalOnly : G.mode;
+}
+
+__global__ __launch_bounds__(kBlock) void k_eval_batch(const BatchGraph* __restrict__ graphs,
+                                                       const int4* __restrict__ list) {
+    constexpr int TS = kTileSlotsLogOdds;
+    constexpr int TN = kTileNodesLogOdds;
+    __shared__ float s_lam[TS];
+    __shared__ unsigned short s_owner[TS];
+    __shared__ unsigned int s_u[TS];
+    __shared__ unsigned short s_ptr[TN + 1];
+    __shared__ float s_L[TN];
+    __shared__ float s_part[kBlock / 64];
+    __shared__ RedScratch red;
+    __shared__ unsigned long long s_red[2];
+    const int4 ent = list[blockIdx.x];  // {graph, tile, oversized node?, 0}
+    const BatchGraph& G = graphs[ent.x];
+    if (G.skip) return;  // not admitted yet, or finished
+    const EvalArgs& a = G.a;
+    const int mode = G.mode_now;
+    const float* m_sel = iteration_prologue(a, s_red, ent.z == 0 && ent.y == 0);
+    if (!m_sel) return;
+    const float* __restrict__ m_in = uniform_ptr(m_sel);
+    float rmax = 0.0f;
+    unsigned int act = 0, sa = 0, sb = 0;
+    const int4 b = ent.z ? ((const int4*)a.big4)[ent.y] : ((const int4*)a.tiles4)[ent.y];
+    if (ent.z) {
+        if (mode == kModeLBP)
+            logodds_big_node<kModeLBP>(a, m_in, b, s_part, rmax, act, sa, sb);
+        else if (mode == kModeRnBP)
+            logodds_big_node<kModeRnBP>(a, m_in, b, s_part, rmax, act, sa, sb);
+        else
+            logodds_big_node<kModeEvalOnly>(a, m_in, b, s_part, rmax, act, sa, sb);
+    } else {
+        if (mode == kModeLBP)
+            logodds_tile_once<kModeLBP>(a, m_in, b, s_lam, s_owner, s_u, s_ptr, s_L, rmax, act, sa, sb);
+        else if (mode == kModeRnBP)
+            logodds_tile_once<kModeRnBP>(a, m_in, b, s_lam, s_owner, s_u, s_ptr, s_L, rmax, act, sa,
+                                         sb);
+        else
+            logodds_tile_once<kModeEvalOnly>(a, m_in, b, s_lam, s_owner, s_u, s_ptr, s_L, rmax, act,
+                                             sa, sb);
     }
     block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
 }
@@ -992,7 +1131,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_mfma32(EvalArgs a) {
     extern __shared__ float smem[];
     __shared__ RedScratch red;
     __shared__ unsigned long long s_red[2];
-    const float* __restrict__ m_in = iteration_prologue(a, s_red);
+    const float* __restrict__ m_in = iteration_prologue(a, s_red, blockIdx.x == 0);
     if (!m_in) return;
     const int tile = tile_of_block(a);
     if (tile >= a.num_tiles) return;
@@ -1013,7 +1152,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
     extern __shared__ float smem[];
     __shared__ RedScratch red;
     __shared__ unsigned long long s_red[2];
-    const float* __restrict__ m_in = iteration_prologue(a, s_red);
+    const float* __restrict__ m_in = iteration_prologue(a, s_red, blockIdx.x == 0);
     if (!m_in) return;
     const int tile = tile_of_block(a);
     if (tile >= a.num_tiles) return;
@@ -1496,6 +1635,28 @@ int logodds_blocks_per_cu(int mode) {
         break;
     }
     return e == hipSuccess ? n : 0;
+}
+
+// The done flag of every graph of a batch, gathered for one readback.
+__global__ void k_batch_status(const BatchGraph* graphs, int num_graphs, unsigned int* done) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= num_graphs) return;
+    const DevState* st = graphs[g].a.st;
+    done[g] = st ? st->done : 0u;
+}
+
+hipError_t launch_batch_status(const BatchGraph* graphs, int num_graphs, unsigned int* done,
+                               hipStream_t s) {
+    k_batch_status<<<(num_graphs + 255) / 256, 256, 0, s>>>(graphs, num_graphs, done);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_batch(BatchGraph* graphs, int num_graphs, const int* list, int num_blocks,
+                             long long launch, hipStream_t s) {
+    if (num_blocks <= 0) return hipSuccess;
+    k_batch_advance<<<(num_graphs + 255) / 256, 256, 0, s>>>(graphs, num_graphs, launch);
+    k_eval_batch<<<num_blocks, kBlock, 0, s>>>(graphs, (const int4*)list);
+    return hipGetLastError();
 }
 
 hipError_t launch_close_run(const EvalArgs& a, hipStream_t s) {

@@ -45,7 +45,7 @@ def test_struct_layouts_match_header(bp, tmp_path):
     """Compile the header with the host C compiler and compare every field offset
     and struct size with the ctypes mirrors."""
     structs = [bp.bp_graph_desc, bp.bp_run_opts, bp.bp_run_stats, bp.bp_iter_state,
-               bp.bp_graph_info]
+               bp.bp_graph_info, bp.bp_server_desc, bp.bp_request]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bp.h"', "int main(void) {"]
     for S in structs:
         n = S.__name__

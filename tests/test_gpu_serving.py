@@ -1,0 +1,86 @@
+"""Batched serving (bp_server_*, through the C ABI): every request's result is
+bitwise identical to bp_run on the same problem and arguments, whatever else
+shares its launches, whether it waited in the queue, and when it joined."""
+import numpy as np
+import pytest
+
+from paper_1909_11469_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1909_11469_amd import bp as mod
+    return mod
+
+
+def _star(n_leaves, seed):
+    rng = np.random.default_rng(seed)
+    n = n_leaves + 1
+    edges = np.array([(0, i) for i in range(1, n)] + [(i, i + 1) for i in range(1, n - 1, 7)],
+                     dtype=np.int32)
+    h = rng.uniform(-1, 1, n)
+    return dict(N=n, K=2, edges=edges, log_unary=np.stack([-h, h], 1), pair_kind=inputs.PAIR_ISING,
+                coupling=rng.uniform(-0.3, 0.3, len(edges)))
+
+
+def _mix():
+    # (problem, schedule, eps, p, seed, max_iters)
+    return [
+        (inputs.ising_grid(12, 13, 1.0, 0), "rnbp", 1e-4, 0.5, 1, 10000),
+        (inputs.ising_grid(20, 20, 2.5, 1), "rnbp", 1e-4, 0.3, 2, 60),    # capped
+        (inputs.ising_grid(33, 17, 1.0, 2), "lbp", 1e-5, 1.0, 0, 10000),
+        (inputs.er_graph(300, 5.0, 1.0, 3), "rnbp", 1e-4, 0.7, 3, 10000),
+        (inputs.chain(500, 2.0, 4), "lbp", 1e-6, 1.0, 0, 10000),
+        (_star(700, 5), "rnbp", 1e-5, 0.5, 4, 10000),                      # oversized node
+        (inputs.ising_grid(40, 41, 4.0, 6), "rnbp", 1e-4, 0.5, 5, 7),      # capped early
+        (inputs.ising_grid(7, 9, 1.5, 7), "lbp", 0.0, 1.0, 0, 25),         # never converges
+        (inputs.er_graph(1000, 7.0, 2.0, 8), "lbp", 1e-4, 1.0, 0, 400),
+        (inputs.ising_grid(25, 25, 1.0, 9), "rnbp", 1e-4, 0.5, 6, 10000),
+    ]
+
+
+def _alone(bp, prob, sched, eps, p, seed, max_iters):
+    with bp.Graph(prob) as g:
+        r = g.run(sched, eps=eps, p=p, seed=seed, max_iters=max_iters)
+        return g.marginals(), r
+
+
+@pytest.mark.parametrize("arena_mb,max_graphs,launches", [(256, 16, 9), (2, 3, 4)])
+def test_serving_bitwise_equals_bp_run(bp, arena_mb, max_graphs, launches):
+    # the small arena holds a few graphs at a time: requests queue and join late
+    mix = _mix()
+    with bp.Server(arena_mb << 20, max_graphs=max_graphs) as srv:
+        ids = [srv.submit(pr, sched, eps=eps, p=p, seed=seed, max_iters=mi)
+               for pr, sched, eps, p, seed, mi in mix]
+        got = {}
+        for _ in range(100000):
+            srv.step(launches)
+            for i in ids:
+                if i not in got:
+                    r = srv.result(i)
+                    if r is not None:
+                        got[i] = r
+            if len(got) == len(ids):
+                break
+        assert srv.counts() == (0, 0, 0)
+    assert len(got) == len(ids)
+    for i, (pr, sched, eps, p, seed, mi) in zip(ids, mix):
+        m_ref, r_ref = _alone(bp, pr, sched, eps, p, seed, mi)
+        m, r = got[i]
+        assert np.array_equal(m, m_ref), (pr["name"] if "name" in pr else i)
+        for k in ("iterations", "converged", "last_active", "committed", "final_t"):
+            assert r[k] == r_ref[k], (i, k, r[k], r_ref[k])
+
+
+def test_serving_rejects_unsupported(bp):
+    with bp.Server(4 << 20, max_graphs=2) as srv:
+        with pytest.raises(bp.BpError):
+            srv.submit(inputs.potts_grid(4, 4, 3, 1.0, 0))
+        with pytest.raises(bp.BpError):
+            srv.submit(inputs.ising_grid(4, 4, 1.0, 0), schedule="rbp")
+        with pytest.raises(bp.BpError):
+            srv.submit(inputs.ising_grid(300, 300, 1.0, 0))  # larger than the arena
