@@ -68,45 +68,63 @@ def serving_mix(inputs, np, n, seed=0):
     return mix
 
 
-def serving_bench(bp, inputs, np, torch, args, n=48, max_iters=2000, p=0.5):
+def serving_bench(bp, inputs, np, torch, args, n=48, max_iters=2000, p=0.5, rate=100.0):
     """Batched serving (one launch per iteration for every resident graph) vs one
     graph per bp_run, on the same requests: RnBP, eps = 1e-4, at most 2000
-    iterations per request.  All requests arrive at time 0; latency is each
-    request's completion time."""
+    iterations per request.  Two arrival patterns: a burst (all at time 0) and
+    a Poisson process at `rate` requests/s.  Latency = completion - arrival;
+    submission (the host builds and validates the layout) is inside it."""
     mix = serving_mix(inputs, np, n)
     msgs = sum(2 * len(pr["edges"]) for pr in mix)
+    out = {"requests": n, "messages_total": msgs, "max_iters": max_iters, "poisson_rate": rate}
+    rng = np.random.default_rng(7)
+    arrivals = {"burst": np.zeros(n), "poisson": np.cumsum(rng.exponential(1.0 / rate, n))}
+
+    def stats(lat, makespan):
+        lat = np.asarray(lat)
+        return {"graphs_per_s": n / makespan, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "makespan_s": makespan}
+
+    # one graph per run, in arrival order: execution times once, then each
+    # arrival pattern by queueing on one worker
     torch.cuda.synchronize()
-    # batched
-    with bp.Server(2 << 30, max_graphs=64) as srv:
-        t0 = time.perf_counter()
-        ids = [srv.submit(pr, "rnbp", eps=args.eps, p=p, seed=i, max_iters=max_iters)
-               for i, pr in enumerate(mix)]
-        done = {}
-        while len(done) < n:
-            srv.step(16)
-            now = time.perf_counter() - t0
-            for i in ids:
-                if i not in done and srv.result(i) is not None:
-                    done[i] = now
-        t_batch = time.perf_counter() - t0
-    lat_b = np.array(sorted(done.values()))
-    # one graph at a time
-    t0 = time.perf_counter()
-    lat_s = []
+    dur = []
     for i, pr in enumerate(mix):
+        a = time.perf_counter()
         with bp.Graph(pr) as g:
             g.run("rnbp", eps=args.eps, p=p, seed=i, max_iters=max_iters, check_every=64)
             g.marginals()
-        lat_s.append(time.perf_counter() - t0)
-    t_seq = time.perf_counter() - t0
-    lat_s = np.array(lat_s)
-    return {"requests": n, "messages_total": msgs, "max_iters": max_iters,
-            "batched": {"graphs_per_s": n / t_batch, "p50_ms": float(np.percentile(lat_b, 50) * 1e3),
-                        "p99_ms": float(np.percentile(lat_b, 99) * 1e3), "makespan_s": t_batch},
-            "one_graph_per_run": {"graphs_per_s": n / t_seq,
-                                  "p50_ms": float(np.percentile(lat_s, 50) * 1e3),
-                                  "p99_ms": float(np.percentile(lat_s, 99) * 1e3),
-                                  "makespan_s": t_seq}}
+        dur.append(time.perf_counter() - a)
+    for name, arr in arrivals.items():
+        free, lat = 0.0, []
+        for i in range(n):
+            free = max(free, arr[i]) + dur[i]
+            lat.append(free - arr[i])
+        out.setdefault(name, {})["one_graph_per_run"] = stats(lat, free)
+
+    # batched serving, arrivals replayed in wall-clock time
+    for name, arr in arrivals.items():
+        with bp.Server(2 << 30, max_graphs=64) as srv:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ids, done, nxt = {}, {}, 0
+            while len(done) < n:
+                now = time.perf_counter() - t0
+                while nxt < n and arr[nxt] <= now:
+                    ids[srv.submit(mix[nxt], "rnbp", eps=args.eps, p=p, seed=nxt,
+                                   max_iters=max_iters)] = nxt
+                    nxt += 1
+                if len(ids) > len(done):
+                    srv.step(8)
+                    now = time.perf_counter() - t0
+                    for rid, k in ids.items():
+                        if k not in done and srv.result(rid) is not None:
+                            done[k] = now
+                else:
+                    time.sleep(max(0.0, min(arr[nxt] - now, 0.001)))
+            makespan = time.perf_counter() - t0
+        out[name]["batched"] = stats([done[k] - arr[k] for k in range(n)], makespan)
+    return out
 
 
 def main():

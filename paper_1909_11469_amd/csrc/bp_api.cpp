@@ -338,6 +338,8 @@ struct bp_graph {
     CounterLine* ctr() const { return at<CounterLine>(off.ctr); }
 };
 
+int create_graph_from_layout(HostLayout&& layout, const bp_graph_desc* desc, bp_graph** out);
+
 extern "C" {
 
 void bp_default_opts(bp_run_opts* o) {
@@ -365,13 +367,20 @@ int bp_workspace_bytes(const bp_graph_desc* desc, uint64_t* bytes) {
 int bp_create_graph(const bp_graph_desc* desc, bp_graph** out) {
     if (!out) return fail(BP_EINVAL, "out is NULL");
     *out = nullptr;
+    HostLayout L;
+    int rc = build_layout(desc, L);
+    if (rc != BP_OK) return rc;
+    return create_graph_from_layout(std::move(L), desc, out);
+}
+
+}  // extern "C"
+
+// A graph from an already built (and validated) layout; desc supplies the
+// stream and the optional workspace.
+int create_graph_from_layout(HostLayout&& layout, const bp_graph_desc* desc, bp_graph** out) {
     bp_graph* g = new (std::nothrow) bp_graph();
     if (!g) return fail(BP_ENOMEM, "host allocation failed");
-    int rc = build_layout(desc, g->L);
-    if (rc != BP_OK) {
-        delete g;
-        return rc;
-    }
+    g->L = std::move(layout);
     g->off = plan(g->L);
     g->stream = (hipStream_t)desc->stream;
     hipError_t e = hipGetDevice(&g->device);
@@ -447,6 +456,8 @@ int bp_create_graph(const bp_graph_desc* desc, bp_graph** out) {
     *out = g;
     return BP_OK;
 }
+
+extern "C" {
 
 void bp_destroy_graph(bp_graph* g) {
     if (!g) return;
@@ -818,10 +829,7 @@ namespace {
 
 struct Request {
     int64_t id = 0;
-    // host copies of the caller's arrays
-    std::vector<int32_t> edges;
-    std::vector<double> log_unary, coupling;
-    bp_graph_desc desc{};
+    HostLayout L;  // built and validated at submission
     bp_request req{};
     uint64_t bytes = 0;
     enum State { kQueued, kResident, kRetired } state = kQueued;
@@ -907,15 +915,12 @@ int server_admit(bp_server* s) {
         Request* r = s->queue.front();
         uint64_t off = 0;
         if (!s->alloc.take(r->bytes, &off)) return BP_OK;  // FIFO: wait for room
-        bp_graph_desc d = r->desc;
-        d.edges = r->edges.data();
-        d.log_unary = r->log_unary.data();
-        d.coupling = r->coupling.data();
+        bp_graph_desc d{};
         d.stream = (void*)s->stream;
         d.workspace = s->base + off;
         d.workspace_bytes = r->bytes;
         bp_graph* g = nullptr;
-        const int rc = bp_create_graph(&d, &g);
+        const int rc = create_graph_from_layout(std::move(r->L), &d, &g);
         if (rc != BP_OK) {
             s->alloc.give(off, r->bytes);
             return rc;
@@ -1099,11 +1104,7 @@ int bp_server_submit(bp_server* s, const bp_graph_desc* graph, const bp_request*
                                            (unsigned long long)need, (unsigned long long)s->bytes);
     Request* r = new (std::nothrow) Request();
     if (!r) return fail(BP_ENOMEM, "host allocation failed");
-    const size_t M = (size_t)graph->num_edges, N = (size_t)graph->num_vars;
-    r->edges.assign(graph->edges, graph->edges + 2 * M);
-    r->log_unary.assign(graph->log_unary, graph->log_unary + 2 * N);
-    if (M) r->coupling.assign(graph->coupling, graph->coupling + M);
-    r->desc = *graph;
+    r->L = std::move(L);
     r->req = *req;
     r->bytes = need;
     r->id = s->next_id++;
