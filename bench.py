@@ -242,22 +242,26 @@ def main():
     }
 
     if not args.no_ttc:
-        # time to convergence, RnBP vs LBP, per coupling scale (graph resident)
+        # time to convergence, LBP vs RnBP at several low settings p, per coupling
+        # scale (graph resident; the paper's C is twice this C)
         ttc = {}
+        scheds = [("lbp", 1.0)] + [("rnbp", q) for q in (0.1, 0.3, 0.5)]
         for C in (1.0, 2.5, 4.0):
-            rows = {"lbp": [], "rnbp": []}
+            rows = {}
             for s in range(args.ttc_seeds):
                 pr = inputs.ising_grid(S, S, C, 100 + s)
                 with bp.Graph(pr) as gg:
-                    for sched in ("lbp", "rnbp"):
+                    for sched, q in scheds:
                         torch.cuda.synchronize()
                         a = time.perf_counter()
-                        rr = gg.run(sched, seed=s, **run_kw)
+                        rr = gg.run(sched, eps=args.eps, p=q, seed=s, max_iters=args.max_iters,
+                                    check_every=args.check_every)
                         torch.cuda.synchronize()
-                        rows[sched].append((rr["converged"], time.perf_counter() - a,
-                                            rr["iterations"]))
-                _log(f"bench: ttc C={C} seed={100 + s} lbp={rows['lbp'][-1]} "
-                     f"rnbp={rows['rnbp'][-1]}")
+                        key = sched if sched == "lbp" else f"rnbp_p={q:g}"
+                        rows.setdefault(key, []).append(
+                            (rr["converged"], time.perf_counter() - a, rr["iterations"]))
+                _log(f"bench: ttc C={C} seed={100 + s} " +
+                     " ".join(f"{k}={v[-1][0]}/{v[-1][2]}" for k, v in rows.items()))
             ttc[f"C={C}"] = {
                 k: {"converged": sum(c for c, _, _ in v), "graphs": len(v),
                     "mean_s_converged": (float(np.mean([t for c, t, _ in v if c]))

@@ -980,7 +980,7 @@ int server_upload_list(bp_server* s) {
 
 // Close the run of a finished graph exactly as bp_run closes its own, take its
 // beliefs and statistics, and return its memory.
-int server_retire(bp_server* s, Request* r, const DevState& h) {
+int server_retire(bp_server* s, Request* r) {
     bp_graph* g = r->g;
     BatchGraph& b = s->rec[r->slot];
     const long long last_it = std::min(s->launch - 1 - b.first, b.max_iters);
@@ -992,7 +992,6 @@ int server_retire(bp_server* s, Request* r, const DevState& h) {
     HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost, s->stream),
            "state readback");
     HIP_OK(hipStreamSynchronize(s->stream), "synchronize");
-    (void)h;
     const DevState& st = *g->host_state;
     const bool converged = st.done != 0;
     const long long final_t = converged ? st.conv_t : st.last_t;
@@ -1146,7 +1145,7 @@ int bp_server_step(bp_server* s, int32_t launches, int32_t* finished) {
         const BatchGraph& b = s->rec[r->slot];
         const long long last_it = s->launch - 1 - b.first;
         if (s->h_done[r->slot] || last_it >= b.max_iters) {
-            rc = server_retire(s, r, *r->g->host_state);
+            rc = server_retire(s, r);
             if (rc != BP_OK) return rc;
             ++n;
             removed = true;
