@@ -119,6 +119,21 @@ typedef struct bp_run_opts {
                                  graph's stream: whole chunks of back-to-back launches when
                                  it is the only kernel of an iteration, else every k-th
                                  launch */
+    int32_t sparse;           /* BP_RNBP on K = 2 graphs without oversized nodes (a node
+                                 whose messages exceed one 512-slot tile): re-evaluate
+                                 only the messages out of nodes that received a committed
+                                 message (candidates and residuals of the others are kept).
+                                 0 (default): full evaluation every iteration;
+                                 1: sparse from the first iteration;
+                                 2: full evaluation until n_t <= E / 16 at a host poll,
+                                    sparse from then on.
+                                 Messages, iteration counts and residuals are bitwise those
+                                 of the full evaluation; only `evaluated` differs.  The
+                                 first sparse run allocates 2 bytes per node and 4 per
+                                 message of device memory outside the graph's workspace,
+                                 held until bp_destroy_graph.  Other schedules and layouts:
+                                 BP_EINVAL. */
+    int32_t reserved;
 } bp_run_opts;
 
 typedef struct bp_run_stats {

@@ -54,7 +54,8 @@ class bp_run_opts(ctypes.Structure):
     _fields_ = [("max_iters", ctypes.c_int64), ("check_every", ctypes.c_int32),
                 ("dynamic_p", ctypes.c_int32), ("high_p", ctypes.c_double),
                 ("ratio_threshold", ctypes.c_double), ("warm_start", ctypes.c_int32),
-                ("profile", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("sparse", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class bp_run_stats(ctypes.Structure):
@@ -246,12 +247,16 @@ class Graph:
         return {f: getattr(i, f) for f, _ in i._fields_}
 
     def run(self, schedule="lbp", eps=1e-4, p=1.0, seed=0, max_iters=10000, check_every=16,
-            dynamic_p=True, high_p=1.0, ratio_threshold=0.9, warm_start=False, profile=False):
+            dynamic_p=True, high_p=1.0, ratio_threshold=0.9, warm_start=False, profile=False,
+            sparse=0):
+        """sparse: 0 full evaluation, 1 sparse re-evaluation, 2 full until n_t <= E/16
+        (RnBP on K = 2 graphs only; see bp_run_opts in include/bp.h)."""
         o = bp_default_opts()
         o.max_iters, o.check_every = int(max_iters), int(check_every)
         o.dynamic_p, o.high_p, o.ratio_threshold = int(bool(dynamic_p)), float(high_p), \
             float(ratio_threshold)
         o.warm_start, o.profile = int(bool(warm_start)), int(profile)
+        o.sparse = int(sparse)
         s = bp_run_stats()
         sched = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
         rc = _check(lib.bp_run(self.handle, sched, float(eps), float(p), int(seed),

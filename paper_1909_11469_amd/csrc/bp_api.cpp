@@ -329,6 +329,12 @@ struct bp_graph {
     DevState* host_state = nullptr;  // pinned mirror
     int num_cus = 0;                 // compute units of the device
     int resident[4] = {0, 0, 0, 0};  // log-odds eval blocks resident per CU, by mode
+    // sparse re-evaluation buffers, allocated by the first sparse run:
+    // dirty u8 [N], active-node flag u8 [N], target node int32 [E]
+    char* sparse_mem = nullptr;
+    unsigned char* sp_dirty = nullptr;
+    unsigned char* sp_hasact = nullptr;
+    int* sp_dst = nullptr;
 
     template <typename T>
     T* at(size_t o) const { return reinterpret_cast<T*>(base + o); }
@@ -465,6 +471,7 @@ void bp_destroy_graph(bp_graph* g) {
         DeviceGuard dg(g->device);
         if (g->base) (void)hipStreamSynchronize(g->stream);
         if (g->owns_memory && g->base) (void)hipFree(g->base);
+        if (g->sparse_mem) (void)hipFree(g->sparse_mem);
         if (g->host_state) (void)hipHostFree(g->host_state);
     }
     delete g;
@@ -578,9 +585,37 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     if (schedule == BP_RNBP && o.dynamic_p && !(o.high_p > 0.0 && o.high_p <= 1.0))
         return fail(BP_EINVAL, "high_p must be in (0, 1]");
     if (!std::isfinite(o.ratio_threshold)) return fail(BP_EINVAL, "ratio_threshold not finite");
+    if (o.sparse < 0 || o.sparse > 2) return fail(BP_EINVAL, "sparse must be 0, 1 or 2");
+    if (o.sparse) {
+        if (schedule != BP_RNBP) return fail(BP_EINVAL, "sparse re-evaluation is for BP_RNBP only");
+        if (g->L.layout != kLayoutLogOdds)
+            return fail(BP_EINVAL, "sparse re-evaluation needs K = 2 Ising potentials");
+        if (!g->L.big4.empty())
+            return fail(BP_EINVAL, "sparse re-evaluation needs every node within one tile");
+    }
     DeviceGuard dg(g->device);
     const HostLayout& L = g->L;
     hipStream_t s = g->stream;
+    if (o.sparse && !g->sparse_mem) {
+        const size_t nb = ((size_t)L.N + 255) / 256 * 256;
+        const size_t bytes = 2 * nb + sizeof(int) * (size_t)L.E + 256;
+        char* mem = nullptr;
+        hipError_t e = hipMalloc(&mem, bytes);
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? BP_ENOMEM : BP_EDEVICE,
+                        "sparse buffers (%zu bytes): %s", bytes, hipGetErrorString(e));
+        g->sparse_mem = mem;
+        g->sp_dirty = (unsigned char*)mem;
+        g->sp_hasact = (unsigned char*)(mem + nb);
+        g->sp_dst = (int*)(mem + 2 * nb);
+        EvalArgs b{};
+        b.node_ptr = g->at<int>(g->off.node_ptr);
+        b.rev = g->at<int>(g->off.rev);
+        b.num_nodes = L.N;
+        b.dirty = g->sp_dirty;
+        b.dst = g->sp_dst;
+        HIP_OK(launch_sparse_setup(b, 1, s), "target index");
+    }
     if (!o.warm_start) {
         const float uni = L.layout == kLayoutLogOdds ? 0.0f : 1.0f / (float)L.K;
         HIP_OK(launch_fill(g->cur(), uni, L.E * L.row, s), "fill");
@@ -594,6 +629,19 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     const int mode = schedule == BP_LBP ? kModeLBP : schedule == BP_RBP ? kModeRBP : kModeRnBP;
     long long rbp_k = 0;
     EvalArgs a = run_args(g, schedule, eps, p, seed, o, rbp_k);
+    a.dirty = g->sp_dirty;
+    a.hasact = g->sp_hasact;
+    a.dst = g->sp_dst;
+    // sparse phase: messages committed in place in the buffer that holds m^t
+    bool sparse_now = false;
+    long long sp_it0 = 0;  // first sparse iteration of this run
+    float* sp_buf = nullptr;
+    if (o.sparse == 1) {
+        sparse_now = true;
+        sp_it0 = 0;
+        sp_buf = g->cur();
+        HIP_OK(launch_sparse_setup(a, 0, s), "dirty flags");
+    }
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     HIP_OK(hipEventCreate(&ev0), "event");
@@ -606,7 +654,7 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     std::vector<hipEvent_t> kev;
     std::vector<int> kev_used;
     const long long prof_every = o.profile > 0 ? o.profile : 0;
-    const bool prof_window = prof_every && mode != kModeRBP && a.num_big == 0;
+    bool prof_window = prof_every && mode != kModeRBP && a.num_big == 0 && !sparse_now;
     if (prof_every) {
         kev.resize(2 * (size_t)o.check_every);
         kev_used.assign((size_t)o.check_every, 0);
@@ -627,6 +675,26 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     for (;; ++it) {
         const long long t = t_start + it;
         final_launched = it == o.max_iters;
+        if (sparse_now) {
+            // one sparse iteration: evaluate the dirty nodes, then close and commit
+            a.in_buf[0] = a.in_buf[1] = sp_buf;
+            a.out_buf[0] = a.out_buf[1] = sp_buf;
+            a.t = (unsigned int)t;
+            a.it = it;
+            a.after_final = final_launched ? 1 : 0;
+            a.sp_first = it == sp_it0 ? 1 : 0;
+            HIP_OK(launch_sparse_iteration(a, s), "sparse iteration");
+            ++in_chunk;
+            if (in_chunk == o.check_every || final_launched) {
+                HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost,
+                                      s),
+                       "state readback");
+                HIP_OK(hipStreamSynchronize(s), "synchronize");
+                in_chunk = 0;
+                if (g->host_state->done || final_launched) break;
+            }
+            continue;
+        }
         if (mode == kModeRBP) {
             // frontier residual BP commits in place after the top-k selection
             a.in_buf[0] = a.in_buf[1] = start_buf;
@@ -685,13 +753,39 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
             }
             in_chunk = 0;
             if (g->host_state->done || final_launched) break;
+            if (o.sparse == 2 && (unsigned long long)g->host_state->last_active * 16ull <=
+                                     (unsigned long long)L.E) {
+                // switch to sparse re-evaluation: close evaluation t (as the next
+                // launch's prologue would), find the buffer that holds m^{t+1},
+                // and continue in place with every node dirty
+                a.t = (unsigned int)(t + 1);
+                a.it = it + 1;
+                a.after_final = 0;
+                HIP_OK(launch_close_run(a, s), "close evaluation");
+                HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost,
+                                      s),
+                       "state readback");
+                HIP_OK(hipStreamSynchronize(s), "synchronize");
+                if (g->host_state->done) break;
+                g->cur_pair = (int)((pair0 + it) & 1) ^ 1;
+                g->cur_sel = (int)g->host_state->in_sel[(t + 1) & 3];
+                sp_buf = g->cur();
+                HIP_OK(launch_sparse_setup(a, 0, s), "dirty flags");
+                sparse_now = true;
+                sp_it0 = it + 1;
+                prof_window = false;
+            }
         }
     }
-    // close the last launched evaluation (a no-op if a later prologue already did)
-    a.t = (unsigned int)(t_start + it + 1);
-    a.it = it + 1;
-    a.after_final = final_launched ? 1 : 0;
-    HIP_OK(launch_close_run(a, s), "close run");
+    if (sparse_now) {
+        HIP_OK(launch_sparse_rmax(a, s), "max residual");
+    } else {
+        // close the last launched evaluation (a no-op if a later prologue already did)
+        a.t = (unsigned int)(t_start + it + 1);
+        a.it = it + 1;
+        a.after_final = final_launched ? 1 : 0;
+        HIP_OK(launch_close_run(a, s), "close run");
+    }
     HIP_OK(hipEventRecord(ev1, s), "event record");
     HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost, s),
            "state readback");
@@ -705,7 +799,7 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     const DevState& h = *g->host_state;
     const bool converged = h.done != 0;
     const long long final_t = converged ? h.conv_t : h.last_t;
-    if (mode != kModeRBP) {
+    if (mode != kModeRBP && !sparse_now) {
         g->cur_pair = (int)((pair0 + (final_t - t_start)) & 1);
         g->cur_sel = (int)h.in_sel[final_t & 3];
     }

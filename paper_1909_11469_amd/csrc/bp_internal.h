@@ -65,6 +65,8 @@ struct DevState {
     unsigned int sel_ties;          // keys equal to the final threshold
     unsigned int sel_rank_ties;     // 1 if ties must be ranked by slot
     unsigned int pad2[3];
+    // sparse re-evaluation: n_t by t & 3
+    unsigned long long sp_n[4];
 };
 
 struct EvalArgs {
@@ -109,6 +111,11 @@ struct EvalArgs {
     int tile_nodes_max;         // [E][K] layout: most nodes in one regular tile
     int tile_big;               // [E][K] layout: 1 if some node's slots exceed a tile
     unsigned long long rbp_k;   // RBP frontier size
+    // sparse re-evaluation (K = 2 log-odds layout, RnBP)
+    unsigned char* dirty;       // [N] 1 if a message into the node was committed
+    unsigned char* hasact;      // [N] 1 if a slot of the node has residual > eps
+    int* dst;                   // [E] target node of each slot
+    int sp_first;               // first sparse iteration of a run (stored residuals invalid)
 };
 
 // One graph of a serving batch (device memory).  `a` holds the graph's
@@ -139,6 +146,11 @@ int logodds_blocks_per_cu(int mode);
 hipError_t launch_marginals(int layout, int kp, const int* node_ptr, const int* rev,
                             const float* unary, const float* m, float* out, int N, int K,
                             hipStream_t s);
+// sparse re-evaluation: one iteration (evaluate the dirty nodes, then close and
+// commit), and the per-graph setup (target index, every node dirty)
+hipError_t launch_sparse_iteration(const EvalArgs& a, hipStream_t s);
+hipError_t launch_sparse_setup(const EvalArgs& a, int build_dst, hipStream_t s);
+hipError_t launch_sparse_rmax(const EvalArgs& a, hipStream_t s);  // R_t after a sparse run
 // frontier residual BP selection
 hipError_t launch_rbp_gate(DevState* st, const CounterLine* ctr, int slot_idx, hipStream_t s);
 hipError_t launch_rbp_select(DevState* st, const unsigned int* keys, const int* rev, int E,

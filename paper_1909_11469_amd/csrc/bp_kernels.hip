@@ -1381,6 +1381,293 @@ __global__ void k_marginals_generic(const int* node_ptr, const int* rev, const f
 }
 
 // ---------------------------------------------------------------------------
+// Sparse re-evaluation (K = 2 log-odds layout, RnBP), messages committed in
+// place.  The candidate of Eq. (2) for i -> j depends only on the messages into
+// i (and on i's own old value for the residual), so after a commit only the
+// messages out of nodes that received a committed message ("dirty" nodes) can
+// change.  Every other stored candidate and residual is, bit for bit, what a
+// full evaluation would compute again: the same arithmetic on the same inputs,
+// and a committed message whose source is clean has candidate = message and
+// residual 0.
+//
+// n_t is carried as a running count: the evaluation adds, per re-evaluated
+// slot, (new residual > eps) - (old residual > eps), and the commit subtracts
+// the committed slots; both add into counter set t & 3 of the iteration whose
+// count they change, and the commit of iteration t reads
+// n_t = n_{t-1} + (sum of set t & 3).  R_t is only reported for the last
+// evaluation of a run, so it is taken once, over the stored residuals, after
+// the run.  A node flag records whether any of the node's slots is active, so
+// the commit visits only such nodes.
+// ---------------------------------------------------------------------------
+constexpr int kSparseChunk = 4;  // slots per group of loads (= words of one Philox call)
+constexpr int kSparseGridMax = 1024;  // blocks of the residual-max pass
+
+__device__ __forceinline__ int sparse_grid_stride() { return (int)(gridDim.x * blockDim.x); }
+
+// Block sum of a signed and an unsigned per-thread count, added into counter
+// copy (blockIdx & 63) of set `set`: the signed one into its active count
+// (wrapping modulo 2^64), the unsigned one into sel_a (evaluated slots) or,
+// with `committed`, into sel_b.
+__device__ __forceinline__ void sparse_accumulate(CounterLine* ctr, unsigned int set, int d,
+                                                  unsigned int ev, int* s_d, unsigned int* s_ev,
+                                                  bool committed) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        d += __shfl_xor(d, o, 64);
+        ev += __shfl_xor(ev, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_d[threadIdx.x >> 6] = d;
+        s_ev[threadIdx.x >> 6] = ev;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long D = 0;
+        unsigned long long EV = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            D += s_d[w];
+            EV += s_ev[w];
+        }
+        CounterLine* c = ctr + (set & 3u) * kCounterCopies + (blockIdx.x & (kCounterCopies - 1));
+        if (D) atomicAdd(&c->active, (unsigned long long)D);
+        if (EV) atomicAdd(committed ? &c->sel_b : &c->sel_a, EV);
+    }
+}
+
+// Operands of up to four consecutive slots c .. c+3 of a node ending at s1
+// (indices clamped into the node, so the loads are unconditional).
+struct SparseChunk {
+    float lin[kSparseChunk], J[kSparseChunk], old[kSparseChunk];
+    unsigned int key[kSparseChunk];
+};
+
+__device__ __forceinline__ void sparse_load_lin(const EvalArgs& a, const float* m, int c, int s1,
+                                                float* lin) {
+#pragma unroll
+    for (int k = 0; k < kSparseChunk; ++k) lin[k] = m[a.rev[min(c + k, s1 - 1)]];
+}
+
+__device__ __forceinline__ void sparse_load_chunk(const EvalArgs& a, const float* m, int c, int s1,
+                                                  SparseChunk& d) {
+#pragma unroll
+    for (int k = 0; k < kSparseChunk; ++k) {
+        const int e = min(c + k, s1 - 1);
+        d.lin[k] = m[a.rev[e]];
+        d.J[k] = a.coupling[e];
+        d.old[k] = m[e];
+        d.key[k] = a.keys[e];
+    }
+}
+
+__device__ __forceinline__ void sparse_eval_chunk(const EvalArgs& a, float L, int c, int s1,
+                                                  const SparseChunk& d, unsigned int& act,
+                                                  unsigned int& old_act) {
+    unsigned int unused = 0;
+#pragma unroll
+    for (int k = 0; k < kSparseChunk; ++k) {
+        if (c + k >= s1) break;
+        old_act += (!a.sp_first && __uint_as_float(d.key[k]) > a.eps) ? 1u : 0u;
+        logodds_slot<kModeRBP>(a, OutPtr{a}, L, d.lin[k], d.J[k], d.old[k], c + k, 0u, act, unused,
+                               unused);
+    }
+}
+
+// Iteration t, evaluation: the slots of every dirty node are evaluated again
+// (the incoming messages are summed in slot order, as the tiled kernel sums
+// them; operands are loaded four slots at a time, and a node of at most four
+// slots is evaluated from one set of loads).  sp_first: the first sparse
+// iteration of a run, whose stored residuals are not yet valid (counted as 0).
+__global__ __launch_bounds__(kBlock) void k_sparse_eval(EvalArgs a) {
+    __shared__ int s_d[kBlock / 64];
+    __shared__ unsigned int s_ev[kBlock / 64];
+    if (a.st->done) return;
+    const float* __restrict__ m = a.in_buf[0];
+    int delta = 0;
+    unsigned int ev = 0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.num_nodes; i += sparse_grid_stride()) {
+        if (!a.dirty[i]) continue;
+        a.dirty[i] = 0;
+        const int s0 = a.node_ptr[i], s1 = a.node_ptr[i + 1];
+        const float u = a.unary[i];
+        unsigned int act = 0, old_act = 0;
+        if (s1 > s0) {
+            SparseChunk d;
+            sparse_load_chunk(a, m, s0, s1, d);
+            float L = u;
+#pragma unroll
+            for (int k = 0; k < kSparseChunk; ++k)
+                if (s0 + k < s1) L += d.lin[k];
+            for (int c = s0 + kSparseChunk; c < s1; c += kSparseChunk) {
+                float lin[kSparseChunk];
+                sparse_load_lin(a, m, c, s1, lin);
+#pragma unroll
+                for (int k = 0; k < kSparseChunk; ++k)
+                    if (c + k < s1) L += lin[k];
+            }
+            sparse_eval_chunk(a, L, s0, s1, d, act, old_act);
+            for (int c = s0 + kSparseChunk; c < s1; c += kSparseChunk) {
+                sparse_load_chunk(a, m, c, s1, d);
+                sparse_eval_chunk(a, L, c, s1, d, act, old_act);
+            }
+        }
+        a.hasact[i] = act ? 1 : 0;
+        delta += (int)act - (int)old_act;
+        ev += (unsigned int)(s1 - s0);
+    }
+    sparse_accumulate(a.ctr, a.t, delta, ev, s_d, s_ev, false);
+}
+
+// Iteration t, commit.  Every block forms n_t and n_{t-1} and takes p_t from
+// EdgeRatio = n_t / n_{t-1} (Sec. IV-A); block 0 also closes evaluation t
+// (IsConverged, statistics including the commits of iteration t - 1, n_t kept
+// for the next iteration) and clears counter set t + 2.  Then the active slots of flagged nodes are drawn (the
+// same Philox words as the tiled kernel, one call per four slots) and the kept
+// ones committed in place; their targets are marked dirty.  After the last
+// allowed commit (after_final) the evaluation is closed and nothing committed.
+// Each thread takes one node; its flag, slot range and first four residuals
+// are loaded before the counters are summed, so the two latencies overlap.
+__global__ __launch_bounds__(kBlock) void k_sparse_commit(EvalArgs a) {
+    __shared__ unsigned long long s_n[3];
+    __shared__ int s_d[kBlock / 64];
+    __shared__ unsigned int s_ev[kBlock / 64];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const bool mine = i < a.num_nodes && a.hasact[i];
+    int s0 = 0, s1 = 0;
+    unsigned int key[kSparseChunk] = {0u, 0u, 0u, 0u};
+    if (mine) {
+        s0 = a.node_ptr[i];
+        s1 = a.node_ptr[i + 1];
+#pragma unroll
+        for (int k = 0; k < kSparseChunk; ++k) key[k] = a.keys[min(s0 + k, s1 - 1)];
+    }
+    // wave 0 reads the done flag once for the block (block 0 may set it during
+    // this launch, so the other waves must not read it themselves)
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const unsigned int done = a.st->done;
+        const CounterLine* c0 = a.ctr + (a.t & 3u) * kCounterCopies + lane;
+        const long long d = (long long)wave_sum64(c0->active);
+        const long long base = a.sp_first ? 0ll : (long long)a.st->sp_n[(a.t - 1u) & 3u];
+        const unsigned long long n1 = (unsigned long long)(base + d);
+        long long n2;
+        if (!a.sp_first)
+            n2 = (long long)a.st->sp_n[(a.t - 1u) & 3u];
+        else if (a.it >= 1)  // switched from the full evaluation: its count of t - 1
+            n2 = (long long)wave_sum64(a.ctr[((a.t - 1u) & 3u) * kCounterCopies + lane].active);
+        else
+            n2 = a.prev_active_host;
+        if (blockIdx.x == 0 && !done) {
+            const unsigned long long ev = wave_sum64(c0->sel_a);
+            // messages committed by iteration t - 1 (none on the first sparse iteration)
+            const unsigned long long cm_prev = a.sp_first ? 0ull : wave_sum64(c0->sel_b);
+            CounterLine* z = a.ctr + ((a.t + 2u) & 3u) * kCounterCopies + lane;
+            z->active = 0ull;
+            z->sel_a = 0ull;
+            z->sel_b = 0ull;
+            z->rmax = 0u;
+            if (lane == 0) {
+                DevState* st = a.st;
+                atomicAdd(&st->evaluated, ev);
+                atomicAdd(&st->evals, 1ull);
+                if (cm_prev) atomicAdd(&st->committed, cm_prev);
+                st->sp_n[a.t & 3u] = n1;
+                st->last_t = (long long)a.t;
+                st->last_active = n1;
+                st->last_rmax = 0u;  // taken after the run
+                st->last_prev = n2;
+                if (n1 == 0ull) {
+                    st->done = 1u;
+                    st->conv_t = (long long)a.t;
+                } else if (!a.after_final) {
+                    atomicAdd(&st->iterations, 1ull);
+                }
+            }
+        }
+        if (lane == 0) {
+            s_n[0] = n1;
+            s_n[1] = (unsigned long long)n2;
+            s_n[2] = done;
+        }
+    }
+    __syncthreads();
+    const unsigned long long n1 = s_n[0];
+    if (s_n[2] || n1 == 0ull || a.after_final) return;
+    const unsigned int thr = select_outcome(a, n1, (long long)s_n[1]) ? a.thr_b : a.thr_a;
+    float* __restrict__ m = a.out_buf[0];
+    unsigned int cm = 0;
+    if (mine) {
+        unsigned int left = 0;
+        for (int c = s0; c < s1; c += kSparseChunk) {
+            if (c != s0) {
+#pragma unroll
+                for (int k = 0; k < kSparseChunk; ++k) key[k] = a.keys[min(c + k, s1 - 1)];
+            }
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < kSparseChunk; ++k)
+                any |= c + k < s1 && __uint_as_float(key[k]) > a.eps;
+            if (!any) continue;
+            const uint4 w = philox4((unsigned int)i, (unsigned int)(c - s0) >> 2, a.t, a.key0, a.key1);
+            const unsigned int u[kSparseChunk] = {w.x >> 8, w.y >> 8, w.z >> 8, w.w >> 8};
+            bool take[kSparseChunk];
+            float cv[kSparseChunk];
+            int dv[kSparseChunk];
+#pragma unroll
+            for (int k = 0; k < kSparseChunk; ++k) {
+                const bool act = c + k < s1 && __uint_as_float(key[k]) > a.eps;
+                take[k] = act && u[k] < thr;
+                left += act && !take[k];
+                if (take[k]) {
+                    cv[k] = a.cand[c + k];
+                    dv[k] = a.dst[c + k];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kSparseChunk; ++k) {
+                if (!take[k]) continue;
+                m[c + k] = cv[k];
+                a.keys[c + k] = 0u;
+                a.dirty[dv[k]] = 1;
+                ++cm;
+            }
+        }
+        if (!left) a.hasact[i] = 0;
+    }
+    // the committed slots leave the count of iteration t + 1; their number is
+    // added to the statistics when iteration t + 1 is closed
+    sparse_accumulate(a.ctr, a.t + 1u, -(int)cm, cm, s_d, s_ev, true);
+}
+
+// Per-graph setup: the target of each slot (slot rev[e] carries the reverse
+// message, whose target is the source of e), then every node dirty.
+__global__ __launch_bounds__(kBlock) void k_sparse_setup(EvalArgs a, int build_dst) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.num_nodes) return;
+    if (build_dst) {
+        for (int e = a.node_ptr[i]; e < a.node_ptr[i + 1]; ++e) a.dst[a.rev[e]] = i;
+    }
+    a.dirty[i] = 1;
+}
+
+// After a sparse run: R_t of its last evaluation, the largest stored residual
+// (no commit followed that evaluation, so the stored residuals are its own).
+// One atomic per block.
+__global__ __launch_bounds__(kBlock) void k_sparse_rmax(EvalArgs a) {
+    __shared__ unsigned int s_r[kBlock / 64];
+    unsigned int r = 0;
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < (long long)a.num_messages;
+         e += (long long)gridDim.x * kBlock)
+        r = max(r, a.keys[e]);
+    r = wave_max32(r);
+    if ((threadIdx.x & 63) == 0) s_r[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) r = max(r, s_r[w]);
+        if (r) atomicMax(&a.st->last_rmax, r);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Greedy top-k for frontier residual BP: most-significant-digit radix select
 // over the FP32 bit patterns of the residuals (monotone for values >= 0),
 // 4 passes of 8 bits, then a commit that takes every key above the threshold
@@ -1674,6 +1961,29 @@ hipError_t launch_marginals(int layout, int kp, const int* node_ptr, const int* 
         k_marginals_logodds<<<grid, 256, 0, s>>>(node_ptr, rev, unary, m, out, N);
     else
         k_marginals_generic<<<grid, 256, 0, s>>>(node_ptr, rev, unary, m, out, N, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_sparse_iteration(const EvalArgs& a, hipStream_t s) {
+    // at least one block, so that a graph without slots still closes its
+    // evaluation (n_t = 0)
+    const int grid = a.num_nodes > 0 ? (a.num_nodes + kBlock - 1) / kBlock : 1;
+    k_sparse_eval<<<grid, kBlock, 0, s>>>(a);
+    k_sparse_commit<<<grid, kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sparse_rmax(const EvalArgs& a, hipStream_t s) {
+    long long g = ((long long)a.num_messages + kBlock - 1) / kBlock;
+    const int grid = g < 1 ? 1 : g > kSparseGridMax ? kSparseGridMax : (int)g;
+    k_sparse_rmax<<<grid, kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sparse_setup(const EvalArgs& a, int build_dst, hipStream_t s) {
+    const int grid = (a.num_nodes + kBlock - 1) / kBlock;
+    if (grid <= 0) return hipSuccess;
+    k_sparse_setup<<<grid, kBlock, 0, s>>>(a, build_dst);
     return hipGetLastError();
 }
 
