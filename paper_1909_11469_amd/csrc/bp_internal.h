@@ -58,7 +58,7 @@ struct DevState {
     unsigned long long iterations;  // commits in this run
     unsigned long long evals;       // evaluations closed in this run
     // greedy top-k selection (frontier residual BP)
-    unsigned int hist[4][256];      // digit histograms of the 4 radix passes
+    unsigned int hist[16][256];     // copies of the digit histogram of a radix pass
     unsigned int sel_prefix;        // key bits fixed so far
     unsigned int sel_mask;
     unsigned int sel_krem;          // how many more keys to take among the prefix

@@ -1683,52 +1683,111 @@ __global__ void k_rbp_gate(DevState* st, const CounterLine* ctr, int slot) {
     if (threadIdx.x == 0) st->rbp_skip = (st->done || n == 0ull) ? 1u : 0u;
 }
 
+// Keys per thread of a histogram pass and positions per thread of the tie
+// count and the commit: loaded as four 16-byte vectors, so that a thread's
+// loads are all in flight at once.
+constexpr int kSelPer = 16;
+constexpr int kHistCopies = 16;  // copies of the global digit histogram
+static_assert(kCommitChunk == kSelBlock * kSelPer, "one commit chunk per block");
+
+// The keys (or slot indices) base[q0 .. q0+15], clamped to n (entries past n
+// are left unchanged).  base is 16-byte aligned (arena offsets are multiples
+// of 256 bytes).
+template <class T>
+__device__ __forceinline__ void sel_load16(const T* base, long long q0, long long n, T* v) {
+    if (q0 + kSelPer <= n) {
+        const uint4* p = (const uint4*)(base + q0);
+#pragma unroll
+        for (int j = 0; j < kSelPer / 4; ++j) {
+            const uint4 w = p[j];
+            v[4 * j + 0] = (T)w.x;
+            v[4 * j + 1] = (T)w.y;
+            v[4 * j + 2] = (T)w.z;
+            v[4 * j + 3] = (T)w.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j)
+            if (q0 + j < n) v[j] = base[q0 + j];
+    }
+}
+
+// Add 1 to LDS bin `bin` for every lane with `on`.  Residual keys share
+// their leading digits, so most lanes of a wave hit one bin: the lanes whose
+// bin equals the first active lane's are counted by a ballot and one atomic,
+// the rest add individually.
+__device__ __forceinline__ void lds_count(unsigned int* h, unsigned int bin, bool on) {
+    const unsigned long long act = __ballot(on);
+    if (!act) return;
+    const int lead = __ffsll((long long)act) - 1;
+    const unsigned int lb = (unsigned int)__shfl((int)bin, lead, 64);
+    const bool same = on && bin == lb;
+    const unsigned long long sm = __ballot(same);
+    if ((int)(threadIdx.x & 63) == lead) atomicAdd(&h[lb], (unsigned int)__popcll(sm));
+    if (on && !same) atomicAdd(&h[bin], 1u);
+}
+
+// One pass of the radix select: histogram of digit `pass` (8 bits, from the
+// top) of the keys that match the prefix fixed so far, added into one of
+// kHistCopies copies of the global histogram (by block index) so that blocks
+// do not queue on one address.
 __global__ __launch_bounds__(kSelBlock) void k_rbp_hist(DevState* st, const unsigned int* keys,
-                                                        int E, int pass, int slot) {
+                                                        int E, int pass, unsigned int* ghist) {
     __shared__ unsigned int h[256];
     if (st->rbp_skip) return;
-    for (int i = threadIdx.x; i < 256; i += kSelBlock) h[i] = 0u;
+    h[threadIdx.x] = 0u;
     __syncthreads();
     const unsigned int prefix = pass ? st->sel_prefix : 0u;
     const unsigned int mask = pass ? st->sel_mask : 0u;
     const int shift = 24 - 8 * pass;
-    for (int e = blockIdx.x * kSelBlock + threadIdx.x; e < E; e += gridDim.x * kSelBlock) {
-        const unsigned int k = keys[e];
-        if ((k & mask) == prefix) atomicAdd(&h[(k >> shift) & 255u], 1u);
-    }
+    const long long q0 = ((long long)blockIdx.x * kSelBlock + threadIdx.x) * kSelPer;
+    unsigned int v[kSelPer];
+    sel_load16(keys, q0, (long long)E, v);
+#pragma unroll
+    for (int j = 0; j < kSelPer; ++j)
+        lds_count(h, (v[j] >> shift) & 255u, q0 + j < E && (v[j] & mask) == prefix);
     __syncthreads();
-    for (int i = threadIdx.x; i < 256; i += kSelBlock)
-        if (h[i]) atomicAdd(&st->hist[pass][i], h[i]);
+    if (h[threadIdx.x])
+        atomicAdd(&ghist[(blockIdx.x & (kHistCopies - 1)) * 256 + threadIdx.x], h[threadIdx.x]);
 }
 
+// Pick the digit of pass `pass`: the largest b whose suffix count S(b) (keys
+// with digit >= b) reaches the number still to take, digit 0 if none; clear
+// the histogram copies for the next pass.
 __global__ __launch_bounds__(kSelBlock) void k_rbp_scan(DevState* st, int pass, unsigned int k,
-                                                        int slot) {
+                                                        unsigned int* ghist) {
     __shared__ unsigned int h[256];
     if (st->rbp_skip) return;
-    const int i = threadIdx.x;
-    h[i] = st->hist[pass][i];
-    st->hist[pass][i] = 0u;
+    const int b = threadIdx.x;
+    unsigned int hb = 0;
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c) {
+        hb += ghist[c * 256 + b];
+        ghist[c * 256 + b] = 0u;
+    }
+    h[b] = hb;
     __syncthreads();
-    if (i == 0) {
-        unsigned int krem = pass ? st->sel_krem : k;
-        unsigned int prefix = pass ? st->sel_prefix : 0u;
-        unsigned int mask = pass ? st->sel_mask : 0u;
+    for (int o = 1; o < 256; o <<= 1) {
+        const unsigned int add = b + o < 256 ? h[b + o] : 0u;
+        __syncthreads();
+        h[b] += add;
+        __syncthreads();
+    }
+    const unsigned int krem = pass ? st->sel_krem : k;
+    const unsigned int S = h[b];
+    const unsigned int S1 = b < 255 ? h[b + 1] : 0u;
+    const bool pick = b == 0 ? S1 < krem : (S >= krem && S1 < krem);
+    if (pick) {
+        const unsigned int prefix = pass ? st->sel_prefix : 0u;
+        const unsigned int mask = pass ? st->sel_mask : 0u;
         const int shift = 24 - 8 * pass;
-        unsigned int above = 0u;
-        int b = 255;
-        for (; b > 0; --b) {
-            if (above + h[b] >= krem) break;
-            above += h[b];
-        }
-        krem -= above;
-        prefix |= (unsigned int)b << shift;
-        mask |= 0xFFu << shift;
-        st->sel_prefix = prefix;
-        st->sel_mask = mask;
-        st->sel_krem = krem;
+        const unsigned int left = krem - S1;
+        st->sel_prefix = prefix | ((unsigned int)b << shift);
+        st->sel_mask = mask | (0xFFu << shift);
+        st->sel_krem = left;
         if (pass == 3) {
-            st->sel_ties = h[b];
-            st->sel_rank_ties = (h[b] != krem) ? 1u : 0u;
+            st->sel_ties = hb;
+            st->sel_rank_ties = (hb != left) ? 1u : 0u;
         }
     }
 }
@@ -1736,85 +1795,137 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_scan(DevState* st, int pass, 
 // Ties at the threshold key are taken in (target, source) order.  Slots are
 // ordered by (source, target), so position p visits the message in slot rev[p],
 // whose (target, source) is the (source, target) of slot p: walking positions
-// in order walks tied messages in (target, source) order.
+// in order walks tied messages in (target, source) order.  Each block counts
+// the ties among its kCommitChunk positions.
 __global__ __launch_bounds__(kSelBlock) void k_rbp_tiecount(DevState* st, const unsigned int* keys,
-                                                            const int* rev, int E, int slot,
+                                                            const int* rev, int E,
                                                             unsigned int* block_ties) {
     __shared__ unsigned int part[kSelBlock / 64];
     if (st->rbp_skip || !st->sel_rank_ties) return;
     const unsigned int T = st->sel_prefix;
-    const int beg = blockIdx.x * kCommitChunk;
-    const int end = min(E, beg + kCommitChunk);
+    const long long q0 = (long long)blockIdx.x * kCommitChunk + (long long)threadIdx.x * kSelPer;
+    int e[kSelPer];
+    sel_load16(rev, q0, (long long)E, e);
     unsigned int c = 0;
-    for (int q = beg + threadIdx.x; q < end; q += kSelBlock) c += keys[rev[q]] == T;
+#pragma unroll
+    for (int j = 0; j < kSelPer; ++j)
+        if (q0 + j < E) c += keys[e[j]] == T;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned int s = 0;
-        for (int i = 0; i < kSelBlock / 64; ++i) s += part[i];
-        block_ties[blockIdx.x] = s;
+        unsigned int sum = 0;
+        for (int i = 0; i < kSelBlock / 64; ++i) sum += part[i];
+        block_ties[blockIdx.x] = sum;
     }
 }
 
-__global__ __launch_bounds__(kSelBlock) void k_rbp_tiescan(DevState* st, int slot,
-                                                           unsigned int* block_ties, int nb) {
+// Exclusive prefix sums of the nb block tie counts, in place (one block: each
+// thread takes a contiguous run, the run totals are scanned in LDS).
+__global__ __launch_bounds__(kSelBlock) void k_rbp_tiescan(DevState* st, unsigned int* block_ties,
+                                                           int nb) {
+    __shared__ unsigned int part[kSelBlock];
     if (st->rbp_skip || !st->sel_rank_ties) return;
-    if (threadIdx.x == 0) {
-        unsigned int run = 0;
-        for (int b = 0; b < nb; ++b) {
-            const unsigned int v = block_ties[b];
-            block_ties[b] = run;
-            run += v;
-        }
+    const int per = (nb + kSelBlock - 1) / kSelBlock;
+    const int r0 = threadIdx.x * per, r1 = min(nb, r0 + per);
+    unsigned int run = 0;
+    for (int i = r0; i < r1; ++i) run += block_ties[i];
+    part[threadIdx.x] = run;
+    __syncthreads();
+    for (int o = 1; o < kSelBlock; o <<= 1) {
+        const unsigned int add = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    unsigned int acc = part[threadIdx.x] - run;
+    for (int i = r0; i < r1; ++i) {
+        const unsigned int v = block_ties[i];
+        block_ties[i] = acc;
+        acc += v;
     }
 }
 
+// Commit the frontier: every key above the threshold, and among keys equal to
+// it the first sel_krem in position order (ranked ties) or all of them.  A
+// thread takes kSelPer consecutive positions; the ties before it come from an
+// exclusive scan over the block's threads plus the block's offset.
 __global__ __launch_bounds__(kSelBlock) void k_rbp_commit(DevState* st, const unsigned int* keys,
                                                           const int* rev, const float* cand,
                                                           float* m, int E, int row, int all,
-                                                          int slot,
                                                           const unsigned int* block_ties) {
-    __shared__ unsigned int wsum[kSelBlock / 64];
+    __shared__ unsigned int part[kSelBlock / 64];
     if (st->rbp_skip) return;
-    const int beg = blockIdx.x * kCommitChunk;
-    const int end = min(E, beg + kCommitChunk);
     const unsigned int T = st->sel_prefix;
     const bool rank = !all && st->sel_rank_ties;
     const unsigned int krem = st->sel_krem;
-    unsigned int offset = rank ? block_ties[blockIdx.x] : 0u;
-    for (int base = beg; base < end; base += kSelBlock) {
-        const int q = base + threadIdx.x;
-        // with ranked ties, position q holds the message in slot rev[q]
-        const int e = (rank && q < end) ? rev[q] : q;
-        bool take = false, tie = false;
-        if (q < end) {
-            if (all) {
-                take = true;
-            } else {
-                const unsigned int k = keys[e];
-                take = k > T;
-                tie = k == T;
-                if (tie && !rank) take = true;
-            }
-        }
+    const long long q0 = (long long)blockIdx.x * kCommitChunk + (long long)threadIdx.x * kSelPer;
+    int e[kSelPer];
+    if (rank) {
+        sel_load16(rev, q0, (long long)E, e);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j) e[j] = (int)(q0 + j);
+    }
+    unsigned int take = 0, tie = 0;  // bit j: position q0 + j
+    if (all) {
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j)
+            if (q0 + j < E) take |= 1u << j;
+    } else {
+        unsigned int kv[kSelPer];
         if (rank) {
-            const unsigned long long mk = __ballot(tie);
-            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-            if (lane == 0) wsum[w] = (unsigned int)__popcll(mk);
-            __syncthreads();
-            unsigned int before = offset;
-            for (int i = 0; i < w; ++i) before += wsum[i];
-            before += (unsigned int)__popcll(mk & ((1ull << lane) - 1ull));
-            if (tie && before < krem) take = true;
-            unsigned int tot = 0;
-            for (int i = 0; i < kSelBlock / 64; ++i) tot += wsum[i];
-            __syncthreads();
-            offset += tot;
+#pragma unroll
+            for (int j = 0; j < kSelPer; ++j) kv[j] = q0 + j < E ? keys[e[j]] : 0u;
+        } else {
+            sel_load16(keys, q0, (long long)E, kv);  // positions are slots: contiguous
         }
-        if (take)
-            for (int x = 0; x < row; ++x) m[(long long)e * row + x] = cand[(long long)e * row + x];
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j) {
+            if (q0 + j >= E) continue;
+            if (kv[j] > T) take |= 1u << j;
+            if (kv[j] == T) tie |= 1u << j;
+        }
+        if (!rank) take |= tie;
+    }
+    if (rank) {
+        // ties before this thread: inclusive scan within the wave, then the
+        // totals of the lower waves
+        const unsigned int c = (unsigned int)__popc(tie);
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        unsigned int x = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned int y = (unsigned int)__shfl_up((int)x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) part[w] = x;
+        __syncthreads();
+        unsigned int before = block_ties[blockIdx.x] + x - c;
+        for (int i = 0; i < w; ++i) before += part[i];
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j) {
+            if (!(tie >> j & 1u)) continue;
+            if (before < krem) take |= 1u << j;
+            ++before;
+        }
+    }
+    if (!take) return;
+    if (row == 1) {
+        float cv[kSelPer];
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j)
+            if (take >> j & 1u) cv[j] = cand[e[j]];
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j)
+            if (take >> j & 1u) m[e[j]] = cv[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j)
+            if (take >> j & 1u)
+                for (int x = 0; x < row; ++x)
+                    m[(long long)e[j] * row + x] = cand[(long long)e[j] * row + x];
     }
 }
 
@@ -1995,26 +2106,26 @@ hipError_t launch_rbp_gate(DevState* st, const CounterLine* ctr, int slot_idx, h
 hipError_t launch_rbp_select(DevState* st, const unsigned int* keys, const int* rev, int E,
                              unsigned int k, int slot_idx, unsigned int* block_ties,
                              hipStream_t s) {
-    int grid = (E + kSelBlock * 16 - 1) / (kSelBlock * 16);
-    if (grid < 1) grid = 1;
-    if (grid > 4096) grid = 4096;
-    for (int pass = 0; pass < 4; ++pass) {
-        k_rbp_hist<<<grid, kSelBlock, 0, s>>>(st, keys, E, pass, slot_idx);
-        k_rbp_scan<<<1, kSelBlock, 0, s>>>(st, pass, k, slot_idx);
-    }
+    (void)slot_idx;
     const int nb = (E + kCommitChunk - 1) / kCommitChunk;
-    k_rbp_tiecount<<<nb > 0 ? nb : 1, kSelBlock, 0, s>>>(st, keys, rev, E, slot_idx, block_ties);
-    k_rbp_tiescan<<<1, kSelBlock, 0, s>>>(st, slot_idx, block_ties, nb);
+    const int grid = nb > 0 ? nb : 1;
+    unsigned int* ghist = &st->hist[0][0];
+    for (int pass = 0; pass < 4; ++pass) {
+        k_rbp_hist<<<grid, kSelBlock, 0, s>>>(st, keys, E, pass, ghist);
+        k_rbp_scan<<<1, kSelBlock, 0, s>>>(st, pass, k, ghist);
+    }
+    k_rbp_tiecount<<<grid, kSelBlock, 0, s>>>(st, keys, rev, E, block_ties);
+    k_rbp_tiescan<<<1, kSelBlock, 0, s>>>(st, block_ties, nb);
     return hipGetLastError();
 }
 
 hipError_t launch_rbp_commit(DevState* st, const unsigned int* keys, const int* rev,
                              const float* cand, float* m, int E, int row, int all, int slot_idx,
                              const unsigned int* block_ties, hipStream_t s) {
+    (void)slot_idx;
     const int nb = (E + kCommitChunk - 1) / kCommitChunk;
     if (nb <= 0) return hipSuccess;
-    k_rbp_commit<<<nb, kSelBlock, 0, s>>>(st, keys, rev, cand, m, E, row, all, slot_idx,
-                                          block_ties);
+    k_rbp_commit<<<nb, kSelBlock, 0, s>>>(st, keys, rev, cand, m, E, row, all, block_ties);
     return hipGetLastError();
 }
 
