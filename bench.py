@@ -148,6 +148,8 @@ def main():
                     help="run one 256 MiB device-to-device copy kernel first (a known-size "
                          "reference for hardware byte counters)")
     ap.add_argument("--ttc-seeds", type=int, default=3)
+    ap.add_argument("--ttc-check-every", type=int, default=16,
+                    help="convergence poll interval of the time-to-convergence runs")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -242,31 +244,36 @@ def main():
     }
 
     if not args.no_ttc:
-        # time to convergence, LBP vs RnBP at several low settings p, per coupling
-        # scale (graph resident; the paper's C is twice this C)
+        # time to convergence, LBP vs RnBP at several low settings p, and RnBP
+        # with sparse re-evaluation once n_t <= E / 16 (bitwise the same run),
+        # per coupling scale (graph resident; the paper's C is twice this C)
         ttc = {}
-        scheds = [("lbp", 1.0)] + [("rnbp", q) for q in (0.1, 0.3, 0.5)]
+        scheds = ([("lbp", 1.0, 0)] + [("rnbp", q, 0) for q in (0.1, 0.3, 0.5)] +
+                  [("rnbp", 0.5, 2)])
         for C in (1.0, 2.5, 4.0):
             rows = {}
             for s in range(args.ttc_seeds):
                 pr = inputs.ising_grid(S, S, C, 100 + s)
                 with bp.Graph(pr) as gg:
-                    for sched, q in scheds:
+                    for sched, q, sp in scheds:
                         torch.cuda.synchronize()
                         a = time.perf_counter()
                         rr = gg.run(sched, eps=args.eps, p=q, seed=s, max_iters=args.max_iters,
-                                    check_every=args.check_every)
+                                    check_every=args.ttc_check_every, sparse=sp)
                         torch.cuda.synchronize()
                         key = sched if sched == "lbp" else f"rnbp_p={q:g}"
+                        key += "_sparse" if sp else ""
                         rows.setdefault(key, []).append(
-                            (rr["converged"], time.perf_counter() - a, rr["iterations"]))
+                            (rr["converged"], time.perf_counter() - a, rr["iterations"],
+                             rr["evaluated"]))
                 _log(f"bench: ttc C={C} seed={100 + s} " +
                      " ".join(f"{k}={v[-1][0]}/{v[-1][2]}" for k, v in rows.items()))
             ttc[f"C={C}"] = {
-                k: {"converged": sum(c for c, _, _ in v), "graphs": len(v),
-                    "mean_s_converged": (float(np.mean([t for c, t, _ in v if c]))
-                                         if any(c for c, _, _ in v) else None),
-                    "mean_iterations": float(np.mean([i for _, _, i in v]))}
+                k: {"converged": sum(r[0] for r in v), "graphs": len(v),
+                    "mean_s_converged": (float(np.mean([r[1] for r in v if r[0]]))
+                                         if any(r[0] for r in v) else None),
+                    "mean_iterations": float(np.mean([r[2] for r in v])),
+                    "mean_evaluated": float(np.mean([r[3] for r in v]))}
                 for k, v in rows.items()}
         out["time_to_convergence"] = ttc
 

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -312,6 +313,10 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
 }
 
 }  // namespace
+
+// The leading fields of DevState the host reads after a run or at a poll
+// (everything before the selection histograms).
+constexpr size_t kStateReadback = offsetof(DevState, hist);
 
 struct bp_graph {
     HostLayout L;
@@ -686,7 +691,7 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
             HIP_OK(launch_sparse_iteration(a, s), "sparse iteration");
             ++in_chunk;
             if (in_chunk == o.check_every || final_launched) {
-                HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost,
+                HIP_OK(hipMemcpyAsync(g->host_state, g->st(), kStateReadback, hipMemcpyDeviceToHost,
                                       s),
                        "state readback");
                 HIP_OK(hipStreamSynchronize(s), "synchronize");
@@ -734,7 +739,7 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
         ++in_chunk;
         if (in_chunk == o.check_every || final_launched) {
             if (prof_window) HIP_OK(hipEventRecord(kev[1], s), "event record");
-            HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost, s),
+            HIP_OK(hipMemcpyAsync(g->host_state, g->st(), kStateReadback, hipMemcpyDeviceToHost, s),
                    "state readback");
             HIP_OK(hipStreamSynchronize(s), "synchronize");
             if (prof_window) {
@@ -762,7 +767,7 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
                 a.it = it + 1;
                 a.after_final = 0;
                 HIP_OK(launch_close_run(a, s), "close evaluation");
-                HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost,
+                HIP_OK(hipMemcpyAsync(g->host_state, g->st(), kStateReadback, hipMemcpyDeviceToHost,
                                       s),
                        "state readback");
                 HIP_OK(hipStreamSynchronize(s), "synchronize");
@@ -787,7 +792,7 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
         HIP_OK(launch_close_run(a, s), "close run");
     }
     HIP_OK(hipEventRecord(ev1, s), "event record");
-    HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost, s),
+    HIP_OK(hipMemcpyAsync(g->host_state, g->st(), kStateReadback, hipMemcpyDeviceToHost, s),
            "state readback");
     HIP_OK(hipStreamSynchronize(s), "synchronize");
     float total_ms = 0.0f;
@@ -1083,7 +1088,7 @@ int server_retire(bp_server* s, Request* r) {
     a.it = last_it + 1;
     a.after_final = last_it == b.max_iters ? 1 : 0;
     HIP_OK(launch_close_run(a, s->stream), "close run");
-    HIP_OK(hipMemcpyAsync(g->host_state, g->st(), sizeof(DevState), hipMemcpyDeviceToHost, s->stream),
+    HIP_OK(hipMemcpyAsync(g->host_state, g->st(), kStateReadback, hipMemcpyDeviceToHost, s->stream),
            "state readback");
     HIP_OK(hipStreamSynchronize(s->stream), "synchronize");
     const DevState& st = *g->host_state;

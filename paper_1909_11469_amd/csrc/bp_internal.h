@@ -19,7 +19,10 @@ constexpr int kBlock = BP_BLOCK;
 #endif
 constexpr int kTileSlotsLogOdds = BP_TILE_SLOTS_LOGODDS;  // K = 2 log-odds layout
 constexpr int kTileNodesLogOdds = kTileSlotsLogOdds / 2;  // nodes per log-odds tile
-constexpr int kTileFloatsGeneric = 4096; // [E][K] layout: tile slots = this / K
+#ifndef BP_TILE_FLOATS_GENERIC
+#define BP_TILE_FLOATS_GENERIC 4096
+#endif
+constexpr int kTileFloatsGeneric = BP_TILE_FLOATS_GENERIC;  // [E][K] layout: tile slots = this / K
 constexpr int kTileNodesMax = 2048;      // nodes per tile (owner index fits in u16)
 constexpr int kMaxK = 64;
 
