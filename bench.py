@@ -248,8 +248,8 @@ def main():
         # with sparse re-evaluation once n_t <= E / 16 (bitwise the same run),
         # per coupling scale (graph resident; the paper's C is twice this C)
         ttc = {}
-        scheds = ([("lbp", 1.0, 0)] + [("rnbp", q, 0) for q in (0.1, 0.3, 0.5)] +
-                  [("rnbp", 0.5, 2)])
+        scheds = ([("lbp", 1.0, 0)] + [("rnbp", q, 0) for q in (0.1, 0.3, 0.5, 1.0)] +
+                  [("rnbp", 0.5, 2)] + [("rbp", q, 0) for q in (0.1, 0.3, 0.5)])
         for C in (1.0, 2.5, 4.0):
             rows = {}
             for s in range(args.ttc_seeds):
@@ -261,7 +261,7 @@ def main():
                         rr = gg.run(sched, eps=args.eps, p=q, seed=s, max_iters=args.max_iters,
                                     check_every=args.ttc_check_every, sparse=sp)
                         torch.cuda.synchronize()
-                        key = sched if sched == "lbp" else f"rnbp_p={q:g}"
+                        key = sched if sched == "lbp" else f"{sched}_p={q:g}"
                         key += "_sparse" if sp else ""
                         rows.setdefault(key, []).append(
                             (rr["converged"], time.perf_counter() - a, rr["iterations"],
@@ -298,22 +298,45 @@ def main():
                 ("er_200k_deg6_C2.5", inputs.er_graph(200000, 6.0, 2.5, 0), 0.3, 1000),
                 ("potts_500x500_K32", inputs.potts_grid(500, 500, 32, 1.0, 0), 0.5, 100)):
             E_, N_, K_ = 2 * len(pr["edges"]), pr["N"], pr["K"]
-            with bp.Graph(pr) as gg:
-                rc = gg.run("rnbp", eps=args.eps, p=p_, seed=1, max_iters=iters, check_every=1)
-                gg.run("rnbp", eps=0.0, p=p_, seed=1, max_iters=5)
-                rr = gg.run("rnbp", eps=0.0, p=p_, seed=2, max_iters=min(iters, 50),
-                            check_every=args.check_every, profile=args.profile_every)
-            us = rr["eval_kernel_ms"] * 1e3 / max(rr["eval_kernel_launches"], 1)
             # K = 2: 20 B per message + 8 per node; [E][K]: own row, two output rows
             # and the reverse index per message, unary row and slot offset per node
             nb = (eval_kernel_bytes(N_, E_) if K_ == 2
                   else E_ * (12 * K_ + 4) + N_ * (4 * K_ + 4))
-            extra[name] = {
-                "schedule": "rnbp", "p": p_, "messages": E_,
-                "iterations_at_eps": rc["iterations"], "converged_at_eps": rc["converged"],
-                "message_updates_per_s": rr["evaluated"] / (rr["device_ms"] / 1e3),
-                "eval_kernel_us": us, "bytes_per_launch": nb,
-                "hbm_frac": nb / (us * 1e-6) / HBM_PEAK if us > 0 else None}
+            row = {"schedule": "rnbp", "p": p_, "messages": E_, "bytes_per_launch": nb}
+            # Potts: the matrix-core product and the FP32 vector path (flag 2)
+            variants = (("", 0),) if K_ == 2 else (("", 0), ("vector_path_", 2))
+            margs = []
+            for tag, flags in variants:
+                with bp.Graph(pr, flags=flags) as gg:
+                    t0 = time.perf_counter()
+                    rc = gg.run("rnbp", eps=args.eps, p=p_, seed=1, max_iters=iters, check_every=1)
+                    t_conv = time.perf_counter() - t0
+                    margs.append(gg.marginals())
+                    gg.run("rnbp", eps=0.0, p=p_, seed=1, max_iters=5)
+                    rr = gg.run("rnbp", eps=0.0, p=p_, seed=2, max_iters=min(iters, 50),
+                                check_every=args.check_every, profile=args.profile_every)
+                    us = rr["eval_kernel_ms"] * 1e3 / max(rr["eval_kernel_launches"], 1)
+                    row.update({
+                        tag + "iterations_at_eps": rc["iterations"],
+                        tag + "converged_at_eps": rc["converged"], tag + "solve_s": t_conv,
+                        tag + "message_updates_per_s": rr["evaluated"] / (rr["device_ms"] / 1e3),
+                        tag + "eval_kernel_us": us,
+                        tag + "hbm_frac": nb / (us * 1e-6) / HBM_PEAK if us > 0 else None})
+                    if K_ == 2:
+                        # the LBP baseline on the same graph
+                        t0 = time.perf_counter()
+                        rl = gg.run("lbp", eps=args.eps, max_iters=iters, check_every=16)
+                        row["lbp_iterations_at_eps"] = rl["iterations"]
+                        row["lbp_converged_at_eps"] = rl["converged"]
+                        row["lbp_solve_s"] = time.perf_counter() - t0
+                        rl = gg.run("lbp", eps=0.0, max_iters=50, check_every=args.check_every,
+                                    profile=args.profile_every)
+                        row["lbp_eval_kernel_us"] = (rl["eval_kernel_ms"] * 1e3 /
+                                                     max(rl["eval_kernel_launches"], 1))
+            if len(margs) == 2:
+                row["max_abs_marginal_diff_matrix_vs_vector"] = float(
+                    np.max(np.abs(margs[0] - margs[1])))
+            extra[name] = row
             _log(f"bench: {name} {extra[name]}")
         # a working set far beyond the 256 MB Infinity Cache: every byte of a
         # sweep comes from HBM (16M variables, 64M messages)

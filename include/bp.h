@@ -85,6 +85,10 @@ typedef enum bp_schedule { BP_LBP = 0, BP_RBP = 1, BP_RNBP = 2 } bp_schedule;
 /* bp_graph_desc.flags */
 #define BP_FLAG_GENERIC_LAYOUT 1u /* K = 2 Ising: keep [E][2] probabilities instead of
                                     one log-odds value per message */
+#define BP_FLAG_NO_MATRIX_CORES 2u /* K = 32 with one symmetric shared table: take the
+                                     Eq. (2) product on the FP32 vector units instead of
+                                     the matrix cores (FP32 MFMA); same results within
+                                     FP32 rounding */
 
 typedef struct bp_graph bp_graph;
 

@@ -23,6 +23,7 @@ BP_EINVAL, BP_ENOMEM, BP_EDEVICE, BP_ESTATE = -1, -2, -3, -4
 BP_PAIR_ISING, BP_PAIR_SHARED, BP_PAIR_DENSE = 0, 1, 2
 BP_LBP, BP_RBP, BP_RNBP = 0, 1, 2
 BP_FLAG_GENERIC_LAYOUT = 1
+BP_FLAG_NO_MATRIX_CORES = 2
 
 SCHEDULES = {"lbp": BP_LBP, "rbp": BP_RBP, "rnbp": BP_RNBP}
 

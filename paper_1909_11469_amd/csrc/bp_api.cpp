@@ -77,6 +77,7 @@ struct HostLayout {
     std::vector<int> tile_slot;       // [T+1] node_ptr[tile_start]
     int tile_nodes_max = 1;           // most nodes in one regular tile
     int tile_big = 0;                 // 1 if some node's slots exceed the tile limit
+    int no_mfma = 0;                  // BP_FLAG_NO_MATRIX_CORES
     std::vector<int> tiles4;          // log-odds layout: regular tiles {n0, n1, s0, s1}
     std::vector<int> big4;            // log-odds layout: single-node tiles over the slot limit
     std::vector<float> coupling;      // [E] (Ising)
@@ -167,7 +168,9 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
     } else {
         return fail(BP_EINVAL, "unknown pair_kind %d", kind);
     }
-    if (d->flags & ~(uint32_t)BP_FLAG_GENERIC_LAYOUT) return fail(BP_EINVAL, "unknown flags");
+    if (d->flags & ~(uint32_t)(BP_FLAG_GENERIC_LAYOUT | BP_FLAG_NO_MATRIX_CORES))
+        return fail(BP_EINVAL, "unknown flags");
+    L.no_mfma = (d->flags & BP_FLAG_NO_MATRIX_CORES) ? 1 : 0;
     {
         std::unordered_set<unsigned long long> seen;
         seen.reserve((size_t)M * 2 + 1);
@@ -558,6 +561,7 @@ static EvalArgs run_args(const bp_graph* g, int schedule, double eps, double p, 
     a.num_nodes = L.N;
     a.tile_nodes_max = L.tile_nodes_max;
     a.tile_big = L.tile_big;
+    a.no_mfma = L.no_mfma;
     a.rbp_k = (unsigned long long)rbp_k;
     a.sel0 = g->cur_sel;
     if (mode == kModeRnBP && o.dynamic_p) {

@@ -113,6 +113,7 @@ struct EvalArgs {
     int num_nodes;
     int tile_nodes_max;         // [E][K] layout: most nodes in one regular tile
     int tile_big;               // [E][K] layout: 1 if some node's slots exceed a tile
+    int no_mfma;                // K = 32 shared table on the vector units (not the matrix cores)
     unsigned long long rbp_k;   // RBP frontier size
     // sparse re-evaluation (K = 2 log-odds layout, RnBP)
     unsigned char* dirty;       // [N] 1 if a message into the node was committed

@@ -1990,7 +1990,7 @@ hipError_t launch_eval(int layout, int kp, int mode, const EvalArgs& a, hipStrea
     const int K = a.num_states;
     const int TS = kTileFloatsGeneric / K;
     const int TN = a.tile_nodes_max;
-    if (K == 32 && a.pair_kind == kPairShared && !a.tile_big) {
+    if (K == 32 && a.pair_kind == kPairShared && !a.tile_big && !a.no_mfma) {
         // no shared table in LDS
         const size_t shm = sizeof(float) * (size_t)(TS * (K + 1) + ((TN * (K + 1) + 3) & ~3)) +
                            sizeof(int) * (size_t)(TS + TN + 1) + sizeof(unsigned short) * (size_t)TS;

@@ -92,6 +92,16 @@ def test_potts_single_sweep(bp, K):
     assert err.max() <= SWEEP_TOL, err.max()
 
 
+def test_potts_k32_vector_path_single_sweep(bp):
+    # K = 32 with a symmetric shared table runs on the matrix cores unless the
+    # graph asks for the FP32 vector path; both meet the sweep tolerance
+    prob = inputs.potts_grid(9, 11, 32, 1.0, 32)
+    state = _random_state(2 * len(prob["edges"]), 32, 32)
+    err_v, _ = _one_sweep_parity(bp, prob, state, flags=bp.BP_FLAG_NO_MATRIX_CORES)
+    err_m, _ = _one_sweep_parity(bp, prob, state)
+    assert err_v.max() <= SWEEP_TOL and err_m.max() <= SWEEP_TOL, (err_v.max(), err_m.max())
+
+
 @pytest.mark.parametrize("K", [5, 32, 64])
 def test_asymmetric_shared_table_single_sweep(bp, K):
     # K = 32 and 64 take the lane-group path with the transposed table for
@@ -227,10 +237,12 @@ def test_tree_dense_marginals_exact(bp):
     assert np.max(np.abs(marg - exact)) <= MARG_TOL
 
 
-def test_potts_converged_marginals(bp):
+@pytest.mark.parametrize("flags", [0, 2])
+def test_potts_converged_marginals(bp, flags):
+    # flags 2: the FP32 vector path instead of the matrix cores
     prob = inputs.potts_grid(12, 12, 32, 1.0, 0)
     ref = oracle.run(prob, oracle.LBP, eps=1e-6, max_iters=10000)
-    with bp.Graph(prob) as g:
+    with bp.Graph(prob, flags=flags) as g:
         r = g.run("rnbp", eps=1e-6, p=0.5, seed=3, max_iters=100000)
         marg = g.marginals()
     assert r["converged"] and ref["converged"]
