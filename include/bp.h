@@ -123,7 +123,7 @@ typedef struct bp_run_opts {
                                  graph's stream: whole chunks of back-to-back launches when
                                  it is the only kernel of an iteration, else every k-th
                                  launch */
-    int32_t sparse;           /* BP_RNBP on K = 2 graphs without oversized nodes (a node
+    int32_t sparse;           /* BP_RNBP, BP_RBP on K = 2 graphs without oversized nodes (a node
                                  whose messages exceed one 512-slot tile): re-evaluate
                                  only the messages out of nodes that received a committed
                                  message (candidates and residuals of the others are kept).

@@ -596,7 +596,8 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     if (!std::isfinite(o.ratio_threshold)) return fail(BP_EINVAL, "ratio_threshold not finite");
     if (o.sparse < 0 || o.sparse > 2) return fail(BP_EINVAL, "sparse must be 0, 1 or 2");
     if (o.sparse) {
-        if (schedule != BP_RNBP) return fail(BP_EINVAL, "sparse re-evaluation is for BP_RNBP only");
+        if (schedule == BP_LBP)
+            return fail(BP_EINVAL, "sparse re-evaluation is for BP_RNBP and BP_RBP only");
         if (g->L.layout != kLayoutLogOdds)
             return fail(BP_EINVAL, "sparse re-evaluation needs K = 2 Ising potentials");
         if (!g->L.big4.empty())
@@ -692,7 +693,22 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
             a.it = it;
             a.after_final = final_launched ? 1 : 0;
             a.sp_first = it == sp_it0 ? 1 : 0;
-            HIP_OK(launch_sparse_iteration(a, s), "sparse iteration");
+            if (mode == kModeRBP) {
+                HIP_OK(launch_sparse_rbp_eval(a, s), "sparse evaluation");
+                if (!final_launched) {
+                    const int all = rbp_k >= L.E;
+                    if (!all)
+                        HIP_OK(launch_rbp_select(g->st(), a.keys, a.rev, (int)L.E,
+                                                 (unsigned int)rbp_k, (int)(t & 3), ties, s),
+                               "top-k select");
+                    const RbpSparse sp{a.dirty, a.dst, a.ctr, a.eps, (int)((t + 1) & 3), 1};
+                    HIP_OK(launch_rbp_commit(g->st(), a.keys, a.rev, a.cand, sp_buf, (int)L.E, L.row,
+                                             all, (int)(t & 3), ties, sp, s),
+                           "top-k commit");
+                }
+            } else {
+                HIP_OK(launch_sparse_iteration(a, s), "sparse iteration");
+            }
             ++in_chunk;
             if (in_chunk == o.check_every || final_launched) {
                 HIP_OK(hipMemcpyAsync(g->host_state, g->st(), kStateReadback, hipMemcpyDeviceToHost,
@@ -737,7 +753,7 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
                                          (int)(t & 3), ties, s),
                        "top-k select");
             HIP_OK(launch_rbp_commit(g->st(), a.keys, a.rev, a.cand, start_buf, (int)L.E, L.row, all,
-                                     (int)(t & 3), ties, s),
+                                     (int)(t & 3), ties, RbpSparse{}, s),
                    "top-k commit");
         }
         ++in_chunk;
@@ -776,9 +792,13 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
                        "state readback");
                 HIP_OK(hipStreamSynchronize(s), "synchronize");
                 if (g->host_state->done) break;
-                g->cur_pair = (int)((pair0 + it) & 1) ^ 1;
-                g->cur_sel = (int)g->host_state->in_sel[(t + 1) & 3];
-                sp_buf = g->cur();
+                if (mode == kModeRBP) {
+                    sp_buf = start_buf;  // frontier residual BP already commits in place
+                } else {
+                    g->cur_pair = (int)((pair0 + it) & 1) ^ 1;
+                    g->cur_sel = (int)g->host_state->in_sel[(t + 1) & 3];
+                    sp_buf = g->cur();
+                }
                 HIP_OK(launch_sparse_setup(a, 0, s), "dirty flags");
                 sparse_now = true;
                 sp_it0 = it + 1;

@@ -160,8 +160,22 @@ hipError_t launch_rbp_gate(DevState* st, const CounterLine* ctr, int slot_idx, h
 hipError_t launch_rbp_select(DevState* st, const unsigned int* keys, const int* rev, int E,
                              unsigned int k, int slot_idx, unsigned int* block_ties,
                              hipStream_t s);
-hipError_t launch_rbp_commit(DevState* st, const unsigned int* keys, const int* rev,
+// Extra work of the top-k commit under sparse re-evaluation (on = 0: none):
+// committed slots get residual key 0 and their targets are marked dirty, and
+// the committed slots with residual > eps leave the running count of set `set`.
+struct RbpSparse {
+    unsigned char* dirty;
+    const int* dst;
+    CounterLine* ctr;
+    float eps;
+    int set;
+    int on;
+};
+hipError_t launch_rbp_commit(DevState* st, unsigned int* keys, const int* rev,
                              const float* cand, float* m, int E, int row, int all, int slot_idx,
-                             const unsigned int* block_ties, hipStream_t s);
+                             const unsigned int* block_ties, const RbpSparse& sp, hipStream_t s);
+// frontier residual BP under sparse re-evaluation: evaluate the dirty nodes,
+// then close the evaluation (one wave) and gate the top-k kernels
+hipError_t launch_sparse_rbp_eval(const EvalArgs& a, hipStream_t s);
 
 }  // namespace bp

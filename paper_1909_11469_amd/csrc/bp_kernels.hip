@@ -1851,11 +1851,13 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_tiescan(DevState* st, unsigne
 // it the first sel_krem in position order (ranked ties) or all of them.  A
 // thread takes kSelPer consecutive positions; the ties before it come from an
 // exclusive scan over the block's threads plus the block's offset.
-__global__ __launch_bounds__(kSelBlock) void k_rbp_commit(DevState* st, const unsigned int* keys,
+__global__ __launch_bounds__(kSelBlock) void k_rbp_commit(DevState* st, unsigned int* keys,
                                                           const int* rev, const float* cand,
                                                           float* m, int E, int row, int all,
-                                                          const unsigned int* block_ties) {
+                                                          const unsigned int* block_ties,
+                                                          RbpSparse sp) {
     __shared__ unsigned int part[kSelBlock / 64];
+    __shared__ unsigned int s_cm[kSelBlock / 64];
     if (st->rbp_skip) return;
     const unsigned int T = st->sel_prefix;
     const bool rank = !all && st->sel_rank_ties;
@@ -1869,12 +1871,13 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_commit(DevState* st, const un
         for (int j = 0; j < kSelPer; ++j) e[j] = (int)(q0 + j);
     }
     unsigned int take = 0, tie = 0;  // bit j: position q0 + j
+    unsigned int kv[kSelPer];
     if (all) {
 #pragma unroll
         for (int j = 0; j < kSelPer; ++j)
             if (q0 + j < E) take |= 1u << j;
+        if (sp.on) sel_load16(keys, q0, (long long)E, kv);
     } else {
-        unsigned int kv[kSelPer];
         if (rank) {
 #pragma unroll
             for (int j = 0; j < kSelPer; ++j) kv[j] = q0 + j < E ? keys[e[j]] : 0u;
@@ -1911,8 +1914,8 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_commit(DevState* st, const un
             ++before;
         }
     }
-    if (!take) return;
-    if (row == 1) {
+    unsigned int cm = 0;  // committed messages whose residual was above eps
+    if (take && row == 1) {
         float cv[kSelPer];
 #pragma unroll
         for (int j = 0; j < kSelPer; ++j)
@@ -1920,12 +1923,93 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_commit(DevState* st, const un
 #pragma unroll
         for (int j = 0; j < kSelPer; ++j)
             if (take >> j & 1u) m[e[j]] = cv[j];
-    } else {
+        if (sp.on) {
+            // sparse re-evaluation: the committed message's residual is 0 until
+            // its source is evaluated again; its target is evaluated again
+            int dv[kSelPer];
+#pragma unroll
+            for (int j = 0; j < kSelPer; ++j)
+                if (take >> j & 1u) dv[j] = sp.dst[e[j]];
+#pragma unroll
+            for (int j = 0; j < kSelPer; ++j) {
+                if (!(take >> j & 1u)) continue;
+                cm += __uint_as_float(kv[j]) > sp.eps ? 1u : 0u;
+                keys[e[j]] = 0u;
+                sp.dirty[dv[j]] = 1;
+            }
+        }
+    } else if (take) {
 #pragma unroll
         for (int j = 0; j < kSelPer; ++j)
             if (take >> j & 1u)
                 for (int x = 0; x < row; ++x)
                     m[(long long)e[j] * row + x] = cand[(long long)e[j] * row + x];
+    }
+    if (sp.on) {
+        // the committed active messages leave the running count of the next iteration
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) cm += __shfl_xor(cm, o, 64);
+        if ((threadIdx.x & 63) == 0) s_cm[threadIdx.x >> 6] = cm;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned int c = 0;
+            for (int w = 0; w < kSelBlock / 64; ++w) c += s_cm[w];
+            CounterLine* z = sp.ctr + (unsigned)sp.set * kCounterCopies +
+                             (blockIdx.x & (kCounterCopies - 1));
+            if (c) atomicAdd(&z->active, (unsigned long long)(-(long long)c));
+        }
+    }
+}
+
+// Frontier residual BP with sparse re-evaluation: close evaluation t after
+// k_sparse_eval (one wave).  n_t = n_{t-1} + the running-count changes of
+// counter set t & 3; statistics as the full path records them (k messages
+// committed per committing iteration); the top-k kernels run only when n_t > 0
+// and t is not the evaluation after the last allowed commit.  Clears counter
+// set t + 2.
+__global__ void k_sparse_rbp_close(EvalArgs a) {
+    const int lane = threadIdx.x;
+    DevState* st = a.st;
+    const unsigned int done = st->done;
+    const CounterLine* c0 = a.ctr + (a.t & 3u) * kCounterCopies + lane;
+    const long long d = (long long)wave_sum64(c0->active);
+    const long long base = a.sp_first ? 0ll : (long long)st->sp_n[(a.t - 1u) & 3u];
+    const unsigned long long n1 = (unsigned long long)(base + d);
+    long long n2;
+    if (!a.sp_first)
+        n2 = (long long)st->sp_n[(a.t - 1u) & 3u];
+    else if (a.it >= 1)  // switched from the full evaluation: its count of t - 1
+        n2 = (long long)wave_sum64(a.ctr[((a.t - 1u) & 3u) * kCounterCopies + lane].active);
+    else
+        n2 = a.prev_active_host;
+    const unsigned long long ev = wave_sum64(c0->sel_a);
+    if (done) {
+        if (lane == 0) st->rbp_skip = 1u;
+        return;
+    }
+    CounterLine* z = a.ctr + ((a.t + 2u) & 3u) * kCounterCopies + lane;
+    z->active = 0ull;
+    z->sel_a = 0ull;
+    z->sel_b = 0ull;
+    z->rmax = 0u;
+    if (lane != 0) return;
+    atomicAdd(&st->evaluated, ev);
+    atomicAdd(&st->evals, 1ull);
+    st->sp_n[a.t & 3u] = n1;
+    st->last_t = (long long)a.t;
+    st->last_active = n1;
+    st->last_rmax = 0u;  // taken after the run
+    st->last_prev = n2;
+    if (n1 == 0ull) {
+        st->done = 1u;
+        st->conv_t = (long long)a.t;
+        st->rbp_skip = 1u;
+    } else if (a.after_final) {
+        st->rbp_skip = 1u;
+    } else {
+        atomicAdd(&st->iterations, 1ull);
+        atomicAdd(&st->committed, a.rbp_k);
+        st->rbp_skip = 0u;
     }
 }
 
@@ -2084,6 +2168,13 @@ hipError_t launch_sparse_iteration(const EvalArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_sparse_rbp_eval(const EvalArgs& a, hipStream_t s) {
+    const int grid = a.num_nodes > 0 ? (a.num_nodes + kBlock - 1) / kBlock : 1;
+    k_sparse_eval<<<grid, kBlock, 0, s>>>(a);
+    k_sparse_rbp_close<<<1, 64, 0, s>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t launch_sparse_rmax(const EvalArgs& a, hipStream_t s) {
     long long g = ((long long)a.num_messages + kBlock - 1) / kBlock;
     const int grid = g < 1 ? 1 : g > kSparseGridMax ? kSparseGridMax : (int)g;
@@ -2119,13 +2210,13 @@ hipError_t launch_rbp_select(DevState* st, const unsigned int* keys, const int* 
     return hipGetLastError();
 }
 
-hipError_t launch_rbp_commit(DevState* st, const unsigned int* keys, const int* rev,
+hipError_t launch_rbp_commit(DevState* st, unsigned int* keys, const int* rev,
                              const float* cand, float* m, int E, int row, int all, int slot_idx,
-                             const unsigned int* block_ties, hipStream_t s) {
+                             const unsigned int* block_ties, const RbpSparse& sp, hipStream_t s) {
     (void)slot_idx;
     const int nb = (E + kCommitChunk - 1) / kCommitChunk;
     if (nb <= 0) return hipSuccess;
-    k_rbp_commit<<<nb, kSelBlock, 0, s>>>(st, keys, rev, cand, m, E, row, all, block_ties);
+    k_rbp_commit<<<nb, kSelBlock, 0, s>>>(st, keys, rev, cand, m, E, row, all, block_ties, sp);
     return hipGetLastError();
 }
 

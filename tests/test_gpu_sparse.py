@@ -31,9 +31,9 @@ def bp():
     return mod
 
 
-def _run(bp, prob, sparse, **kw):
+def _run(bp, prob, sparse, schedule="rnbp", **kw):
     with bp.Graph(prob) as g:
-        r = g.run("rnbp", sparse=sparse, **kw)
+        r = g.run(schedule, sparse=sparse, **kw)
         m, st = g.get_state()
         marg = g.marginals()
     return r, m, st, marg
@@ -73,6 +73,20 @@ def test_sparse_bitwise_equals_full(bp, name, dynamic_p, p):
         assert _run(bp, prob, 1, **kw)[0]["evaluated"] < full[0]["evaluated"]
 
 
+@pytest.mark.parametrize("name", ["grid_C1", "grid_C2.5", "er"])
+@pytest.mark.parametrize("p", [1 / 256, 0.05, 0.5, 1.0])
+def test_sparse_rbp_bitwise_equals_full(bp, name, p):
+    # frontier residual BP: the top-k reads every stored residual, which the
+    # sparse path keeps equal to what the full evaluation recomputes
+    prob = PROBS[name]()
+    kw = dict(eps=1e-4, p=p, max_iters=60, check_every=4)
+    full = _run(bp, prob, 0, "rbp", **kw)
+    for sparse in (1, 2):
+        got = _run(bp, prob, sparse, "rbp", **kw)
+        _assert_same(full, got)
+        assert got[0]["evaluated"] <= full[0]["evaluated"]
+
+
 def test_sparse_switch_happens_and_saves(bp):
     # a converging grid: n_t falls below E / 16, the run switches to the sparse
     # path and evaluates fewer messages than the full evaluation
@@ -85,14 +99,15 @@ def test_sparse_switch_happens_and_saves(bp):
     assert auto[0]["evaluated"] < full[0]["evaluated"]
 
 
+@pytest.mark.parametrize("schedule", ["rnbp", "rbp"])
 @pytest.mark.parametrize("first,second", [(0, 1), (1, 0), (1, 1), (2, 2)])
-def test_sparse_warm_start_continuation(bp, first, second):
+def test_sparse_warm_start_continuation(bp, schedule, first, second):
     prob = inputs.ising_grid(33, 29, 2.5, 5)
     kw = dict(eps=1e-4, p=0.4, seed=21, check_every=3)
-    ref = _run(bp, prob, 0, max_iters=80, **kw)
+    ref = _run(bp, prob, 0, schedule, max_iters=80, **kw)
     with bp.Graph(prob) as g:
-        r1 = g.run("rnbp", sparse=first, max_iters=35, **kw)
-        r2 = g.run("rnbp", sparse=second, max_iters=45, warm_start=True, **kw)
+        r1 = g.run(schedule, sparse=first, max_iters=35, **kw)
+        r2 = g.run(schedule, sparse=second, max_iters=45, warm_start=True, **kw)
         m, st = g.get_state()
         marg = g.marginals()
     assert r1["iterations"] + r2["iterations"] == ref[0]["iterations"]
@@ -156,9 +171,8 @@ def test_sparse_degenerate_cases(bp):
 def test_sparse_rejected_where_not_built(bp):
     prob = inputs.ising_grid(8, 8, 1.0, 0)
     with bp.Graph(prob) as g:
-        for sched in ("lbp", "rbp"):
-            with pytest.raises(bp.BpError):
-                g.run(sched, p=0.5, sparse=1)
+        with pytest.raises(bp.BpError):
+            g.run("lbp", p=0.5, sparse=1)
         with pytest.raises(bp.BpError):
             g.run("rnbp", p=0.5, sparse=3)
     with bp.Graph(inputs.potts_grid(6, 6, 3, 1.0, 0)) as g:
