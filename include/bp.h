@@ -258,7 +258,8 @@ typedef struct bp_request {
     double p;               /* as bp_run (RnBP low setting) */
     uint64_t seed;          /* as bp_run */
     bp_run_opts opts;       /* max_iters, dynamic_p, high_p, ratio_threshold as bp_run;
-                               check_every, warm_start and profile are ignored */
+                               check_every, warm_start and profile are ignored;
+                               sparse must be 0 (BP_EINVAL otherwise) */
 } bp_request;
 
 /* Create a server.  Errors: BP_EINVAL, BP_ENOMEM, BP_EDEVICE; *out NULL on error. */

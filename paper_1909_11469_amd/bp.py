@@ -356,7 +356,7 @@ class Server:
         self.close()
 
     def submit(self, problem, schedule="rnbp", eps=1e-4, p=0.5, seed=0, max_iters=10000,
-               dynamic_p=True, high_p=1.0, ratio_threshold=0.9):
+               dynamic_p=True, high_p=1.0, ratio_threshold=0.9, sparse=0):
         d, keep = _make_desc(problem)
         r = bp_request()
         r.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
@@ -365,6 +365,7 @@ class Server:
         r.opts.max_iters = int(max_iters)
         r.opts.dynamic_p, r.opts.high_p = int(bool(dynamic_p)), float(high_p)
         r.opts.ratio_threshold = float(ratio_threshold)
+        r.opts.sparse = int(sparse)  # the server accepts 0 only
         i = ctypes.c_int64()
         _check(lib.bp_server_submit(self.handle, ctypes.byref(d), ctypes.byref(r), ctypes.byref(i)))
         del keep

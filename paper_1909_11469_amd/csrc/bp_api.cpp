@@ -614,17 +614,22 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
         if (e != hipSuccess)
             return fail(e == hipErrorOutOfMemory ? BP_ENOMEM : BP_EDEVICE,
                         "sparse buffers (%zu bytes): %s", bytes, hipGetErrorString(e));
-        g->sparse_mem = mem;
-        g->sp_dirty = (unsigned char*)mem;
-        g->sp_hasact = (unsigned char*)(mem + nb);
-        g->sp_dst = (int*)(mem + 2 * nb);
         EvalArgs b{};
         b.node_ptr = g->at<int>(g->off.node_ptr);
         b.rev = g->at<int>(g->off.rev);
         b.num_nodes = L.N;
-        b.dirty = g->sp_dirty;
-        b.dst = g->sp_dst;
-        HIP_OK(launch_sparse_setup(b, 1, s), "target index");
+        b.dirty = (unsigned char*)mem;
+        b.dst = (int*)(mem + 2 * nb);
+        e = launch_sparse_setup(b, 1, s);
+        if (e != hipSuccess) {
+            // keep the graph without sparse buffers, so that a later run retries
+            (void)hipFree(mem);
+            return hip_fail(e, "target index");
+        }
+        g->sparse_mem = mem;
+        g->sp_dirty = (unsigned char*)mem;
+        g->sp_hasact = (unsigned char*)(mem + nb);
+        g->sp_dst = (int*)(mem + 2 * nb);
     }
     if (!o.warm_start) {
         const float uni = L.layout == kLayoutLogOdds ? 0.0f : 1.0f / (float)L.K;
@@ -1217,6 +1222,7 @@ int bp_server_submit(bp_server* s, const bp_graph_desc* graph, const bp_request*
     if (req->schedule == BP_RNBP && o.dynamic_p && !(o.high_p > 0.0 && o.high_p <= 1.0))
         return fail(BP_EINVAL, "high_p must be in (0, 1]");
     if (!std::isfinite(o.ratio_threshold)) return fail(BP_EINVAL, "ratio_threshold not finite");
+    if (o.sparse) return fail(BP_EINVAL, "serving runs the full evaluation (opts.sparse must be 0)");
     HostLayout L;
     int rc = build_layout(graph, L);  // full validation
     if (rc != BP_OK) return rc;

@@ -83,4 +83,6 @@ def test_serving_rejects_unsupported(bp):
         with pytest.raises(bp.BpError):
             srv.submit(inputs.ising_grid(4, 4, 1.0, 0), schedule="rbp")
         with pytest.raises(bp.BpError):
+            srv.submit(inputs.ising_grid(4, 4, 1.0, 0), sparse=1)
+        with pytest.raises(bp.BpError):
             srv.submit(inputs.ising_grid(300, 300, 1.0, 0))  # larger than the arena
