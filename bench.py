@@ -148,6 +148,9 @@ def main():
                     help="run one 256 MiB device-to-device copy kernel first (a known-size "
                          "reference for hardware byte counters)")
     ap.add_argument("--ttc-seeds", type=int, default=3)
+    ap.add_argument("--er-seeds", type=int, default=0,
+                    help="time to convergence on this many 200k-node ER graphs (RnBP p = 0.3 "
+                         "vs LBP, C = 2.5); 0 = skip")
     ap.add_argument("--ttc-check-every", type=int, default=16,
                     help="convergence poll interval of the time-to-convergence runs")
     args = ap.parse_args()
@@ -276,6 +279,28 @@ def main():
                     "mean_evaluated": float(np.mean([r[3] for r in v]))}
                 for k, v in rows.items()}
         out["time_to_convergence"] = ttc
+
+    if args.er_seeds > 0:
+        rows = {}
+        for s in range(args.er_seeds):
+            pr = inputs.er_graph(200000, 6.0, 2.5, 100 + s)
+            with bp.Graph(pr) as gg:
+                for sched, q in (("lbp", 1.0), ("rnbp", 0.3)):
+                    torch.cuda.synchronize()
+                    a = time.perf_counter()
+                    rr = gg.run(sched, eps=args.eps, p=q, seed=s, max_iters=args.max_iters,
+                                check_every=args.ttc_check_every)
+                    torch.cuda.synchronize()
+                    rows.setdefault(sched, []).append(
+                        (rr["converged"], time.perf_counter() - a, rr["iterations"]))
+            _log(f"bench: er ttc seed={100 + s} " +
+                 " ".join(f"{k}={v[-1][0]}/{v[-1][2]}" for k, v in rows.items()))
+        out["er_time_to_convergence"] = {
+            k: {"converged": sum(r[0] for r in v), "graphs": len(v),
+                "mean_s_converged": (float(np.mean([r[1] for r in v if r[0]]))
+                                     if any(r[0] for r in v) else None),
+                "mean_iterations": float(np.mean([r[2] for r in v]))}
+            for k, v in rows.items()}
 
     if not args.no_extra:
         extra = {}
