@@ -68,17 +68,22 @@ def serving_mix(inputs, np, n, seed=0):
     return mix
 
 
-def serving_bench(bp, inputs, np, torch, args, n=48, max_iters=2000, p=0.5, rate=100.0):
+def serving_bench(bp, inputs, np, torch, args, n=48, max_iters=2000, p=0.5,
+                  rates=(25.0, 50.0, 100.0, 200.0)):
     """Batched serving (one launch per iteration for every resident graph) vs one
     graph per bp_run, on the same requests: RnBP, eps = 1e-4, at most 2000
-    iterations per request.  Two arrival patterns: a burst (all at time 0) and
-    a Poisson process at `rate` requests/s.  Latency = completion - arrival;
-    submission (the host builds and validates the layout) is inside it."""
+    iterations per request.  Arrival patterns: a burst (all at time 0) and
+    Poisson processes at each of `rates` requests/s.  Latency = completion -
+    arrival; submission (the host builds and validates the layout) is inside it."""
     mix = serving_mix(inputs, np, n)
     msgs = sum(2 * len(pr["edges"]) for pr in mix)
-    out = {"requests": n, "messages_total": msgs, "max_iters": max_iters, "poisson_rate": rate}
+    out = {"requests": n, "messages_total": msgs, "max_iters": max_iters,
+           "poisson_rates": list(rates)}
     rng = np.random.default_rng(7)
-    arrivals = {"burst": np.zeros(n), "poisson": np.cumsum(rng.exponential(1.0 / rate, n))}
+    gaps = rng.exponential(1.0, n)  # one unit-rate draw, scaled per rate
+    arrivals = {"burst": np.zeros(n)}
+    for rate in rates:
+        arrivals[f"poisson_{rate:g}/s"] = np.cumsum(gaps / rate)
 
     def stats(lat, makespan):
         lat = np.asarray(lat)
