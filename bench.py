@@ -53,17 +53,17 @@ def counter_traffic(path, kernel_src):
 
 
 def serving_mix(inputs, np, n, seed=0):
-    """The serving workload: Ising grids with side ~ U{32..256} and Erdos-Renyi
-    graphs with n ~ U[1k, 20k], average degree ~ U{4..8}; C ~ U[1, 3]."""
+    """The serving workload: Ising grids with side ~ U{32..512} and Erdos-Renyi
+    graphs with n ~ U[1k, 50k], average degree ~ U{4..8}; C ~ U[1, 3]."""
     rng = np.random.default_rng(seed)
     mix = []
     for i in range(n):
         C = float(rng.uniform(1.0, 3.0))
         if rng.random() < 0.5:
-            side = int(rng.integers(32, 257))
+            side = int(rng.integers(32, 513))
             mix.append(inputs.ising_grid(side, side, C, 1000 + i))
         else:
-            mix.append(inputs.er_graph(int(rng.integers(1000, 20001)), float(rng.integers(4, 9)), C,
+            mix.append(inputs.er_graph(int(rng.integers(1000, 50001)), float(rng.integers(4, 9)), C,
                                        1000 + i))
     return mix
 
