@@ -161,8 +161,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding design); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     lib = os.path.join(ROOT, "paper_1909_11469_amd", "libbp.so")
