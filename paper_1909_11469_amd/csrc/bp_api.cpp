@@ -321,6 +321,12 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
 // (everything before the selection histograms).
 constexpr size_t kStateReadback = offsetof(DevState, hist);
 
+// Sparse mode 2 switches to sparse re-evaluation once n_t <= E / kSparseSwitch.
+#ifndef BP_SPARSE_SWITCH
+#define BP_SPARSE_SWITCH 16
+#endif
+constexpr unsigned long long kSparseSwitch = BP_SPARSE_SWITCH;
+
 struct bp_graph {
     HostLayout L;
     Offsets off;
@@ -783,7 +789,7 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
             }
             in_chunk = 0;
             if (g->host_state->done || final_launched) break;
-            if (o.sparse == 2 && (unsigned long long)g->host_state->last_active * 16ull <=
+            if (o.sparse == 2 && (unsigned long long)g->host_state->last_active * kSparseSwitch <=
                                      (unsigned long long)L.E) {
                 // switch to sparse re-evaluation: close evaluation t (as the next
                 // launch's prologue would), find the buffer that holds m^{t+1},
