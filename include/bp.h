@@ -89,6 +89,11 @@ typedef enum bp_schedule { BP_LBP = 0, BP_RBP = 1, BP_RNBP = 2 } bp_schedule;
                                      Eq. (2) product on the FP32 vector units instead of
                                      the matrix cores (FP32 MFMA); same results within
                                      FP32 rounding */
+#define BP_FLAG_SPARSE_BUFFERS 4u  /* one-log-odds-per-message graphs: hold the buffers of
+                                     sparse re-evaluation (bp_run_opts.sparse) in the
+                                     graph's memory (counted by bp_workspace_bytes) instead
+                                     of allocating them at the first sparse run; ignored
+                                     for the [E][K] layout */
 
 typedef struct bp_graph bp_graph;
 
@@ -133,9 +138,11 @@ typedef struct bp_run_opts {
                                     sparse from then on.
                                  Messages, iteration counts and residuals are bitwise those
                                  of the full evaluation; only `evaluated` differs.  The
-                                 first sparse run allocates 2 bytes per node and 4 per
-                                 message of device memory outside the graph's workspace,
-                                 held until bp_destroy_graph.  Other schedules and layouts:
+                                 buffers (2 bytes per node and 4 per message) are in the
+                                 graph's memory when it was created with
+                                 BP_FLAG_SPARSE_BUFFERS; otherwise the first sparse run
+                                 allocates them outside the workspace, held until
+                                 bp_destroy_graph.  Other schedules and layouts:
                                  BP_EINVAL. */
     int32_t reserved;
 } bp_run_opts;
@@ -154,9 +161,14 @@ typedef struct bp_run_stats {
     int64_t eval_kernel_launches; /* profile: number of evaluation launches timed */
 } bp_run_stats;
 
-/* Iteration state carried between runs (checkpoint / resume, Alg. 1 loop). */
+/* Iteration state carried between runs (checkpoint / resume, Alg. 1 loop).
+ * p_t is not stored: BP_RNBP with dynamic p derives it when iteration t is
+ * evaluated, from n_t (that evaluation's count) and n_{t-1} = prev_active:
+ * p_t = p (the low setting) if prev_active > 0 and n_t / prev_active >
+ * ratio_threshold, else high_p (EdgeRatio, Sec. IV-A). */
 typedef struct bp_iter_state {
-    int64_t t;            /* global iteration number of the next evaluation */
+    int64_t t;            /* global iteration number of the next evaluation (the
+                             RNG counter word of the random filter) */
     int64_t prev_active;  /* n_{t-1}, or -1 if none (then p_t = high_p) */
 } bp_iter_state;
 
@@ -181,8 +193,9 @@ int bp_workspace_bytes(const bp_graph_desc* desc, uint64_t* bytes);
 
 /* Validate the problem (ranges, self-loops, duplicate edges, positivity and
  * finiteness of potentials, K range), build the device layout (directed
- * messages grouped by target, reverse-message index, node tiles), upload it
- * and set messages to uniform.  *out receives the handle.
+ * messages grouped by source node and sorted by target inside a source,
+ * reverse-message index, node tiles), upload it and set messages to uniform.
+ * *out receives the handle.
  * Errors: BP_EINVAL, BP_ENOMEM, BP_EDEVICE; *out is NULL on error. */
 int bp_create_graph(const bp_graph_desc* desc, bp_graph** out);
 
@@ -281,7 +294,10 @@ int bp_server_step(bp_server* s, int32_t launches, int32_t* finished);
 /* Result of a retired request: Eq. (3) beliefs into host [N][2] FP32 and the
  * run statistics as bp_run reports them (device_ms and the profile fields are
  * 0).  Returns BP_OK and forgets the request, BP_ESTATE if the request is
- * still queued or resident, BP_EINVAL for an unknown id. */
+ * still queued or resident, BP_EINVAL for an unknown id.  A request whose
+ * admission failed (its graph could not be created in the arena) is retired
+ * without a result: this call returns that error (BP_ENOMEM, BP_EDEVICE) and
+ * forgets the request; the other requests are not affected. */
 int bp_server_result(bp_server* s, int64_t id, float* marginals, bp_run_stats* stats);
 
 /* Requests waiting for room, resident in the batch, and retired but not yet
@@ -291,6 +307,11 @@ int bp_server_counts(const bp_server* s, int64_t* queued, int64_t* resident, int
 /* Release the server's device memory (not a caller arena) and every request.
  * NULL is ignored. */
 void bp_server_destroy(bp_server* s);
+
+/* Test hook for the failure path of admission: the next `admissions`
+ * admissions fail as a device error during graph creation would (the request
+ * is retired with BP_EDEVICE, its arena room returned).  0 turns it off. */
+int bp_server_inject_failures(bp_server* s, int32_t admissions);
 
 #ifdef __cplusplus
 }

@@ -14,9 +14,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# BP_LIBRARY selects another build of the same library (tuning builds); the
-# default is the in-tree libbp.so.
-LIB_PATH = os.environ.get("BP_LIBRARY") or os.path.join(_HERE, "libbp.so")
+LIB_PATH = os.path.join(_HERE, "libbp.so")
 
 BP_OK, BP_NOT_CONVERGED = 0, 1
 BP_EINVAL, BP_ENOMEM, BP_EDEVICE, BP_ESTATE = -1, -2, -3, -4
@@ -24,6 +22,7 @@ BP_PAIR_ISING, BP_PAIR_SHARED, BP_PAIR_DENSE = 0, 1, 2
 BP_LBP, BP_RBP, BP_RNBP = 0, 1, 2
 BP_FLAG_GENERIC_LAYOUT = 1
 BP_FLAG_NO_MATRIX_CORES = 2
+BP_FLAG_SPARSE_BUFFERS = 4
 
 SCHEDULES = {"lbp": BP_LBP, "rbp": BP_RBP, "rnbp": BP_RNBP}
 
@@ -32,7 +31,7 @@ EXPORTED = ["bp_default_opts", "bp_workspace_bytes", "bp_create_graph", "bp_run"
             "bp_marginals", "bp_marginals_device", "bp_get_state", "bp_set_state",
             "bp_graph_info_get", "bp_destroy_graph", "bp_last_error",
             "bp_server_create", "bp_server_submit", "bp_server_step", "bp_server_result",
-            "bp_server_counts", "bp_server_destroy"]
+            "bp_server_counts", "bp_server_destroy", "bp_server_inject_failures"]
 
 
 class BpError(RuntimeError):
@@ -135,6 +134,8 @@ def _load():
     lib.bp_server_counts.restype = ctypes.c_int
     lib.bp_server_destroy.argtypes = [P]
     lib.bp_server_destroy.restype = None
+    lib.bp_server_inject_failures.argtypes = [P, ctypes.c_int32]
+    lib.bp_server_inject_failures.restype = ctypes.c_int
     return lib
 
 
@@ -204,12 +205,18 @@ def _torch_cuda():
 
 
 class Graph:
-    """A problem resident on the GPU (bp_create_graph ... bp_destroy_graph)."""
+    """A problem resident on the GPU (bp_create_graph ... bp_destroy_graph).
 
-    def __init__(self, problem, flags=0, use_torch=True):
+    Binary Ising graphs are created with BP_FLAG_SPARSE_BUFFERS unless
+    sparse_buffers is False, so that all of their device memory is the one
+    workspace tensor."""
+
+    def __init__(self, problem, flags=0, use_torch=True, sparse_buffers=True):
         self.N, self.K = int(problem["N"]), int(problem["K"])
         self.M = int(np.asarray(problem["edges"]).reshape(-1, 2).shape[0])
         self.E = 2 * self.M
+        if sparse_buffers and int(problem["pair_kind"]) == BP_PAIR_ISING:
+            flags = int(flags) | BP_FLAG_SPARSE_BUFFERS
         d, keep = _make_desc(problem, flags)
         self._workspace = None
         torch = _torch_cuda() if use_torch else None
@@ -388,6 +395,10 @@ class Server:
         out = {f: getattr(s, f) for f, _ in s._fields_ if f != "reserved0"}
         out["converged"] = bool(out["converged"])
         return m, out
+
+    def inject_failures(self, admissions):
+        """Test hook: the next `admissions` admissions fail (bp_server_inject_failures)."""
+        _check(lib.bp_server_inject_failures(self.handle, int(admissions)))
 
     def counts(self):
         q, a, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

@@ -18,17 +18,22 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
 
 
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
-    """Compile and link libbp.so.  ``defines`` (e.g. a tile size) and ``out``
-    produce an alternative build for tuning; the default is the shipped one."""
-    objs = []
+    """Compile (the sources in parallel) and link libbp.so.  ``defines`` (e.g. a
+    tile size) and ``out`` produce an alternative build; the default is the
+    shipped one."""
+    from concurrent.futures import ThreadPoolExecutor
     tag = "" if out == LIB else "." + os.path.basename(out)
+    jobs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.basename(src) + tag + ".o")
         cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ["-D" + d for d in defines] + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        jobs.append((cmd, obj))
+    with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        for f in [ex.submit(subprocess.run, cmd, check=True) for cmd, _ in jobs]:
+            f.result()
+    objs = [obj for _, obj in jobs]
     tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

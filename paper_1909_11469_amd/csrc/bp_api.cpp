@@ -78,6 +78,7 @@ struct HostLayout {
     int tile_nodes_max = 1;           // most nodes in one regular tile
     int tile_big = 0;                 // 1 if some node's slots exceed the tile limit
     int no_mfma = 0;                  // BP_FLAG_NO_MATRIX_CORES
+    int sparse_reserved = 0;          // BP_FLAG_SPARSE_BUFFERS on a log-odds graph
     std::vector<int> tiles4;          // log-odds layout: regular tiles {n0, n1, s0, s1}
     std::vector<int> big4;            // log-odds layout: single-node tiles over the slot limit
     std::vector<float> coupling;      // [E] (Ising)
@@ -97,8 +98,15 @@ struct Arena {
 
 struct Offsets {
     size_t node_ptr, rev, tile, tile_slot, tiles4, big4, coupling, unary, pair, orient, msg[4], cand, keys, ties, state,
-        ctr, marg, total;
+        ctr, marg, sparse, total;
 };
+
+// Device bytes of the sparse re-evaluation buffers of a log-odds graph: dirty
+// and active-node flags u8 [N] each (256-byte rounded), target node i32 [E].
+size_t sparse_bytes(const HostLayout& L) {
+    const size_t nb = ((size_t)L.N + 255) / 256 * 256;
+    return 2 * nb + sizeof(int) * (size_t)L.E + 256;
+}
 
 Offsets plan(const HostLayout& L) {
     Arena a;
@@ -121,6 +129,7 @@ Offsets plan(const HostLayout& L) {
     o.state = a.take(sizeof(DevState));
     o.ctr = a.take(sizeof(CounterLine) * 4 * kCounterCopies);
     o.marg = a.take(sizeof(float) * (size_t)L.N * L.K);
+    o.sparse = L.sparse_reserved ? a.take(sparse_bytes(L)) : 0;
     o.total = a.off;
     return o;
 }
@@ -168,7 +177,8 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
     } else {
         return fail(BP_EINVAL, "unknown pair_kind %d", kind);
     }
-    if (d->flags & ~(uint32_t)(BP_FLAG_GENERIC_LAYOUT | BP_FLAG_NO_MATRIX_CORES))
+    if (d->flags & ~(uint32_t)(BP_FLAG_GENERIC_LAYOUT | BP_FLAG_NO_MATRIX_CORES |
+                               BP_FLAG_SPARSE_BUFFERS))
         return fail(BP_EINVAL, "unknown flags");
     L.no_mfma = (d->flags & BP_FLAG_NO_MATRIX_CORES) ? 1 : 0;
     {
@@ -197,6 +207,7 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
                    ? kLayoutLogOdds
                    : kLayoutGeneric;
     L.row = L.layout == kLayoutLogOdds ? 1 : (int)K;
+    L.sparse_reserved = (L.layout == kLayoutLogOdds && (d->flags & BP_FLAG_SPARSE_BUFFERS)) ? 1 : 0;
     const long long E = L.E;
     auto csrc = [&](long long c) { return d->edges[2 * (c >> 1) + ((c & 1) ? 1 : 0)]; };
     auto cdst = [&](long long c) { return d->edges[2 * (c >> 1) + ((c & 1) ? 0 : 1)]; };
@@ -343,9 +354,13 @@ struct bp_graph {
     DevState* host_state = nullptr;  // pinned mirror
     int num_cus = 0;                 // compute units of the device
     int resident[4] = {0, 0, 0, 0};  // log-odds eval blocks resident per CU, by mode
-    // sparse re-evaluation buffers, allocated by the first sparse run:
-    // dirty u8 [N], active-node flag u8 [N], target node int32 [E]
+    // sparse re-evaluation buffers: dirty u8 [N], active-node flag u8 [N],
+    // target node int32 [E]; in the graph's memory (BP_FLAG_SPARSE_BUFFERS) or
+    // allocated by the first sparse run (sparse_owned); the target index is
+    // built once (sparse_ready)
     char* sparse_mem = nullptr;
+    bool sparse_owned = false;
+    bool sparse_ready = false;
     unsigned char* sp_dirty = nullptr;
     unsigned char* sp_hasact = nullptr;
     int* sp_dst = nullptr;
@@ -358,7 +373,8 @@ struct bp_graph {
     CounterLine* ctr() const { return at<CounterLine>(off.ctr); }
 };
 
-int create_graph_from_layout(HostLayout&& layout, const bp_graph_desc* desc, bp_graph** out);
+int create_graph_from_layout(HostLayout& layout, const bp_graph_desc* desc, bp_graph** out,
+                              bool fail_upload = false);
 
 extern "C" {
 
@@ -390,51 +406,55 @@ int bp_create_graph(const bp_graph_desc* desc, bp_graph** out) {
     HostLayout L;
     int rc = build_layout(desc, L);
     if (rc != BP_OK) return rc;
-    return create_graph_from_layout(std::move(L), desc, out);
+    return create_graph_from_layout(L, desc, out);
 }
 
 }  // extern "C"
 
 // A graph from an already built (and validated) layout; desc supplies the
-// stream and the optional workspace.
-int create_graph_from_layout(HostLayout&& layout, const bp_graph_desc* desc, bp_graph** out) {
+// stream and the optional workspace.  The layout is moved into the graph on
+// success and left with the caller on failure (the server admits it again or
+// reports it).  fail_upload makes the upload step fail as a device error would
+// (bp_server_inject_failures).
+int create_graph_from_layout(HostLayout& layout, const bp_graph_desc* desc, bp_graph** out,
+                             bool fail_upload) {
     bp_graph* g = new (std::nothrow) bp_graph();
     if (!g) return fail(BP_ENOMEM, "host allocation failed");
     g->L = std::move(layout);
+    // every failure below hands the layout back before the graph is released
+    auto give_back = [&](int code) {
+        layout = std::move(g->L);
+        bp_destroy_graph(g);
+        return code;
+    };
     g->off = plan(g->L);
     g->stream = (hipStream_t)desc->stream;
     hipError_t e = hipGetDevice(&g->device);
-    if (e != hipSuccess) {
-        delete g;
-        return hip_fail(e, "hipGetDevice");
-    }
+    if (e != hipSuccess) return give_back(hip_fail(e, "hipGetDevice"));
     if (desc->workspace) {
-        if ((uintptr_t)desc->workspace % 256 != 0) {
-            delete g;
-            return fail(BP_EINVAL, "workspace must be 256-byte aligned");
-        }
-        if (desc->workspace_bytes < g->off.total) {
-            delete g;
-            return fail(BP_ENOMEM, "workspace of %llu bytes < %llu needed",
-                        (unsigned long long)desc->workspace_bytes,
-                        (unsigned long long)g->off.total);
-        }
+        if ((uintptr_t)desc->workspace % 256 != 0)
+            return give_back(fail(BP_EINVAL, "workspace must be 256-byte aligned"));
+        if (desc->workspace_bytes < g->off.total)
+            return give_back(fail(BP_ENOMEM, "workspace of %llu bytes < %llu needed",
+                                  (unsigned long long)desc->workspace_bytes,
+                                  (unsigned long long)g->off.total));
         g->base = (char*)desc->workspace;
     } else {
         e = hipMalloc((void**)&g->base, g->off.total);
         if (e != hipSuccess) {
-            delete g;
+            g->base = nullptr;
             (void)hipGetLastError();
-            return fail(e == hipErrorOutOfMemory ? BP_ENOMEM : BP_EDEVICE, "hipMalloc(%zu): %s",
-                        g->off.total, hipGetErrorString(e));
+            return give_back(fail(e == hipErrorOutOfMemory ? BP_ENOMEM : BP_EDEVICE,
+                                  "hipMalloc(%zu): %s", g->off.total, hipGetErrorString(e)));
         }
         g->owns_memory = true;
     }
     e = hipHostMalloc((void**)&g->host_state, sizeof(DevState), hipHostMallocDefault);
     if (e != hipSuccess) {
-        bp_destroy_graph(g);
-        return hip_fail(e, "hipHostMalloc");
+        g->host_state = nullptr;
+        return give_back(hip_fail(e, "hipHostMalloc"));
     }
+    if (fail_upload) return give_back(fail(BP_EDEVICE, "upload: injected failure"));
     const HostLayout& L = g->L;
     hipStream_t s = g->stream;
     auto up = [&](size_t o, const void* p, size_t n) -> hipError_t {
@@ -453,25 +473,16 @@ int create_graph_from_layout(HostLayout&& layout, const bp_graph_desc* desc, bp_
         up(g->off.pair, L.pair_tab.data(), sizeof(float) * L.pair_tab.size()),
         up(g->off.orient, L.orient.data(), L.orient.size())};
     for (hipError_t x : errs)
-        if (x != hipSuccess) {
-            bp_destroy_graph(g);
-            return hip_fail(x, "upload");
-        }
+        if (x != hipSuccess) return give_back(hip_fail(x, "upload"));
     const float uni = L.layout == kLayoutLogOdds ? 0.0f : 1.0f / (float)L.K;
     e = launch_fill(g->msg(0, 0), uni, L.E * L.row, s);
     if (e == hipSuccess) e = launch_init_state(g->st(), g->ctr(), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-        bp_destroy_graph(g);
-        return hip_fail(e, "initialise");
-    }
+    if (e != hipSuccess) return give_back(hip_fail(e, "initialise"));
     g->cur_pair = 0;
     g->cur_sel = 0;
     e = hipDeviceGetAttribute(&g->num_cus, hipDeviceAttributeMultiprocessorCount, g->device);
-    if (e != hipSuccess) {
-        bp_destroy_graph(g);
-        return hip_fail(e, "hipDeviceGetAttribute");
-    }
+    if (e != hipSuccess) return give_back(hip_fail(e, "hipDeviceGetAttribute"));
     for (int m = 0; m < 4; ++m) g->resident[m] = logodds_blocks_per_cu(m);
     *out = g;
     return BP_OK;
@@ -485,7 +496,7 @@ void bp_destroy_graph(bp_graph* g) {
         DeviceGuard dg(g->device);
         if (g->base) (void)hipStreamSynchronize(g->stream);
         if (g->owns_memory && g->base) (void)hipFree(g->base);
-        if (g->sparse_mem) (void)hipFree(g->sparse_mem);
+        if (g->sparse_owned && g->sparse_mem) (void)hipFree(g->sparse_mem);
         if (g->host_state) (void)hipHostFree(g->host_state);
     }
     delete g;
@@ -585,8 +596,20 @@ static EvalArgs run_args(const bp_graph* g, int schedule, double eps, double p, 
     return a;
 }
 
-int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const bp_run_opts* opts,
-           bp_run_stats* stats) {
+}  // extern "C"
+
+// Device memory of one run besides the graph's arrays: iteration state,
+// counters and the per-block tie counts of the top-k.  bp_run takes them from
+// the graph's memory, bp_run_noalloc from the library's static scratch array.
+struct RunScratch {
+    DevState* st;
+    CounterLine* ctr;
+    unsigned int* ties;
+    bool noalloc;  // no events, no buffer allocation
+};
+
+static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t seed,
+                    const bp_run_opts* opts, bp_run_stats* stats, const RunScratch& rs) {
     if (!g) return fail(BP_EINVAL, "graph is NULL");
     if (schedule != BP_LBP && schedule != BP_RBP && schedule != BP_RNBP)
         return fail(BP_EINVAL, "unknown schedule %d", schedule);
@@ -609,30 +632,42 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
         if (!g->L.big4.empty())
             return fail(BP_EINVAL, "sparse re-evaluation needs every node within one tile");
     }
+    if (rs.noalloc && o.profile)
+        return fail(BP_EINVAL, "profile needs HIP events, which bp_run_noalloc does not create");
     DeviceGuard dg(g->device);
     const HostLayout& L = g->L;
     hipStream_t s = g->stream;
-    if (o.sparse && !g->sparse_mem) {
+    if (o.sparse && !g->sparse_ready) {
         const size_t nb = ((size_t)L.N + 255) / 256 * 256;
-        const size_t bytes = 2 * nb + sizeof(int) * (size_t)L.E + 256;
-        char* mem = nullptr;
-        hipError_t e = hipMalloc(&mem, bytes);
-        if (e != hipSuccess)
-            return fail(e == hipErrorOutOfMemory ? BP_ENOMEM : BP_EDEVICE,
-                        "sparse buffers (%zu bytes): %s", bytes, hipGetErrorString(e));
+        const size_t bytes = sparse_bytes(L);
+        char* mem = g->sparse_mem;
+        bool owned = g->sparse_owned;
+        if (!mem && L.sparse_reserved) mem = g->at<char>(g->off.sparse);
+        if (!mem) {
+            if (rs.noalloc)
+                return fail(BP_EINVAL, "sparse re-evaluation without allocation needs a graph "
+                                       "created with BP_FLAG_SPARSE_BUFFERS");
+            hipError_t e = hipMalloc(&mem, bytes);
+            if (e != hipSuccess)
+                return fail(e == hipErrorOutOfMemory ? BP_ENOMEM : BP_EDEVICE,
+                            "sparse buffers (%zu bytes): %s", bytes, hipGetErrorString(e));
+            owned = true;
+        }
         EvalArgs b{};
         b.node_ptr = g->at<int>(g->off.node_ptr);
         b.rev = g->at<int>(g->off.rev);
         b.num_nodes = L.N;
         b.dirty = (unsigned char*)mem;
         b.dst = (int*)(mem + 2 * nb);
-        e = launch_sparse_setup(b, 1, s);
+        hipError_t e = launch_sparse_setup(b, 1, s);
         if (e != hipSuccess) {
-            // keep the graph without sparse buffers, so that a later run retries
-            (void)hipFree(mem);
+            // keep the graph without a target index, so that a later run retries
+            if (owned && mem != g->sparse_mem) (void)hipFree(mem);
             return hip_fail(e, "target index");
         }
         g->sparse_mem = mem;
+        g->sparse_owned = owned;
+        g->sparse_ready = true;
         g->sp_dirty = (unsigned char*)mem;
         g->sp_hasact = (unsigned char*)(mem + nb);
         g->sp_dst = (int*)(mem + 2 * nb);
@@ -645,11 +680,13 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     }
     if (g->t_next + o.max_iters + 1 > 0xFFFFFFFFLL)
         return fail(BP_EINVAL, "iteration counter would pass 2^32");
-    HIP_OK(launch_init_state(g->st(), g->ctr(), s), "init state");
+    HIP_OK(launch_init_state(rs.st, rs.ctr, s), "init state");
 
     const int mode = schedule == BP_LBP ? kModeLBP : schedule == BP_RBP ? kModeRBP : kModeRnBP;
     long long rbp_k = 0;
     EvalArgs a = run_args(g, schedule, eps, p, seed, o, rbp_k);
+    a.st = rs.st;
+    a.ctr = rs.ctr;
     a.dirty = g->sp_dirty;
     a.hasact = g->sp_hasact;
     a.dst = g->sp_dst;
@@ -665,8 +702,10 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     }
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    HIP_OK(hipEventCreate(&ev0), "event");
-    HIP_OK(hipEventCreate(&ev1), "event");
+    if (!rs.noalloc) {
+        HIP_OK(hipEventCreate(&ev0), "event");
+        HIP_OK(hipEventCreate(&ev1), "event");
+    }
     // profile = k > 0.  When the evaluation kernel is the only launch of an
     // iteration (LBP / RnBP without oversized nodes), a pair of events brackets
     // each chunk of back-to-back launches: chunk time / launches is the kernel's
@@ -683,13 +722,13 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
     }
     double kernel_ms = 0.0;
     long long kernel_launches = 0;
-    HIP_OK(hipEventRecord(ev0, s), "event record");
+    if (ev0) HIP_OK(hipEventRecord(ev0, s), "event record");
 
     const int kp = kpad(L.K);
     const long long t_start = g->t_next;
     const int pair0 = g->cur_pair;
     float* const start_buf = g->cur();
-    unsigned int* ties = g->at<unsigned int>(g->off.ties);
+    unsigned int* ties = rs.ties;
     int in_chunk = 0;
     long long it = 0;
     bool final_launched = false;
@@ -709,11 +748,11 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
                 if (!final_launched) {
                     const int all = rbp_k >= L.E;
                     if (!all)
-                        HIP_OK(launch_rbp_select(g->st(), a.keys, a.rev, (int)L.E,
+                        HIP_OK(launch_rbp_select(rs.st, a.keys, a.rev, (int)L.E,
                                                  (unsigned int)rbp_k, (int)(t & 3), ties, s),
                                "top-k select");
                     const RbpSparse sp{a.dirty, a.dst, a.ctr, a.eps, (int)((t + 1) & 3), 1};
-                    HIP_OK(launch_rbp_commit(g->st(), a.keys, a.rev, a.cand, sp_buf, (int)L.E, L.row,
+                    HIP_OK(launch_rbp_commit(rs.st, a.keys, a.rev, a.cand, sp_buf, (int)L.E, L.row,
                                              all, (int)(t & 3), ties, sp, s),
                            "top-k commit");
                 }
@@ -722,7 +761,7 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
             }
             ++in_chunk;
             if (in_chunk == o.check_every || final_launched) {
-                HIP_OK(hipMemcpyAsync(g->host_state, g->st(), kStateReadback, hipMemcpyDeviceToHost,
+                HIP_OK(hipMemcpyAsync(g->host_state, rs.st, kStateReadback, hipMemcpyDeviceToHost,
                                       s),
                        "state readback");
                 HIP_OK(hipStreamSynchronize(s), "synchronize");
@@ -758,19 +797,19 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
         if (prof_every && !prof_window) kev_used[in_chunk] = timed ? 1 : 0;
         if (mode == kModeRBP && !final_launched) {
             const int all = rbp_k >= L.E;
-            HIP_OK(launch_rbp_gate(g->st(), g->ctr(), (int)(t & 3), s), "top-k gate");
+            HIP_OK(launch_rbp_gate(rs.st, rs.ctr, (int)(t & 3), s), "top-k gate");
             if (!all)
-                HIP_OK(launch_rbp_select(g->st(), a.keys, a.rev, (int)L.E, (unsigned int)rbp_k,
+                HIP_OK(launch_rbp_select(rs.st, a.keys, a.rev, (int)L.E, (unsigned int)rbp_k,
                                          (int)(t & 3), ties, s),
                        "top-k select");
-            HIP_OK(launch_rbp_commit(g->st(), a.keys, a.rev, a.cand, start_buf, (int)L.E, L.row, all,
+            HIP_OK(launch_rbp_commit(rs.st, a.keys, a.rev, a.cand, start_buf, (int)L.E, L.row, all,
                                      (int)(t & 3), ties, RbpSparse{}, s),
                    "top-k commit");
         }
         ++in_chunk;
         if (in_chunk == o.check_every || final_launched) {
             if (prof_window) HIP_OK(hipEventRecord(kev[1], s), "event record");
-            HIP_OK(hipMemcpyAsync(g->host_state, g->st(), kStateReadback, hipMemcpyDeviceToHost, s),
+            HIP_OK(hipMemcpyAsync(g->host_state, rs.st, kStateReadback, hipMemcpyDeviceToHost, s),
                    "state readback");
             HIP_OK(hipStreamSynchronize(s), "synchronize");
             if (prof_window) {
@@ -798,7 +837,7 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
                 a.it = it + 1;
                 a.after_final = 0;
                 HIP_OK(launch_close_run(a, s), "close evaluation");
-                HIP_OK(hipMemcpyAsync(g->host_state, g->st(), kStateReadback, hipMemcpyDeviceToHost,
+                HIP_OK(hipMemcpyAsync(g->host_state, rs.st, kStateReadback, hipMemcpyDeviceToHost,
                                       s),
                        "state readback");
                 HIP_OK(hipStreamSynchronize(s), "synchronize");
@@ -826,14 +865,16 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
         a.after_final = final_launched ? 1 : 0;
         HIP_OK(launch_close_run(a, s), "close run");
     }
-    HIP_OK(hipEventRecord(ev1, s), "event record");
-    HIP_OK(hipMemcpyAsync(g->host_state, g->st(), kStateReadback, hipMemcpyDeviceToHost, s),
+    if (ev1) HIP_OK(hipEventRecord(ev1, s), "event record");
+    HIP_OK(hipMemcpyAsync(g->host_state, rs.st, kStateReadback, hipMemcpyDeviceToHost, s),
            "state readback");
     HIP_OK(hipStreamSynchronize(s), "synchronize");
     float total_ms = 0.0f;
-    HIP_OK(hipEventElapsedTime(&total_ms, ev0, ev1), "event time");
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
+    if (ev0) {
+        HIP_OK(hipEventElapsedTime(&total_ms, ev0, ev1), "event time");
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+    }
     for (auto& x : kev) (void)hipEventDestroy(x);
 
     const DevState& h = *g->host_state;
@@ -861,6 +902,41 @@ int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const
         stats->eval_kernel_launches = kernel_launches;
     }
     return converged ? BP_OK : BP_NOT_CONVERGED;
+}
+
+// Scratch bytes of a run for a graph of E messages: state, counters, ties.
+size_t bp::run_scratch_bytes(long long E) {
+    const size_t st = (sizeof(DevState) + 255) & ~size_t(255);
+    const size_t ctr = sizeof(CounterLine) * 4 * kCounterCopies;
+    return st + ctr + sizeof(unsigned int) * (size_t)(E / 4096 + 2);
+}
+
+int bp::run_with_scratch(bp_graph* g, int schedule, double eps, double p, uint64_t seed,
+                         const bp_run_opts* opts, bp_run_stats* stats, char* scratch,
+                         size_t scratch_bytes) {
+    if (!g) return fail(BP_EINVAL, "graph is NULL");
+    const size_t need = run_scratch_bytes(g->L.E);
+    if (need > scratch_bytes)
+        return fail(BP_EINVAL, "graph of %lld messages needs %zu bytes of run scratch, the "
+                               "static scratch holds %zu",
+                    (long long)g->L.E, need, scratch_bytes);
+    const size_t st = (sizeof(DevState) + 255) & ~size_t(255);
+    RunScratch rs{(DevState*)scratch, (CounterLine*)(scratch + st),
+                  (unsigned int*)(scratch + st + sizeof(CounterLine) * 4 * kCounterCopies), true};
+    return run_impl(g, schedule, eps, p, seed, opts, stats, rs);
+}
+
+int bp::graph_device(const bp_graph* g) { return g ? g->device : -1; }
+
+int bp::report_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+extern "C" {
+
+int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed, const bp_run_opts* opts,
+           bp_run_stats* stats) {
+    if (!g) return fail(BP_EINVAL, "graph is NULL");
+    const RunScratch rs{g->st(), g->ctr(), g->at<unsigned int>(g->off.ties), false};
+    return run_impl(g, schedule, eps, p, seed, opts, stats, rs);
 }
 
 int bp_marginals_device(bp_graph* g, float* out_device) {
@@ -972,6 +1048,8 @@ struct Request {
     int slot = -1;
     std::vector<float> marg;
     bp_run_stats stats{};
+    int error = BP_OK;          // retired without a result: the admission's error
+    std::string error_msg;
 };
 
 // First-fit allocator over the arena, 256-byte granules.
@@ -1033,6 +1111,7 @@ struct bp_server {
     int64_t next_id = 1;
     uint64_t done_off = 0;                 // unsigned [max_graphs]: gathered done flags
     unsigned int* h_done = nullptr;        // pinned mirror
+    int inject_failures = 0;               // admissions still to fail (test hook)
 };
 
 namespace {
@@ -1054,12 +1133,20 @@ int server_admit(bp_server* s) {
         d.workspace = s->base + off;
         d.workspace_bytes = r->bytes;
         bp_graph* g = nullptr;
-        const int rc = create_graph_from_layout(std::move(r->L), &d, &g);
-        if (rc != BP_OK) {
-            s->alloc.give(off, r->bytes);
-            return rc;
-        }
+        const bool inject = s->inject_failures > 0;
+        if (inject) --s->inject_failures;
+        const int rc = create_graph_from_layout(r->L, &d, &g, inject);
         s->queue.pop_front();
+        if (rc != BP_OK) {
+            // the request leaves the queue with the error as its result; the
+            // requests behind it are admitted as usual
+            s->alloc.give(off, r->bytes);
+            r->error = rc;
+            r->error_msg = g_last_error;
+            r->state = Request::kRetired;
+            r->L = HostLayout();
+            continue;
+        }
         r->g = g;
         r->off = off;
         r->slot = slot;
@@ -1305,6 +1392,13 @@ int bp_server_result(bp_server* s, int64_t id, float* marginals, bp_run_stats* s
     if (it == s->reqs.end()) return fail(BP_EINVAL, "unknown request %lld", (long long)id);
     Request* r = it->second;
     if (r->state != Request::kRetired) return BP_ESTATE;
+    if (r->error != BP_OK) {
+        const int code = r->error;
+        fail(code, "request %lld was not admitted: %s", (long long)id, r->error_msg.c_str());
+        s->reqs.erase(it);
+        delete r;
+        return code;
+    }
     if (marginals) std::memcpy(marginals, r->marg.data(), sizeof(float) * r->marg.size());
     if (stats) *stats = r->stats;
     s->reqs.erase(it);
@@ -1323,6 +1417,13 @@ int bp_server_counts(const bp_server* s, int64_t* queued, int64_t* resident, int
     if (queued) *queued = q;
     if (resident) *resident = a;
     if (retired) *retired = d;
+    return BP_OK;
+}
+
+int bp_server_inject_failures(bp_server* s, int32_t admissions) {
+    if (!s) return fail(BP_EINVAL, "server is NULL");
+    if (admissions < 0) return fail(BP_EINVAL, "admissions < 0");
+    s->inject_failures = admissions;
     return BP_OK;
 }
 

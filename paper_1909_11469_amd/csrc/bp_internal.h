@@ -3,7 +3,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+#include "../../include/bp.h"
 
 namespace bp {
 
@@ -177,5 +180,17 @@ hipError_t launch_rbp_commit(DevState* st, unsigned int* keys, const int* rev,
 // frontier residual BP under sparse re-evaluation: evaluate the dirty nodes,
 // then close the evaluation (one wave) and gate the top-k kernels
 hipError_t launch_sparse_rbp_eval(const EvalArgs& a, hipStream_t s);
+
+// Host side (bp_api.cpp) used by other translation units of the library.
+// bp_run with its per-run device scratch (iteration state, counters, top-k
+// tie counts) taken from `scratch` instead of the graph's memory, and without
+// creating events or buffers.
+size_t run_scratch_bytes(long long num_messages);
+int run_with_scratch(bp_graph* g, int schedule, double eps, double p, uint64_t seed,
+                     const bp_run_opts* opts, bp_run_stats* stats, char* scratch,
+                     size_t scratch_bytes);
+int graph_device(const bp_graph* g);
+// Record an error for bp_last_error() and return `code`.
+int report_error(int code, const char* msg);
 
 }  // namespace bp

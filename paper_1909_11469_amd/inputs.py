@@ -155,3 +155,20 @@ def random_dense_graph(n: int, m: int, K: int, seed: int, coupling_scale: float 
     pair = np.exp(coupling_scale * rng.standard_normal(size=(m, K, K)))
     return dict(N=n, K=K, edges=edges, log_unary=lu, pair_kind=PAIR_DENSE, pair=pair,
                 name=f"dense{n}_{m}_K{K}_s{seed}")
+
+
+def shared_table_graph(n: int, m: int, K: int, seed: int, tree: bool = False) -> dict:
+    """Small graph with one shared K x K table exp(N(0, 1)) (not symmetric) and a
+    per-edge scale ~ U[0.5, 1.5]: a random labelled tree on n nodes when `tree`,
+    else G(n, m).  Log-unaries ~ N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    if tree:
+        parent = np.array([rng.integers(0, i) for i in range(1, n)], dtype=np.int64)
+        edges = np.stack([parent, np.arange(1, n)], axis=1).astype(np.int32)
+    else:
+        edges = er_edges(n, m, rng)
+    lu = rng.standard_normal(size=(n, K))
+    shared = np.exp(rng.standard_normal(size=(K, K)))
+    scale = rng.uniform(0.5, 1.5, size=edges.shape[0])
+    return dict(N=n, K=K, edges=edges, log_unary=lu, pair_kind=PAIR_SHARED, shared=shared,
+                edge_scale=scale, name=f"shared{n}_K{K}_{'tree' if tree else m}_s{seed}")

@@ -1,0 +1,162 @@
+"""Multi-iteration runs of the HIP path, checked iteration by iteration
+against the FP64 oracle.
+
+A run of max_iters = k from a state S_0 performs the same launches as the run
+of max_iters = k - 1 and one more (same arguments, same device, bitwise
+deterministic), so its state S_k is the continuous run's state after k
+iterations.  Iteration k of the continuous run is then checked against one
+oracle step of Alg. 1 from S_{k-1}: the same global iteration number t (the
+random filter's counter) and the same n_{t-1} (the EdgeRatio rule of
+Sec. IV-A), read back from the GPU after the (k - 1)-run.  Ten iterations
+cover two and a half rotations of the four counter sets of the device loop, the
+choice between the two outputs of a dynamic-p RnBP launch (LowP = 0.5 and
+HighP = 1 differ) in every iteration, and the carried state of sparse
+re-evaluation.
+
+Tolerances (the one-sweep bar): messages of the frontier within 1e-6 relative
+of the oracle's Eq. (2) candidates; every other message bitwise unchanged; the
+frontier equal except for messages whose FP64 residual lies within 1e-6 of the
+decision threshold, which must be rare.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_11469_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SWEEP_TOL = 1e-6
+BAND = 1e-6
+
+
+@pytest.fixture(scope="module")
+def bp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1909_11469_amd import bp as mod
+    return mod
+
+
+def _rel_err(m_gpu, m_ref):
+    d = np.max(np.abs(m_gpu.astype(np.float64) - m_ref), axis=1)
+    return d / np.max(np.abs(m_ref), axis=1)
+
+
+def _random_state(E, seed, lo):
+    m = np.random.default_rng(seed).uniform(lo, 1.0, size=(E, 2))
+    m /= m.sum(1, keepdims=True)
+    return m.astype(np.float32)
+
+
+def _gpu_prefix_runs(bp, prob, S0, t0, kmax, schedule, p, seed, eps, dynamic_p=True, sparse=0):
+    """States, iteration states and stats of the runs with max_iters = 0..kmax from S0."""
+    out = []
+    with bp.Graph(prob) as g:
+        for k in range(kmax + 1):
+            g.set_state(S0, t=t0, prev_active=-1)
+            r = g.run(schedule, eps=eps, p=p, seed=seed, max_iters=k, warm_start=True,
+                      dynamic_p=dynamic_p, sparse=sparse, check_every=3)
+            m, st = g.get_state()
+            out.append((m, st, r))
+    return out
+
+
+def _check_iteration(prob, prev_state, state, r, schedule, p, seed, eps, dynamic_p, max_band=3):
+    """Iteration k of the GPU run (prev_state -> state) against one oracle step.
+    Returns the oracle's p_t and the number of band messages."""
+    m_prev, st_prev, _ = prev_state
+    m_now, st_now, _ = state
+    E = m_prev.shape[0]
+    start = m_prev.astype(np.float64)
+    ref = oracle.run(prob, {"rnbp": oracle.RNBP, "rbp": oracle.RBP, "lbp": oracle.LBP}[schedule],
+                     eps=eps, p=p, seed=seed, dynamic_p=dynamic_p, max_iters=1, init_msgs=start,
+                     t0=st_prev["t"], prev_active=st_prev["prev_active"], trace=True)
+    cand, res = oracle.evaluate(prob, start)
+    want = np.any(ref["msgs"] != start, axis=1)
+    if schedule == "rbp":
+        k = max(1, int(np.ceil(p * E)))
+        thr = np.sort(res)[::-1][k - 1]
+    else:
+        thr = eps
+    band = np.abs(res - thr) < BAND
+    changed = np.any(m_now != m_prev, axis=1)
+    assert np.array_equal(changed[~band], want[~band]), \
+        f"frontier differs at t={st_prev['t']}: {np.sum(changed[~band] != want[~band])} messages"
+    assert band.sum() <= max_band
+    sel = want & ~band
+    if sel.any():
+        assert _rel_err(m_now[sel], cand[sel]).max() <= SWEEP_TOL
+    # messages outside the frontier keep their bits
+    assert np.array_equal(m_now[~changed], m_prev[~changed])
+    # the iteration state: t advanced by one, n_{t} carried as the next n_{t-1}
+    assert st_now["t"] == st_prev["t"] + 1
+    n_t = int(ref["trace"]["active"][0])
+    assert abs(st_now["prev_active"] - n_t) <= band.sum()
+    return float(ref["trace"]["p"][0]), int(band.sum())
+
+
+CASES = [  # (side, C, eps, lo of the random start state)
+    (20, 1.0, 1e-3, 0.3),
+    (20, 2.5, 3e-3, 0.45),
+    (30, 1.0, 3e-3, 0.45),
+    (30, 2.5, 1e-2, 0.3),
+]
+
+
+@pytest.mark.parametrize("side,C,eps,lo", CASES)
+def test_rnbp_dynamic_p_ten_iterations_against_oracle(bp, side, C, eps, lo):
+    prob = inputs.ising_grid(side, side, C, 2)
+    E = 2 * len(prob["edges"])
+    S0 = _random_state(E, 5, lo)
+    p, seed, t0, kmax = 0.5, 11, 3, 10
+    runs = _gpu_prefix_runs(bp, prob, S0, t0, kmax, "rnbp", p, seed, eps)
+    ps = []
+    for k in range(1, kmax + 1):
+        assert runs[k][2]["iterations"] == k
+        pt, _ = _check_iteration(prob, runs[k - 1], runs[k], runs[k][2], "rnbp", p, seed, eps,
+                                 True)
+        ps.append(pt)
+    # both settings of the EdgeRatio rule occurred
+    assert 0.5 in ps and 1.0 in ps, ps
+    # committed counts add up over the run
+    assert runs[kmax][2]["committed"] == sum(
+        int(np.any(runs[k][0] != runs[k - 1][0], axis=1).sum()) for k in range(1, kmax + 1))
+
+
+@pytest.mark.parametrize("sparse", [1, 2])
+@pytest.mark.parametrize("side,C,eps,lo", CASES[:2])
+def test_sparse_rnbp_iterations_against_oracle(bp, sparse, side, C, eps, lo):
+    # sparse re-evaluation carries dirty flags, stored residuals and a running
+    # count across iterations; every iteration must still be Alg. 1's
+    prob = inputs.ising_grid(side, side, C, 2)
+    E = 2 * len(prob["edges"])
+    S0 = _random_state(E, 5, lo)
+    p, seed, t0, kmax = 0.5, 11, 3, 6
+    runs = _gpu_prefix_runs(bp, prob, S0, t0, kmax, "rnbp", p, seed, eps, sparse=sparse)
+    for k in range(1, kmax + 1):
+        _check_iteration(prob, runs[k - 1], runs[k], runs[k][2], "rnbp", p, seed, eps, True)
+
+
+@pytest.mark.parametrize("sparse", [0, 1])
+def test_rbp_iterations_against_oracle(bp, sparse):
+    prob = inputs.ising_grid(20, 20, 2.5, 4)
+    E = 2 * len(prob["edges"])
+    S0 = _random_state(E, 6, 0.3)
+    p, kmax = 0.05, 6
+    runs = _gpu_prefix_runs(bp, prob, S0, 0, kmax, "rbp", p, 0, 1e-9, sparse=sparse)
+    for k in range(1, kmax + 1):
+        _check_iteration(prob, runs[k - 1], runs[k], runs[k][2], "rbp", p, 0, 1e-9, True)
+
+
+def test_ising_1000_dynamic_p_three_iterations_full_size(bp):
+    # the benchmark's workload and launch configuration (1000 x 1000, C = 2.5,
+    # RnBP LowP = 0.5, eps = 1e-4, persistent grid), every message compared
+    prob = inputs.ising_grid(1000, 1000, 2.5, 0)
+    E = 2 * len(prob["edges"])
+    S0 = _random_state(E, 9, 0.3)
+    p, seed, eps, t0, kmax = 0.5, 3, 1e-4, 5, 3
+    runs = _gpu_prefix_runs(bp, prob, S0, t0, kmax, "rnbp", p, seed, eps)
+    for k in range(1, kmax + 1):
+        _check_iteration(prob, runs[k - 1], runs[k], runs[k][2], "rnbp", p, seed, eps, True,
+                         max_band=E // 100000)

@@ -86,3 +86,81 @@ def test_serving_rejects_unsupported(bp):
             srv.submit(inputs.ising_grid(4, 4, 1.0, 0), sparse=1)
         with pytest.raises(bp.BpError):
             srv.submit(inputs.ising_grid(300, 300, 1.0, 0))  # larger than the arena
+
+
+def _serve(bp, mix, arena_mb=256, max_graphs=16, launches=8, inject=0):
+    """Serve every request of the mix; returns {index: (marginals, stats)} and
+    {index: error code} for requests retired without a result."""
+    got, failed = {}, {}
+    with bp.Server(arena_mb << 20, max_graphs=max_graphs) as srv:
+        ids = [srv.submit(pr, sched, eps=eps, p=p, seed=seed, max_iters=mi)
+               for pr, sched, eps, p, seed, mi in mix]
+        if inject:
+            srv.inject_failures(inject)
+        for _ in range(100000):
+            srv.step(launches)
+            for k, i in enumerate(ids):
+                if k in got or k in failed:
+                    continue
+                try:
+                    r = srv.result(i)
+                except bp.BpError as e:
+                    failed[k] = e.code
+                    continue
+                if r is not None:
+                    got[k] = r
+            if len(got) + len(failed) == len(ids):
+                break
+        assert srv.counts() == (0, 0, 0)
+    return got, failed
+
+
+def test_serving_results_against_oracle(bp):
+    import oracle
+    # problems with a unique fixed point (weak coupling, a chain): served to
+    # convergence, their beliefs match the oracle's converged beliefs (1e-4);
+    # requests capped after one iteration from uniform messages (p_0 = HighP =
+    # 1, so the RnBP step commits every message above eps) match one oracle
+    # iteration, FP32 against FP64 (1e-5)
+    conv = [
+        (inputs.ising_grid(15, 16, 0.5, 0), "rnbp", 1e-7, 0.5, 1, 10000),
+        (inputs.ising_grid(21, 9, 0.4, 1), "lbp", 1e-7, 1.0, 0, 10000),
+        (inputs.chain(300, 2.0, 3), "lbp", 1e-8, 1.0, 0, 10000),
+        (inputs.er_graph(400, 4.0, 0.4, 4), "rnbp", 1e-7, 0.7, 4, 10000),
+        (_star(600, 5), "rnbp", 1e-7, 0.5, 4, 10000),  # oversized node
+    ]
+    capped = [
+        (inputs.ising_grid(20, 20, 2.5, 1), "lbp", 1e-4, 1.0, 0, 1),
+        (inputs.ising_grid(17, 23, 4.0, 2), "rnbp", 1e-4, 0.3, 9, 1),
+        (inputs.er_graph(500, 6.0, 2.5, 5), "lbp", 1e-4, 1.0, 0, 1),
+    ]
+    mix = conv + capped
+    got, failed = _serve(bp, mix, launches=16)
+    assert not failed and len(got) == len(mix)
+    for k, (pr, sched, eps, p, seed, mi) in enumerate(conv):
+        m, r = got[k]
+        assert r["converged"], k
+        ref = oracle.run(pr, oracle.LBP, eps=1e-11, max_iters=20000)
+        assert ref["converged"]
+        assert np.max(np.abs(m - ref["marginals"])) <= 1e-4, k
+    for j, (pr, sched, eps, p, seed, mi) in enumerate(capped):
+        m, r = got[len(conv) + j]
+        assert r["iterations"] == 1 and not r["converged"]
+        ref = oracle.run(pr, oracle.LBP if sched == "lbp" else oracle.RNBP, eps=eps, p=p,
+                         seed=seed, max_iters=1)
+        assert np.max(np.abs(m - ref["marginals"])) <= 1e-5, j
+
+
+def test_serving_failed_admission_is_reported_and_others_served(bp):
+    # the first admission fails (test hook): that request is retired with the
+    # device error, its arena room returned, and every other request is served
+    # exactly as bp_run serves it
+    mix = _mix()[:5]
+    got, failed = _serve(bp, mix, arena_mb=64, max_graphs=4, inject=1)
+    assert failed == {0: bp.BP_EDEVICE}
+    for k in range(1, len(mix)):
+        pr, sched, eps, p, seed, mi = mix[k]
+        m_ref, r_ref = _alone(bp, pr, sched, eps, p, seed, mi)
+        m, r = got[k]
+        assert np.array_equal(m, m_ref), k
+        assert r["iterations"] == r_ref["iterations"] and r["committed"] == r_ref["committed"]

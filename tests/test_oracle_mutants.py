@@ -83,6 +83,29 @@ def pin_two_node_beliefs(lib):
     return np.allclose(r["marginals"][0], ba / ba.sum(), atol=1e-13)
 
 
+def pin_shared_tree(lib):
+    prob = inputs.shared_table_graph(7, 0, 3, 0, tree=True)
+    r = oracle.run(prob, oracle.LBP, eps=1e-13, max_iters=100, lib=lib)
+    return r["converged"] and np.allclose(r["marginals"],
+                                          exact_refs.brute_force_marginals(prob), atol=1e-10)
+
+
+def pin_beliefs_entry(lib):
+    prob = inputs.shared_table_graph(6, 8, 3, 2)
+    E = 2 * len(prob["edges"])
+    m = _rand_state(E, 3, 4)
+    b = oracle.beliefs(prob, m, lib=lib)
+    src, dst = oracle.canonical_src_dst(prob)
+    for i in range(prob["N"]):
+        w = np.exp(prob["log_unary"][i])
+        for f in range(E):
+            if dst[f] == i:
+                w = w * m[f]
+        if not np.allclose(b[i], w / w.sum(), atol=1e-14):
+            return False
+    return True
+
+
 def pin_philox(lib):
     out = oracle.philox4x32_10([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344],
                                [0xa4093822, 0x299f31d0], lib=lib)
@@ -142,7 +165,8 @@ def pin_weak_coupling_agree(lib):
     return np.allclose(ref["marginals"], r["marginals"], atol=1e-9)
 
 
-BATTERY = [pin_tree, pin_chain, pin_closed_form, pin_normalised, pin_two_node_beliefs,
+BATTERY = [pin_tree, pin_shared_tree, pin_beliefs_entry, pin_chain, pin_closed_form,
+           pin_normalised, pin_two_node_beliefs,
            pin_philox, pin_rnbp_definition, pin_rbp_sorted, pin_rbp_full_is_lbp,
            pin_dynamic_p, pin_weak_coupling_agree]
 
@@ -173,6 +197,11 @@ MUTANTS = {
                                     "if (da != db) return da > db ? -1 : 1;"),
     "philox_multiplier": ("const uint32_t M0 = 0xD2511F53u", "const uint32_t M0 = 0xD2511F55u"),
     "eps_filter_dropped": ("if (!(res[e] > eps)) continue;", ";"),
+    "shared_table_transposed": ("return g->edge_scale[u] * g->shared[xa * K + xb];",
+                                "return g->edge_scale[u] * g->shared[xb * K + xa];"),
+    "beliefs_skip_last_neighbour": (
+        "for (int64_t q = g->in_ptr[i]; q < g->in_ptr[i + 1]; ++q)\n                xmul(&b,",
+        "for (int64_t q = g->in_ptr[i]; q + 1 < g->in_ptr[i + 1]; ++q)\n                xmul(&b,"),
 }
 
 

@@ -209,6 +209,94 @@ def test_dense_update_against_explicit_formula_small():
 
 
 # --------------------------------------------------------------------------
+# Shared K x K table with a per-edge scale (the Potts parameterisation):
+# psi_u(x_a, x_b) = scale_u * shared[x_a, x_b], first index the state of edges[u, 0]
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,K,seed", [(7, 3, 0), (9, 4, 1), (6, 5, 2)])
+def test_shared_asymmetric_table_tree_equals_enumeration(n, K, seed):
+    # BP is exact on a tree (Sec. II-A); an asymmetric table makes the
+    # orientation of psi for each direction of an edge visible in the marginals
+    prob = inputs.shared_table_graph(n, 0, K, seed, tree=True)
+    assert not np.allclose(prob["shared"], prob["shared"].T)
+    assert np.ptp(prob["edge_scale"]) > 0.1
+    r = oracle.run(prob, oracle.LBP, eps=1e-14, max_iters=200)
+    assert r["converged"]
+    np.testing.assert_allclose(r["marginals"], exact_refs.brute_force_marginals(prob),
+                               atol=1e-11, rtol=0)
+
+
+def test_shared_table_update_both_directions_explicit():
+    # Eq. (2) written out for both messages of every edge of a loopy graph:
+    # a -> b sums psi(x_a, x_b) over x_a, b -> a sums psi(x_a, x_b) over x_b
+    prob = inputs.shared_table_graph(7, 11, 4, 3)
+    E = 2 * len(prob["edges"])
+    m = _random_state(E, 4, np.random.default_rng(4))
+    cand, res = oracle.evaluate(prob, m)
+    src, dst = oracle.canonical_src_dst(prob)
+    psi_i = np.exp(prob["log_unary"])
+    S = np.asarray(prob["shared"])
+    for e in range(E):
+        u, i, j = e // 2, src[e], dst[e]
+        g = psi_i[i].copy()
+        for f in range(E):
+            if dst[f] == i and src[f] != j:
+                g = g * m[f]
+        s = prob["edge_scale"][u]
+        if e % 2 == 0:   # i = edges[u, 0]: psi(x_i, x_j) = s * S[x_i, x_j]
+            c = np.array([sum(s * S[xi, xj] * g[xi] for xi in range(4)) for xj in range(4)])
+        else:            # i = edges[u, 1]: psi(x_j, x_i) = s * S[x_j, x_i]
+            c = np.array([sum(s * S[xj, xi] * g[xi] for xi in range(4)) for xj in range(4)])
+        np.testing.assert_allclose(cand[e], c / c.sum(), atol=1e-14)
+        assert res[e] == pytest.approx(np.max(np.abs(c / c.sum() - m[e])), abs=1e-14)
+
+
+def test_shared_table_loopy_run_equals_expanded_dense_tables():
+    # the same model written as per-edge dense tables (expanded here with numpy)
+    # runs the same iteration: every message and belief agrees to rounding
+    prob = inputs.shared_table_graph(9, 16, 3, 5)
+    dense = dict(prob)
+    dense["pair_kind"] = inputs.PAIR_DENSE
+    dense["pair"] = prob["edge_scale"][:, None, None] * np.asarray(prob["shared"])[None]
+    a = oracle.run(prob, oracle.RNBP, eps=1e-6, p=0.5, seed=3, max_iters=40)
+    b = oracle.run(dense, oracle.RNBP, eps=1e-6, p=0.5, seed=3, max_iters=40)
+    assert a["iterations"] == b["iterations"] and a["committed"] == b["committed"]
+    np.testing.assert_allclose(a["msgs"], b["msgs"], atol=1e-13, rtol=0)
+    np.testing.assert_allclose(a["marginals"], b["marginals"], atol=1e-13, rtol=0)
+
+
+# --------------------------------------------------------------------------
+# Eq. (3) on its own (oracle.beliefs): from a message set, not a run
+# --------------------------------------------------------------------------
+def test_beliefs_of_random_messages_explicit():
+    prob = inputs.shared_table_graph(8, 12, 3, 6)
+    E = 2 * len(prob["edges"])
+    m = _random_state(E, 3, np.random.default_rng(9))
+    b = oracle.beliefs(prob, m)
+    src, dst = oracle.canonical_src_dst(prob)
+    for i in range(prob["N"]):
+        w = np.exp(prob["log_unary"][i])
+        for f in range(E):
+            if dst[f] == i:
+                w = w * m[f]
+        np.testing.assert_allclose(b[i], w / w.sum(), atol=1e-15)
+
+
+def test_beliefs_of_tree_fixed_point_equal_enumeration():
+    prob = inputs.random_tree(9, 3, 7)
+    r = oracle.run(prob, oracle.LBP, eps=1e-14, max_iters=100)
+    assert r["converged"]
+    np.testing.assert_allclose(oracle.beliefs(prob, r["msgs"]),
+                               exact_refs.brute_force_marginals(prob), atol=1e-12, rtol=0)
+    # no neighbour: the belief is the normalised unary
+    iso = dict(N=3, K=2, edges=np.zeros((0, 2), np.int32),
+               log_unary=np.array([[0.0, 1.0], [2.0, -1.0], [0.5, 0.5]]),
+               pair_kind=inputs.PAIR_ISING, coupling=np.zeros(0))
+    want = np.exp(iso["log_unary"])
+    np.testing.assert_allclose(oracle.beliefs(iso, np.zeros((0, 2))),
+                               want / want.sum(1, keepdims=True), atol=1e-15)
+
+
+# --------------------------------------------------------------------------
 # The paper's correctness protocol (Sec. IV-E): 10 x 10 Ising, C = 2,
 # exact marginals by variable elimination, KL(exact || BP)
 # --------------------------------------------------------------------------
