@@ -28,13 +28,41 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def iteration_bytes(N, E, K=2, K_unary=1):
+    """Algorithmic bytes of one dense iteration (the workload's definition):
+    every message read once and written once as K FP32 values, the pairwise
+    parameter of every undirected edge (4), K_unary FP32 unary values per node,
+    the slot offsets (N + 1 int32) and two int32 indices per message:
+    2 E K 4 + (E / 2) 4 + N K_unary 4 + (N + 1) 4 + 2 E 4.
+    1000 x 1000 Ising: 111.9 MB (28.0 B per message)."""
+    return 2 * E * K * 4 + (E // 2) * 4 + N * K_unary * 4 + (N + 1) * 4 + 2 * E * 4
+
+
 def eval_kernel_bytes(N, E, two_outputs=True):
-    """Algorithmic bytes of one launch of the K = 2 evaluation kernel, each
-    array element moved once: per directed message the in-slot log-odds (4),
-    the reverse index (4), the coupling (4) and the committed value (4), and in
-    RnBP mode the committed value under the second keep threshold (4); per node
-    the slot offset (4) and the unary log-odds (4)."""
+    """Bytes the K = 2 log-odds evaluation kernel must move, each array element
+    once: per directed message the in-slot log-odds (4), the reverse index (4),
+    the coupling (4) and the committed value (4), and in RnBP mode the committed
+    value under the second keep threshold (4); per node the slot offset (4) and
+    the unary log-odds (4).  (The stored layout keeps one value per K = 2
+    message, hence fewer bytes than iteration_bytes.)"""
     return (20 if two_outputs else 16) * E + 8 * N
+
+
+def host_cpu():
+    """Host cores and CPU model (for the CPU baseline)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": usable, "logical_cpus": os.cpu_count(), "model": model}
 
 
 def counter_traffic(path, kernel_src):
@@ -153,6 +181,9 @@ def main():
                     help="run one 256 MiB device-to-device copy kernel first (a known-size "
                          "reference for hardware byte counters)")
     ap.add_argument("--ttc-seeds", type=int, default=3)
+    ap.add_argument("--ttc-seeds-c1", type=int, default=50,
+                    help="graphs of the C = 1 time-to-convergence study for LBP and RnBP p = 0.5")
+    ap.add_argument("--cpu-omp-iters", type=int, default=100)
     ap.add_argument("--er-seeds", type=int, default=0,
                     help="time to convergence on this many 200k-node ER graphs (RnBP p = 0.3 "
                          "vs LBP, C = 2.5); 0 = skip")
@@ -219,16 +250,26 @@ def main():
          f"{conv} converged")
 
     avg_kernel_s = kern_ms / max(kern_n, 1) / 1e3
-    nbytes = eval_kernel_bytes(N, E)
+    # algorithmic bytes per launch: 28.0 B per directed message (the workload's
+    # definition, iteration_bytes) x E messages per launch
+    nbytes = iteration_bytes(N, E)
     achieved = nbytes / avg_kernel_s if avg_kernel_s > 0 else 0.0
+    stored = eval_kernel_bytes(N, E)
     traffic = counter_traffic(
         os.path.join(ROOT, "profiles", "k_eval_logodds_rnbp_ising1000_counters.txt"),
         os.path.join(ROOT, "paper_1909_11469_amd", "csrc", "bp_kernels.hip"))
     roofline = {"bound": "hbm", "kernel": "k_eval_logodds<RnBP>",
                 "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK, "traffic": traffic,
-                "bytes_per_launch": nbytes, "avg_kernel_us": avg_kernel_s * 1e6,
-                "launches": kern_n}
+                "bytes_per_launch": nbytes, "bytes_per_message": nbytes / E,
+                "bytes_definition": "2EK4 + (E/2)4 + N4 + (N+1)4 + 2E4 (each message read and "
+                                    "written once as K = 2 FP32 values, parameters, topology)",
+                "frac_stored_layout": (stored / avg_kernel_s / HBM_PEAK
+                                       if avg_kernel_s > 0 else None),
+                "stored_layout_bytes_per_launch": stored,
+                "frac_counter_traffic": (traffic / avg_kernel_s / HBM_PEAK
+                                         if traffic and avg_kernel_s > 0 else None),
+                "avg_kernel_us": avg_kernel_s * 1e6, "launches": kern_n}
 
     out = {
         "metric": "message updates/s (1000x1000 Ising, RnBP)",
@@ -254,13 +295,18 @@ def main():
     if not args.no_ttc:
         # time to convergence, LBP vs RnBP at several low settings p, and RnBP
         # with sparse re-evaluation once n_t <= E / 16 (bitwise the same run),
-        # per coupling scale (graph resident; the paper's C is twice this C)
+        # per coupling scale (graph resident; the paper's C is twice this C).
+        # At C = 1 (where schedules converge) LBP and RnBP p = 0.5 run on
+        # --ttc-seeds-c1 graphs, the other schedules on the first --ttc-seeds.
         ttc = {}
-        scheds = ([("lbp", 1.0, 0)] + [("rnbp", q, 0) for q in (0.1, 0.3, 0.5, 1.0)] +
-                  [("rnbp", 0.5, 2)] + [("rbp", q, 0) for q in (0.1, 0.3, 0.5)])
+        scheds_all = ([("lbp", 1.0, 0)] + [("rnbp", q, 0) for q in (0.1, 0.3, 0.5, 1.0)] +
+                      [("rnbp", 0.5, 2)] + [("rbp", q, 0) for q in (0.1, 0.3, 0.5)])
+        scheds_core = [("lbp", 1.0, 0), ("rnbp", 0.5, 0), ("rnbp", 0.5, 2)]
         for C in (1.0, 2.5, 4.0):
             rows = {}
-            for s in range(args.ttc_seeds):
+            nseeds = max(args.ttc_seeds, args.ttc_seeds_c1) if C == 1.0 else args.ttc_seeds
+            for s in range(nseeds):
+                scheds = scheds_all if s < args.ttc_seeds else scheds_core
                 pr = inputs.ising_grid(S, S, C, 100 + s)
                 with bp.Graph(pr) as gg:
                     for sched, q, sp in scheds:
@@ -328,10 +374,8 @@ def main():
                 ("er_200k_deg6_C2.5", inputs.er_graph(200000, 6.0, 2.5, 0), 0.3, 1000),
                 ("potts_500x500_K32", inputs.potts_grid(500, 500, 32, 1.0, 0), 0.5, 100)):
             E_, N_, K_ = 2 * len(pr["edges"]), pr["N"], pr["K"]
-            # K = 2: 20 B per message + 8 per node; [E][K]: own row, two output rows
-            # and the reverse index per message, unary row and slot offset per node
-            nb = (eval_kernel_bytes(N_, E_) if K_ == 2
-                  else E_ * (12 * K_ + 4) + N_ * (4 * K_ + 4))
+            # the workload's algorithmic bytes per iteration (iteration_bytes)
+            nb = iteration_bytes(N_, E_, K_, 1 if K_ == 2 else K_)
             row = {"schedule": "rnbp", "p": p_, "messages": E_, "bytes_per_launch": nb}
             # Potts: the matrix-core product and the FP32 vector path (flag 2)
             variants = (("", 0),) if K_ == 2 else (("", 0), ("vector_path_", 2))
@@ -379,7 +423,7 @@ def main():
                 rr = gg.run(sched, eps=args.eps, p=args.p, seed=1, max_iters=60,
                             check_every=args.check_every, profile=args.profile_every)
                 us = rr["eval_kernel_ms"] * 1e3 / max(rr["eval_kernel_launches"], 1)
-                nb = eval_kernel_bytes(N4, E4, two_outputs=sched == "rnbp")
+                nb = iteration_bytes(N4, E4)
                 row[sched] = {"eval_kernel_us": us, "bytes_per_launch": nb,
                               "hbm_frac": nb / (us * 1e-6) / HBM_PEAK if us > 0 else None,
                               "message_updates_per_s": rr["evaluated"] / (rr["device_ms"] / 1e3)}
@@ -390,18 +434,32 @@ def main():
         out["extra"] = extra
 
     if not args.no_cpu_baseline:
+        # the oracle as it is, on the host's cores: the parity build (one
+        # thread) and the same loop split over OpenMP threads
         import oracle
-        _log(f"bench: cpu baseline, {args.cpu_iters} oracle iterations")
+        host = host_cpu()
+        _log(f"bench: cpu baseline, {args.cpu_iters} oracle iterations (1 thread), "
+             f"{args.cpu_omp_iters} (OpenMP), host {host}")
         a = time.perf_counter()
         rr = oracle.run(prob, oracle.RNBP, eps=args.eps, p=args.p, seed=0,
                         max_iters=args.cpu_iters)
         dt = time.perf_counter() - a
+        single = {"value": rr["evaluated"] / dt, "unit": "message updates/s", "cores": 1,
+                  "sample": f"{args.cpu_iters} RnBP iterations ({rr['evaluated']} Eq. (2) "
+                            f"evaluations) of the same {S}x{S} grid, FP64, {dt:.1f} s"}
+        omp = oracle.load_openmp()
+        threads = oracle.num_threads(omp)
+        a = time.perf_counter()
+        ro = oracle.run(prob, oracle.RNBP, eps=args.eps, p=args.p, seed=0,
+                        max_iters=args.cpu_omp_iters, lib=omp)
+        dto = time.perf_counter() - a
         out["cpu_baseline"] = {
-            "value": rr["evaluated"] / dt, "unit": "message updates/s", "cores": 1,
+            "value": ro["evaluated"] / dto, "unit": "message updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{args.cpu_iters} RnBP iterations ({rr['evaluated']} Eq. (2) "
-                      f"evaluations) of the same {S}x{S} grid, FP64, single thread, "
-                      f"{dt:.1f} s"}
+            "sample": f"{args.cpu_omp_iters} RnBP iterations ({ro['evaluated']} Eq. (2) "
+                      f"evaluations) of the same {S}x{S} grid, FP64, evaluation loop over "
+                      f"{threads} OpenMP threads, {dto:.1f} s wall",
+            "single_thread": single, "host": host}
     g.close()
     print(json.dumps(out), flush=True)
 

@@ -64,6 +64,8 @@ def _configure(lib):
     lib.oracle_bp_evaluate.restype = ctypes.c_int
     lib.oracle_bp_beliefs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, P, P, P, P]
     lib.oracle_bp_beliefs.restype = ctypes.c_int
+    lib.oracle_num_threads.argtypes = []
+    lib.oracle_num_threads.restype = ctypes.c_int
     return lib
 
 
@@ -84,6 +86,19 @@ def _load(lib=None):
         build_oracle.build()
     _lib = load_library(_LIB_PATH)
     return _lib
+
+
+def load_openmp():
+    """The timing build: the same oracle with its evaluation loop split over
+    OpenMP threads (the benchmark's multi-core CPU baseline)."""
+    from . import build_oracle
+    if not os.path.exists(build_oracle.LIB_OMP):
+        build_oracle.build()
+    return load_library(build_oracle.LIB_OMP)
+
+
+def num_threads(lib=None):
+    return int(_load(lib).oracle_num_threads())
 
 
 def _ptr(a):

@@ -26,6 +26,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_PAIR_ISING 0
 #define OR_PAIR_SHARED 1
@@ -237,6 +240,49 @@ static void eval_message(const model_t* g, const double* m, int64_t e, double* o
     for (int xj = 0; xj < K; ++xj) out[xj] /= z;
 }
 
+/* f_BP(m) for every message and its residual (Eq. (4), L-infinity norm).
+ * Every candidate reads m only, so the messages are independent: the timing
+ * build (liboracle_omp.so, compiled with OpenMP) splits them over threads,
+ * the parity build ignores the pragmas.  Each message is computed the same way
+ * in both, so both give the same bits. */
+static int evaluate_all(const model_t* g, const double* m, double* cand, double* res) {
+    int K = g->K;
+    int bad = 0;
+#pragma omp parallel
+    {
+        double* work = (double*)malloc(sizeof(double) * (size_t)K);
+        xprod* pw = (xprod*)malloc(sizeof(xprod) * (size_t)K);
+        int ok = work && pw;
+        if (!ok) {
+#pragma omp atomic write
+            bad = 1;
+        }
+#pragma omp for schedule(static)
+        for (int64_t e = 0; e < g->E; ++e) {
+            if (!ok) continue;
+            eval_message(g, m, e, cand + e * K, work, pw);
+            double r = 0.0;
+            for (int x = 0; x < K; ++x) {
+                double d = fabs(cand[e * K + x] - m[e * K + x]);
+                if (d > r) r = d;
+            }
+            res[e] = r;
+        }
+        free(work);
+        free(pw);
+    }
+    return bad ? -2 : 0;
+}
+
+/* Threads the evaluation uses (1 in the parity build). */
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* Eq. (3): b_i(x) proportional to psi_i(x) prod_{k in Gamma_i} m_{k->i}(x). */
 static int beliefs(const model_t* g, const double* m, double* out) {
     int K = g->K;
@@ -338,18 +384,16 @@ int oracle_bp_run(int N, int K, int64_t M, const int32_t* edges, const double* l
     for (int64_t it = 0;; ++it) {
         int64_t t = t0 + it;
         /* f_BP(m^t) and the residual of Eq. (4), L-infinity norm */
+        if (evaluate_all(&g, m, cand, res) != 0) {
+            free(m); free(cand); free(res); free(sel); free(order); free(work); free(pw);
+            free_model(&g);
+            return -2;
+        }
         int64_t n_t = 0;
         double r_max = 0.0;
         for (int64_t e = 0; e < E; ++e) {
-            eval_message(&g, m, e, cand + e * K, work, pw);
-            double r = 0.0;
-            for (int x = 0; x < K; ++x) {
-                double d = fabs(cand[e * K + x] - m[e * K + x]);
-                if (d > r) r = d;
-            }
-            res[e] = r;
-            if (r > eps) ++n_t;
-            if (r > r_max) r_max = r;
+            if (res[e] > eps) ++n_t;
+            if (res[e] > r_max) r_max = res[e];
         }
         st.evaluated += E;
         st.last_active = n_t;

@@ -20,6 +20,21 @@ def test_eval_kernel_bytes_1000x1000():
     assert bench.eval_kernel_bytes(N, E, two_outputs=False) == 16 * 3996000 + 8 * 1000000
 
 
+def test_iteration_bytes_matches_workload_definition():
+    # 28.0 B per directed message at 1000 x 1000 (111.9 MB), 298.5 MB for the
+    # 500 x 500 K = 32 Potts grid, 32.8 MB for the 200k-node ER graph
+    N, E = 1000 * 1000, 3996000
+    assert bench.iteration_bytes(N, E) == 111896004
+    assert abs(bench.iteration_bytes(N, E) / E - 28.0) < 0.01
+    assert bench.iteration_bytes(250000, 998000, 32, 32) == 298468004
+    assert bench.iteration_bytes(200000, 1200000) == 32800004
+
+
+def test_host_cpu_reports_cores():
+    h = bench.host_cpu()
+    assert h["nproc"] >= 1 and h["logical_cpus"] >= h["nproc"]
+
+
 def test_committed_counter_summary():
     # the summary's algorithmic bytes follow the byte model; its traffic is
     # reported exactly when it was taken on the kernel source as it stands

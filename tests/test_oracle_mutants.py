@@ -182,9 +182,10 @@ MUTANTS = {
     "product_exponent_dropped": ("p->ex += e;", ";"),
     "residual_l1_not_linf": ("if (d > r) r = d;\n            }\n            res[e] = r;",
                              "r += d;\n            }\n            res[e] = r;"),
-    "asynchronous_commit": ("            res[e] = r;\n",
-                            "            res[e] = r;\n            if (schedule == OR_LBP) "
-                            "for (int x = 0; x < K; ++x) m[e * K + x] = cand[e * K + x];\n"),
+    "asynchronous_commit": ("            res[e] = r;\n        }\n        free(work);",
+                            "            res[e] = r;\n            for (int x = 0; x < K; ++x) "
+                            "((double*)m)[e * K + x] = cand[e * K + x];\n        }\n"
+                            "        free(work);"),
     "rng_counter_source_is_target": (
         "double u = oracle_uniform(seed, (uint32_t)msg_src(&g, e),",
         "double u = oracle_uniform(seed, (uint32_t)msg_dst(&g, e),"),
