@@ -66,6 +66,9 @@ def _configure(lib):
     lib.oracle_bp_beliefs.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_srbp_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, P, P, ctypes.c_int,
+                                    P, P, P, P, ctypes.c_double, ctypes.c_int64, P, P, P, P]
+    lib.oracle_srbp_run.restype = ctypes.c_int
     return lib
 
 
@@ -186,6 +189,28 @@ def run(problem, schedule=LBP, eps=1e-4, p=1.0, high_p=1.0, ratio_threshold=0.9,
         n = st.final_t - int(t0) + 1
         res["trace"] = {k: v[:n] for k, v in tr.items()}
     return res
+
+
+def srbp(problem, eps=1e-4, max_updates=100000, trace=False, lib=None):
+    """Serial residual BP (one message at a time, largest residual first, ties
+    by (target, source)).  Returns msgs, marginals, converged, updates and (if
+    trace) the message id of every commit."""
+    lib = _load(lib)
+    N, K, M, edges, lu, kind, cp, sh, sc, pr = _prep(problem)
+    E = 2 * M
+    out_m = np.zeros((E, K), np.float64)
+    out_b = np.zeros((N, K), np.float64)
+    n = ctypes.c_int64()
+    tr = np.zeros(max(int(max_updates), 1), np.int64) if trace else None
+    rc = lib.oracle_srbp_run(N, K, M, _ptr(edges), _ptr(lu), kind, _ptr(cp), _ptr(sh), _ptr(sc),
+                             _ptr(pr), float(eps), int(max_updates), _ptr(out_m), _ptr(out_b),
+                             ctypes.byref(n), _ptr(tr))
+    if rc < 0:
+        raise ValueError(f"oracle_srbp_run failed with {rc}")
+    out = dict(msgs=out_m, marginals=out_b, converged=rc == 0, updates=int(n.value))
+    if trace:
+        out["trace"] = tr[:n.value]
+    return out
 
 
 def evaluate(problem, msgs, lib=None):

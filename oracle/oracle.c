@@ -517,3 +517,76 @@ int oracle_bp_beliefs(int N, int K, int64_t M, const int32_t* edges, const doubl
     free_model(&g);
     return rc;
 }
+
+/*
+ * Serial residual BP (Sec. II-B; the paper's serial CPU baseline, Sec. III-B):
+ * one message at a time, always the one with the largest residual, using the
+ * newest messages.  Written plainly: after every commit every message is
+ * evaluated again and the largest residual found by a scan.  Ties are taken
+ * in (target, source) ascending order, as for the greedy frontier.
+ *   max_updates  cap on commits; converged when the largest residual <= eps
+ *   trace        optional, length max_updates: the message id of each commit
+ * Returns 0 if converged, 1 if not, negative on bad input.
+ */
+int oracle_srbp_run(int N, int K, int64_t M, const int32_t* edges, const double* log_unary,
+                    int pair_kind, const double* coupling, const double* shared,
+                    const double* edge_scale, const double* pair, double eps,
+                    int64_t max_updates, double* out_msgs, double* out_marginals,
+                    int64_t* out_updates, int64_t* trace) {
+    if (N < 0 || K < 2 || M < 0 || max_updates < 0) return -1;
+    if (pair_kind == OR_PAIR_ISING && K != 2) return -1;
+    model_t g;
+    if (build_model(&g, N, K, M, edges, log_unary, pair_kind, coupling, shared, edge_scale,
+                    pair) != 0) {
+        free_model(&g);
+        return -2;
+    }
+    const int64_t E = g.E;
+    size_t msz = sizeof(double) * (size_t)E * (size_t)K + 1;
+    double* m = (double*)malloc(msz);
+    double* cand = (double*)malloc(msz);
+    double* res = (double*)malloc(sizeof(double) * (size_t)E + 1);
+    if (!m || !cand || !res) {
+        free(m); free(cand); free(res);
+        free_model(&g);
+        return -2;
+    }
+    for (int64_t q = 0; q < E * K; ++q) m[q] = 1.0 / K;
+    int converged = 0;
+    int64_t updates = 0;
+    int rc = 0;
+    for (;;) {
+        if (evaluate_all(&g, m, cand, res) != 0) {
+            rc = -2;
+            break;
+        }
+        /* the message with the largest residual, ties by (target, source) */
+        int64_t best = -1;
+        for (int64_t e = 0; e < E; ++e) {
+            if (best < 0 || res[e] > res[best]) {
+                best = e;
+                continue;
+            }
+            if (res[e] < res[best]) continue;
+            int de = msg_dst(&g, e), db = msg_dst(&g, best);
+            if (de < db || (de == db && msg_src(&g, e) < msg_src(&g, best))) best = e;
+        }
+        if (best < 0 || !(res[best] > eps)) {
+            converged = 1;
+            break;
+        }
+        if (updates == max_updates) break;
+        for (int x = 0; x < K; ++x) m[best * K + x] = cand[best * K + x];
+        if (trace) trace[updates] = best;
+        ++updates;
+    }
+    if (rc == 0) {
+        if (out_msgs) memcpy(out_msgs, m, sizeof(double) * (size_t)E * (size_t)K);
+        if (out_marginals) rc = beliefs(&g, m, out_marginals);
+        if (out_updates) *out_updates = updates;
+    }
+    free(m); free(cand); free(res);
+    free_model(&g);
+    if (rc != 0) return rc;
+    return converged ? 0 : 1;
+}

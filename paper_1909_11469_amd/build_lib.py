@@ -7,6 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbp.so")
+LIB_SRBP = os.path.join(HERE, "libsrbp.so")
+SRBP_SOURCE = os.path.join(CSRC, "srbp.cpp")
 SOURCES = [os.path.join(CSRC, "bp_kernels.hip"), os.path.join(CSRC, "bp_api.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -24,6 +26,11 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     from concurrent.futures import ThreadPoolExecutor
     tag = "" if out == LIB else "." + os.path.basename(out)
     jobs = []
+    if out == LIB:
+        # serial residual BP: host code only
+        jobs.append((["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+                      "-I" + os.path.join(ROOT, "include"), "-o", LIB_SRBP + ".tmp", SRBP_SOURCE],
+                     None))
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.basename(src) + tag + ".o")
         cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ["-D" + d for d in defines] + ["-c", src, "-o", obj]
@@ -33,7 +40,9 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         for f in [ex.submit(subprocess.run, cmd, check=True) for cmd, _ in jobs]:
             f.result()
-    objs = [obj for _, obj in jobs]
+    if out == LIB:
+        os.replace(LIB_SRBP + ".tmp", LIB_SRBP)
+    objs = [obj for _, obj in jobs if obj is not None]
     tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -106,6 +106,26 @@ def pin_beliefs_entry(lib):
     return True
 
 
+def pin_srbp_replay(lib):
+    edges = inputs.grid_edges(3, 4)
+    prob = dict(N=12, K=2, edges=edges, log_unary=np.tile([-0.4, 0.4], (12, 1)),
+                pair_kind=inputs.PAIR_ISING, coupling=np.full(len(edges), 0.7))
+    prob["coupling"][3] = 0.2  # one edge apart: ties and non-ties both occur
+    r = oracle.srbp(prob, eps=1e-9, max_updates=40, trace=True, lib=lib)
+    src, dst = oracle.canonical_src_dst(prob)
+    E = 2 * len(edges)
+    m = np.full((E, 2), 0.5)
+    picks = []
+    for _ in range(40):
+        cand, res = oracle.evaluate(prob, m)  # the reference build
+        e = int(np.lexsort((src, dst, -res))[0])
+        if not res[e] > 1e-9:
+            break
+        m[e] = cand[e]
+        picks.append(e)
+    return r["trace"].tolist() == picks
+
+
 def pin_philox(lib):
     out = oracle.philox4x32_10([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344],
                                [0xa4093822, 0x299f31d0], lib=lib)
@@ -168,7 +188,7 @@ def pin_weak_coupling_agree(lib):
 BATTERY = [pin_tree, pin_shared_tree, pin_beliefs_entry, pin_chain, pin_closed_form,
            pin_normalised, pin_two_node_beliefs,
            pin_philox, pin_rnbp_definition, pin_rbp_sorted, pin_rbp_full_is_lbp,
-           pin_dynamic_p, pin_weak_coupling_agree]
+           pin_dynamic_p, pin_weak_coupling_agree, pin_srbp_replay]
 
 MUTANTS = {
     "reverse_message_not_excluded": ("if (f == back) continue;", ";"),
@@ -200,6 +220,13 @@ MUTANTS = {
     "eps_filter_dropped": ("if (!(res[e] > eps)) continue;", ";"),
     "shared_table_transposed": ("return g->edge_scale[u] * g->shared[xa * K + xb];",
                                 "return g->edge_scale[u] * g->shared[xb * K + xa];"),
+    "srbp_tie_break_descending_target": (
+        "if (de < db || (de == db && msg_src(&g, e) < msg_src(&g, best))) best = e;",
+        "if (de > db || (de == db && msg_src(&g, e) < msg_src(&g, best))) best = e;"),
+    "srbp_smallest_residual": ("if (best < 0 || res[e] > res[best]) {",
+                               "if (best < 0 || res[e] < res[best]) {"),
+    "srbp_commit_skipped": ("for (int x = 0; x < K; ++x) m[best * K + x] = cand[best * K + x];",
+                            ";"),
     "beliefs_skip_last_neighbour": (
         "for (int64_t q = g->in_ptr[i]; q < g->in_ptr[i + 1]; ++q)\n                xmul(&b,",
         "for (int64_t q = g->in_ptr[i]; q + 1 < g->in_ptr[i + 1]; ++q)\n                xmul(&b,"),

@@ -500,3 +500,73 @@ def test_lower_parallelism_converges_more_often():
                                    max_iters=1500)["converged"]
     assert conv["rnbp"] >= conv["lbp"]
     assert conv["rnbp"] > 0
+
+
+# --------------------------------------------------------------------------
+# Serial residual BP (Sec. II-B): one message at a time, the largest residual
+# first (ties by (target, source)), always from the newest messages
+# --------------------------------------------------------------------------
+def _srbp_replay(prob, eps, steps):
+    """The serial rule written out over oracle.evaluate: evaluate, pick, commit."""
+    E = 2 * len(prob["edges"])
+    K = int(prob["K"])
+    src, dst = oracle.canonical_src_dst(prob)
+    m = np.full((E, K), 1.0 / K)
+    picks = []
+    for _ in range(steps):
+        cand, res = oracle.evaluate(prob, m)
+        order = np.lexsort((src, dst, -res))
+        e = int(order[0])
+        if not res[e] > eps:
+            break
+        m[e] = cand[e]
+        picks.append(e)
+    return picks, m
+
+
+@pytest.mark.parametrize("n,K,seed", [(9, 3, 2), (12, 2, 4), (7, 4, 5)])
+def test_srbp_tree_equals_enumeration(n, K, seed):
+    prob = inputs.random_tree(n, K, seed)
+    r = oracle.srbp(prob, eps=1e-13, max_updates=100000)
+    assert r["converged"]
+    np.testing.assert_allclose(r["marginals"], exact_refs.brute_force_marginals(prob),
+                               atol=1e-11, rtol=0)
+
+
+def test_srbp_chain_equals_forward_backward():
+    prob = inputs.chain(40, 2.5, 6)
+    r = oracle.srbp(prob, eps=1e-13, max_updates=1000000)
+    assert r["converged"]
+    np.testing.assert_allclose(r["marginals"], exact_refs.chain_marginals(prob), atol=1e-11)
+
+
+def test_srbp_two_nodes_two_updates():
+    # each message of a single edge depends only on its source's unary, so one
+    # commit per message converges exactly
+    prob = inputs.random_tree(2, 3, 11)
+    r = oracle.srbp(prob, eps=1e-15, max_updates=100, trace=True)
+    assert r["converged"] and r["updates"] == 2 and sorted(r["trace"].tolist()) == [0, 1]
+
+
+@pytest.mark.parametrize("which", ["random", "ties"])
+def test_srbp_sequence_equals_replay(which):
+    if which == "random":
+        prob = inputs.ising_grid(4, 5, 2.0, 3)
+    else:
+        # equal fields and couplings: residuals tie exactly, so the order is
+        # decided by (target, source)
+        edges = inputs.grid_edges(3, 4)
+        prob = dict(N=12, K=2, edges=edges, log_unary=np.tile([-0.4, 0.4], (12, 1)),
+                    pair_kind=inputs.PAIR_ISING, coupling=np.full(len(edges), 0.7))
+    r = oracle.srbp(prob, eps=1e-9, max_updates=60, trace=True)
+    picks, m = _srbp_replay(prob, 1e-9, 60)
+    assert r["trace"].tolist() == picks
+    np.testing.assert_array_equal(r["msgs"], m)
+
+
+def test_srbp_weak_coupling_agrees_with_lbp():
+    prob = inputs.ising_grid(6, 7, 0.3, 2)
+    a = oracle.run(prob, oracle.LBP, eps=1e-13, max_iters=5000)
+    b = oracle.srbp(prob, eps=1e-13, max_updates=10 ** 6)
+    assert a["converged"] and b["converged"]
+    np.testing.assert_allclose(a["marginals"], b["marginals"], atol=1e-10)
