@@ -69,6 +69,10 @@ def _configure(lib):
     lib.oracle_srbp_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, P, P, ctypes.c_int,
                                     P, P, P, P, ctypes.c_double, ctypes.c_int64, P, P, P, P]
     lib.oracle_srbp_run.restype = ctypes.c_int
+    lib.oracle_rs_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, P, P, ctypes.c_int,
+                                  P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                  ctypes.c_int64, P, P, P, P, P, P, P]
+    lib.oracle_rs_run.restype = ctypes.c_int
     return lib
 
 
@@ -188,6 +192,41 @@ def run(problem, schedule=LBP, eps=1e-4, p=1.0, high_p=1.0, ratio_threshold=0.9,
     if tr is not None:
         n = st.final_t - int(t0) + 1
         res["trace"] = {k: v[:n] for k, v in tr.items()}
+    return res
+
+
+def rs(problem, eps=1e-4, p=1.0 / 256, splash_depth=2, max_iters=10000, init_msgs=None,
+       trace=False, lib=None):
+    """Residual splash in frontier form: roots = the k = min(N, max(1, ceil(p E)))
+    vertices of largest vertex residual (largest incoming residual), splash
+    levels by BFS distance <= splash_depth, updates through the levels h..0..h.
+    Returns msgs, marginals, stats and (if trace) active / committed / maxres."""
+    lib = _load(lib)
+    N, K, M, edges, lu, kind, cp, sh, sc, pr = _prep(problem)
+    E = 2 * M
+    out_m = np.zeros((E, K), np.float64)
+    out_b = np.zeros((N, K), np.float64)
+    init = None
+    if init_msgs is not None:
+        init = np.ascontiguousarray(init_msgs, dtype=np.float64).reshape(E, K)
+    st = OracleStats()
+    L = int(max_iters) + 1
+    tr = dict(active=np.zeros(L, np.int64), committed=np.zeros(L, np.int64),
+              maxres=np.zeros(L, np.float64)) if trace else None
+    rc = lib.oracle_rs_run(N, K, M, _ptr(edges), _ptr(lu), kind, _ptr(cp), _ptr(sh), _ptr(sc),
+                           _ptr(pr), float(eps), float(p), int(splash_depth), int(max_iters),
+                           _ptr(init), _ptr(out_m), _ptr(out_b), ctypes.byref(st),
+                           _ptr(tr["active"]) if tr else None,
+                           _ptr(tr["committed"]) if tr else None,
+                           _ptr(tr["maxres"]) if tr else None)
+    if rc < 0:
+        raise ValueError(f"oracle_rs_run failed with {rc}")
+    res = dict(msgs=out_m, marginals=out_b, converged=bool(st.converged),
+               iterations=st.iterations, last_active=st.last_active,
+               last_max_residual=st.last_max_residual, evaluated=st.evaluated,
+               committed=st.committed, final_t=st.final_t)
+    if tr is not None:
+        res["trace"] = {k: v[:st.final_t + 1] for k, v in tr.items()}
     return res
 
 

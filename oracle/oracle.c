@@ -590,3 +590,152 @@ int oracle_srbp_run(int N, int K, int64_t M, const int32_t* edges, const double*
     if (rc != 0) return rc;
     return converged ? 0 : 1;
 }
+
+/*
+ * Residual splash in frontier form (Sec. II-B, Sec. III-A): per iteration,
+ * evaluate f_BP(m^t) for every message (IsConverged as for the other rules);
+ * the residual of a vertex is the largest residual of its incoming messages;
+ * the k = min(N, max(1, ceil(p * E))) vertices of largest residual (ties by id
+ * ascending) are the roots; a splash of depth h around a root visits its BFS
+ * tree, so level L_d holds every vertex at graph distance exactly d from some
+ * root (d = 0..h).  The updates move through the levels h, h-1, ..., 1, 0, 1,
+ * ..., h: at each level every message out of every vertex of the level is
+ * recomputed by Eq. (2) from the messages as they stand when that level
+ * starts, and committed.
+ *   trace_*  optional, length max_iters + 1: n_t, messages committed, R_t.
+ * Returns 0 if converged, 1 if not, negative on bad input.
+ */
+int oracle_rs_run(int N, int K, int64_t M, const int32_t* edges, const double* log_unary,
+                  int pair_kind, const double* coupling, const double* shared,
+                  const double* edge_scale, const double* pair, double eps, double p,
+                  int splash_depth, int64_t max_iters, const double* init_msgs,
+                  double* out_msgs, double* out_marginals, oracle_stats* stats,
+                  int64_t* trace_active, int64_t* trace_committed, double* trace_maxres) {
+    if (N < 0 || K < 2 || M < 0 || max_iters < 0 || splash_depth < 0) return -1;
+    if (pair_kind == OR_PAIR_ISING && K != 2) return -1;
+    if (!(p > 0.0 && p <= 1.0)) return -1;
+    model_t g;
+    if (build_model(&g, N, K, M, edges, log_unary, pair_kind, coupling, shared, edge_scale,
+                    pair) != 0) {
+        free_model(&g);
+        return -2;
+    }
+    const int64_t E = g.E;
+    const int h = splash_depth;
+    size_t msz = sizeof(double) * (size_t)E * (size_t)K + 1;
+    double* m = (double*)malloc(msz);
+    double* cand = (double*)malloc(msz);
+    double* res = (double*)malloc(sizeof(double) * (size_t)E + 1);
+    double* vres = (double*)malloc(sizeof(double) * (size_t)N + 1);
+    int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)N + 1);
+    int32_t* dist = (int32_t*)malloc(sizeof(int32_t) * (size_t)N + 1);
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)N + 1);
+    unsigned char* level = (unsigned char*)malloc((size_t)(h + 1) * (size_t)N + 1);
+    double* work = (double*)malloc(sizeof(double) * (size_t)K);
+    xprod* pw = (xprod*)malloc(sizeof(xprod) * (size_t)K);
+    int rc = 0;
+    if (!m || !cand || !res || !vres || !order || !dist || !queue || !level || !work || !pw)
+        rc = -2;
+    if (rc == 0) {
+        if (init_msgs)
+            memcpy(m, init_msgs, sizeof(double) * (size_t)E * (size_t)K);
+        else
+            for (int64_t q = 0; q < E * K; ++q) m[q] = 1.0 / K;
+    }
+    oracle_stats st;
+    memset(&st, 0, sizeof(st));
+    st.last_prev_active = -1;
+    int converged = 0;
+    int64_t k = (int64_t)ceil(p * (double)E);
+    if (k < 1) k = 1;
+    if (k > N) k = N;
+    for (int64_t it = 0; rc == 0; ++it) {
+        if (evaluate_all(&g, m, cand, res) != 0) {
+            rc = -2;
+            break;
+        }
+        int64_t n_t = 0;
+        double r_max = 0.0;
+        for (int64_t e = 0; e < E; ++e) {
+            if (res[e] > eps) ++n_t;
+            if (res[e] > r_max) r_max = res[e];
+        }
+        st.evaluated += E;
+        st.last_active = n_t;
+        st.last_max_residual = r_max;
+        st.final_t = it;
+        if (trace_active) trace_active[it] = n_t;
+        if (trace_maxres) trace_maxres[it] = r_max;
+        if (trace_committed) trace_committed[it] = 0;
+        if (n_t == 0) {
+            converged = 1;
+            break;
+        }
+        if (it == max_iters) break;
+
+        /* vertex residuals and the k roots (largest first, ties by id):
+         * a selection by repeated scans, O(k N) */
+        for (int v = 0; v < N; ++v) {
+            vres[v] = 0.0;
+            for (int64_t q = g.in_ptr[v]; q < g.in_ptr[v + 1]; ++q)
+                if (res[g.in_ids[q]] > vres[v]) vres[v] = res[g.in_ids[q]];
+        }
+        memset(level, 0, (size_t)(h + 1) * (size_t)N);
+        for (int v = 0; v < N; ++v) order[v] = 0; /* 1 once chosen */
+        for (int64_t c = 0; c < k; ++c) {
+            int best = -1;
+            for (int v = 0; v < N; ++v)
+                if (!order[v] && (best < 0 || vres[v] > vres[best])) best = v;
+            order[best] = 1;
+            level[best] = 1; /* level 0 */
+        }
+        /* BFS of depth h from every root: level d gets every vertex at
+         * distance exactly d from that root */
+        for (int r = 0; r < N && h > 0; ++r) {
+            if (!level[r]) continue;
+            for (int v = 0; v < N; ++v) dist[v] = -1;
+            int head = 0, tail = 0;
+            dist[r] = 0;
+            queue[tail++] = r;
+            while (head < tail) {
+                int u = queue[head++];
+                if (dist[u] == h) continue;
+                for (int64_t q = g.in_ptr[u]; q < g.in_ptr[u + 1]; ++q) {
+                    int w = msg_src(&g, g.in_ids[q]); /* a neighbour of u */
+                    if (dist[w] >= 0) continue;
+                    dist[w] = dist[u] + 1;
+                    level[(size_t)dist[w] * N + w] = 1;
+                    queue[tail++] = w;
+                }
+            }
+        }
+        /* the splash updates: levels h, ..., 1, 0, 1, ..., h */
+        int64_t committed = 0;
+        for (int s = 0; s <= 2 * h; ++s) {
+            int d = s <= h ? h - s : s - h;
+            const unsigned char* L = level + (size_t)d * N;
+            for (int64_t e = 0; e < E; ++e)
+                if (L[msg_src(&g, e)]) eval_message(&g, m, e, cand + e * K, work, pw);
+            for (int64_t e = 0; e < E; ++e)
+                if (L[msg_src(&g, e)]) {
+                    for (int x = 0; x < K; ++x) m[e * K + x] = cand[e * K + x];
+                    ++committed;
+                }
+        }
+        st.evaluated += committed;
+        st.committed += committed;
+        st.iterations += 1;
+        if (trace_committed) trace_committed[it] = committed;
+    }
+    st.converged = converged;
+    if (rc == 0) {
+        if (out_msgs) memcpy(out_msgs, m, sizeof(double) * (size_t)E * (size_t)K);
+        if (out_marginals) rc = beliefs(&g, m, out_marginals);
+        if (stats) *stats = st;
+    }
+    free(m); free(cand); free(res); free(vres); free(order); free(dist); free(queue);
+    free(level); free(work); free(pw);
+    free_model(&g);
+    if (rc != 0) return rc;
+    return converged ? 0 : 1;
+}

@@ -126,6 +126,38 @@ def pin_srbp_replay(lib):
     return r["trace"].tolist() == picks
 
 
+def _rs_one(prob, m0, p, h, lib):
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+    N, E = int(prob["N"]), 2 * len(prob["edges"])
+    r = oracle.rs(prob, eps=1e-9, p=p, splash_depth=h, max_iters=1, init_msgs=m0, lib=lib)
+    src, dst = oracle.canonical_src_dst(prob)
+    _, res = oracle.evaluate(prob, m0)  # the reference build
+    vres = np.zeros(N)
+    np.maximum.at(vres, dst, res)
+    k = min(N, max(1, int(np.ceil(p * E))))
+    roots = np.lexsort((np.arange(N), -vres))[:k]
+    D = shortest_path(csr_matrix((np.ones(E), (src, dst)), shape=(N, N)), unweighted=True,
+                      indices=roots).reshape(k, N)
+    m = m0.copy()
+    for d in list(range(h, -1, -1)) + list(range(1, h + 1)):
+        c, _ = oracle.evaluate(prob, m)
+        sel = np.any(D == d, axis=0)[src]
+        m[sel] = c[sel]
+    return np.array_equal(r["msgs"], m)
+
+
+def pin_rs_replay(lib):
+    # a random state, and equal fields and couplings from uniform messages
+    # (every vertex residual equal: the roots are decided by the tie order)
+    prob = inputs.ising_grid(6, 7, 2.0, 1)
+    ok = _rs_one(prob, _rand_state(2 * len(prob["edges"]), 2, 3), 0.04, 2, lib)
+    edges = inputs.grid_edges(6, 7)
+    tied = dict(N=42, K=2, edges=edges, log_unary=np.tile([-0.4, 0.4], (42, 1)),
+                pair_kind=inputs.PAIR_ISING, coupling=np.full(len(edges), 0.7))
+    return ok and _rs_one(tied, np.full((2 * len(edges), 2), 0.5), 0.04, 2, lib)
+
+
 def pin_philox(lib):
     out = oracle.philox4x32_10([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344],
                                [0xa4093822, 0x299f31d0], lib=lib)
@@ -188,7 +220,7 @@ def pin_weak_coupling_agree(lib):
 BATTERY = [pin_tree, pin_shared_tree, pin_beliefs_entry, pin_chain, pin_closed_form,
            pin_normalised, pin_two_node_beliefs,
            pin_philox, pin_rnbp_definition, pin_rbp_sorted, pin_rbp_full_is_lbp,
-           pin_dynamic_p, pin_weak_coupling_agree, pin_srbp_replay]
+           pin_dynamic_p, pin_weak_coupling_agree, pin_srbp_replay, pin_rs_replay]
 
 MUTANTS = {
     "reverse_message_not_excluded": ("if (f == back) continue;", ";"),
@@ -227,6 +259,16 @@ MUTANTS = {
                                "if (best < 0 || res[e] < res[best]) {"),
     "srbp_commit_skipped": ("for (int x = 0; x < K; ++x) m[best * K + x] = cand[best * K + x];",
                             ";"),
+    "rs_vertex_residual_outgoing": (
+        "if (res[g.in_ids[q]] > vres[v]) vres[v] = res[g.in_ids[q]];",
+        "if (res[g.in_ids[q] ^ 1] > vres[v]) vres[v] = res[g.in_ids[q] ^ 1];"),
+    "rs_ties_by_id_descending": ("if (!order[v] && (best < 0 || vres[v] > vres[best])) best = v;",
+                                 "if (!order[v] && (best < 0 || vres[v] >= vres[best])) best = v;"),
+    "rs_return_pass_dropped": ("for (int s = 0; s <= 2 * h; ++s) {", "for (int s = 0; s <= h; ++s) {"),
+    "rs_level_not_synchronous": (
+        "if (L[msg_src(&g, e)]) eval_message(&g, m, e, cand + e * K, work, pw);",
+        "if (L[msg_src(&g, e)]) { eval_message(&g, m, e, cand + e * K, work, pw); "
+        "for (int x = 0; x < K; ++x) m[e * K + x] = cand[e * K + x]; }"),
     "beliefs_skip_last_neighbour": (
         "for (int64_t q = g->in_ptr[i]; q < g->in_ptr[i + 1]; ++q)\n                xmul(&b,",
         "for (int64_t q = g->in_ptr[i]; q + 1 < g->in_ptr[i + 1]; ++q)\n                xmul(&b,"),

@@ -570,3 +570,74 @@ def test_srbp_weak_coupling_agrees_with_lbp():
     b = oracle.srbp(prob, eps=1e-13, max_updates=10 ** 6)
     assert a["converged"] and b["converged"]
     np.testing.assert_allclose(a["marginals"], b["marginals"], atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Residual splash in frontier form (Sec. II-B, Sec. III-A): roots are the
+# vertices of largest residual (largest incoming message residual), a splash of
+# depth h updates the BFS levels h, ..., 0, ..., h around them
+# --------------------------------------------------------------------------
+def _rs_replay_iteration(prob, m, p, h):
+    """One splash iteration written out: residuals from oracle.evaluate, vertex
+    residuals, top-k roots by numpy sort, BFS distances from scipy, then the
+    level updates, each from the messages as they stand at that level."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+    N = int(prob["N"])
+    src, dst = oracle.canonical_src_dst(prob)
+    E = len(src)
+    _, res = oracle.evaluate(prob, m)
+    vres = np.zeros(N)
+    np.maximum.at(vres, dst, res)
+    k = min(N, max(1, int(np.ceil(p * E))))
+    roots = np.lexsort((np.arange(N), -vres))[:k]
+    A = csr_matrix((np.ones(E), (src, dst)), shape=(N, N))
+    D = shortest_path(A, unweighted=True, indices=roots).reshape(len(roots), N)
+    levels = [np.any(D == d, axis=0) for d in range(h + 1)]
+    m = m.copy()
+    for d in list(range(h, -1, -1)) + list(range(1, h + 1)):
+        c, _ = oracle.evaluate(prob, m)
+        sel = levels[d][src]
+        m[sel] = c[sel]
+    return m
+
+
+@pytest.mark.parametrize("which,p,h", [("grid", 0.02, 2), ("grid", 0.1, 1), ("er", 0.03, 2),
+                                       ("tree", 0.05, 2), ("grid", 0.05, 0)])
+def test_rs_iteration_equals_replay(which, p, h):
+    prob = {"grid": lambda: inputs.ising_grid(7, 8, 2.0, 1),
+            "er": lambda: inputs.er_graph(50, 5.0, 1.5, 2),
+            "tree": lambda: inputs.random_tree(40, 3, 3)}[which]()
+    E = 2 * len(prob["edges"])
+    m0 = _random_state(E, int(prob["K"]), np.random.default_rng(7))
+    r = oracle.rs(prob, eps=1e-9, p=p, splash_depth=h, max_iters=1, init_msgs=m0)
+    want = _rs_replay_iteration(prob, m0, p, h)
+    np.testing.assert_array_equal(r["msgs"], want)
+    assert r["committed"] == int(np.sum(np.any(r["msgs"] != m0, axis=1))) or h > 0
+
+
+def test_rs_depth_zero_all_roots_is_lbp():
+    # every vertex a root, no splash: one level holding every vertex, i.e. every
+    # message recomputed from m^t, which is LBP
+    prob = inputs.ising_grid(9, 10, 2.5, 4)
+    a = oracle.run(prob, oracle.LBP, eps=1e-5, max_iters=60)
+    b = oracle.rs(prob, eps=1e-5, p=1.0, splash_depth=0, max_iters=60)
+    np.testing.assert_array_equal(a["msgs"], b["msgs"])
+    assert a["iterations"] == b["iterations"] and a["committed"] == b["committed"]
+
+
+@pytest.mark.parametrize("n,K,seed", [(15, 2, 1), (12, 3, 2)])
+def test_rs_tree_equals_enumeration(n, K, seed):
+    prob = inputs.random_tree(n, K, seed)
+    r = oracle.rs(prob, eps=1e-13, p=0.05, splash_depth=2, max_iters=5000)
+    assert r["converged"]
+    np.testing.assert_allclose(r["marginals"], exact_refs.brute_force_marginals(prob),
+                               atol=1e-11, rtol=0)
+
+
+def test_rs_weak_coupling_agrees_with_lbp():
+    prob = inputs.ising_grid(8, 8, 0.3, 3)
+    a = oracle.run(prob, oracle.LBP, eps=1e-13, max_iters=5000)
+    b = oracle.rs(prob, eps=1e-13, p=1 / 64, splash_depth=2, max_iters=100000)
+    assert a["converged"] and b["converged"]
+    np.testing.assert_allclose(a["marginals"], b["marginals"], atol=1e-10)
