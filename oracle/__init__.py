@@ -18,6 +18,13 @@ A problem is a plain dict:
                     2 dense (pair [M, K, K] > 0, first index = state of edges[u, 0])
 Messages are in canonical order: row 2u is edges[u,0] -> edges[u,1], row 2u+1 the
 reverse.
+
+A problem with "var_states" (int32 [N], the states K_i of each variable; K is
+then the largest) has ragged arrays: log_unary float64 [sum_i K_i], pair_kind 2
+with pair float64 [sum_u K_a K_b] (the K_a x K_b table of edge u = (a, b),
+state of a first, row after row); messages are then 1-D [sum_e K_dst(e)] in
+canonical order (message e a distribution over its target's states) and
+marginals 1-D [sum_i K_i].
 """
 import ctypes
 import os
@@ -64,6 +71,14 @@ def _configure(lib):
     lib.oracle_bp_evaluate.restype = ctypes.c_int
     lib.oracle_bp_beliefs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, P, P, P, P]
     lib.oracle_bp_beliefs.restype = ctypes.c_int
+    lib.oracle_bp_run_v.argtypes = lib.oracle_bp_run.argtypes[:4] + [P] + \
+        lib.oracle_bp_run.argtypes[4:]
+    lib.oracle_bp_run_v.restype = ctypes.c_int
+    lib.oracle_bp_evaluate_v.argtypes = lib.oracle_bp_evaluate.argtypes[:4] + [P] + \
+        lib.oracle_bp_evaluate.argtypes[4:]
+    lib.oracle_bp_evaluate_v.restype = ctypes.c_int
+    lib.oracle_bp_beliefs_v.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, P, P, P, P, P]
+    lib.oracle_bp_beliefs_v.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_srbp_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, P, P, ctypes.c_int,
@@ -117,7 +132,10 @@ def _prep(problem):
     K = int(problem["K"])
     edges = np.ascontiguousarray(problem["edges"], dtype=np.int32).reshape(-1, 2)
     M = edges.shape[0]
-    lu = np.ascontiguousarray(problem["log_unary"], dtype=np.float64).reshape(N, K)
+    if problem.get("var_states") is not None:
+        lu = np.ascontiguousarray(problem["log_unary"], dtype=np.float64).reshape(-1)
+    else:
+        lu = np.ascontiguousarray(problem["log_unary"], dtype=np.float64).reshape(N, K)
     kind = int(problem["pair_kind"])
 
     def f64(name):
@@ -156,27 +174,55 @@ def neighbour_rank(problem):
     return rank
 
 
+def _var_states(problem):
+    v = problem.get("var_states")
+    return None if v is None else np.ascontiguousarray(v, dtype=np.int32)
+
+
+def message_offsets(problem):
+    """Offsets [E + 1] of the canonical messages in a ragged message array (the
+    states of each message's target)."""
+    vs = _var_states(problem)
+    _, dst = canonical_src_dst(problem)
+    if vs is None:
+        ks = np.full(len(dst), int(problem["K"]), np.int64)
+    else:
+        ks = vs[dst].astype(np.int64)
+    return np.concatenate([[0], np.cumsum(ks)])
+
+
+def _shapes(problem, N, K, E):
+    """Shapes of the message and marginal arrays."""
+    vs = _var_states(problem)
+    if vs is None:
+        return (E, K), (N, K)
+    return (int(message_offsets(problem)[-1]),), (int(vs.sum()),)
+
+
 def run(problem, schedule=LBP, eps=1e-4, p=1.0, high_p=1.0, ratio_threshold=0.9,
         dynamic_p=True, seed=0, max_iters=10000, init_msgs=None, t0=0, prev_active=-1,
         trace=False, lib=None):
-    """Alg. 1 in FP64.  Returns a dict with msgs [E,K], marginals [N,K], stats and
-    (if trace) per-evaluation arrays active / frontier / p / maxres."""
+    """Alg. 1 in FP64.  Returns a dict with msgs [E,K] (ragged: 1-D), marginals
+    [N,K] (ragged: 1-D), stats and (if trace) per-evaluation arrays active /
+    frontier / p / maxres."""
     lib = _load(lib)
     N, K, M, edges, lu, kind, cp, sh, sc, pr = _prep(problem)
     E = 2 * M
-    out_m = np.zeros((E, K), dtype=np.float64)
-    out_b = np.zeros((N, K), dtype=np.float64)
+    vs = _var_states(problem)
+    mshape, bshape = _shapes(problem, N, K, E)
+    out_m = np.zeros(mshape, dtype=np.float64)
+    out_b = np.zeros(bshape, dtype=np.float64)
     init = None
     if init_msgs is not None:
-        init = np.ascontiguousarray(init_msgs, dtype=np.float64).reshape(E, K)
+        init = np.ascontiguousarray(init_msgs, dtype=np.float64).reshape(mshape)
     st = OracleStats()
     tr = None
     if trace:
         L = int(max_iters) + 1
         tr = dict(active=np.zeros(L, np.int64), frontier=np.zeros(L, np.int64),
                   p=np.zeros(L, np.float64), maxres=np.zeros(L, np.float64))
-    rc = lib.oracle_bp_run(
-        N, K, M, _ptr(edges), _ptr(lu), kind, _ptr(cp), _ptr(sh), _ptr(sc), _ptr(pr),
+    rc = lib.oracle_bp_run_v(
+        N, K, M, _ptr(edges), _ptr(vs), _ptr(lu), kind, _ptr(cp), _ptr(sh), _ptr(sc), _ptr(pr),
         int(schedule), float(eps), float(p), float(high_p), float(ratio_threshold),
         int(bool(dynamic_p)), int(seed), int(max_iters), _ptr(init), int(t0),
         int(prev_active), _ptr(out_m), _ptr(out_b), ctypes.byref(st),
@@ -257,11 +303,13 @@ def evaluate(problem, msgs, lib=None):
     lib = _load(lib)
     N, K, M, edges, lu, kind, cp, sh, sc, pr = _prep(problem)
     E = 2 * M
-    m = np.ascontiguousarray(msgs, dtype=np.float64).reshape(E, K)
-    cand = np.zeros((E, K), np.float64)
+    vs = _var_states(problem)
+    mshape, _ = _shapes(problem, N, K, E)
+    m = np.ascontiguousarray(msgs, dtype=np.float64).reshape(mshape)
+    cand = np.zeros(mshape, np.float64)
     res = np.zeros(E, np.float64)
-    rc = lib.oracle_bp_evaluate(N, K, M, _ptr(edges), _ptr(lu), kind, _ptr(cp), _ptr(sh),
-                                _ptr(sc), _ptr(pr), _ptr(m), _ptr(cand), _ptr(res))
+    rc = lib.oracle_bp_evaluate_v(N, K, M, _ptr(edges), _ptr(vs), _ptr(lu), kind, _ptr(cp),
+                                  _ptr(sh), _ptr(sc), _ptr(pr), _ptr(m), _ptr(cand), _ptr(res))
     if rc < 0:
         raise ValueError(f"oracle_bp_evaluate failed with {rc}")
     return cand, res
@@ -271,9 +319,11 @@ def beliefs(problem, msgs, lib=None):
     """Eq. (3) marginals [N, K] from a canonical message set."""
     lib = _load(lib)
     N, K, M, edges, lu, kind, cp, sh, sc, pr = _prep(problem)
-    m = np.ascontiguousarray(msgs, dtype=np.float64).reshape(2 * M, K)
-    out = np.zeros((N, K), np.float64)
-    rc = lib.oracle_bp_beliefs(N, K, M, _ptr(edges), _ptr(lu), _ptr(m), _ptr(out))
+    vs = _var_states(problem)
+    mshape, bshape = _shapes(problem, N, K, 2 * M)
+    m = np.ascontiguousarray(msgs, dtype=np.float64).reshape(mshape)
+    out = np.zeros(bshape, np.float64)
+    rc = lib.oracle_bp_beliefs_v(N, K, M, _ptr(edges), _ptr(vs), _ptr(lu), _ptr(m), _ptr(out))
     if rc < 0:
         raise ValueError(f"oracle_bp_beliefs failed with {rc}")
     return out

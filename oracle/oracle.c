@@ -20,6 +20,13 @@
  *
  * Message ids are canonical: for undirected edge u = (a, b) given in input
  * order, id 2u is a->b and id 2u+1 is b->a (two messages per edge, Sec. II-A).
+ *
+ * Variables may have different numbers of states (the _v entry points take
+ * the per-variable counts K_i; the others use one K for every variable).  A
+ * message i -> j is a distribution over the K_j states of its target; arrays
+ * over variables or messages are stored row after row with these lengths
+ * ("ragged": unaries [sum_i K_i], messages [sum_e K_dst(e)] in canonical
+ * order, dense tables [sum_u K_a K_b] with the state of edges[u][0] first).
  */
 #include <limits.h>
 #include <math.h>
@@ -94,15 +101,19 @@ double oracle_uniform(uint64_t seed, uint32_t src, uint32_t rank, uint32_t t) {
 /* Model                                                               */
 /* ------------------------------------------------------------------ */
 typedef struct {
-    int N, K;
+    int N, K;                  /* K: the largest state count */
     int64_t M, E;
     const int32_t* edges;      /* [M][2] */
-    double* unary;             /* psi_i(x) = exp(log_unary), [N][K] */
+    int32_t* Kv;               /* [N] states of each variable */
+    int64_t* uoff;             /* [N+1] row offsets of per-variable arrays */
+    int64_t* moff;             /* [E+1] row offsets of messages (K of the target) */
+    int64_t* poff;             /* [M+1] offsets of dense tables (K_a K_b) */
+    double* unary;             /* psi_i(x) = exp(log_unary), ragged [sum K_i] */
     int pair_kind;
     const double* coupling;    /* Ising J, [M] */
     const double* shared;      /* [K][K] */
     const double* edge_scale;  /* [M] */
-    const double* pair;        /* [M][K][K] */
+    const double* pair;        /* ragged [sum_u K_a K_b] */
     int64_t* in_ptr;           /* [N+1]: incoming message ids grouped by target */
     int64_t* in_ids;           /* [E] */
     int32_t* rank;             /* [E]: rank of the target among the source's neighbours */
@@ -130,7 +141,7 @@ static double pair_psi(const model_t* g, int64_t u, int xa, int xb) {
     case OR_PAIR_SHARED:
         return g->edge_scale[u] * g->shared[xa * K + xb];
     default:
-        return g->pair[(u * K + xa) * K + xb];
+        return g->pair[g->poff[u] + xa * g->Kv[g->edges[2 * u + 1]] + xb];
     }
 }
 
@@ -140,21 +151,40 @@ static double msg_psi(const model_t* g, int64_t e, int xi, int xj) {
     return (e & 1) ? pair_psi(g, u, xj, xi) : pair_psi(g, u, xi, xj);
 }
 
+/* var_states: the K_i of every variable, or NULL for K states each.  With
+ * var_states only dense tables are accepted; K is then the largest K_i. */
 static int build_model(model_t* g, int N, int K, int64_t M, const int32_t* edges,
-                       const double* log_unary, int pair_kind, const double* coupling,
-                       const double* shared, const double* edge_scale,
-                       const double* pair) {
+                       const int32_t* var_states, const double* log_unary, int pair_kind,
+                       const double* coupling, const double* shared,
+                       const double* edge_scale, const double* pair) {
     memset(g, 0, sizeof(*g));
     g->N = N; g->K = K; g->M = M; g->E = 2 * M;
     g->edges = edges;
     g->pair_kind = pair_kind;
     g->coupling = coupling; g->shared = shared; g->edge_scale = edge_scale;
     g->pair = pair;
-    g->unary = (double*)malloc(sizeof(double) * (size_t)N * (size_t)K + 1);
+    g->Kv = (int32_t*)malloc(sizeof(int32_t) * (size_t)N + 1);
+    g->uoff = (int64_t*)malloc(sizeof(int64_t) * ((size_t)N + 1));
+    g->moff = (int64_t*)malloc(sizeof(int64_t) * ((size_t)g->E + 1));
+    g->poff = (int64_t*)malloc(sizeof(int64_t) * ((size_t)M + 1));
     g->in_ptr = (int64_t*)calloc((size_t)N + 1, sizeof(int64_t));
     g->in_ids = (int64_t*)malloc(sizeof(int64_t) * (size_t)g->E + 1);
-    if (!g->unary || !g->in_ptr || !g->in_ids) return -2;
-    for (int64_t i = 0; i < (int64_t)N * K; ++i) g->unary[i] = exp(log_unary[i]);
+    if (!g->Kv || !g->uoff || !g->moff || !g->poff || !g->in_ptr || !g->in_ids) return -2;
+    if (var_states && pair_kind != OR_PAIR_DENSE) return -1;
+    g->uoff[0] = 0;
+    for (int i = 0; i < N; ++i) {
+        g->Kv[i] = var_states ? var_states[i] : K;
+        if (g->Kv[i] < 2 || g->Kv[i] > K) return -1;
+        g->uoff[i + 1] = g->uoff[i] + g->Kv[i];
+    }
+    g->moff[0] = 0;
+    for (int64_t e = 0; e < g->E; ++e) g->moff[e + 1] = g->moff[e] + g->Kv[msg_dst(g, e)];
+    g->poff[0] = 0;
+    for (int64_t u = 0; u < M; ++u)
+        g->poff[u + 1] = g->poff[u] + (int64_t)g->Kv[edges[2 * u]] * g->Kv[edges[2 * u + 1]];
+    g->unary = (double*)malloc(sizeof(double) * (size_t)g->uoff[N] + 1);
+    if (!g->unary) return -2;
+    for (int64_t i = 0; i < g->uoff[N]; ++i) g->unary[i] = exp(log_unary[i]);
     /* neighbour lists Gamma_i, as incoming message ids, in message-id order */
     for (int64_t e = 0; e < g->E; ++e) g->in_ptr[msg_dst(g, e) + 1]++;
     for (int i = 0; i < N; ++i) g->in_ptr[i + 1] += g->in_ptr[i];
@@ -181,6 +211,10 @@ static int build_model(model_t* g, int N, int K, int64_t M, const int32_t* edges
 }
 
 static void free_model(model_t* g) {
+    free(g->Kv);
+    free(g->uoff);
+    free(g->moff);
+    free(g->poff);
     free(g->unary);
     free(g->in_ptr);
     free(g->in_ids);
@@ -213,31 +247,32 @@ static void xprod_to_double(const xprod* p, int K, double* out) {
 
 /* Eq. (2) for message e = i -> j, from the message set m (read only):
  *   c(x_j) = sum_{x_i} psi_ij(x_i, x_j) psi_i(x_i) prod_{k in Gamma_i \ j} m_{k->i}(x_i)
- * then normalised to sum 1 (Sec. II-A).  pw holds K products, work K doubles. */
+ * then normalised to sum 1 (Sec. II-A); x_i ranges over the K_i states of i,
+ * x_j over the K_j of j.  pw holds K_i products, work K_i doubles. */
 static void eval_message(const model_t* g, const double* m, int64_t e, double* out,
                          double* work, xprod* pw) {
-    int K = g->K;
     int i = msg_src(g, e);
+    int Ki = g->Kv[i], Kj = g->Kv[msg_dst(g, e)];
     int64_t back = e ^ 1; /* the message j -> i, excluded from the product */
-    for (int xi = 0; xi < K; ++xi) {
+    for (int xi = 0; xi < Ki; ++xi) {
         xprod prod = {1.0, 0};
-        xmul(&prod, g->unary[(int64_t)i * K + xi]);
+        xmul(&prod, g->unary[g->uoff[i] + xi]);
         for (int64_t q = g->in_ptr[i]; q < g->in_ptr[i + 1]; ++q) {
             int64_t f = g->in_ids[q];
             if (f == back) continue;
-            xmul(&prod, m[f * K + xi]);
+            xmul(&prod, m[g->moff[f] + xi]);
         }
         pw[xi] = prod;
     }
-    xprod_to_double(pw, K, work);
+    xprod_to_double(pw, Ki, work);
     double z = 0.0;
-    for (int xj = 0; xj < K; ++xj) {
+    for (int xj = 0; xj < Kj; ++xj) {
         double s = 0.0;
-        for (int xi = 0; xi < K; ++xi) s += msg_psi(g, e, xi, xj) * work[xi];
+        for (int xi = 0; xi < Ki; ++xi) s += msg_psi(g, e, xi, xj) * work[xi];
         out[xj] = s;
         z += s;
     }
-    for (int xj = 0; xj < K; ++xj) out[xj] /= z;
+    for (int xj = 0; xj < Kj; ++xj) out[xj] /= z;
 }
 
 /* f_BP(m) for every message and its residual (Eq. (4), L-infinity norm).
@@ -260,10 +295,11 @@ static int evaluate_all(const model_t* g, const double* m, double* cand, double*
 #pragma omp for schedule(static)
         for (int64_t e = 0; e < g->E; ++e) {
             if (!ok) continue;
-            eval_message(g, m, e, cand + e * K, work, pw);
+            int64_t o = g->moff[e];
+            eval_message(g, m, e, cand + o, work, pw);
             double r = 0.0;
-            for (int x = 0; x < K; ++x) {
-                double d = fabs(cand[e * K + x] - m[e * K + x]);
+            for (int64_t q = o; q < g->moff[e + 1]; ++q) {
+                double d = fabs(cand[q] - m[q]);
                 if (d > r) r = d;
             }
             res[e] = r;
@@ -285,25 +321,37 @@ int oracle_num_threads(void) {
 
 /* Eq. (3): b_i(x) proportional to psi_i(x) prod_{k in Gamma_i} m_{k->i}(x). */
 static int beliefs(const model_t* g, const double* m, double* out) {
-    int K = g->K;
-    xprod* pw = (xprod*)malloc(sizeof(xprod) * (size_t)K);
+    xprod* pw = (xprod*)malloc(sizeof(xprod) * (size_t)g->K);
     if (!pw) return -2;
     for (int i = 0; i < g->N; ++i) {
-        for (int x = 0; x < K; ++x) {
+        int Ki = g->Kv[i];
+        for (int x = 0; x < Ki; ++x) {
             xprod b = {1.0, 0};
-            xmul(&b, g->unary[(int64_t)i * K + x]);
+            xmul(&b, g->unary[g->uoff[i] + x]);
             for (int64_t q = g->in_ptr[i]; q < g->in_ptr[i + 1]; ++q)
-                xmul(&b, m[g->in_ids[q] * K + x]);
+                xmul(&b, m[g->moff[g->in_ids[q]] + x]);
             pw[x] = b;
         }
-        double* row = out + (int64_t)i * K;
-        xprod_to_double(pw, K, row);
+        double* row = out + g->uoff[i];
+        xprod_to_double(pw, Ki, row);
         double z = 0.0;
-        for (int x = 0; x < K; ++x) z += row[x];
-        for (int x = 0; x < K; ++x) row[x] /= z;
+        for (int x = 0; x < Ki; ++x) z += row[x];
+        for (int x = 0; x < Ki; ++x) row[x] /= z;
     }
     free(pw);
     return 0;
+}
+
+/* Uniform messages: 1/K_j for every entry of every message into j (Sec. II-A). */
+static void uniform_messages(const model_t* g, double* m) {
+    for (int64_t e = 0; e < g->E; ++e)
+        for (int64_t q = g->moff[e]; q < g->moff[e + 1]; ++q)
+            m[q] = 1.0 / g->Kv[msg_dst(g, e)];
+}
+
+/* Commit the candidate of message e. */
+static void commit_message(const model_t* g, double* m, const double* cand, int64_t e) {
+    for (int64_t q = g->moff[e]; q < g->moff[e + 1]; ++q) m[q] = cand[q];
 }
 
 /* Ordering for the greedy frontier of Sec. III-A: larger residual first; equal
@@ -341,24 +389,26 @@ static int cmp_topk(const void* pa, const void* pb) {
  *             n_t, |F_t| (0 on the converged/final evaluation), p_t, R_t.
  * Returns 0 if converged, 1 if not, negative on bad input.
  */
-int oracle_bp_run(int N, int K, int64_t M, const int32_t* edges, const double* log_unary,
-                  int pair_kind, const double* coupling, const double* shared,
-                  const double* edge_scale, const double* pair, int schedule, double eps,
-                  double p, double high_p, double ratio_threshold, int dynamic_p,
-                  uint64_t seed, int64_t max_iters, const double* init_msgs, int64_t t0,
-                  int64_t prev_active, double* out_msgs, double* out_marginals,
-                  oracle_stats* stats, int64_t* trace_active, int64_t* trace_frontier,
-                  double* trace_p, double* trace_maxres) {
+int oracle_bp_run_v(int N, int K, int64_t M, const int32_t* edges, const int32_t* var_states,
+                    const double* log_unary, int pair_kind, const double* coupling,
+                    const double* shared, const double* edge_scale, const double* pair,
+                    int schedule, double eps, double p, double high_p, double ratio_threshold,
+                    int dynamic_p, uint64_t seed, int64_t max_iters, const double* init_msgs,
+                    int64_t t0, int64_t prev_active, double* out_msgs, double* out_marginals,
+                    oracle_stats* stats, int64_t* trace_active, int64_t* trace_frontier,
+                    double* trace_p, double* trace_maxres) {
     if (N < 0 || K < 2 || M < 0 || max_iters < 0) return -1;
     if (pair_kind == OR_PAIR_ISING && K != 2) return -1;
     model_t g;
-    if (build_model(&g, N, K, M, edges, log_unary, pair_kind, coupling, shared, edge_scale,
-                    pair) != 0) {
+    int brc = build_model(&g, N, K, M, edges, var_states, log_unary, pair_kind, coupling,
+                          shared, edge_scale, pair);
+    if (brc != 0) {
         free_model(&g);
-        return -2;
+        return brc;
     }
     const int64_t E = g.E;
-    size_t msz = sizeof(double) * (size_t)E * (size_t)K + 1;
+    const int64_t EK = g.moff[E];  /* message entries */
+    size_t msz = sizeof(double) * (size_t)EK + 1;
     double* m = (double*)malloc(msz);       /* m^t */
     double* cand = (double*)malloc(msz);    /* f_BP(m^t) */
     double* res = (double*)malloc(sizeof(double) * (size_t)E + 1);
@@ -372,9 +422,9 @@ int oracle_bp_run(int N, int K, int64_t M, const int32_t* edges, const double* l
         return -2;
     }
     if (init_msgs)
-        memcpy(m, init_msgs, sizeof(double) * (size_t)E * (size_t)K);
+        memcpy(m, init_msgs, sizeof(double) * (size_t)EK);
     else
-        for (int64_t q = 0; q < E * K; ++q) m[q] = 1.0 / K;
+        uniform_messages(&g, m);
 
     oracle_stats st;
     memset(&st, 0, sizeof(st));
@@ -447,16 +497,15 @@ int oracle_bp_run(int N, int K, int64_t M, const int32_t* edges, const double* l
         }
         /* Update: synchronous commit, every candidate was computed from m^t */
         for (int64_t e = 0; e < E; ++e)
-            if (sel[e])
-                for (int x = 0; x < K; ++x) m[e * K + x] = cand[e * K + x];
+            if (sel[e]) commit_message(&g, m, cand, e);
         st.committed += nsel;
         st.iterations += 1;
         if (trace_frontier) trace_frontier[it] = nsel;
         n_prev = n_t;
     }
     st.converged = converged;
-    if (out_msgs) memcpy(out_msgs, m, sizeof(double) * (size_t)E * (size_t)K);
-    int brc = out_marginals ? beliefs(&g, m, out_marginals) : 0;
+    if (out_msgs) memcpy(out_msgs, m, sizeof(double) * (size_t)EK);
+    brc = out_marginals ? beliefs(&g, m, out_marginals) : 0;
     if (stats) *stats = st;
     free(m); free(cand); free(res); free(sel); free(order); free(work); free(pw);
     if (brc != 0) {
@@ -469,16 +518,18 @@ int oracle_bp_run(int N, int K, int64_t M, const int32_t* edges, const double* l
 
 /* One evaluation of f_BP and Eq. (4) for a given message set, nothing
  * committed: the candidates [E][K] and residuals [E] in canonical order. */
-int oracle_bp_evaluate(int N, int K, int64_t M, const int32_t* edges,
-                       const double* log_unary, int pair_kind, const double* coupling,
-                       const double* shared, const double* edge_scale, const double* pair,
-                       const double* msgs, double* out_cand, double* out_res) {
+int oracle_bp_evaluate_v(int N, int K, int64_t M, const int32_t* edges,
+                         const int32_t* var_states, const double* log_unary, int pair_kind,
+                         const double* coupling, const double* shared,
+                         const double* edge_scale, const double* pair, const double* msgs,
+                         double* out_cand, double* out_res) {
     if (N < 0 || K < 2 || M < 0) return -1;
     model_t g;
-    if (build_model(&g, N, K, M, edges, log_unary, pair_kind, coupling, shared, edge_scale,
-                    pair) != 0) {
+    int brc = build_model(&g, N, K, M, edges, var_states, log_unary, pair_kind, coupling,
+                          shared, edge_scale, pair);
+    if (brc != 0) {
         free_model(&g);
-        return -2;
+        return brc;
     }
     double* work = (double*)malloc(sizeof(double) * (size_t)K);
     xprod* pw = (xprod*)malloc(sizeof(xprod) * (size_t)K);
@@ -488,10 +539,10 @@ int oracle_bp_evaluate(int N, int K, int64_t M, const int32_t* edges,
         return -2;
     }
     for (int64_t e = 0; e < g.E; ++e) {
-        eval_message(&g, msgs, e, out_cand + e * K, work, pw);
+        eval_message(&g, msgs, e, out_cand + g.moff[e], work, pw);
         double r = 0.0;
-        for (int x = 0; x < K; ++x) {
-            double d = fabs(out_cand[e * K + x] - msgs[e * K + x]);
+        for (int64_t q = g.moff[e]; q < g.moff[e + 1]; ++q) {
+            double d = fabs(out_cand[q] - msgs[q]);
             if (d > r) r = d;
         }
         out_res[e] = r;
@@ -503,19 +554,49 @@ int oracle_bp_evaluate(int N, int K, int64_t M, const int32_t* edges,
 }
 
 /* Eq. (3) for a given message set. */
-int oracle_bp_beliefs(int N, int K, int64_t M, const int32_t* edges, const double* log_unary,
-                      const double* msgs, double* out_marginals) {
+int oracle_bp_beliefs_v(int N, int K, int64_t M, const int32_t* edges,
+                        const int32_t* var_states, const double* log_unary, const double* msgs,
+                        double* out_marginals) {
     if (N < 0 || K < 2 || M < 0) return -1;
     model_t g;
     /* the pairwise potentials do not enter Eq. (3) */
-    if (build_model(&g, N, K, M, edges, log_unary, OR_PAIR_DENSE, NULL, NULL, NULL, NULL) !=
-        0) {
+    int brc = build_model(&g, N, K, M, edges, var_states, log_unary, OR_PAIR_DENSE, NULL, NULL,
+                          NULL, NULL);
+    if (brc != 0) {
         free_model(&g);
-        return -2;
+        return brc;
     }
     int rc = beliefs(&g, msgs, out_marginals);
     free_model(&g);
     return rc;
+}
+
+/* The same entry points with K states for every variable. */
+int oracle_bp_run(int N, int K, int64_t M, const int32_t* edges, const double* log_unary,
+                  int pair_kind, const double* coupling, const double* shared,
+                  const double* edge_scale, const double* pair, int schedule, double eps,
+                  double p, double high_p, double ratio_threshold, int dynamic_p,
+                  uint64_t seed, int64_t max_iters, const double* init_msgs, int64_t t0,
+                  int64_t prev_active, double* out_msgs, double* out_marginals,
+                  oracle_stats* stats, int64_t* trace_active, int64_t* trace_frontier,
+                  double* trace_p, double* trace_maxres) {
+    return oracle_bp_run_v(N, K, M, edges, NULL, log_unary, pair_kind, coupling, shared,
+                           edge_scale, pair, schedule, eps, p, high_p, ratio_threshold, dynamic_p,
+                           seed, max_iters, init_msgs, t0, prev_active, out_msgs, out_marginals,
+                           stats, trace_active, trace_frontier, trace_p, trace_maxres);
+}
+
+int oracle_bp_evaluate(int N, int K, int64_t M, const int32_t* edges,
+                       const double* log_unary, int pair_kind, const double* coupling,
+                       const double* shared, const double* edge_scale, const double* pair,
+                       const double* msgs, double* out_cand, double* out_res) {
+    return oracle_bp_evaluate_v(N, K, M, edges, NULL, log_unary, pair_kind, coupling, shared,
+                                edge_scale, pair, msgs, out_cand, out_res);
+}
+
+int oracle_bp_beliefs(int N, int K, int64_t M, const int32_t* edges, const double* log_unary,
+                      const double* msgs, double* out_marginals) {
+    return oracle_bp_beliefs_v(N, K, M, edges, NULL, log_unary, msgs, out_marginals);
 }
 
 /*
@@ -536,13 +617,13 @@ int oracle_srbp_run(int N, int K, int64_t M, const int32_t* edges, const double*
     if (N < 0 || K < 2 || M < 0 || max_updates < 0) return -1;
     if (pair_kind == OR_PAIR_ISING && K != 2) return -1;
     model_t g;
-    if (build_model(&g, N, K, M, edges, log_unary, pair_kind, coupling, shared, edge_scale,
+    if (build_model(&g, N, K, M, edges, NULL, log_unary, pair_kind, coupling, shared, edge_scale,
                     pair) != 0) {
         free_model(&g);
         return -2;
     }
     const int64_t E = g.E;
-    size_t msz = sizeof(double) * (size_t)E * (size_t)K + 1;
+    size_t msz = sizeof(double) * (size_t)g.moff[E] + 1;
     double* m = (double*)malloc(msz);
     double* cand = (double*)malloc(msz);
     double* res = (double*)malloc(sizeof(double) * (size_t)E + 1);
@@ -551,7 +632,7 @@ int oracle_srbp_run(int N, int K, int64_t M, const int32_t* edges, const double*
         free_model(&g);
         return -2;
     }
-    for (int64_t q = 0; q < E * K; ++q) m[q] = 1.0 / K;
+    uniform_messages(&g, m);
     int converged = 0;
     int64_t updates = 0;
     int rc = 0;
@@ -576,12 +657,12 @@ int oracle_srbp_run(int N, int K, int64_t M, const int32_t* edges, const double*
             break;
         }
         if (updates == max_updates) break;
-        for (int x = 0; x < K; ++x) m[best * K + x] = cand[best * K + x];
+        commit_message(&g, m, cand, best);
         if (trace) trace[updates] = best;
         ++updates;
     }
     if (rc == 0) {
-        if (out_msgs) memcpy(out_msgs, m, sizeof(double) * (size_t)E * (size_t)K);
+        if (out_msgs) memcpy(out_msgs, m, sizeof(double) * (size_t)g.moff[E]);
         if (out_marginals) rc = beliefs(&g, m, out_marginals);
         if (out_updates) *out_updates = updates;
     }
@@ -615,14 +696,14 @@ int oracle_rs_run(int N, int K, int64_t M, const int32_t* edges, const double* l
     if (pair_kind == OR_PAIR_ISING && K != 2) return -1;
     if (!(p > 0.0 && p <= 1.0)) return -1;
     model_t g;
-    if (build_model(&g, N, K, M, edges, log_unary, pair_kind, coupling, shared, edge_scale,
+    if (build_model(&g, N, K, M, edges, NULL, log_unary, pair_kind, coupling, shared, edge_scale,
                     pair) != 0) {
         free_model(&g);
         return -2;
     }
     const int64_t E = g.E;
     const int h = splash_depth;
-    size_t msz = sizeof(double) * (size_t)E * (size_t)K + 1;
+    size_t msz = sizeof(double) * (size_t)g.moff[E] + 1;
     double* m = (double*)malloc(msz);
     double* cand = (double*)malloc(msz);
     double* res = (double*)malloc(sizeof(double) * (size_t)E + 1);
@@ -638,9 +719,9 @@ int oracle_rs_run(int N, int K, int64_t M, const int32_t* edges, const double* l
         rc = -2;
     if (rc == 0) {
         if (init_msgs)
-            memcpy(m, init_msgs, sizeof(double) * (size_t)E * (size_t)K);
+            memcpy(m, init_msgs, sizeof(double) * (size_t)g.moff[E]);
         else
-            for (int64_t q = 0; q < E * K; ++q) m[q] = 1.0 / K;
+            uniform_messages(&g, m);
     }
     oracle_stats st;
     memset(&st, 0, sizeof(st));
@@ -715,10 +796,10 @@ int oracle_rs_run(int N, int K, int64_t M, const int32_t* edges, const double* l
             int d = s <= h ? h - s : s - h;
             const unsigned char* L = level + (size_t)d * N;
             for (int64_t e = 0; e < E; ++e)
-                if (L[msg_src(&g, e)]) eval_message(&g, m, e, cand + e * K, work, pw);
+                if (L[msg_src(&g, e)]) eval_message(&g, m, e, cand + g.moff[e], work, pw);
             for (int64_t e = 0; e < E; ++e)
                 if (L[msg_src(&g, e)]) {
-                    for (int x = 0; x < K; ++x) m[e * K + x] = cand[e * K + x];
+                    commit_message(&g, m, cand, e);
                     ++committed;
                 }
         }
@@ -729,7 +810,7 @@ int oracle_rs_run(int N, int K, int64_t M, const int32_t* edges, const double* l
     }
     st.converged = converged;
     if (rc == 0) {
-        if (out_msgs) memcpy(out_msgs, m, sizeof(double) * (size_t)E * (size_t)K);
+        if (out_msgs) memcpy(out_msgs, m, sizeof(double) * (size_t)g.moff[E]);
         if (out_marginals) rc = beliefs(&g, m, out_marginals);
         if (stats) *stats = st;
     }

@@ -172,3 +172,65 @@ def shared_table_graph(n: int, m: int, K: int, seed: int, tree: bool = False) ->
     scale = rng.uniform(0.5, 1.5, size=edges.shape[0])
     return dict(N=n, K=K, edges=edges, log_unary=lu, pair_kind=PAIR_SHARED, shared=shared,
                 edge_scale=scale, name=f"shared{n}_K{K}_{'tree' if tree else m}_s{seed}")
+
+
+def _ragged_tables(rng, Kv, edges, coupling_scale):
+    """Dense tables exp(coupling_scale * N(0, 1)) of every edge, K_a x K_b with
+    the state of edges[u, 0] first, concatenated."""
+    return np.concatenate([np.exp(coupling_scale * rng.standard_normal(int(Kv[a]) * int(Kv[b])))
+                           for a, b in edges]) if len(edges) else np.zeros(0)
+
+
+def vark_graph(n: int, m: int, kmax: int, seed: int, tree: bool = False,
+               coupling_scale: float = 1.0) -> dict:
+    """Small graph whose variables have 2..kmax states each (uniform draw):
+    a random labelled tree on n nodes when `tree`, else G(n, m).  Ragged arrays:
+    log_unary [sum K_i] ~ N(0, 1), pair [sum_u K_a K_b] (dense tables)."""
+    rng = np.random.default_rng(seed)
+    Kv = rng.integers(2, kmax + 1, size=n).astype(np.int32)
+    if tree:
+        parent = np.array([rng.integers(0, i) for i in range(1, n)], dtype=np.int64)
+        edges = np.stack([parent, np.arange(1, n)], axis=1).astype(np.int32)
+    else:
+        edges = er_edges(n, m, rng)
+    lu = rng.standard_normal(size=int(Kv.sum()))
+    pair = _ragged_tables(rng, Kv, edges, coupling_scale)
+    return dict(N=n, K=int(Kv.max()), var_states=Kv, edges=edges, log_unary=lu,
+                pair_kind=PAIR_DENSE, pair=pair, name=f"vark{n}_{'tree' if tree else m}_s{seed}")
+
+
+def protein_like_graph(n: int, avg_degree: float, seed: int, kmin: int = 2, kmax: int = 81,
+                       coupling_scale: float = 0.5) -> dict:
+    """Synthetic stand-in for side-chain (protein folding) models with 2..81
+    states per variable: n points uniform in a unit cube, an edge between every
+    pair closer than the radius that gives the requested average degree (a
+    contact graph: irregular degrees, spatial structure); K_i log-uniform on
+    [kmin, kmax]; log-unaries ~ N(0, 1); dense tables
+    exp(coupling_scale * N(0, 1)) per edge (ragged, state of edges[u, 0] first)."""
+    rng = np.random.default_rng(seed)
+    pts = rng.random(size=(n, 3))
+    # radius for the expected degree of a Poisson process in a unit cube
+    r = (3.0 * avg_degree / (4.0 * np.pi * n)) ** (1.0 / 3.0)
+    cells = np.floor(pts / r).astype(np.int64)
+    ncell = int(np.ceil(1.0 / r)) + 1
+    key = (cells[:, 0] * ncell + cells[:, 1]) * ncell + cells[:, 2]
+    order = np.argsort(key, kind="stable")
+    skey = key[order]
+    edges = []
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dz in (-1, 0, 1):
+                nb = ((cells[:, 0] + dx) * ncell + (cells[:, 1] + dy)) * ncell + cells[:, 2] + dz
+                lo = np.searchsorted(skey, nb, side="left")
+                hi = np.searchsorted(skey, nb, side="right")
+                for i in range(n):
+                    for j in order[lo[i]:hi[i]]:
+                        if j > i and np.sum((pts[i] - pts[j]) ** 2) < r * r:
+                            edges.append((i, j))
+    edges = np.array(sorted(set(edges)), dtype=np.int32).reshape(-1, 2)
+    Kv = np.exp(rng.uniform(np.log(kmin), np.log(kmax + 1), size=n)).astype(np.int32)
+    Kv = np.clip(Kv, kmin, kmax).astype(np.int32)
+    lu = rng.standard_normal(size=int(Kv.sum()))
+    pair = _ragged_tables(rng, Kv, edges, coupling_scale)
+    return dict(N=n, K=int(Kv.max()), var_states=Kv, edges=edges, log_unary=lu,
+                pair_kind=PAIR_DENSE, pair=pair, name=f"protein_like{n}_d{avg_degree}_s{seed}")

@@ -16,10 +16,32 @@ import itertools
 import numpy as np
 
 
+def _states(problem):
+    """States of every variable."""
+    vs = problem.get("var_states")
+    N = int(problem["N"])
+    return np.full(N, int(problem["K"])) if vs is None else np.asarray(vs, int)
+
+
+def _unary(problem):
+    """Log-unaries as a list of per-variable arrays (ragged or [N, K])."""
+    ks = _states(problem)
+    lu = np.asarray(problem["log_unary"], float).reshape(-1)
+    off = np.concatenate([[0], np.cumsum(ks)])
+    return [lu[off[i]:off[i + 1]] for i in range(len(ks))]
+
+
 def _pair_table(problem, u):
-    """K x K table psi_u[x_a, x_b] of undirected edge u."""
+    """Table psi_u[x_a, x_b] of undirected edge u = (a, b) (K_a x K_b)."""
     kind = int(problem["pair_kind"])
     K = int(problem["K"])
+    if problem.get("var_states") is not None:
+        ks = _states(problem)
+        edges = np.asarray(problem["edges"]).reshape(-1, 2)
+        sizes = ks[edges[:, 0]] * ks[edges[:, 1]]
+        o = int(np.sum(sizes[:u]))
+        a, b = int(edges[u, 0]), int(edges[u, 1])
+        return np.asarray(problem["pair"], float)[o:o + ks[a] * ks[b]].reshape(ks[a], ks[b])
     if kind == 0:
         J = float(problem["coupling"][u])
         s = np.array([-1.0, 1.0])
@@ -30,48 +52,51 @@ def _pair_table(problem, u):
 
 
 def brute_force_marginals(problem):
-    """Exact marginals by summing Eq. (1) over all K^N joint states."""
+    """Exact marginals by summing Eq. (1) over every joint state ([N, K], or
+    ragged [sum K_i] for a problem with per-variable state counts)."""
     N, K = int(problem["N"]), int(problem["K"])
-    if K ** N > 1 << 20:
+    ks = _states(problem)
+    if np.prod(ks.astype(float)) > 1 << 20:
         raise ValueError("too large for enumeration")
     edges = np.asarray(problem["edges"]).reshape(-1, 2)
-    lu = np.asarray(problem["log_unary"], float)
+    lu = _unary(problem)
     tables = [np.log(_pair_table(problem, u)) for u in range(len(edges))]
-    states = np.array(list(itertools.product(range(K), repeat=N)), dtype=np.int64)
+    states = np.array(list(itertools.product(*[range(k) for k in ks])), dtype=np.int64)
     logp = np.zeros(len(states))
     for i in range(N):
-        logp += lu[i, states[:, i]]
+        logp += lu[i][states[:, i]]
     for u, (a, b) in enumerate(edges):
         logp += tables[u][states[:, a], states[:, b]]
     w = np.exp(logp - logp.max())
     w /= w.sum()
-    out = np.zeros((N, K))
-    for i in range(N):
-        for x in range(K):
-            out[i, x] = w[states[:, i] == x].sum()
-    return out
+    rows = [np.array([w[states[:, i] == x].sum() for x in range(ks[i])]) for i in range(N)]
+    if problem.get("var_states") is not None:
+        return np.concatenate(rows)
+    return np.stack(rows)
 
 
 def chain_marginals(problem):
-    """Forward-backward on a chain whose edges are (i, i + 1) in order."""
-    N, K = int(problem["N"]), int(problem["K"])
+    """Forward-backward on a chain whose edges are (i, i + 1) in order ([N, K],
+    or ragged [sum K_i] with per-variable state counts)."""
+    N = int(problem["N"])
     edges = np.asarray(problem["edges"]).reshape(-1, 2)
     assert len(edges) == N - 1 and all(int(a) == i and int(b) == i + 1
                                        for i, (a, b) in enumerate(edges))
-    phi = np.exp(np.asarray(problem["log_unary"], float))
+    phi = [np.exp(u) for u in _unary(problem)]
     T = [_pair_table(problem, u) for u in range(N - 1)]
-    alpha = np.zeros((N, K))
-    beta = np.zeros((N, K))
+    alpha, beta = [None] * N, [None] * N
     alpha[0] = phi[0] / phi[0].sum()
     for i in range(1, N):
         a = (alpha[i - 1] @ T[i - 1]) * phi[i]
         alpha[i] = a / a.sum()
-    beta[N - 1] = 1.0
+    beta[N - 1] = np.ones(len(phi[N - 1]))
     for i in range(N - 2, -1, -1):
         b = T[i] @ (phi[i + 1] * beta[i + 1])
         beta[i] = b / b.sum()
-    m = alpha * beta
-    return m / m.sum(axis=1, keepdims=True)
+    rows = [alpha[i] * beta[i] / np.sum(alpha[i] * beta[i]) for i in range(N)]
+    if problem.get("var_states") is not None:
+        return np.concatenate(rows)
+    return np.stack(rows)
 
 
 def grid_marginals_transfer(problem, H, W):

@@ -158,6 +158,18 @@ def pin_rs_replay(lib):
     return ok and _rs_one(tied, np.full((2 * len(edges), 2), 0.5), 0.04, 2, lib)
 
 
+def pin_vark_tree(lib):
+    prob = inputs.vark_graph(7, 0, 5, 1, tree=True)
+    r = oracle.run(prob, oracle.LBP, eps=1e-13, max_iters=100, lib=lib)
+    # the start state (no commit): every message uniform over its target's states
+    r0 = oracle.run(prob, oracle.LBP, eps=1e-13, max_iters=0, lib=lib)
+    _, dst = oracle.canonical_src_dst(prob)
+    ks = np.asarray(prob["var_states"])
+    want0 = np.concatenate([np.full(ks[j], 1.0 / ks[j]) for j in dst])
+    return (r["converged"] and np.array_equal(r0["msgs"], want0) and
+            np.allclose(r["marginals"], exact_refs.brute_force_marginals(prob), atol=1e-10))
+
+
 def pin_philox(lib):
     out = oracle.philox4x32_10([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344],
                                [0xa4093822, 0x299f31d0], lib=lib)
@@ -220,23 +232,24 @@ def pin_weak_coupling_agree(lib):
 BATTERY = [pin_tree, pin_shared_tree, pin_beliefs_entry, pin_chain, pin_closed_form,
            pin_normalised, pin_two_node_beliefs,
            pin_philox, pin_rnbp_definition, pin_rbp_sorted, pin_rbp_full_is_lbp,
-           pin_dynamic_p, pin_weak_coupling_agree, pin_srbp_replay, pin_rs_replay]
+           pin_dynamic_p, pin_weak_coupling_agree, pin_srbp_replay, pin_rs_replay,
+           pin_vark_tree]
 
 MUTANTS = {
     "reverse_message_not_excluded": ("if (f == back) continue;", ";"),
-    "unary_dropped_from_update": ("xmul(&prod, g->unary[(int64_t)i * K + xi]);", ";"),
+    "unary_dropped_from_update": ("xmul(&prod, g->unary[g->uoff[i] + xi]);", ";"),
     "pairwise_not_transposed_for_reverse": (
         "return (e & 1) ? pair_psi(g, u, xj, xi) : pair_psi(g, u, xi, xj);",
         "return pair_psi(g, u, xi, xj);"),
     "spin_sign_of_one_end": ("double sa = xa ? 1.0 : -1.0,", "double sa = xa ? -1.0 : 1.0,"),
-    "update_not_normalised": ("for (int xj = 0; xj < K; ++xj) out[xj] /= z;", ";"),
-    "belief_unary_dropped": ("xmul(&b, g->unary[(int64_t)i * K + x]);", ";"),
+    "update_not_normalised": ("for (int xj = 0; xj < Kj; ++xj) out[xj] /= z;", ";"),
+    "belief_unary_dropped": ("xmul(&b, g->unary[g->uoff[i] + x]);", ";"),
     "product_exponent_dropped": ("p->ex += e;", ";"),
     "residual_l1_not_linf": ("if (d > r) r = d;\n            }\n            res[e] = r;",
                              "r += d;\n            }\n            res[e] = r;"),
     "asynchronous_commit": ("            res[e] = r;\n        }\n        free(work);",
-                            "            res[e] = r;\n            for (int x = 0; x < K; ++x) "
-                            "((double*)m)[e * K + x] = cand[e * K + x];\n        }\n"
+                            "            res[e] = r;\n            for (int64_t q = o; "
+                            "q < g->moff[e + 1]; ++q) ((double*)m)[q] = cand[q];\n        }\n"
                             "        free(work);"),
     "rng_counter_source_is_target": (
         "double u = oracle_uniform(seed, (uint32_t)msg_src(&g, e),",
@@ -257,8 +270,7 @@ MUTANTS = {
         "if (de > db || (de == db && msg_src(&g, e) < msg_src(&g, best))) best = e;"),
     "srbp_smallest_residual": ("if (best < 0 || res[e] > res[best]) {",
                                "if (best < 0 || res[e] < res[best]) {"),
-    "srbp_commit_skipped": ("for (int x = 0; x < K; ++x) m[best * K + x] = cand[best * K + x];",
-                            ";"),
+    "srbp_commit_skipped": ("commit_message(&g, m, cand, best);", ";"),
     "rs_vertex_residual_outgoing": (
         "if (res[g.in_ids[q]] > vres[v]) vres[v] = res[g.in_ids[q]];",
         "if (res[g.in_ids[q] ^ 1] > vres[v]) vres[v] = res[g.in_ids[q] ^ 1];"),
@@ -266,9 +278,14 @@ MUTANTS = {
                                  "if (!order[v] && (best < 0 || vres[v] >= vres[best])) best = v;"),
     "rs_return_pass_dropped": ("for (int s = 0; s <= 2 * h; ++s) {", "for (int s = 0; s <= h; ++s) {"),
     "rs_level_not_synchronous": (
-        "if (L[msg_src(&g, e)]) eval_message(&g, m, e, cand + e * K, work, pw);",
-        "if (L[msg_src(&g, e)]) { eval_message(&g, m, e, cand + e * K, work, pw); "
-        "for (int x = 0; x < K; ++x) m[e * K + x] = cand[e * K + x]; }"),
+        "if (L[msg_src(&g, e)]) eval_message(&g, m, e, cand + g.moff[e], work, pw);",
+        "if (L[msg_src(&g, e)]) { eval_message(&g, m, e, cand + g.moff[e], work, pw); "
+        "commit_message(&g, m, cand, e); }"),
+    "vark_table_row_stride_of_source": (
+        "return g->pair[g->poff[u] + xa * g->Kv[g->edges[2 * u + 1]] + xb];",
+        "return g->pair[g->poff[u] + xa * g->Kv[g->edges[2 * u]] + xb];"),
+    "vark_uniform_start_uses_source_states": (
+        "m[q] = 1.0 / g->Kv[msg_dst(g, e)];", "m[q] = 1.0 / g->Kv[msg_src(g, e)];"),
     "beliefs_skip_last_neighbour": (
         "for (int64_t q = g->in_ptr[i]; q < g->in_ptr[i + 1]; ++q)\n                xmul(&b,",
         "for (int64_t q = g->in_ptr[i]; q + 1 < g->in_ptr[i + 1]; ++q)\n                xmul(&b,"),

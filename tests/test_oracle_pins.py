@@ -641,3 +641,81 @@ def test_rs_weak_coupling_agrees_with_lbp():
     b = oracle.rs(prob, eps=1e-13, p=1 / 64, splash_depth=2, max_iters=100000)
     assert a["converged"] and b["converged"]
     np.testing.assert_allclose(a["marginals"], b["marginals"], atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Variables with different numbers of states (ragged rows): a message i -> j
+# is a distribution over the K_j states of j, tables are K_i x K_j
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,kmax,seed", [(7, 5, 1), (9, 4, 2), (6, 7, 3)])
+def test_vark_tree_equals_enumeration(n, kmax, seed):
+    prob = inputs.vark_graph(n, 0, kmax, seed, tree=True)
+    assert len(set(prob["var_states"].tolist())) > 1
+    r = oracle.run(prob, oracle.LBP, eps=1e-14, max_iters=200)
+    assert r["converged"]
+    np.testing.assert_allclose(r["marginals"], exact_refs.brute_force_marginals(prob),
+                               atol=1e-11, rtol=0)
+    np.testing.assert_allclose(oracle.beliefs(prob, r["msgs"]), r["marginals"], atol=1e-15)
+
+
+def test_vark_start_state_is_uniform_over_target_states():
+    prob = inputs.vark_graph(9, 14, 6, 8)
+    r = oracle.run(prob, oracle.LBP, eps=1e-9, max_iters=0)
+    _, dst = oracle.canonical_src_dst(prob)
+    ks = np.asarray(prob["var_states"])
+    np.testing.assert_array_equal(r["msgs"], np.concatenate([np.full(ks[j], 1.0 / ks[j])
+                                                             for j in dst]))
+
+
+def test_vark_chain_equals_forward_backward():
+    rng = np.random.default_rng(4)
+    n = 30
+    Kv = rng.integers(2, 9, size=n).astype(np.int32)
+    edges = np.stack([np.arange(n - 1), np.arange(1, n)], 1).astype(np.int32)
+    prob = dict(N=n, K=int(Kv.max()), var_states=Kv, edges=edges,
+                log_unary=rng.standard_normal(int(Kv.sum())), pair_kind=inputs.PAIR_DENSE,
+                pair=np.exp(rng.standard_normal(int(np.sum(Kv[:-1] * Kv[1:])))))
+    for sched, kw in ((oracle.LBP, {}), (oracle.RNBP, dict(p=0.4, seed=3)),
+                      (oracle.RBP, dict(p=0.1))):
+        r = oracle.run(prob, sched, eps=1e-14, max_iters=100000, **kw)
+        assert r["converged"]
+        np.testing.assert_allclose(r["marginals"], exact_refs.chain_marginals(prob), atol=1e-11)
+
+
+def test_vark_update_both_directions_explicit():
+    prob = inputs.vark_graph(8, 12, 5, 5)
+    ks = np.asarray(prob["var_states"])
+    off = oracle.message_offsets(prob)
+    src, dst = oracle.canonical_src_dst(prob)
+    E = len(src)
+    rng = np.random.default_rng(6)
+    m = np.concatenate([rng.uniform(0.05, 1.0, ks[dst[e]]) for e in range(E)])
+    for e in range(E):
+        m[off[e]:off[e + 1]] /= m[off[e]:off[e + 1]].sum()
+    cand, res = oracle.evaluate(prob, m)
+    uoff = np.concatenate([[0], np.cumsum(ks)])
+    for e in range(E):
+        u, i, j = e // 2, src[e], dst[e]
+        T = exact_refs._pair_table(prob, u)          # [x_a, x_b]
+        T = T if e % 2 == 0 else T.T                # [x_i, x_j]
+        g = np.exp(prob["log_unary"][uoff[i]:uoff[i + 1]])
+        for f in range(E):
+            if dst[f] == i and src[f] != j:
+                g = g * m[off[f]:off[f + 1]]
+        c = np.array([sum(T[xi, xj] * g[xi] for xi in range(ks[i])) for xj in range(ks[j])])
+        np.testing.assert_allclose(cand[off[e]:off[e + 1]], c / c.sum(), atol=1e-14)
+        assert res[e] == pytest.approx(np.max(np.abs(c / c.sum() - m[off[e]:off[e + 1]])),
+                                       abs=1e-14)
+
+
+def test_vark_equal_counts_equal_the_uniform_run():
+    # a ragged problem whose variables all have K states is the uniform problem
+    prob = inputs.random_dense_graph(10, 18, 3, 7)
+    rag = dict(prob)
+    rag["var_states"] = np.full(10, 3, np.int32)
+    rag["log_unary"] = np.asarray(prob["log_unary"]).reshape(-1)
+    rag["pair"] = np.asarray(prob["pair"]).reshape(-1)
+    a = oracle.run(prob, oracle.RNBP, eps=1e-6, p=0.5, seed=2, max_iters=50)
+    b = oracle.run(rag, oracle.RNBP, eps=1e-6, p=0.5, seed=2, max_iters=50)
+    np.testing.assert_array_equal(a["msgs"].reshape(-1), b["msgs"])
+    np.testing.assert_array_equal(a["marginals"].reshape(-1), b["marginals"])
