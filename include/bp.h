@@ -210,6 +210,28 @@ int bp_create_graph(const bp_graph_desc* desc, bp_graph** out);
 int bp_run(bp_graph* g, int schedule, double eps, double p, uint64_t seed,
            const bp_run_opts* opts, bp_run_stats* stats);
 
+/* bp_run for callers that cannot allocate device memory or create events at
+ * run time: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results and return codes as bp_run (the
+ * messages, statistics and iteration state are bitwise those of bp_run),
+ * except:
+ *   - the run's scratch (iteration state, per-iteration counters and the
+ *     top-k tie counts: about 49 KiB plus 4 bytes per 4096 messages) is taken
+ *     from a static device array of 1 MiB that each GPU holds until the
+ *     process ends, not from the graph's memory; a graph whose scratch would
+ *     not fit (more than about 1.0e9 messages) is rejected with BP_EINVAL;
+ *   - no HIP events are created: stats->device_ms and the profile fields are
+ *     0, and opts->profile must be 0 (BP_EINVAL otherwise);
+ *   - opts->sparse != 0 needs a graph created with BP_FLAG_SPARSE_BUFFERS
+ *     (BP_EINVAL otherwise), so that no buffer is allocated.
+ * All calls on one GPU share that GPU's array and it keeps the last call's
+ * contents (each call clears what must start at zero with a kernel): calls
+ * that overlap on one GPU, from other threads or on other streams, race and
+ * give wrong results; the caller serialises them.  The graph must exist
+ * already (created with a caller workspace if nothing may be allocated). */
+int bp_run_noalloc(bp_graph* g, int schedule, double eps, double p, uint64_t seed,
+                   const bp_run_opts* opts, bp_run_stats* stats);
+
 /* Eq. (3) beliefs from the current messages into host [N][K] FP32; each row
  * sums to 1 up to rounding. */
 int bp_marginals(bp_graph* g, float* out);

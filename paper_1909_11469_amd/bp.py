@@ -28,7 +28,7 @@ SCHEDULES = {"lbp": BP_LBP, "rbp": BP_RBP, "rnbp": BP_RNBP}
 
 # Every symbol include/bp.h declares.
 EXPORTED = ["bp_default_opts", "bp_workspace_bytes", "bp_create_graph", "bp_run",
-            "bp_marginals", "bp_marginals_device", "bp_get_state", "bp_set_state",
+            "bp_run_noalloc", "bp_marginals", "bp_marginals_device", "bp_get_state", "bp_set_state",
             "bp_graph_info_get", "bp_destroy_graph", "bp_last_error",
             "bp_server_create", "bp_server_submit", "bp_server_step", "bp_server_result",
             "bp_server_counts", "bp_server_destroy", "bp_server_inject_failures"]
@@ -106,6 +106,8 @@ def _load():
     lib.bp_run.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
                            ctypes.POINTER(bp_run_opts), ctypes.POINTER(bp_run_stats)]
     lib.bp_run.restype = ctypes.c_int
+    lib.bp_run_noalloc.argtypes = lib.bp_run.argtypes
+    lib.bp_run_noalloc.restype = ctypes.c_int
     lib.bp_marginals.argtypes = [P, P]
     lib.bp_marginals.restype = ctypes.c_int
     lib.bp_marginals_device.argtypes = [P, P]
@@ -256,9 +258,10 @@ class Graph:
 
     def run(self, schedule="lbp", eps=1e-4, p=1.0, seed=0, max_iters=10000, check_every=16,
             dynamic_p=True, high_p=1.0, ratio_threshold=0.9, warm_start=False, profile=False,
-            sparse=0):
+            sparse=0, noalloc=False):
         """sparse: 0 full evaluation, 1 sparse re-evaluation, 2 full until n_t <= E/16
-        (RnBP on K = 2 graphs only; see bp_run_opts in include/bp.h)."""
+        (RnBP on K = 2 graphs only; see bp_run_opts in include/bp.h).  noalloc: call
+        bp_run_noalloc (static per-GPU scratch, no events) instead of bp_run."""
         o = bp_default_opts()
         o.max_iters, o.check_every = int(max_iters), int(check_every)
         o.dynamic_p, o.high_p, o.ratio_threshold = int(bool(dynamic_p)), float(high_p), \
@@ -267,8 +270,9 @@ class Graph:
         o.sparse = int(sparse)
         s = bp_run_stats()
         sched = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
-        rc = _check(lib.bp_run(self.handle, sched, float(eps), float(p), int(seed),
-                               ctypes.byref(o), ctypes.byref(s)))
+        fn = lib.bp_run_noalloc if noalloc else lib.bp_run
+        rc = _check(fn(self.handle, sched, float(eps), float(p), int(seed),
+                       ctypes.byref(o), ctypes.byref(s)))
         out = {f: getattr(s, f) for f, _ in s._fields_ if f != "reserved0"}
         out["converged"] = bool(out["converged"])
         out["status"] = rc
@@ -307,6 +311,10 @@ def bp_create_graph(problem, flags=0, use_torch=True):
 
 def bp_run(graph, schedule, eps, p, seed, **opts):
     return graph.run(schedule, eps=eps, p=p, seed=seed, **opts)
+
+
+def bp_run_noalloc(graph, schedule, eps, p, seed, **opts):
+    return graph.run(schedule, eps=eps, p=p, seed=seed, noalloc=True, **opts)
 
 
 def bp_marginals(graph):

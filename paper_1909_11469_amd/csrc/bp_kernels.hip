@@ -2221,3 +2221,50 @@ hipError_t launch_rbp_commit(DevState* st, unsigned int* keys, const int* rev,
 }
 
 }  // namespace bp
+
+// ---------------------------------------------------------------------------
+// bp_run_noalloc: bp_run with its per-run scratch (iteration state, counters,
+// top-k tie counts) in a file-scope device array instead of the graph's
+// memory.  Each GPU holds its own copy of the array; its device address is
+// looked up once per device, with that device current, and only that address
+// is handed to kernels (the array's name is a host-side stand-in).
+// ---------------------------------------------------------------------------
+#include <mutex>
+
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t(1) << 20;  // graphs up to ~10^9 messages
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[kNoAllocMaxDevices];
+}  // namespace
+
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+extern "C" int bp_run_noalloc(bp_graph* g, int schedule, double eps, double p, uint64_t seed,
+                              const bp_run_opts* opts, bp_run_stats* stats) {
+    if (!g) return bp::report_error(BP_EINVAL, "graph is NULL");
+    const int dev = bp::graph_device(g);
+    if (dev < 0 || dev >= kNoAllocMaxDevices)
+        return bp::report_error(BP_EDEVICE, "device index out of the static scratch table");
+    char* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        ptr = g_noalloc_ptr[dev];
+        if (!ptr) {
+            int prev = -1;
+            if (hipGetDevice(&prev) != hipSuccess)
+                return bp::report_error(BP_EDEVICE, "hipGetDevice failed");
+            if (prev != dev && hipSetDevice(dev) != hipSuccess)
+                return bp::report_error(BP_EDEVICE, "hipSetDevice failed");
+            void* addr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+            if (prev != dev) (void)hipSetDevice(prev);
+            if (e != hipSuccess || !addr)
+                return bp::report_error(BP_EDEVICE, "hipGetSymbolAddress(scratch) failed");
+            ptr = (char*)addr;
+            g_noalloc_ptr[dev] = ptr;
+        }
+    }
+    return bp::run_with_scratch(g, schedule, eps, p, seed, opts, stats, ptr,
+                                kNoAllocScratchBytes);
+}
