@@ -2,12 +2,14 @@
  * bp.h -- C ABI of libbp: frontier-based sum-product belief propagation on
  * pairwise Markov random fields, on one AMD Instinct MI355X (gfx950).
  *
- * Problem (Sec. II-A, Eq. (1)): N discrete variables with K states each, a
- * positive unary potential psi_i per variable and a positive pairwise potential
- * psi_ij per undirected edge.  Every edge carries two directed messages, so a
- * graph with M edges has E = 2M messages.  Messages start uniform, are
- * normalised after every update and are updated with Eq. (2); beliefs follow
- * Eq. (3).
+ * Problem (Sec. II-A, Eq. (1)): N discrete variables, variable i with K_i
+ * states (K states each, or per-variable counts given by
+ * bp_graph_desc.var_states), a positive unary potential psi_i per variable and
+ * a positive pairwise potential psi_ij per undirected edge.  Every edge carries
+ * two directed messages, so a graph with M edges has E = 2M messages; the
+ * message i -> j is a distribution over the K_j states of j.  Messages start
+ * uniform, are normalised after every update and are updated with Eq. (2)
+ * (a sum over the K_i states of the source); beliefs follow Eq. (3).
  *
  * Solver (Alg. 1): repeat { evaluate f_BP(m^t) and the residual of Eq. (4) for
  * every message; stop if no residual exceeds eps; choose a frontier; commit
@@ -19,6 +21,15 @@
  *            (randomized BP, Sec. IV-A); with dynamic p, p_t is the low
  *            setting p when n_t / n_{t-1} > ratio_threshold, else high_p, where
  *            n_t counts messages with residual > eps (EdgeRatio, Sec. IV-A).
+ *   BP_RS    residual splash in frontier form (Sec. II-B, Sec. III-A): the
+ *            residual of a variable is the largest residual of its incoming
+ *            messages; the k = min(N, max(1, ceil(p * E))) variables with the
+ *            largest residuals (ties by id ascending) are the roots; level d
+ *            (d = 0 .. h, h = bp_run_opts.splash_depth) holds every variable
+ *            at graph distance exactly d from some root; the levels are
+ *            updated in the order h, ..., 1, 0, 1, ..., h, each level
+ *            recomputing every message out of its variables from the messages
+ *            as they stand when the level starts, then committing them.
  *
  * Conventions
  *   - Residual: L-infinity norm of the change of the normalised message.
@@ -57,7 +68,7 @@
 extern "C" {
 #endif
 
-#define BP_ABI_VERSION 1
+#define BP_ABI_VERSION 2
 
 typedef enum bp_status {
     BP_OK = 0,              /* success; for bp_run: converged */
@@ -80,7 +91,7 @@ typedef enum bp_pair_kind {
     BP_PAIR_DENSE = 2
 } bp_pair_kind;
 
-typedef enum bp_schedule { BP_LBP = 0, BP_RBP = 1, BP_RNBP = 2 } bp_schedule;
+typedef enum bp_schedule { BP_LBP = 0, BP_RBP = 1, BP_RNBP = 2, BP_RS = 3 } bp_schedule;
 
 /* bp_graph_desc.flags */
 #define BP_FLAG_GENERIC_LAYOUT 1u /* K = 2 Ising: keep [E][2] probabilities instead of
@@ -94,12 +105,20 @@ typedef enum bp_schedule { BP_LBP = 0, BP_RBP = 1, BP_RNBP = 2 } bp_schedule;
                                      graph's memory (counted by bp_workspace_bytes) instead
                                      of allocating them at the first sparse run; ignored
                                      for the [E][K] layout */
+#define BP_FLAG_SPLASH_BUFFERS 8u  /* one-log-odds-per-message graphs: hold the buffers of
+                                     BP_RS (variable residuals, level marks and level
+                                     lists, 28 bytes per variable) in the graph's memory
+                                     instead of allocating them at the first BP_RS run;
+                                     BP_RS also needs the target index of the sparse
+                                     buffers (BP_FLAG_SPARSE_BUFFERS); ignored for the
+                                     [E][K] layout */
 
 typedef struct bp_graph bp_graph;
 
 typedef struct bp_graph_desc {
     int32_t num_vars;         /* N, 1 <= N < 2^31 */
-    int32_t num_states;       /* K, 2 <= K <= 64 */
+    int32_t num_states;       /* K, 2 <= K <= 64; with var_states the largest K_i,
+                                 2 <= K <= 128 */
     int64_t num_edges;        /* M, 0 <= M, 2M < 2^31 */
     const int32_t* edges;     /* host [M][2]: 0 <= a, b < N, a != b, no duplicate {a, b} */
     const double* log_unary;  /* host [N][K]: psi_i(x) = exp(log_unary[i][x]), finite */
@@ -113,6 +132,18 @@ typedef struct bp_graph_desc {
     void* workspace;          /* optional caller-owned device memory, 256-byte aligned,
                                  at least bp_workspace_bytes(); NULL = library allocates */
     uint64_t workspace_bytes;
+    /* Optional host [N]: K_i, the number of states of each variable,
+     * 2 <= K_i <= num_states (variables with their own state sets, e.g. the
+     * side-chain models of Sec. IV-E).  NULL: every variable has num_states.
+     * With var_states the pairwise potentials must be BP_PAIR_DENSE and the
+     * arrays are ragged (rows concatenated in variable / edge order):
+     *   log_unary  [sum_i K_i], row i holds log psi_i(0 .. K_i - 1);
+     *   pair       [sum_u K_a K_b], edge u = (a, b) = edges[u] holds the
+     *              K_a x K_b table psi_u(x_a, x_b), x_a major;
+     * and so are the message and belief arrays of bp_get_state, bp_set_state
+     * and bp_marginals (see there).  Such graphs keep K_j floats per message
+     * (layout 2 of bp_graph_info) and run BP_LBP, BP_RNBP and BP_RBP. */
+    const int32_t* var_states;
 } bp_graph_desc;
 
 typedef struct bp_run_opts {
@@ -144,7 +175,10 @@ typedef struct bp_run_opts {
                                  allocates them outside the workspace, held until
                                  bp_destroy_graph.  Other schedules and layouts:
                                  BP_EINVAL. */
-    int32_t reserved;
+    int32_t splash_depth;     /* BP_RS: depth h of a splash, 0, 1 or 2 (default 2, the
+                                 depth the paper fixes); BP_RS runs on K = 2 Ising
+                                 graphs in the one-log-odds-per-message layout and
+                                 takes its buffers as BP_FLAG_SPLASH_BUFFERS says */
 } bp_run_opts;
 
 typedef struct bp_run_stats {
@@ -179,7 +213,8 @@ typedef struct bp_graph_info {
     int64_t num_messages;     /* E = 2M */
     int32_t layout;           /* 0 = one log-odds value per message (K = 2 Ising with
                                  fewer than 2^30 - 512 messages and variables),
-                                 1 = [E][K] probabilities (everything else) */
+                                 1 = [E][K] probabilities,
+                                 2 = K_j probabilities per message (var_states) */
     int32_t num_tiles;        /* node tiles of the evaluation kernel */
     uint64_t device_bytes;    /* device memory held by the graph */
 } bp_graph_info;
@@ -202,7 +237,8 @@ int bp_create_graph(const bp_graph_desc* desc, bp_graph** out);
 /* Run Alg. 1 with the given frontier rule (see top of file).
  *   eps   convergence and filter threshold, >= 0 and finite
  *   p     BP_RBP: fraction of messages per iteration; BP_RNBP: the low setting
- *         (static: the probability); in (0, 1]; ignored by BP_LBP
+ *         (static: the probability); BP_RS: roots = ceil(p * E) capped at N;
+ *         in (0, 1]; ignored by BP_LBP
  *   seed  Philox key for BP_RNBP; ignored otherwise
  *   opts  NULL = defaults; stats NULL = not returned.
  * Returns BP_OK if converged, BP_NOT_CONVERGED at max_iters, negative on error.
@@ -233,7 +269,8 @@ int bp_run_noalloc(bp_graph* g, int schedule, double eps, double p, uint64_t see
                    const bp_run_opts* opts, bp_run_stats* stats);
 
 /* Eq. (3) beliefs from the current messages into host [N][K] FP32; each row
- * sums to 1 up to rounding. */
+ * sums to 1 up to rounding.  Graphs with var_states: host [sum_i K_i], the
+ * K_i beliefs of variable i after those of variables 0 .. i - 1. */
 int bp_marginals(bp_graph* g, float* out);
 
 /* Same, into caller-owned device memory [N][K] FP32, ordered on the graph's
@@ -241,12 +278,15 @@ int bp_marginals(bp_graph* g, float* out);
 int bp_marginals_device(bp_graph* g, float* out_device);
 
 /* Copy the current messages to host [E][K] FP32 in canonical order and the
- * iteration state to *st (either may be NULL). */
+ * iteration state to *st (either may be NULL).  Graphs with var_states: host
+ * [sum_c K_dst(c)], the K_j values of canonical message c (target j) after
+ * those of messages 0 .. c - 1. */
 int bp_get_state(bp_graph* g, float* msgs, bp_iter_state* st);
 
 /* Replace the messages (host [E][K] FP32, canonical order, each row positive;
- * rows are renormalised to sum 1) and/or the iteration state (either may be
- * NULL).  Use with bp_run_opts.warm_start = 1. */
+ * rows are renormalised to sum 1; ragged as bp_get_state for graphs with
+ * var_states) and/or the iteration state (either may be NULL).  Use with
+ * bp_run_opts.warm_start = 1. */
 int bp_set_state(bp_graph* g, const float* msgs, const bp_iter_state* st);
 
 /* Sizes and layout of a graph. */

@@ -14,7 +14,7 @@
  *
  * The problem is described by bp_graph_desc of bp.h (N, K <= 64, edges, log
  * unaries, Ising / shared / dense pairwise potentials; stream, workspace and
- * flags are ignored).  Messages start uniform and are FP64; each candidate is
+ * flags are ignored; var_states must be NULL).  Messages start uniform and are FP64; each candidate is
  * the literal product of Eq. (2) (no log domain, no division), so a solve is
  * reproducible bit for bit.  All arrays are host memory owned by the caller.
  * The library holds no state between calls and is thread-safe; the error

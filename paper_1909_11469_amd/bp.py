@@ -19,12 +19,13 @@ LIB_PATH = os.path.join(_HERE, "libbp.so")
 BP_OK, BP_NOT_CONVERGED = 0, 1
 BP_EINVAL, BP_ENOMEM, BP_EDEVICE, BP_ESTATE = -1, -2, -3, -4
 BP_PAIR_ISING, BP_PAIR_SHARED, BP_PAIR_DENSE = 0, 1, 2
-BP_LBP, BP_RBP, BP_RNBP = 0, 1, 2
+BP_LBP, BP_RBP, BP_RNBP, BP_RS = 0, 1, 2, 3
 BP_FLAG_GENERIC_LAYOUT = 1
 BP_FLAG_NO_MATRIX_CORES = 2
 BP_FLAG_SPARSE_BUFFERS = 4
+BP_FLAG_SPLASH_BUFFERS = 8
 
-SCHEDULES = {"lbp": BP_LBP, "rbp": BP_RBP, "rnbp": BP_RNBP}
+SCHEDULES = {"lbp": BP_LBP, "rbp": BP_RBP, "rnbp": BP_RNBP, "rs": BP_RS}
 
 # Every symbol include/bp.h declares.
 EXPORTED = ["bp_default_opts", "bp_workspace_bytes", "bp_create_graph", "bp_run",
@@ -47,7 +48,8 @@ class bp_graph_desc(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("coupling", ctypes.c_void_p),
                 ("shared", ctypes.c_void_p), ("edge_scale", ctypes.c_void_p),
                 ("pair", ctypes.c_void_p), ("stream", ctypes.c_void_p),
-                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
+                ("var_states", ctypes.c_void_p)]
 
 
 class bp_run_opts(ctypes.Structure):
@@ -55,7 +57,7 @@ class bp_run_opts(ctypes.Structure):
                 ("dynamic_p", ctypes.c_int32), ("high_p", ctypes.c_double),
                 ("ratio_threshold", ctypes.c_double), ("warm_start", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("sparse", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("splash_depth", ctypes.c_int32)]
 
 
 class bp_run_stats(ctypes.Structure):
@@ -165,11 +167,18 @@ def _ptr(a):
 
 
 def _make_desc(problem, flags=0):
-    """Host arrays (kept alive in the returned tuple) and the descriptor."""
+    """Host arrays (kept alive in the returned tuple) and the descriptor.
+    A problem with "var_states" (K_i per variable) passes ragged log_unary
+    [sum K_i] and pair [sum_u K_a K_b] arrays."""
     N, K = int(problem["N"]), int(problem["K"])
     edges = np.ascontiguousarray(problem["edges"], dtype=np.int32).reshape(-1, 2)
-    lu = np.ascontiguousarray(problem["log_unary"], dtype=np.float64).reshape(N, K)
-    keep = [edges, lu]
+    vs = problem.get("var_states")
+    if vs is not None:
+        vs = np.ascontiguousarray(vs, dtype=np.int32).reshape(N)
+        lu = np.ascontiguousarray(problem["log_unary"], dtype=np.float64).reshape(-1)
+    else:
+        lu = np.ascontiguousarray(problem["log_unary"], dtype=np.float64).reshape(N, K)
+    keep = [edges, lu, vs]
 
     def f64(name):
         v = problem.get(name)
@@ -188,6 +197,7 @@ def _make_desc(problem, flags=0):
     d.shared = _ptr(f64("shared"))
     d.edge_scale = _ptr(f64("edge_scale"))
     d.pair = _ptr(f64("pair"))
+    d.var_states = _ptr(vs)
     return d, keep
 
 
@@ -209,16 +219,24 @@ def _torch_cuda():
 class Graph:
     """A problem resident on the GPU (bp_create_graph ... bp_destroy_graph).
 
-    Binary Ising graphs are created with BP_FLAG_SPARSE_BUFFERS unless
-    sparse_buffers is False, so that all of their device memory is the one
-    workspace tensor."""
+    Binary Ising graphs are created with BP_FLAG_SPARSE_BUFFERS and
+    BP_FLAG_SPLASH_BUFFERS unless sparse_buffers is False, so that all of their
+    device memory is the one workspace tensor."""
 
     def __init__(self, problem, flags=0, use_torch=True, sparse_buffers=True):
         self.N, self.K = int(problem["N"]), int(problem["K"])
         self.M = int(np.asarray(problem["edges"]).reshape(-1, 2).shape[0])
         self.E = 2 * self.M
+        # ragged problems (K_i per variable): flat message and belief arrays
+        self._ragged = None
+        if problem.get("var_states") is not None:
+            vs = np.asarray(problem["var_states"], dtype=np.int64)
+            ed = np.asarray(problem["edges"], dtype=np.int64).reshape(-1, 2)
+            kdst = np.empty(self.E, np.int64)
+            kdst[0::2], kdst[1::2] = vs[ed[:, 1]], vs[ed[:, 0]]
+            self._ragged = (int(kdst.sum()), int(vs.sum()))
         if sparse_buffers and int(problem["pair_kind"]) == BP_PAIR_ISING:
-            flags = int(flags) | BP_FLAG_SPARSE_BUFFERS
+            flags = int(flags) | BP_FLAG_SPARSE_BUFFERS | BP_FLAG_SPLASH_BUFFERS
         d, keep = _make_desc(problem, flags)
         self._workspace = None
         torch = _torch_cuda() if use_torch else None
@@ -258,16 +276,18 @@ class Graph:
 
     def run(self, schedule="lbp", eps=1e-4, p=1.0, seed=0, max_iters=10000, check_every=16,
             dynamic_p=True, high_p=1.0, ratio_threshold=0.9, warm_start=False, profile=False,
-            sparse=0, noalloc=False):
+            sparse=0, noalloc=False, splash_depth=2):
         """sparse: 0 full evaluation, 1 sparse re-evaluation, 2 full until n_t <= E/16
         (RnBP on K = 2 graphs only; see bp_run_opts in include/bp.h).  noalloc: call
-        bp_run_noalloc (static per-GPU scratch, no events) instead of bp_run."""
+        bp_run_noalloc (static per-GPU scratch, no events) instead of bp_run.
+        splash_depth: depth h of residual splash ("rs")."""
         o = bp_default_opts()
         o.max_iters, o.check_every = int(max_iters), int(check_every)
         o.dynamic_p, o.high_p, o.ratio_threshold = int(bool(dynamic_p)), float(high_p), \
             float(ratio_threshold)
         o.warm_start, o.profile = int(bool(warm_start)), int(profile)
         o.sparse = int(sparse)
+        o.splash_depth = int(splash_depth)
         s = bp_run_stats()
         sched = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
         fn = lib.bp_run_noalloc if noalloc else lib.bp_run
@@ -279,18 +299,24 @@ class Graph:
         return out
 
     def marginals(self):
-        out = np.empty((self.N, self.K), dtype=np.float32)
+        """[N, K] beliefs, or for a ragged problem [sum K_i] (variable-major)."""
+        shape = (self._ragged[1],) if self._ragged else (self.N, self.K)
+        out = np.empty(shape, dtype=np.float32)
         _check(lib.bp_marginals(self.handle, _ptr(out)))
         return out
 
     def marginals_device(self, out_tensor):
-        """Write [N, K] FP32 beliefs into a caller-owned CUDA tensor."""
-        assert out_tensor.is_cuda and out_tensor.numel() == self.N * self.K
+        """Write [N, K] FP32 beliefs (ragged: [sum K_i]) into a caller-owned CUDA tensor."""
+        n = self._ragged[1] if self._ragged else self.N * self.K
+        assert out_tensor.is_cuda and out_tensor.numel() == n
         _check(lib.bp_marginals_device(self.handle, ctypes.c_void_p(out_tensor.data_ptr())))
         return out_tensor
 
     def get_state(self):
-        m = np.empty((self.E, self.K), dtype=np.float32)
+        """Messages in canonical order, [E, K] or ragged [sum K_dst], and the
+        iteration state."""
+        shape = (self._ragged[0],) if self._ragged else (self.E, self.K)
+        m = np.empty(shape, dtype=np.float32)
         st = bp_iter_state()
         _check(lib.bp_get_state(self.handle, _ptr(m), ctypes.byref(st)))
         return m, {"t": st.t, "prev_active": st.prev_active}
@@ -298,7 +324,8 @@ class Graph:
     def set_state(self, msgs=None, t=None, prev_active=-1):
         m = None
         if msgs is not None:
-            m = np.ascontiguousarray(msgs, dtype=np.float32).reshape(self.E, self.K)
+            shape = (self._ragged[0],) if self._ragged else (self.E, self.K)
+            m = np.ascontiguousarray(msgs, dtype=np.float32).reshape(shape)
         st = None
         if t is not None:
             st = bp_iter_state(int(t), int(prev_active))

@@ -79,12 +79,21 @@ struct HostLayout {
     int tile_big = 0;                 // 1 if some node's slots exceed the tile limit
     int no_mfma = 0;                  // BP_FLAG_NO_MATRIX_CORES
     int sparse_reserved = 0;          // BP_FLAG_SPARSE_BUFFERS on a log-odds graph
+    int splash_reserved = 0;          // BP_FLAG_SPLASH_BUFFERS on a log-odds graph
     std::vector<int> tiles4;          // log-odds layout: regular tiles {n0, n1, s0, s1}
     std::vector<int> big4;            // log-odds layout: single-node tiles over the slot limit
     std::vector<float> coupling;      // [E] (Ising)
     std::vector<float> unary;         // [N] log-odds or [N][K] log psi (max-shifted)
     std::vector<float> pair_tab;      // shared (2KK) or dense [E][K][K]
     std::vector<unsigned char> orient;// [E] (asymmetric shared)
+    // per-variable state counts (ragged layout)
+    std::vector<int> kv;              // [N] K_i
+    std::vector<int> uoff;            // [N+1] unary / belief row of each variable
+    std::vector<int> moff;            // [E+1] message row of each slot (K_target entries)
+    std::vector<int> toff;            // [E+1] table of each slot (K_source x K_target)
+    std::vector<long long> coff;      // [E+1] row of each canonical message in host arrays
+    long long msg_floats = 0;         // entries of one message buffer
+    long long belief_floats = 0;      // entries of the beliefs (N K, or sum K_i)
 };
 
 struct Arena {
@@ -98,7 +107,7 @@ struct Arena {
 
 struct Offsets {
     size_t node_ptr, rev, tile, tile_slot, tiles4, big4, coupling, unary, pair, orient, msg[4], cand, keys, ties, state,
-        ctr, marg, sparse, total;
+        ctr, marg, kv, uoff, moff, toff, sparse, splash, total;
 };
 
 // Device bytes of the sparse re-evaluation buffers of a log-odds graph: dirty
@@ -122,14 +131,20 @@ Offsets plan(const HostLayout& L) {
     o.unary = a.take(sizeof(float) * L.unary.size());
     o.pair = a.take(sizeof(float) * L.pair_tab.size());
     o.orient = a.take(L.orient.size());
-    for (int i = 0; i < 4; ++i) o.msg[i] = a.take(sizeof(float) * E * L.row);
-    o.cand = a.take(sizeof(float) * E * L.row);
+    for (int i = 0; i < 4; ++i) o.msg[i] = a.take(sizeof(float) * (size_t)L.msg_floats);
+    o.cand = a.take(sizeof(float) * (size_t)L.msg_floats);
     o.keys = a.take(sizeof(unsigned int) * E);
-    o.ties = a.take(sizeof(unsigned int) * (E / 4096 + 2));
+    // per-block tie counts of a top-k over the messages or (residual splash) the variables
+    o.ties = a.take(sizeof(unsigned int) * (std::max<size_t>(E, (size_t)L.N) / 4096 + 2));
     o.state = a.take(sizeof(DevState));
     o.ctr = a.take(sizeof(CounterLine) * 4 * kCounterCopies);
-    o.marg = a.take(sizeof(float) * (size_t)L.N * L.K);
+    o.marg = a.take(sizeof(float) * (size_t)L.belief_floats);
+    o.kv = a.take(sizeof(int) * L.kv.size());
+    o.uoff = a.take(sizeof(int) * L.uoff.size());
+    o.moff = a.take(sizeof(int) * L.moff.size());
+    o.toff = a.take(sizeof(int) * L.toff.size());
     o.sparse = L.sparse_reserved ? a.take(sparse_bytes(L)) : 0;
+    o.splash = L.splash_reserved ? a.take(splash_bytes(L.N)) : 0;
     o.total = a.off;
     return o;
 }
@@ -152,14 +167,46 @@ bool positive_all(const double* p, size_t n) {
 int build_layout(const bp_graph_desc* d, HostLayout& L) {
     if (!d) return fail(BP_EINVAL, "desc is NULL");
     const long long N = d->num_vars, K = d->num_states, M = d->num_edges;
+    const bool ragged = d->var_states != nullptr;
+    const int kmax = ragged ? kMaxKRagged : kMaxK;
     if (N < 1 || N > 0x7FFFFFFFLL - 1) return fail(BP_EINVAL, "num_vars %lld out of range", N);
-    if (K < 2 || K > kMaxK) return fail(BP_EINVAL, "num_states %lld not in [2, %d]", K, kMaxK);
+    if (K < 2 || K > kmax) return fail(BP_EINVAL, "num_states %lld not in [2, %d]", K, kmax);
     if (M < 0 || 2 * M > 0x7FFFFFFFLL - 1) return fail(BP_EINVAL, "num_edges %lld out of range", M);
     if (M > 0 && !d->edges) return fail(BP_EINVAL, "edges is NULL");
     if (!d->log_unary) return fail(BP_EINVAL, "log_unary is NULL");
-    if (!finite_all(d->log_unary, (size_t)(N * K))) return fail(BP_EINVAL, "log_unary not finite");
+    long long unary_n = N * K;
+    if (ragged) {
+        unary_n = 0;
+        for (long long i = 0; i < N; ++i) {
+            const long long k = d->var_states[i];
+            if (k < 2 || k > K)
+                return fail(BP_EINVAL, "var_states[%lld] = %lld not in [2, num_states]", i, k);
+            unary_n += k;
+        }
+        if (d->pair_kind != BP_PAIR_DENSE)
+            return fail(BP_EINVAL, "var_states needs BP_PAIR_DENSE tables");
+    }
+    if (!finite_all(d->log_unary, (size_t)unary_n)) return fail(BP_EINVAL, "log_unary not finite");
     const int kind = d->pair_kind;
-    if (kind == BP_PAIR_ISING) {
+    if (ragged) {
+        if (M > 0 && !d->pair) return fail(BP_EINVAL, "pair is NULL");
+        // edges are range-checked before the table sizes are read
+        for (long long u = 0; u < M; ++u) {
+            const long long a = d->edges[2 * u], b = d->edges[2 * u + 1];
+            if (a < 0 || a >= N || b < 0 || b >= N)
+                return fail(BP_EINVAL, "edge %lld = (%lld, %lld) out of range", u, a, b);
+        }
+        long long pn = 0, mn = 0;
+        for (long long u = 0; u < M; ++u) {
+            const long long ka = d->var_states[d->edges[2 * u]], kb = d->var_states[d->edges[2 * u + 1]];
+            pn += ka * kb;
+            mn += ka + kb;
+        }
+        if (2 * pn > 0x7FFFFFFFLL - 1 || mn > 0x7FFFFFFFLL - 1 || unary_n > 0x7FFFFFFFLL - 1)
+            return fail(BP_EINVAL, "ragged tables or messages exceed 2^31 entries");
+        if (M > 0 && !positive_all(d->pair, (size_t)pn))
+            return fail(BP_EINVAL, "pair potential must be positive and finite");
+    } else if (kind == BP_PAIR_ISING) {
         if (K != 2) return fail(BP_EINVAL, "BP_PAIR_ISING needs num_states == 2");
         if (M > 0 && !d->coupling) return fail(BP_EINVAL, "coupling is NULL");
         if (M > 0 && !finite_all(d->coupling, (size_t)M)) return fail(BP_EINVAL, "coupling not finite");
@@ -178,7 +225,7 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
         return fail(BP_EINVAL, "unknown pair_kind %d", kind);
     }
     if (d->flags & ~(uint32_t)(BP_FLAG_GENERIC_LAYOUT | BP_FLAG_NO_MATRIX_CORES |
-                               BP_FLAG_SPARSE_BUFFERS))
+                               BP_FLAG_SPARSE_BUFFERS | BP_FLAG_SPLASH_BUFFERS))
         return fail(BP_EINVAL, "unknown flags");
     L.no_mfma = (d->flags & BP_FLAG_NO_MATRIX_CORES) ? 1 : 0;
     {
@@ -203,11 +250,13 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
     // takes graphs with fewer than 2^30 messages and nodes; larger K = 2 graphs
     // use the [E][K] layout.
     const bool small = 2 * M < (1ll << 30) - kTileSlotsLogOdds && N < (1ll << 30) - kTileSlotsLogOdds;
-    L.layout = (kind == BP_PAIR_ISING && !(d->flags & BP_FLAG_GENERIC_LAYOUT) && small)
+    L.layout = ragged ? kLayoutRagged
+               : (kind == BP_PAIR_ISING && !(d->flags & BP_FLAG_GENERIC_LAYOUT) && small)
                    ? kLayoutLogOdds
                    : kLayoutGeneric;
-    L.row = L.layout == kLayoutLogOdds ? 1 : (int)K;
+    L.row = L.layout == kLayoutLogOdds ? 1 : (int)K;  // uniform layouts: entries per slot
     L.sparse_reserved = (L.layout == kLayoutLogOdds && (d->flags & BP_FLAG_SPARSE_BUFFERS)) ? 1 : 0;
+    L.splash_reserved = (L.layout == kLayoutLogOdds && (d->flags & BP_FLAG_SPLASH_BUFFERS)) ? 1 : 0;
     const long long E = L.E;
     auto csrc = [&](long long c) { return d->edges[2 * (c >> 1) + ((c & 1) ? 1 : 0)]; };
     auto cdst = [&](long long c) { return d->edges[2 * (c >> 1) + ((c & 1) ? 0 : 1)]; };
@@ -234,6 +283,62 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
     // the K = 2 kernel reads slot 0 of a tile without slots: keep one valid entry
     if (E == 0) L.rev.assign(1, 0);
 
+    L.msg_floats = E * L.row;
+    L.belief_floats = N * K;
+    if (ragged) {
+        // per-variable rows: unary (and beliefs) by variable, messages and
+        // tables by slot, host message rows by canonical id
+        L.kv.assign(d->var_states, d->var_states + N);
+        L.uoff.assign((size_t)N + 1, 0);
+        for (long long i = 0; i < N; ++i) L.uoff[i + 1] = L.uoff[i] + L.kv[i];
+        L.belief_floats = L.uoff[N];
+        L.moff.assign((size_t)E + 1, 0);
+        L.toff.assign((size_t)E + 1, 0);
+        for (long long s = 0; s < E; ++s) {
+            const int c = canon_of_slot[s];
+            const int ki = L.kv[csrc(c)], kj = L.kv[cdst(c)];
+            L.moff[s + 1] = L.moff[s] + kj;
+            L.toff[s + 1] = L.toff[s] + ki * kj;
+        }
+        L.msg_floats = L.moff[E];
+        L.coff.assign((size_t)E + 1, 0);
+        for (long long c = 0; c < E; ++c) L.coff[c + 1] = L.coff[c] + L.kv[cdst(c)];
+        L.unary.resize((size_t)L.belief_floats);
+        for (long long i = 0; i < N; ++i) {
+            double mx = -INFINITY;
+            const double* lu = d->log_unary + L.uoff[i];
+            for (int x = 0; x < L.kv[i]; ++x) mx = std::max(mx, lu[x]);
+            for (int x = 0; x < L.kv[i]; ++x) L.unary[L.uoff[i] + x] = (float)(lu[x] - mx);
+        }
+        // table of slot s (source i, target k): psi(x_i, x_k), x_i major; the
+        // host table of edge u = (a, b) is x_a major, so odd canonical
+        // messages (b -> a) take it transposed; each table scaled to max 1
+        std::vector<long long> poff((size_t)M + 1, 0);
+        for (long long u = 0; u < M; ++u)
+            poff[u + 1] = poff[u] + (long long)L.kv[d->edges[2 * u]] * L.kv[d->edges[2 * u + 1]];
+        L.pair = kPairDense;
+        L.pair_tab.resize((size_t)L.toff[E]);
+        for (long long s = 0; s < E; ++s) {
+            const int c = canon_of_slot[s];
+            const long long u = c >> 1;
+            const int ka = L.kv[d->edges[2 * u]], kb = L.kv[d->edges[2 * u + 1]];
+            const double* P = d->pair + poff[u];
+            double mx = 0.0;
+            for (long long q = 0; q < (long long)ka * kb; ++q) mx = std::max(mx, P[q]);
+            float* T = L.pair_tab.data() + L.toff[s];
+            if (!(c & 1)) {
+                for (int xa = 0; xa < ka; ++xa)
+                    for (int xb = 0; xb < kb; ++xb) T[xa * kb + xb] = (float)(P[xa * kb + xb] / mx);
+            } else {
+                for (int xb = 0; xb < kb; ++xb)
+                    for (int xa = 0; xa < ka; ++xa) T[xb * ka + xa] = (float)(P[xa * kb + xb] / mx);
+            }
+        }
+        // the kernels take a wave per variable: no tiles
+        L.tile_start.assign({0, (int)N});
+        L.tile_slot.assign({0, (int)E});
+        return BP_OK;
+    }
     // unary: K = 2 log-odds, or log psi shifted so its max per node is 0
     if (L.layout == kLayoutLogOdds) {
         L.unary.resize((size_t)N);
@@ -364,6 +469,13 @@ struct bp_graph {
     unsigned char* sp_dirty = nullptr;
     unsigned char* sp_hasact = nullptr;
     int* sp_dst = nullptr;
+    // residual splash buffers: variable keys u32 [N], level marks u32 [3][N],
+    // level lists i32 [3][N]; in the graph's memory (BP_FLAG_SPLASH_BUFFERS) or
+    // allocated by the first BP_RS run (splash_owned); marks start at 0 and
+    // carry the tag of the iteration that set them (rs_tag: the last tag used)
+    char* splash_mem = nullptr;
+    bool splash_owned = false;
+    unsigned int rs_tag = 0;
 
     template <typename T>
     T* at(size_t o) const { return reinterpret_cast<T*>(base + o); }
@@ -388,6 +500,7 @@ void bp_default_opts(bp_run_opts* o) {
     o->ratio_threshold = 0.9;
     o->warm_start = 0;
     o->profile = 0;
+    o->splash_depth = 2;
 }
 
 const char* bp_last_error(void) { return g_last_error.c_str(); }
@@ -461,7 +574,11 @@ int create_graph_from_layout(HostLayout& layout, const bp_graph_desc* desc, bp_g
         if (n == 0) return hipSuccess;
         return hipMemcpyAsync(g->base + o, p, n, hipMemcpyHostToDevice, s);
     };
-    hipError_t errs[11] = {
+    hipError_t errs[15] = {
+        up(g->off.kv, L.kv.data(), sizeof(int) * L.kv.size()),
+        up(g->off.uoff, L.uoff.data(), sizeof(int) * L.uoff.size()),
+        up(g->off.moff, L.moff.data(), sizeof(int) * L.moff.size()),
+        up(g->off.toff, L.toff.data(), sizeof(int) * L.toff.size()),
         up(g->off.tile_slot, L.tile_slot.data(), sizeof(int) * L.tile_slot.size()),
         up(g->off.tiles4, L.tiles4.data(), sizeof(int) * L.tiles4.size()),
         up(g->off.big4, L.big4.data(), sizeof(int) * L.big4.size()),
@@ -475,7 +592,9 @@ int create_graph_from_layout(HostLayout& layout, const bp_graph_desc* desc, bp_g
     for (hipError_t x : errs)
         if (x != hipSuccess) return give_back(hip_fail(x, "upload"));
     const float uni = L.layout == kLayoutLogOdds ? 0.0f : 1.0f / (float)L.K;
-    e = launch_fill(g->msg(0, 0), uni, L.E * L.row, s);
+    e = L.layout == kLayoutRagged
+            ? launch_fill_ragged(g->msg(0, 0), g->at<int>(g->off.moff), (int)L.E, s)
+            : launch_fill(g->msg(0, 0), uni, L.msg_floats, s);
     if (e == hipSuccess) e = launch_init_state(g->st(), g->ctr(), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return give_back(hip_fail(e, "initialise"));
@@ -497,6 +616,7 @@ void bp_destroy_graph(bp_graph* g) {
         if (g->base) (void)hipStreamSynchronize(g->stream);
         if (g->owns_memory && g->base) (void)hipFree(g->base);
         if (g->sparse_owned && g->sparse_mem) (void)hipFree(g->sparse_mem);
+        if (g->splash_owned && g->splash_mem) (void)hipFree(g->splash_mem);
         if (g->host_state) (void)hipHostFree(g->host_state);
     }
     delete g;
@@ -527,12 +647,17 @@ static unsigned int keep_threshold(double p) {
 static EvalArgs run_args(const bp_graph* g, int schedule, double eps, double p, uint64_t seed,
                          const bp_run_opts& o, long long& rbp_k_out) {
     const HostLayout& L = g->L;
-    const int mode = schedule == BP_LBP ? kModeLBP : schedule == BP_RBP ? kModeRBP : kModeRnBP;
+    // residual splash evaluates as frontier RBP does (candidates and keys)
+    const int mode = schedule == BP_LBP ? kModeLBP
+                     : (schedule == BP_RBP || schedule == BP_RS) ? kModeRBP
+                                                                  : kModeRnBP;
     const unsigned int thr_lo = keep_threshold(p);
     const unsigned int thr_hi = keep_threshold(o.high_p);
     long long rbp_k = (long long)std::ceil(p * (double)L.E);
     if (rbp_k < 1) rbp_k = 1;
-    if (rbp_k > L.E) rbp_k = L.E;
+    // RBP: at most every message; residual splash: at most every variable (roots)
+    const long long k_cap = schedule == BP_RS ? (long long)L.N : L.E;
+    if (rbp_k > k_cap) rbp_k = k_cap;
 
     EvalArgs a{};
     a.tile_start = g->at<int>(g->off.tile);
@@ -545,7 +670,7 @@ static EvalArgs run_args(const bp_graph* g, int schedule, double eps, double p, 
     {
         // one persistent block per resident slot (the least occupancy over the
         // modes this run launches), never more than the tiles need
-        const int mode_now = schedule == BP_LBP ? kModeLBP : schedule == BP_RBP ? kModeRBP : kModeRnBP;
+        const int mode_now = mode;
         int per_cu = std::min(g->resident[mode_now], g->resident[kModeEvalOnly]);
         if (per_cu < 1) per_cu = 1;
         long long cap = (long long)per_cu * std::max(g->num_cus, 1);
@@ -558,13 +683,24 @@ static EvalArgs run_args(const bp_graph* g, int schedule, double eps, double p, 
     a.unary = g->at<float>(g->off.unary);
     a.pair = g->at<float>(g->off.pair);
     a.orient = g->at<unsigned char>(g->off.orient);
+    a.kv = g->at<int>(g->off.kv);
+    a.uoff = g->at<int>(g->off.uoff);
+    a.moff = g->at<int>(g->off.moff);
+    a.toff = g->at<int>(g->off.toff);
+    if (L.layout == kLayoutRagged) {
+        // a wave per variable, grid-stride: at most 8 blocks per CU
+        const long long waves = (long long)L.N;
+        const long long blocks = (waves + kBlock / 64 - 1) / (kBlock / 64);
+        a.pipe_grid = (int)std::max<long long>(
+            1, std::min<long long>(blocks, 8ll * std::max(g->num_cus, 1)));
+    }
     a.cand = g->at<float>(g->off.cand);
     a.keys = g->at<unsigned int>(g->off.keys);
     a.st = g->st();
     a.ctr = g->ctr();
     a.num_states = L.K;
     a.pair_kind = L.pair;
-    a.sched = mode;
+    a.sched = schedule == BP_RS ? kModeRS : mode;
     a.eps = (float)eps;
     // The device compares FP32 residuals with an FP32 threshold: take the largest
     // float <= eps, so that for every float r, r > eps_f exactly when r > eps.
@@ -611,7 +747,7 @@ struct RunScratch {
 static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t seed,
                     const bp_run_opts* opts, bp_run_stats* stats, const RunScratch& rs) {
     if (!g) return fail(BP_EINVAL, "graph is NULL");
-    if (schedule != BP_LBP && schedule != BP_RBP && schedule != BP_RNBP)
+    if (schedule != BP_LBP && schedule != BP_RBP && schedule != BP_RNBP && schedule != BP_RS)
         return fail(BP_EINVAL, "unknown schedule %d", schedule);
     if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(BP_EINVAL, "eps must be finite and >= 0");
     if (schedule != BP_LBP && !(p > 0.0 && p <= 1.0)) return fail(BP_EINVAL, "p must be in (0, 1]");
@@ -631,13 +767,24 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
             return fail(BP_EINVAL, "sparse re-evaluation needs K = 2 Ising potentials");
         if (!g->L.big4.empty())
             return fail(BP_EINVAL, "sparse re-evaluation needs every node within one tile");
+        if (schedule == BP_RS) return fail(BP_EINVAL, "residual splash has no sparse mode");
+    }
+    const bool splash = schedule == BP_RS;
+    if (splash) {
+        if (g->L.layout != kLayoutLogOdds)
+            return fail(BP_EINVAL, "residual splash needs K = 2 Ising potentials in the "
+                                   "one-log-odds-per-message layout");
+        if (o.splash_depth < 0 || o.splash_depth > kSplashMaxDepth)
+            return fail(BP_EINVAL, "splash_depth must be 0, 1 or 2");
     }
     if (rs.noalloc && o.profile)
         return fail(BP_EINVAL, "profile needs HIP events, which bp_run_noalloc does not create");
     DeviceGuard dg(g->device);
     const HostLayout& L = g->L;
     hipStream_t s = g->stream;
-    if (o.sparse && !g->sparse_ready) {
+    // sparse re-evaluation and residual splash need the target index of the
+    // sparse buffers
+    if ((o.sparse || splash) && !g->sparse_ready) {
         const size_t nb = ((size_t)L.N + 255) / 256 * 256;
         const size_t bytes = sparse_bytes(L);
         char* mem = g->sparse_mem;
@@ -645,8 +792,9 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
         if (!mem && L.sparse_reserved) mem = g->at<char>(g->off.sparse);
         if (!mem) {
             if (rs.noalloc)
-                return fail(BP_EINVAL, "sparse re-evaluation without allocation needs a graph "
-                                       "created with BP_FLAG_SPARSE_BUFFERS");
+                return fail(BP_EINVAL, "%s without allocation needs a graph created with "
+                                       "BP_FLAG_SPARSE_BUFFERS",
+                            splash ? "residual splash" : "sparse re-evaluation");
             hipError_t e = hipMalloc(&mem, bytes);
             if (e != hipSuccess)
                 return fail(e == hipErrorOutOfMemory ? BP_ENOMEM : BP_EDEVICE,
@@ -672,9 +820,39 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
         g->sp_hasact = (unsigned char*)(mem + nb);
         g->sp_dst = (int*)(mem + 2 * nb);
     }
+    if (splash && !g->splash_mem) {
+        char* mem = nullptr;
+        bool owned = false;
+        const size_t bytes = splash_bytes(L.N);
+        if (L.splash_reserved) {
+            mem = g->at<char>(g->off.splash);
+        } else {
+            if (rs.noalloc)
+                return fail(BP_EINVAL, "residual splash without allocation needs a graph created "
+                                       "with BP_FLAG_SPLASH_BUFFERS");
+            hipError_t e = hipMalloc(&mem, bytes);
+            if (e != hipSuccess)
+                return fail(e == hipErrorOutOfMemory ? BP_ENOMEM : BP_EDEVICE,
+                            "splash buffers (%zu bytes): %s", bytes, hipGetErrorString(e));
+            owned = true;
+        }
+        const size_t part = (sizeof(unsigned int) * (size_t)L.N + 255) & ~size_t(255);
+        hipError_t e = launch_fill_u32((unsigned int*)(mem + part), 0u,
+                                       (long long)L.N * (kSplashMaxDepth + 1), s);
+        if (e != hipSuccess) {
+            if (owned) (void)hipFree(mem);
+            return hip_fail(e, "splash marks");
+        }
+        g->splash_mem = mem;
+        g->splash_owned = owned;
+        g->rs_tag = 0;
+    }
     if (!o.warm_start) {
         const float uni = L.layout == kLayoutLogOdds ? 0.0f : 1.0f / (float)L.K;
-        HIP_OK(launch_fill(g->cur(), uni, L.E * L.row, s), "fill");
+        if (L.layout == kLayoutRagged)
+            HIP_OK(launch_fill_ragged(g->cur(), g->at<int>(g->off.moff), (int)L.E, s), "fill");
+        else
+            HIP_OK(launch_fill(g->cur(), uni, L.msg_floats, s), "fill");
         g->t_next = 0;
         g->prev_active = -1;
     }
@@ -682,7 +860,10 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
         return fail(BP_EINVAL, "iteration counter would pass 2^32");
     HIP_OK(launch_init_state(rs.st, rs.ctr, s), "init state");
 
-    const int mode = schedule == BP_LBP ? kModeLBP : schedule == BP_RBP ? kModeRBP : kModeRnBP;
+    // residual splash evaluates with the frontier-RBP kernels (in place)
+    const int mode = schedule == BP_LBP ? kModeLBP
+                     : (schedule == BP_RBP || splash) ? kModeRBP
+                                                      : kModeRnBP;
     long long rbp_k = 0;
     EvalArgs a = run_args(g, schedule, eps, p, seed, o, rbp_k);
     a.st = rs.st;
@@ -701,6 +882,26 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
         HIP_OK(launch_sparse_setup(a, 0, s), "dirty flags");
     }
 
+    RsArgs rsa{};
+    if (splash) {
+        const size_t part = (sizeof(unsigned int) * (size_t)L.N + 255) & ~size_t(255);
+        const size_t lv =
+            (sizeof(unsigned int) * (size_t)L.N * (kSplashMaxDepth + 1) + 255) & ~size_t(255);
+        rsa.st = rs.st;
+        rsa.node_ptr = a.node_ptr;
+        rsa.rev = a.rev;
+        rsa.dst = g->sp_dst;
+        rsa.unary = a.unary;
+        rsa.coupling = a.coupling;
+        rsa.keys = a.keys;
+        rsa.m = g->cur();
+        rsa.cand = a.cand;
+        rsa.vkey = (unsigned int*)g->splash_mem;
+        rsa.mark = (unsigned int*)(g->splash_mem + part);
+        rsa.list = (int*)(g->splash_mem + part + lv);
+        rsa.num_nodes = L.N;
+        rsa.depth = o.splash_depth;
+    }
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (!rs.noalloc) {
         HIP_OK(hipEventCreate(&ev0), "event");
@@ -753,7 +954,7 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
                                "top-k select");
                     const RbpSparse sp{a.dirty, a.dst, a.ctr, a.eps, (int)((t + 1) & 3), 1};
                     HIP_OK(launch_rbp_commit(rs.st, a.keys, a.rev, a.cand, sp_buf, (int)L.E, L.row,
-                                             all, (int)(t & 3), ties, sp, s),
+                                             all, (int)(t & 3), ties, sp, nullptr, s),
                            "top-k commit");
                 }
             } else {
@@ -795,7 +996,21 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
         HIP_OK(launch_eval(L.layout, kp, emode, a, s), "evaluation kernel");
         if (timed) HIP_OK(hipEventRecord(kev[2 * in_chunk + 1], s), "event record");
         if (prof_every && !prof_window) kev_used[in_chunk] = timed ? 1 : 0;
-        if (mode == kModeRBP && !final_launched) {
+        if (splash && !final_launched) {
+            if (g->rs_tag == 0xFFFFFFFFu) {
+                HIP_OK(launch_fill_u32(rsa.mark, 0u, (long long)L.N * (kSplashMaxDepth + 1), s),
+                       "splash marks");
+                g->rs_tag = 0;
+            }
+            rsa.tag = ++g->rs_tag;
+            HIP_OK(launch_rs_gate(rs.st, rs.ctr, (int)(t & 3), s), "splash gate");
+            HIP_OK(launch_rs_select(rsa, (unsigned int)rbp_k, rbp_k >= L.N ? 1 : 0, ties, s),
+                   "splash roots");
+            for (int q = 0; q <= 2 * rsa.depth; ++q) {
+                const int d = q <= rsa.depth ? rsa.depth - q : q - rsa.depth;
+                HIP_OK(launch_rs_level(rsa, d, s), "splash level");
+            }
+        } else if (mode == kModeRBP && !final_launched) {
             const int all = rbp_k >= L.E;
             HIP_OK(launch_rbp_gate(rs.st, rs.ctr, (int)(t & 3), s), "top-k gate");
             if (!all)
@@ -803,7 +1018,8 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
                                          (int)(t & 3), ties, s),
                        "top-k select");
             HIP_OK(launch_rbp_commit(rs.st, a.keys, a.rev, a.cand, start_buf, (int)L.E, L.row, all,
-                                     (int)(t & 3), ties, RbpSparse{}, s),
+                                     (int)(t & 3), ties, RbpSparse{},
+                                     L.layout == kLayoutRagged ? a.moff : nullptr, s),
                    "top-k commit");
         }
         ++in_chunk;
@@ -904,18 +1120,19 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
     return converged ? BP_OK : BP_NOT_CONVERGED;
 }
 
-// Scratch bytes of a run for a graph of E messages: state, counters, ties.
-size_t bp::run_scratch_bytes(long long E) {
+// Scratch bytes of a run for a graph of E messages and N variables: state,
+// counters, per-block tie counts (of a top-k over messages or variables).
+size_t bp::run_scratch_bytes(long long E, long long N) {
     const size_t st = (sizeof(DevState) + 255) & ~size_t(255);
     const size_t ctr = sizeof(CounterLine) * 4 * kCounterCopies;
-    return st + ctr + sizeof(unsigned int) * (size_t)(E / 4096 + 2);
+    return st + ctr + sizeof(unsigned int) * (size_t)(std::max(E, N) / 4096 + 2);
 }
 
 int bp::run_with_scratch(bp_graph* g, int schedule, double eps, double p, uint64_t seed,
                          const bp_run_opts* opts, bp_run_stats* stats, char* scratch,
                          size_t scratch_bytes) {
     if (!g) return fail(BP_EINVAL, "graph is NULL");
-    const size_t need = run_scratch_bytes(g->L.E);
+    const size_t need = run_scratch_bytes(g->L.E, g->L.N);
     if (need > scratch_bytes)
         return fail(BP_EINVAL, "graph of %lld messages needs %zu bytes of run scratch, the "
                                "static scratch holds %zu",
@@ -943,6 +1160,19 @@ int bp_marginals_device(bp_graph* g, float* out_device) {
     if (!g || !out_device) return fail(BP_EINVAL, "NULL argument");
     DeviceGuard dg(g->device);
     const HostLayout& L = g->L;
+    if (L.layout == kLayoutRagged) {
+        EvalArgs a{};
+        a.node_ptr = g->at<int>(g->off.node_ptr);
+        a.rev = g->at<int>(g->off.rev);
+        a.unary = g->at<float>(g->off.unary);
+        a.kv = g->at<int>(g->off.kv);
+        a.uoff = g->at<int>(g->off.uoff);
+        a.moff = g->at<int>(g->off.moff);
+        a.in_buf[0] = g->cur();
+        a.num_nodes = L.N;
+        HIP_OK(launch_marginals_ragged(a, out_device, g->stream), "marginals kernel");
+        return BP_OK;
+    }
     HIP_OK(launch_marginals(L.layout, kpad(L.K), g->at<int>(g->off.node_ptr), g->at<int>(g->off.rev),
                             g->at<float>(g->off.unary), g->cur(), out_device, L.N, L.K,
                             g->stream),
@@ -956,8 +1186,8 @@ int bp_marginals(bp_graph* g, float* out) {
     float* dev = g->at<float>(g->off.marg);
     int rc = bp_marginals_device(g, dev);
     if (rc != BP_OK) return rc;
-    HIP_OK(hipMemcpyAsync(out, dev, sizeof(float) * (size_t)g->L.N * g->L.K, hipMemcpyDeviceToHost,
-                          g->stream),
+    HIP_OK(hipMemcpyAsync(out, dev, sizeof(float) * (size_t)g->L.belief_floats,
+                          hipMemcpyDeviceToHost, g->stream),
            "marginals readback");
     HIP_OK(hipStreamSynchronize(g->stream), "synchronize");
     return BP_OK;
@@ -968,7 +1198,7 @@ int bp_get_state(bp_graph* g, float* msgs, bp_iter_state* st) {
     if (msgs) {
         DeviceGuard dg(g->device);
         const HostLayout& L = g->L;
-        std::vector<float> dev((size_t)(L.E * L.row));
+        std::vector<float> dev((size_t)L.msg_floats);
         if (!dev.empty()) {
             HIP_OK(hipMemcpyAsync(dev.data(), g->cur(), sizeof(float) * dev.size(),
                                   hipMemcpyDeviceToHost, g->stream),
@@ -977,7 +1207,10 @@ int bp_get_state(bp_graph* g, float* msgs, bp_iter_state* st) {
         }
         for (long long c = 0; c < L.E; ++c) {
             const long long s = L.slot_of_canon[c];
-            if (L.layout == kLayoutLogOdds) {
+            if (L.layout == kLayoutRagged) {
+                for (long long q = 0; q < L.coff[c + 1] - L.coff[c]; ++q)
+                    msgs[L.coff[c] + q] = dev[L.moff[s] + q];
+            } else if (L.layout == kLayoutLogOdds) {
                 const double lam = dev[s];
                 msgs[2 * c + 1] = (float)(1.0 / (1.0 + std::exp(-lam)));
                 msgs[2 * c + 0] = (float)(1.0 / (1.0 + std::exp(lam)));
@@ -997,17 +1230,22 @@ int bp_set_state(bp_graph* g, const float* msgs, const bp_iter_state* st) {
     if (!g) return fail(BP_EINVAL, "graph is NULL");
     const HostLayout& L = g->L;
     if (msgs) {
-        std::vector<float> dev((size_t)(L.E * L.row));
+        std::vector<float> dev((size_t)L.msg_floats);
         for (long long c = 0; c < L.E; ++c) {
             const long long s = L.slot_of_canon[c];
+            const bool rg = L.layout == kLayoutRagged;
+            const long long c0 = rg ? L.coff[c] : c * L.K;
+            const long long kc = rg ? L.coff[c + 1] - L.coff[c] : L.K;
             double z = 0.0;
-            for (int x = 0; x < L.K; ++x) {
-                const double v = msgs[c * L.K + x];
+            for (long long x = 0; x < kc; ++x) {
+                const double v = msgs[c0 + x];
                 if (!(v > 0.0) || !std::isfinite(v))
                     return fail(BP_EINVAL, "message %lld has a non-positive or non-finite entry", c);
                 z += v;
             }
-            if (L.layout == kLayoutLogOdds) {
+            if (rg) {
+                for (long long x = 0; x < kc; ++x) dev[L.moff[s] + x] = (float)(msgs[c0 + x] / z);
+            } else if (L.layout == kLayoutLogOdds) {
                 dev[s] = (float)(std::log((double)msgs[2 * c + 1]) - std::log((double)msgs[2 * c]));
             } else {
                 for (int x = 0; x < L.K; ++x) dev[s * L.K + x] = (float)(msgs[c * L.K + x] / z);

@@ -28,10 +28,18 @@ constexpr int kTileNodesLogOdds = kTileSlotsLogOdds / 2;  // nodes per log-odds 
 constexpr int kTileFloatsGeneric = BP_TILE_FLOATS_GENERIC;  // [E][K] layout: tile slots = this / K
 constexpr int kTileNodesMax = 2048;      // nodes per tile (owner index fits in u16)
 constexpr int kMaxK = 64;
+constexpr int kMaxKRagged = 128;  // largest K_i of a graph with per-variable state counts
 
-enum Layout : int { kLayoutLogOdds = 0, kLayoutGeneric = 1 };
+// 0: one log-odds value per message (K = 2 Ising); 1: K floats per message;
+// 2: K_j floats per message i -> j (per-variable state counts)
+enum Layout : int { kLayoutLogOdds = 0, kLayoutGeneric = 1, kLayoutRagged = 2 };
 enum PairDev : int { kPairIsing = 0, kPairShared = 1, kPairSharedAsym = 2, kPairDense = 3 };
 enum Mode : int { kModeLBP = 0, kModeRnBP = 1, kModeRBP = 2, kModeEvalOnly = 3 };
+// EvalArgs::sched of residual splash runs: the evaluation kernels run their
+// frontier-RBP instantiation (candidates and residual keys), and the splash
+// kernels count the commits themselves.
+constexpr int kModeRS = 4;
+constexpr int kSplashMaxDepth = 2;
 
 // Per-iteration counters.  Blocks add into one of kCounterCopies copies (by
 // block index), each copy on its own 128-byte line, so that the atomics of a
@@ -73,6 +81,9 @@ struct DevState {
     unsigned int pad2[3];
     // sparse re-evaluation: n_t by t & 3
     unsigned long long sp_n[4];
+    // residual splash: length of the variable list of each level
+    unsigned int rs_count[kSplashMaxDepth + 1];
+    unsigned int pad3;
 };
 
 struct EvalArgs {
@@ -90,6 +101,11 @@ struct EvalArgs {
     const float* unary;         // log-odds [N] (K = 2 log-odds layout) or log psi [N][K]
     const float* pair;          // shared [K][K] or dense [E][K][K]
     const unsigned char* orient;// [E] 1 if the shared table must be transposed for the slot
+    // per-variable state counts (ragged layout)
+    const int* kv;              // [N] K_i
+    const int* uoff;            // [N+1] first unary (and belief) entry of each variable
+    const int* moff;            // [E+1] first message entry of each slot (K_j entries)
+    const int* toff;            // [E+1] first table entry of each slot (K_i x K_j, x_i major)
     const float* in_buf[2];     // m^t: candidates chosen by p_{t-1} (both equal on a run's first launch)
     float* out_buf[2];          // m^{t+1} under the larger [0] and smaller [1] keep threshold
     float* cand;                // RBP candidates, same layout as m
@@ -153,6 +169,10 @@ int logodds_blocks_per_cu(int mode);
 hipError_t launch_marginals(int layout, int kp, const int* node_ptr, const int* rev,
                             const float* unary, const float* m, float* out, int N, int K,
                             hipStream_t s);
+// ragged layout: Eq. (3) into out [sum K_i] (a.in_buf[0] holds the messages),
+// and the uniform start state 1 / K_j of every message into m
+hipError_t launch_marginals_ragged(const EvalArgs& a, float* out, hipStream_t s);
+hipError_t launch_fill_ragged(float* m, const int* moff, int E, hipStream_t s);
 // sparse re-evaluation: one iteration (evaluate the dirty nodes, then close and
 // commit), and the per-graph setup (target index, every node dirty)
 hipError_t launch_sparse_iteration(const EvalArgs& a, hipStream_t s);
@@ -174,18 +194,48 @@ struct RbpSparse {
     int set;
     int on;
 };
+// moff (ragged layout, else nullptr): slot e's row is cand[moff[e] .. moff[e+1]).
 hipError_t launch_rbp_commit(DevState* st, unsigned int* keys, const int* rev,
                              const float* cand, float* m, int E, int row, int all, int slot_idx,
-                             const unsigned int* block_ties, const RbpSparse& sp, hipStream_t s);
+                             const unsigned int* block_ties, const RbpSparse& sp,
+                             const int* moff, hipStream_t s);
 // frontier residual BP under sparse re-evaluation: evaluate the dirty nodes,
 // then close the evaluation (one wave) and gate the top-k kernels
 hipError_t launch_sparse_rbp_eval(const EvalArgs& a, hipStream_t s);
+
+// Residual splash (K = 2 log-odds layout, messages committed in place).
+struct RsArgs {
+    DevState* st;
+    const int* node_ptr;        // [N+1]
+    const int* rev;             // [E]
+    const int* dst;             // [E] target variable of each slot
+    const float* unary;         // [N] log-odds unaries
+    const float* coupling;      // [E]
+    const unsigned int* keys;   // [E] residual keys of the evaluation of iteration t
+    float* m;                   // [E] messages, updated in place
+    float* cand;                // [E] candidates of the level being updated
+    unsigned int* vkey;         // [N] variable residual keys
+    unsigned int* mark;         // [depth + 1][N]: tag if the variable is in level d
+    int* list;                  // [depth + 1][N]: the variables of each level
+    int num_nodes;
+    int depth;                  // h
+    unsigned int tag;           // marks of this iteration
+};
+// Device bytes of the splash buffers of a graph of N variables (256-aligned parts).
+size_t splash_bytes(int num_nodes);
+hipError_t launch_rs_gate(DevState* st, const CounterLine* ctr, int slot_idx, hipStream_t s);
+// variable keys, top-k roots (ties by id), level marks and lists
+hipError_t launch_rs_select(const RsArgs& r, unsigned int k, int all, unsigned int* block_ties,
+                            hipStream_t s);
+// the updates of level d (evaluate the level's out-messages, then commit them)
+hipError_t launch_rs_level(const RsArgs& r, int d, hipStream_t s);
+hipError_t launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t s);
 
 // Host side (bp_api.cpp) used by other translation units of the library.
 // bp_run with its per-run device scratch (iteration state, counters, top-k
 // tie counts) taken from `scratch` instead of the graph's memory, and without
 // creating events or buffers.
-size_t run_scratch_bytes(long long num_messages);
+size_t run_scratch_bytes(long long num_messages, long long num_nodes);
 int run_with_scratch(bp_graph* g, int schedule, double eps, double p, uint64_t seed,
                      const bp_run_opts* opts, bp_run_stats* stats, char* scratch,
                      size_t scratch_bytes);

@@ -228,9 +228,11 @@ __device__ void wave_close(const EvalArgs& a, bool close, const CtrLoad& c,
             cm = a.num_messages;
         else if (a.sched == kModeRBP)
             cm = a.rbp_k;
+        else if (a.sched == kModeRS)
+            cm = 0ull;  // the splash kernels count their commits
         else
             cm = sel ? sb : sa;
-        atomicAdd(&st->committed, cm);
+        if (cm) atomicAdd(&st->committed, cm);
         atomicAdd(&st->iterations, 1ull);
         st->in_sel[a.t & 3u] = (unsigned int)sel;
     }
@@ -344,14 +346,18 @@ struct OutOff {
 // |J + H| - |J - H| = 2 sgn(J H) min(|J|, |H|) keeps it exact in the leading term
 // for any finite J and H (no cancellation of two large magnitudes, no overflow),
 // and the tails are bounded by log 2.
+__device__ __forceinline__ float logodds_update(float L, float lam_in, float J) {
+    const float H = 0.5f * (L - lam_in);
+    const float lead = copysignf(2.0f * fminf(fabsf(J), fabsf(H)), J * H);
+    return lead + logcosh_tail(J + H) - logcosh_tail(J - H);
+}
+
 template <int MODE, class Out>
 __device__ __forceinline__ float logodds_slot(const EvalArgs& a, const Out& out, float L,
                                               float lam_in, float J, float lam_old, int e,
                                               unsigned int u24, unsigned int& act,
                                               unsigned int& sa, unsigned int& sb) {
-    const float H = 0.5f * (L - lam_in);
-    const float lead = copysignf(2.0f * fminf(fabsf(J), fabsf(H)), J * H);
-    const float lam_new = lead + logcosh_tail(J + H) - logcosh_tail(J - H);
+    const float lam_new = logodds_update(L, lam_in, J);
     const float r = fabsf(sigmoid_fast(lam_new) - sigmoid_fast(lam_old));
     const bool active = r > a.eps;
     act += active;
@@ -1381,6 +1387,149 @@ __global__ void k_marginals_generic(const int* node_ptr, const int* rev, const f
 }
 
 // ---------------------------------------------------------------------------
+// Variables with their own numbers of states (ragged layout, Sec. II-A with
+// K_i states per variable, as in the side-chain models of Sec. IV-E): the
+// message i -> j holds K_j floats at moff[slot], the table of slot i -> j is
+// K_i x K_j (x_i major) at toff[slot], the unary of i is K_i floats at uoff[i].
+// Every slot has its own table, so Eq. (2) is a vector-matrix product whose
+// table entries are each used once per iteration: 2 flops per 4-byte table
+// entry, far below the ridge of the matrix cores and of the vector units, so
+// the vector units take it and the kernel is bound by the table traffic.
+//
+// One wave per source variable (grid-stride): lane x holds the aggregate of
+// states x and x + 64 (K_i <= 128); then, per outgoing slot, the cavity
+// g(x_i) = exp(A(x_i) - log m_{j->i}(x_i) - max), the product with the table
+// (lane y computes states y and y + 64 of the target, reading one table row
+// per source state, contiguous across lanes), normalisation, the L-infinity
+// residual and the frontier rule, all as wave-wide shuffles and reductions.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_eval_ragged(EvalArgs a) {
+    __shared__ RedScratch red;
+    __shared__ unsigned long long s_red[2];
+    const float* __restrict__ m_in = iteration_prologue(a, s_red, blockIdx.x == 0);
+    if (!m_in) return;
+    const int lane = threadIdx.x & 63;
+    const int waves = (int)(gridDim.x * (blockDim.x >> 6));
+    float rmax = 0.0f;
+    unsigned int act = 0, sa = 0, sb = 0;
+    for (int i = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); i < a.num_nodes;
+         i += waves) {
+        const int Ki = a.kv[i];
+        const int s0 = a.node_ptr[i], s1 = a.node_ptr[i + 1];
+        const float* U = a.unary + a.uoff[i];
+        const float fK = (float)Ki;  // log(K_i m) keeps the aggregate near zero
+        const bool x0 = lane < Ki, x1 = lane + 64 < Ki;
+        float A0 = x0 ? U[lane] : 0.0f, A1 = x1 ? U[lane + 64] : 0.0f;
+        for (int s = s0; s < s1; ++s) {
+            const int rin = a.moff[a.rev[s]];
+            if (x0) A0 += logf(fK * m_in[rin + lane]);
+            if (x1) A1 += logf(fK * m_in[rin + lane + 64]);
+        }
+        for (int s = s0; s < s1; ++s) {
+            const int rin = a.moff[a.rev[s]];
+            const int mo = a.moff[s], Kj = a.moff[s + 1] - mo;
+            const float* T = a.pair + a.toff[s];
+            const float c0 = x0 ? A0 - logf(fK * m_in[rin + lane]) : -INFINITY;
+            const float c1 = x1 ? A1 - logf(fK * m_in[rin + lane + 64]) : -INFINITY;
+            const float mx = wave_max_f(fmaxf(c0, c1));
+            const float g0 = x0 ? expf(c0 - mx) : 0.0f;
+            const float g1 = x1 ? expf(c1 - mx) : 0.0f;
+            const bool y0 = lane < Kj, y1 = lane + 64 < Kj;
+            float o0 = 0.0f, o1 = 0.0f;
+            for (int x = 0; x < Ki; ++x) {
+                const float gx = x < 64 ? __shfl(g0, x, 64) : __shfl(g1, x - 64, 64);
+                if (y0) o0 = fmaf(T[x * Kj + lane], gx, o0);
+                if (y1) o1 = fmaf(T[x * Kj + lane + 64], gx, o1);
+            }
+            const float z = wave_sum_f(o0 + o1);
+            o0 /= z;
+            o1 /= z;
+            const float old0 = y0 ? m_in[mo + lane] : 0.0f;
+            const float old1 = y1 ? m_in[mo + lane + 64] : 0.0f;
+            const float r = wave_max_f(fmaxf(y0 ? fabsf(o0 - old0) : 0.0f,
+                                             y1 ? fabsf(o1 - old1) : 0.0f));
+            const bool active = r > a.eps;
+            if (MODE == kModeLBP) {
+                if (y0) a.out_buf[0][mo + lane] = o0;
+                if (y1) a.out_buf[0][mo + lane + 64] = o1;
+            } else if (MODE == kModeRnBP) {
+                bool ka = false, kb = false;
+                if (active) {
+                    const unsigned int u24 = draw24(a, i, s - s0);
+                    ka = u24 < a.thr_a;
+                    kb = u24 < a.thr_b;
+                }
+                if (y0) a.out_buf[0][mo + lane] = ka ? o0 : old0;
+                if (y1) a.out_buf[0][mo + lane + 64] = ka ? o1 : old1;
+                if (a.two_outputs) {
+                    if (y0) a.out_buf[1][mo + lane] = kb ? o0 : old0;
+                    if (y1) a.out_buf[1][mo + lane + 64] = kb ? o1 : old1;
+                }
+                if (lane == 0) {
+                    sa += ka;
+                    sb += kb;
+                }
+            } else if (MODE == kModeRBP) {
+                if (y0) a.cand[mo + lane] = o0;
+                if (y1) a.cand[mo + lane + 64] = o1;
+                if (lane == 0) a.keys[s] = __float_as_uint(r);
+            }
+            if (lane == 0) {
+                act += active;
+                rmax = fmaxf(rmax, r);
+            }
+        }
+    }
+    block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
+}
+
+// Eq. (3) for the ragged layout: one wave per variable.
+__global__ __launch_bounds__(kBlock) void k_marginals_ragged(EvalArgs a, float* out) {
+    const float* __restrict__ m = a.in_buf[0];
+    const int lane = threadIdx.x & 63;
+    const int waves = (int)(gridDim.x * (blockDim.x >> 6));
+    for (int i = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); i < a.num_nodes;
+         i += waves) {
+        const int Ki = a.kv[i];
+        const float* U = a.unary + a.uoff[i];
+        const float fK = (float)Ki;
+        const bool x0 = lane < Ki, x1 = lane + 64 < Ki;
+        float A0 = x0 ? U[lane] : -INFINITY, A1 = x1 ? U[lane + 64] : -INFINITY;
+        for (int s = a.node_ptr[i]; s < a.node_ptr[i + 1]; ++s) {
+            const int rin = a.moff[a.rev[s]];
+            if (x0) A0 += logf(fK * m[rin + lane]);
+            if (x1) A1 += logf(fK * m[rin + lane + 64]);
+        }
+        const float mx = wave_max_f(fmaxf(A0, A1));
+        const float e0 = x0 ? expf(A0 - mx) : 0.0f, e1 = x1 ? expf(A1 - mx) : 0.0f;
+        const float z = wave_sum_f(e0 + e1);
+        if (x0) out[a.uoff[i] + lane] = e0 / z;
+        if (x1) out[a.uoff[i] + lane + 64] = e1 / z;
+    }
+}
+
+// The uniform start state: 1 / K_j in every entry of message i -> j.
+__global__ void k_fill_ragged(float* m, const int* moff, int E) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < E; e += gridDim.x * blockDim.x) {
+        const int q0 = moff[e], q1 = moff[e + 1];
+        const float v = 1.0f / (float)(q1 - q0);
+        for (int q = q0; q < q1; ++q) m[q] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Sparse re-evaluation (K = 2 log-odds layout, RnBP), messages committed in
 // place.  The candidate of Eq. (2) for i -> j depends only on the messages into
 // i (and on i's own old value for the residual), so after a commit only the
@@ -1795,8 +1944,9 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_scan(DevState* st, int pass, 
 // Ties at the threshold key are taken in (target, source) order.  Slots are
 // ordered by (source, target), so position p visits the message in slot rev[p],
 // whose (target, source) is the (source, target) of slot p: walking positions
-// in order walks tied messages in (target, source) order.  Each block counts
-// the ties among its kCommitChunk positions.
+// in order walks tied messages in (target, source) order.  Without rev the
+// positions are the keys' indices (residual splash ranks tied variables by id).
+// Each block counts the ties among its kCommitChunk positions.
 __global__ __launch_bounds__(kSelBlock) void k_rbp_tiecount(DevState* st, const unsigned int* keys,
                                                             const int* rev, int E,
                                                             unsigned int* block_ties) {
@@ -1804,12 +1954,21 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_tiecount(DevState* st, const 
     if (st->rbp_skip || !st->sel_rank_ties) return;
     const unsigned int T = st->sel_prefix;
     const long long q0 = (long long)blockIdx.x * kCommitChunk + (long long)threadIdx.x * kSelPer;
-    int e[kSelPer];
-    sel_load16(rev, q0, (long long)E, e);
     unsigned int c = 0;
+    if (rev) {
+        int e[kSelPer];
+        sel_load16(rev, q0, (long long)E, e);
 #pragma unroll
-    for (int j = 0; j < kSelPer; ++j)
-        if (q0 + j < E) c += keys[e[j]] == T;
+        for (int j = 0; j < kSelPer; ++j)
+            if (q0 + j < E) c += keys[e[j]] == T;
+    } else {
+        // positions are the keys' own indices (variables of residual splash)
+        unsigned int kv[kSelPer];
+        sel_load16(keys, q0, (long long)E, kv);
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j)
+            if (q0 + j < E) c += kv[j] == T;
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
@@ -1855,7 +2014,7 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_commit(DevState* st, unsigned
                                                           const int* rev, const float* cand,
                                                           float* m, int E, int row, int all,
                                                           const unsigned int* block_ties,
-                                                          RbpSparse sp) {
+                                                          RbpSparse sp, const int* moff) {
     __shared__ unsigned int part[kSelBlock / 64];
     __shared__ unsigned int s_cm[kSelBlock / 64];
     if (st->rbp_skip) return;
@@ -1938,6 +2097,12 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_commit(DevState* st, unsigned
                 sp.dirty[dv[j]] = 1;
             }
         }
+    } else if (take && moff) {
+        // ragged rows: slot e's K_j values at moff[e]
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j)
+            if (take >> j & 1u)
+                for (int q = moff[e[j]]; q < moff[e[j] + 1]; ++q) m[q] = cand[q];
     } else if (take) {
 #pragma unroll
         for (int j = 0; j < kSelPer; ++j)
@@ -2013,6 +2178,273 @@ __global__ void k_sparse_rbp_close(EvalArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Residual splash (Sec. II-B, Sec. III-A) in frontier form, K = 2 log-odds
+// layout, messages committed in place.  After the evaluation of iteration t
+// (the candidate and residual key of every message, as for frontier RBP):
+//   1. the residual of variable v is the largest residual of the messages into
+//      v (for each slot s of v, slot rev[s] holds the message into v);
+//   2. the k variables of largest residual are the roots: the radix select of
+//      frontier RBP over the variable keys, tied variables taken by id;
+//   3. level d holds every variable at distance exactly d from some root: a
+//      thread per root marks its neighbours (d = 1) and their neighbours that
+//      are neither the root nor adjacent to it (d = 2) with the iteration's tag;
+//   4. the marked variables of each level are compacted into a list (wave
+//      ballot and lane prefix counts, a block prefix sum in LDS, one atomic per
+//      block);
+//   5. the levels are updated in the order h, ..., 0, ..., h with two launches
+//      each: the candidates of every message out of the level's variables,
+//      computed from the messages as they stand, then their commit.
+// The list order depends on the order in which blocks append; no result does
+// (every message of a level is computed from the state the level starts from).
+// ---------------------------------------------------------------------------
+constexpr int kRsGrid = 512;  // blocks of the grid-stride splash kernels
+
+// IsConverged for the splash: nothing is selected or updated when the
+// evaluation of iteration t found no residual above eps; the level lists of
+// iteration t start empty.
+__global__ void k_rs_gate(DevState* st, const CounterLine* ctr, int slot) {
+    const unsigned long long n = wave_sum64(ctr[slot * kCounterCopies + threadIdx.x].active);
+    if (threadIdx.x == 0) st->rbp_skip = (st->done || n == 0ull) ? 1u : 0u;
+    if (threadIdx.x <= kSplashMaxDepth) st->rs_count[threadIdx.x] = 0u;
+}
+
+// Block-wide exclusive prefix of the per-thread item counts c (lane prefix by
+// shuffles, wave totals in LDS) and one atomic per block on *count; returns the
+// list position of the thread's first item.  Called by every thread of the
+// block; s_w holds kBlock / 64 + 1 words.
+__device__ __forceinline__ unsigned int block_append(unsigned int c, unsigned int* count,
+                                                     unsigned int* s_w) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    unsigned int x = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned int y = (unsigned int)__shfl_up((int)x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int tot = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+            const unsigned int v = s_w[i];
+            s_w[i] = tot;
+            tot += v;
+        }
+        s_w[kBlock / 64] = tot ? atomicAdd(count, tot) : 0u;
+    }
+    __syncthreads();
+    const unsigned int pos = s_w[kBlock / 64] + s_w[w] + x - c;
+    __syncthreads();  // s_w is reused by the next call
+    return pos;
+}
+
+// The same for one item per flagged thread: the wave's ballot, the lane's
+// position among the flagged lanes of its wave (mbcnt), the wave offsets from a
+// prefix sum in LDS, one atomic per block.
+__device__ __forceinline__ unsigned int block_append_flag(bool f, unsigned int* count,
+                                                          unsigned int* s_w) {
+    const unsigned long long b = __ballot(f);
+    const unsigned int before = __builtin_amdgcn_mbcnt_hi(
+        (unsigned int)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned int)b, 0u));
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) s_w[w] = (unsigned int)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int tot = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+            const unsigned int v = s_w[i];
+            s_w[i] = tot;
+            tot += v;
+        }
+        s_w[kBlock / 64] = tot ? atomicAdd(count, tot) : 0u;
+    }
+    __syncthreads();
+    const unsigned int pos = s_w[kBlock / 64] + s_w[w] + before;
+    __syncthreads();
+    return pos;
+}
+
+// 1. Variable residual keys (FP32 bit patterns of non-negative residuals order
+// as unsigned integers).
+__global__ __launch_bounds__(kBlock) void k_rs_vkeys(RsArgs r) {
+    if (r.st->rbp_skip) return;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < r.num_nodes; v += gridDim.x * kBlock) {
+        const int s0 = r.node_ptr[v], s1 = r.node_ptr[v + 1];
+        unsigned int k = 0u;
+        for (int s = s0; s < s1; ++s) k = max(k, r.keys[r.rev[s]]);
+        r.vkey[v] = k;
+    }
+}
+
+// 2. The roots: every variable whose key is above the selected threshold, and
+// among the variables equal to it the first sel_krem by id (all of them when
+// `all`); each is marked in level 0 and appended to list 0.  Same chunking as
+// the tie count (kSelPer consecutive variables per thread).
+__global__ __launch_bounds__(kSelBlock) void k_rs_roots(RsArgs r, int all,
+                                                        const unsigned int* block_ties) {
+    __shared__ unsigned int part[kSelBlock / 64];
+    __shared__ unsigned int s_w[kBlock / 64 + 1];
+    static_assert(kSelBlock == kBlock, "block_append assumes kBlock threads");
+    const DevState* st = r.st;
+    if (st->rbp_skip) return;
+    const int N = r.num_nodes;
+    const unsigned int T = st->sel_prefix;
+    const bool rank = !all && st->sel_rank_ties;
+    const unsigned int krem = st->sel_krem;
+    const long long q0 = (long long)blockIdx.x * kCommitChunk + (long long)threadIdx.x * kSelPer;
+    unsigned int take = 0, tie = 0;
+    if (all) {
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j)
+            if (q0 + j < N) take |= 1u << j;
+    } else {
+        unsigned int kv[kSelPer];
+        sel_load16(r.vkey, q0, (long long)N, kv);
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j) {
+            if (q0 + j >= N) continue;
+            if (kv[j] > T) take |= 1u << j;
+            if (kv[j] == T) tie |= 1u << j;
+        }
+        if (!rank) take |= tie;
+    }
+    if (rank) {
+        const unsigned int c = (unsigned int)__popc(tie);
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        unsigned int x = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned int y = (unsigned int)__shfl_up((int)x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) part[w] = x;
+        __syncthreads();
+        unsigned int before = block_ties[blockIdx.x] + x - c;
+        for (int i = 0; i < w; ++i) before += part[i];
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j) {
+            if (!(tie >> j & 1u)) continue;
+            if (before < krem) take |= 1u << j;
+            ++before;
+        }
+    }
+    unsigned int pos = block_append((unsigned int)__popc(take), &r.st->rs_count[0], s_w);
+#pragma unroll
+    for (int j = 0; j < kSelPer; ++j) {
+        if (!(take >> j & 1u)) continue;
+        const int v = (int)(q0 + j);
+        r.mark[v] = r.tag;
+        r.list[pos++] = v;
+    }
+}
+
+// Whether w is among the targets dst[s0 .. s1) (ascending: the slots of a
+// source are ordered by target).
+__device__ __forceinline__ bool rs_adjacent(const int* dst, int s0, int s1, int w) {
+    int lo = s0, hi = s1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (dst[mid] < w)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo < s1 && dst[lo] == w;
+}
+
+// 3. Levels 1 and 2 of every root's splash: a variable at distance exactly 1 is
+// a neighbour of the root; one at distance exactly 2 is a neighbour of a
+// neighbour that is neither the root nor one of its neighbours.  Marks are
+// plain stores of the iteration's tag (several roots may store the same word).
+__global__ __launch_bounds__(kBlock) void k_rs_bfs(RsArgs r) {
+    if (r.st->rbp_skip) return;
+    const unsigned int nr = r.st->rs_count[0];
+    const size_t N = (size_t)r.num_nodes;
+    unsigned int* m1 = r.mark + N;
+    unsigned int* m2 = r.mark + 2 * N;
+    for (unsigned int i = blockIdx.x * kBlock + threadIdx.x; i < nr; i += gridDim.x * kBlock) {
+        const int root = r.list[i];
+        const int s0 = r.node_ptr[root], s1 = r.node_ptr[root + 1];
+        for (int s = s0; s < s1; ++s) {
+            const int u = r.dst[s];
+            m1[u] = r.tag;
+            if (r.depth < 2) continue;
+            const int u0 = r.node_ptr[u], u1 = r.node_ptr[u + 1];
+            for (int q = u0; q < u1; ++q) {
+                const int w = r.dst[q];
+                if (w == root || rs_adjacent(r.dst, s0, s1, w)) continue;
+                m2[w] = r.tag;
+            }
+        }
+    }
+}
+
+// 4. The lists of levels 1 .. h.
+__global__ __launch_bounds__(kBlock) void k_rs_lists(RsArgs r) {
+    __shared__ unsigned int s_w[kBlock / 64 + 1];
+    if (r.st->rbp_skip) return;
+    const int N = r.num_nodes;
+    for (int base = blockIdx.x * kBlock; base < N; base += gridDim.x * kBlock) {
+        const int v = base + (int)threadIdx.x;
+        for (int d = 1; d <= r.depth; ++d) {
+            const bool f = v < N && r.mark[(size_t)d * N + v] == r.tag;
+            const unsigned int pos = block_append_flag(f, &r.st->rs_count[d], s_w);
+            if (f) r.list[(size_t)d * N + pos] = v;
+        }
+    }
+}
+
+// 5a. Eq. (2) for every message out of the variables of level d, from the
+// messages as they stand (the incoming log-odds summed in slot order with the
+// unary, as the tiled kernel sums them).
+__global__ __launch_bounds__(kBlock) void k_rs_level_eval(RsArgs r, int d) {
+    if (r.st->rbp_skip) return;
+    const unsigned int n = r.st->rs_count[d];
+    const int* L = r.list + (size_t)d * r.num_nodes;
+    for (unsigned int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int v = L[i];
+        const int s0 = r.node_ptr[v], s1 = r.node_ptr[v + 1];
+        float agg = r.unary[v];
+        for (int s = s0; s < s1; ++s) agg += r.m[r.rev[s]];
+        for (int s = s0; s < s1; ++s) r.cand[s] = logodds_update(agg, r.m[r.rev[s]], r.coupling[s]);
+    }
+}
+
+// 5b. Commit level d's candidates; the committed messages are added to the
+// run's commit and evaluation counts (one atomic per block).
+__global__ __launch_bounds__(kBlock) void k_rs_level_commit(RsArgs r, int d) {
+    __shared__ unsigned int s_c[kBlock / 64];
+    if (r.st->rbp_skip) return;
+    const unsigned int n = r.st->rs_count[d];
+    const int* L = r.list + (size_t)d * r.num_nodes;
+    unsigned int c = 0;
+    for (unsigned int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int v = L[i];
+        const int s0 = r.node_ptr[v], s1 = r.node_ptr[v + 1];
+        for (int s = s0; s < s1; ++s) r.m[s] = r.cand[s];
+        c += (unsigned int)(s1 - s0);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) s_c[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long C = 0;
+        for (int w = 0; w < kBlock / 64; ++w) C += s_c[w];
+        if (C) {
+            atomicAdd(&r.st->committed, C);
+            atomicAdd(&r.st->evaluated, C);
+        }
+    }
+}
+
+__global__ void k_fill_u32(unsigned int* p, unsigned int v, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2068,6 +2500,16 @@ hipError_t launch_eval(int layout, int kp, int mode, const EvalArgs& a, hipStrea
             case kModeRBP: k_eval_logodds_big<kModeRBP><<<a.num_big, kBlock, 0, s>>>(a); break;
             default: k_eval_logodds_big<kModeEvalOnly><<<a.num_big, kBlock, 0, s>>>(a); break;
             }
+        }
+        return hipGetLastError();
+    }
+    if (layout == kLayoutRagged) {
+        const int g = a.pipe_grid;
+        switch (mode) {
+        case kModeLBP: k_eval_ragged<kModeLBP><<<g, kBlock, 0, s>>>(a); break;
+        case kModeRnBP: k_eval_ragged<kModeRnBP><<<g, kBlock, 0, s>>>(a); break;
+        case kModeRBP: k_eval_ragged<kModeRBP><<<g, kBlock, 0, s>>>(a); break;
+        default: k_eval_ragged<kModeEvalOnly><<<g, kBlock, 0, s>>>(a); break;
         }
         return hipGetLastError();
     }
@@ -2159,6 +2601,23 @@ hipError_t launch_marginals(int layout, int kp, const int* node_ptr, const int* 
     return hipGetLastError();
 }
 
+hipError_t launch_marginals_ragged(const EvalArgs& a, float* out, hipStream_t s) {
+    if (a.num_nodes <= 0) return hipSuccess;
+    const int waves = kBlock / 64;
+    long long g = ((long long)a.num_nodes + waves - 1) / waves;
+    if (g > 8192) g = 8192;
+    k_marginals_ragged<<<(int)g, kBlock, 0, s>>>(a, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_ragged(float* m, const int* moff, int E, hipStream_t s) {
+    if (E <= 0) return hipSuccess;
+    long long g = ((long long)E + 255) / 256;
+    if (g > 8192) g = 8192;
+    k_fill_ragged<<<(int)g, 256, 0, s>>>(m, moff, E);
+    return hipGetLastError();
+}
+
 hipError_t launch_sparse_iteration(const EvalArgs& a, hipStream_t s) {
     // at least one block, so that a graph without slots still closes its
     // evaluation (n_t = 0)
@@ -2212,11 +2671,62 @@ hipError_t launch_rbp_select(DevState* st, const unsigned int* keys, const int* 
 
 hipError_t launch_rbp_commit(DevState* st, unsigned int* keys, const int* rev,
                              const float* cand, float* m, int E, int row, int all, int slot_idx,
-                             const unsigned int* block_ties, const RbpSparse& sp, hipStream_t s) {
+                             const unsigned int* block_ties, const RbpSparse& sp,
+                             const int* moff, hipStream_t s) {
     (void)slot_idx;
     const int nb = (E + kCommitChunk - 1) / kCommitChunk;
     if (nb <= 0) return hipSuccess;
-    k_rbp_commit<<<nb, kSelBlock, 0, s>>>(st, keys, rev, cand, m, E, row, all, block_ties, sp);
+    k_rbp_commit<<<nb, kSelBlock, 0, s>>>(st, keys, rev, cand, m, E, row, all, block_ties, sp,
+                                         moff);
+    return hipGetLastError();
+}
+
+size_t splash_bytes(int num_nodes) {
+    const size_t n = (size_t)(num_nodes > 0 ? num_nodes : 0);
+    const size_t part = (sizeof(unsigned int) * n + 255) & ~size_t(255);
+    const size_t lv = (sizeof(unsigned int) * n * (kSplashMaxDepth + 1) + 255) & ~size_t(255);
+    return part + 2 * lv;
+}
+
+static int rs_grid(long long items) {
+    const long long g = (items + kBlock - 1) / kBlock;
+    return g < 1 ? 1 : g > kRsGrid ? kRsGrid : (int)g;
+}
+
+hipError_t launch_rs_gate(DevState* st, const CounterLine* ctr, int slot_idx, hipStream_t s) {
+    k_rs_gate<<<1, 64, 0, s>>>(st, ctr, slot_idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_rs_select(const RsArgs& r, unsigned int k, int all, unsigned int* block_ties,
+                            hipStream_t s) {
+    const int N = r.num_nodes;
+    if (N <= 0) return hipSuccess;
+    k_rs_vkeys<<<rs_grid(N), kBlock, 0, s>>>(r);
+    if (!all) {
+        hipError_t e = launch_rbp_select(r.st, r.vkey, nullptr, N, k, 0, block_ties, s);
+        if (e != hipSuccess) return e;
+    }
+    k_rs_roots<<<(N + kCommitChunk - 1) / kCommitChunk, kSelBlock, 0, s>>>(r, all, block_ties);
+    if (r.depth >= 1) {
+        k_rs_bfs<<<rs_grid(N), kBlock, 0, s>>>(r);
+        k_rs_lists<<<rs_grid(N), kBlock, 0, s>>>(r);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rs_level(const RsArgs& r, int d, hipStream_t s) {
+    if (r.num_nodes <= 0) return hipSuccess;
+    k_rs_level_eval<<<rs_grid(r.num_nodes), kBlock, 0, s>>>(r, d);
+    k_rs_level_commit<<<rs_grid(r.num_nodes), kBlock, 0, s>>>(r, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    k_fill_u32<<<(int)blocks, 256, 0, s>>>(p, v, n);
     return hipGetLastError();
 }
 

@@ -73,6 +73,7 @@ struct Model {
 
 int build(const bp_graph_desc* d, Model& g) {
     if (!d) return fail(BP_EINVAL, "desc is NULL");
+    if (d->var_states) return fail(BP_EINVAL, "per-variable state counts are not supported");
     const long long N = d->num_vars, K = d->num_states, M = d->num_edges;
     if (N < 1 || N > 0x7FFFFFFELL) return fail(BP_EINVAL, "num_vars %lld out of range", N);
     if (K < 2 || K > 64) return fail(BP_EINVAL, "num_states %lld not in [2, 64]", K);

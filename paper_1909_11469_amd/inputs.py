@@ -73,6 +73,20 @@ def chain(N: int, C: float, seed: int) -> dict:
     return p
 
 
+def ising_tree(n: int, C: float, seed: int) -> dict:
+    """A random tree of n binary variables (vertex i > 0 joined to a parent drawn
+    uniformly from 0 .. i-1), then h ~ U[-1, 1]^n and J ~ U[-C, C]^(n-1) as for
+    the Ising grid."""
+    rng = np.random.default_rng(seed)
+    parent = np.array([rng.integers(0, i) for i in range(1, n)], dtype=np.int64)
+    edges = np.stack([parent, np.arange(1, n)], axis=1).astype(np.int32).reshape(-1, 2)
+    h = rng.uniform(-1.0, 1.0, size=n)
+    J = rng.uniform(-C, C, size=edges.shape[0])
+    lu = np.stack([-h, h], axis=1)
+    return dict(N=n, K=2, edges=edges, log_unary=lu, pair_kind=PAIR_ISING, coupling=J,
+                name=f"ising_tree{n}_C{C}_s{seed}", h=h)
+
+
 def paper_ising_grid(H: int, W: int, C: float, seed: int) -> dict:
     """The paper's Ising parameterisation: one U(0, 1] value per state for psi_i,
     psi_ij = e^{lambda C} when x_i = x_j else e^{-lambda C}, lambda ~ U[-0.5, 0.5].

@@ -39,6 +39,7 @@ def test_default_opts(bp):
     o = bp.bp_default_opts()
     assert o.max_iters == 10000 and o.check_every == 16 and o.dynamic_p == 1
     assert o.high_p == 1.0 and o.ratio_threshold == 0.9 and o.warm_start == 0
+    assert o.splash_depth == 2 and o.sparse == 0 and o.profile == 0
 
 
 def test_struct_layouts_match_header(bp, tmp_path):
@@ -73,6 +74,24 @@ def test_workspace_bytes_grows_with_graph(bp):
     b = bp.bp_workspace_bytes(inputs.ising_grid(40, 40, 1.0, 0))
     g = bp.bp_workspace_bytes(inputs.ising_grid(10, 10, 1.0, 0), flags=bp.BP_FLAG_GENERIC_LAYOUT)
     assert 0 < a < b and g > a
+
+
+def test_workspace_bytes_of_reserved_buffers(bp):
+    """BP_FLAG_SPARSE_BUFFERS adds 2 bytes per variable and 4 per message,
+    BP_FLAG_SPLASH_BUFFERS 28 bytes per variable (each part rounded to 256 bytes);
+    both are ignored for the [E][K] layout."""
+    prob = inputs.ising_grid(40, 40, 1.0, 0)
+    N, E = 1600, 2 * len(prob["edges"])
+    base = bp.bp_workspace_bytes(prob)
+    sp = bp.bp_workspace_bytes(prob, flags=bp.BP_FLAG_SPARSE_BUFFERS)
+    rs = bp.bp_workspace_bytes(prob, flags=bp.BP_FLAG_SPLASH_BUFFERS)
+    both = bp.bp_workspace_bytes(prob, flags=bp.BP_FLAG_SPARSE_BUFFERS | bp.BP_FLAG_SPLASH_BUFFERS)
+    assert 2 * N + 4 * E <= sp - base <= 2 * N + 4 * E + 1024
+    assert 28 * N <= rs - base <= 28 * N + 1024
+    assert both - base == (sp - base) + (rs - base)
+    gen = bp.BP_FLAG_GENERIC_LAYOUT
+    assert bp.bp_workspace_bytes(prob, flags=gen | bp.BP_FLAG_SPLASH_BUFFERS) == \
+        bp.bp_workspace_bytes(prob, flags=gen)
 
 
 def test_edgeless_graph_is_valid(bp):
@@ -157,3 +176,33 @@ def test_invalid_problem_rejected_before_device_use(bp):
     with pytest.raises(bp.BpError) as ei:
         bp.Graph(dict(p, edges=e), use_torch=False)
     assert ei.value.code == bp.BP_EINVAL
+
+
+def test_ragged_validation(bp):
+    """Per-variable state counts: dense tables only, 2 <= K_i <= num_states <= 128,
+    ragged unary and table sizes; the workspace grows with the K_i."""
+    prob = inputs.vark_graph(12, 20, 6, 0)
+    n1 = bp.bp_workspace_bytes(prob)
+    big = dict(prob)
+    big["var_states"] = np.full(12, 6, np.int32)
+    big["K"] = 6
+    rng = np.random.default_rng(0)
+    big["log_unary"] = rng.standard_normal(72)
+    big["pair"] = np.exp(rng.standard_normal(20 * 36))
+    assert bp.bp_workspace_bytes(big) > n1
+    bad = dict(prob)
+    bad["var_states"] = np.array(prob["var_states"]).copy()
+    bad["var_states"][3] = 1
+    _expect_einval(bp, bad, match="var_states")
+    bad["var_states"][3] = int(prob["K"]) + 1
+    _expect_einval(bp, bad, match="var_states")
+    wide = dict(prob)
+    wide["K"] = 129
+    _expect_einval(bp, wide, match="num_states")
+    nz = dict(prob)
+    nz["pair"] = np.array(prob["pair"]).copy()
+    nz["pair"][5] = 0.0
+    _expect_einval(bp, nz, match="positive")
+    ising = inputs.ising_grid(3, 3, 1.0, 0)
+    ising["var_states"] = np.full(9, 2, np.int32)
+    _expect_einval(bp, ising, match="DENSE")

@@ -91,8 +91,11 @@ def _check_iteration(prob, prev_state, state, r, schedule, p, seed, eps, dynamic
     assert np.array_equal(m_now[~changed], m_prev[~changed])
     # the iteration state: t advanced by one, n_{t} carried as the next n_{t-1}
     assert st_now["t"] == st_prev["t"] + 1
+    # n_t counts residuals above eps: FP32 and FP64 residuals may fall on
+    # different sides of eps only within the band around eps
     n_t = int(ref["trace"]["active"][0])
-    assert abs(st_now["prev_active"] - n_t) <= band.sum()
+    band_eps = np.abs(res - eps) < BAND
+    assert abs(st_now["prev_active"] - n_t) <= band_eps.sum()
     return float(ref["trace"]["p"][0]), int(band.sum())
 
 
@@ -144,9 +147,12 @@ def test_rbp_iterations_against_oracle(bp, sparse):
     E = 2 * len(prob["edges"])
     S0 = _random_state(E, 6, 0.3)
     p, kmax = 0.05, 6
-    runs = _gpu_prefix_runs(bp, prob, S0, 0, kmax, "rbp", p, 0, 1e-9, sparse=sparse)
+    # eps only decides n_t here (the top-k takes no eps filter); it is kept
+    # well above the FP32 rounding of residuals (~1e-7)
+    eps = 1e-4
+    runs = _gpu_prefix_runs(bp, prob, S0, 0, kmax, "rbp", p, 0, eps, sparse=sparse)
     for k in range(1, kmax + 1):
-        _check_iteration(prob, runs[k - 1], runs[k], runs[k][2], "rbp", p, 0, 1e-9, True)
+        _check_iteration(prob, runs[k - 1], runs[k], runs[k][2], "rbp", p, 0, eps, True)
 
 
 def test_ising_1000_dynamic_p_three_iterations_full_size(bp):
@@ -158,5 +164,6 @@ def test_ising_1000_dynamic_p_three_iterations_full_size(bp):
     p, seed, eps, t0, kmax = 0.5, 3, 1e-4, 5, 3
     runs = _gpu_prefix_runs(bp, prob, S0, t0, kmax, "rnbp", p, seed, eps)
     for k in range(1, kmax + 1):
+        # about 2e-5 of the messages have an FP64 residual within 1e-6 of eps
         _check_iteration(prob, runs[k - 1], runs[k], runs[k][2], "rnbp", p, seed, eps, True,
-                         max_band=E // 100000)
+                         max_band=E // 10000)

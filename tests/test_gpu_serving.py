@@ -125,7 +125,10 @@ def test_serving_results_against_oracle(bp):
     conv = [
         (inputs.ising_grid(15, 16, 0.5, 0), "rnbp", 1e-7, 0.5, 1, 10000),
         (inputs.ising_grid(21, 9, 0.4, 1), "lbp", 1e-7, 1.0, 0, 10000),
-        (inputs.chain(300, 2.0, 3), "lbp", 1e-8, 1.0, 0, 10000),
+        # (eps above the FP32 floor: the cavity is taken by subtracting the
+        # target's message from the aggregate, so residuals of ~1e-7 can
+        # persist at a fixed point)
+        (inputs.chain(300, 2.0, 3), "lbp", 1e-6, 1.0, 0, 10000),
         (inputs.er_graph(400, 4.0, 0.4, 4), "rnbp", 1e-7, 0.7, 4, 10000),
         (_star(600, 5), "rnbp", 1e-7, 0.5, 4, 10000),  # oversized node
     ]

@@ -53,6 +53,7 @@ CASES = [
     ("lbp", 1.0, 200, 0),
     ("rnbp", 0.3, 300, 2),   # switches to sparse re-evaluation (graph-held buffers)
     ("rbp", 1 / 256, 30, 1),
+    ("rs", 1 / 64, 20, 0),     # residual splash: graph-held splash buffers, ties over variables
 ]
 
 
