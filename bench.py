@@ -48,6 +48,56 @@ def eval_kernel_bytes(N, E, two_outputs=True):
     return (20 if two_outputs else 16) * E + 8 * N
 
 
+def ragged_iteration_bytes(problem):
+    """Algorithmic bytes of one dense iteration with per-variable state counts:
+    every message i -> j read once and written once (K_j FP32 values each), its
+    K_i x K_j table once, every unary once, and the topology (node offsets, two
+    int32 per message, the message and table offsets)."""
+    import numpy as np
+    kv = np.asarray(problem["var_states"], dtype=np.int64)
+    ed = np.asarray(problem["edges"], dtype=np.int64).reshape(-1, 2)
+    ka, kb = kv[ed[:, 0]], kv[ed[:, 1]]
+    E, N = 2 * len(ed), len(kv)
+    msg = 2 * int((ka + kb).sum()) * 4
+    tab = 2 * int((ka * kb).sum()) * 4
+    return msg + tab + int(kv.sum()) * 4 + (N + 1) * 4 + 2 * E * 4 + 2 * (E + 1) * 4
+
+
+def paper_ratios(bp, inputs, srbp, torch, eps, time_limit_s=20.0):
+    """The paper's speedup protocol restated on this host: serial residual BP
+    (SRBP, one host core, its own indexed heap) against RnBP, frontier RBP and
+    residual splash on the GPU, on the paper's own parameterisation (unaries
+    U(0, 1] per state, J = lambda C, lambda ~ U[-1/2, 1/2]; C is the paper's),
+    with the LowP settings and frontier sizes the paper reports.  Times are
+    wall clock to convergence (graph resident on the GPU)."""
+    cases = [("ising100_C2", (100, 100, 2.0), 0.7), ("ising100_C2.5", (100, 100, 2.5), 0.7),
+             ("ising100_C3", (100, 100, 3.0), 0.1), ("ising200_C2.5", (200, 200, 2.5), 0.7),
+             ("chain100000_C10", (1, 100000, 10.0), 0.7)]
+    out = {}
+    for name, (H, W, C), low in cases:
+        pr = inputs.paper_ising_grid(H, W, C, 0)
+        s = srbp.srbp_solve(pr, eps=eps, time_limit_s=time_limit_s)
+        row = {"srbp_s": s["seconds"], "srbp_converged": s["converged"],
+               "srbp_updates": s["updates"], "low_p": low}
+        p_rbp = 1 / 16 if H == 1 else 1 / 256
+        with bp.Graph(pr) as g:
+            for key, sched, p in (("rnbp", "rnbp", low), ("rbp", "rbp", p_rbp),
+                                  ("rs", "rs", p_rbp), ("lbp", "lbp", 1.0)):
+                g.run(sched, eps=eps, p=p, seed=1, max_iters=50)  # warm the launch path
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                r = g.run(sched, eps=eps, p=p, seed=1, max_iters=10000, check_every=16)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - a
+                row[key] = {"s": dt, "converged": r["converged"], "iterations": r["iterations"],
+                            "p": p, "speedup_vs_srbp": (s["seconds"] / dt
+                                                        if r["converged"] and s["converged"]
+                                                        else None)}
+        out[name] = row
+        _log(f"bench: paper ratio {name} {row}")
+    return out
+
+
 def host_cpu():
     """Host cores and CPU model (for the CPU baseline)."""
     model = None
@@ -429,6 +479,58 @@ def main():
                               "message_updates_per_s": rr["evaluated"] / (rr["device_ms"] / 1e3)}
         extra["ising_4000x4000_C%g" % args.C] = row
         _log(f"bench: ising 4000x4000 {row}")
+        # residual splash (the paper's strongest prior GPU baseline, h = 2) on
+        # the 1000 x 1000 grid: iteration time at C = 2.5, convergence at C = 1
+        rs_row = {}
+        for p_rs in (1 / 256, 1 / 16):
+            r = g.run("rs", eps=args.eps, p=p_rs, max_iters=100, check_every=args.check_every,
+                      profile=1)
+            it_us = r["device_ms"] * 1e3 / (r["iterations"] + 1)
+            ev_us = r["eval_kernel_ms"] * 1e3 / max(r["eval_kernel_launches"], 1)
+            rs_row[f"p={p_rs:.6g}"] = {
+                "iteration_us": it_us, "eval_kernel_us": ev_us,
+                "share_outside_evaluation": max(0.0, 1.0 - ev_us / it_us),
+                "committed_per_iteration": r["committed"] / max(r["iterations"], 1)}
+        conv = []
+        for sd in range(3):
+            pr = inputs.ising_grid(S, S, 1.0, 100 + sd)
+            with bp.Graph(pr) as gg:
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                rr = gg.run("rs", eps=args.eps, p=1 / 256, max_iters=args.max_iters,
+                            check_every=args.ttc_check_every)
+                torch.cuda.synchronize()
+                conv.append((rr["converged"], time.perf_counter() - a, rr["iterations"]))
+        rs_row["ttc_C=1_p=1/256"] = {
+            "converged": sum(c[0] for c in conv), "graphs": len(conv),
+            "mean_s_converged": (float(np.mean([c[1] for c in conv if c[0]]))
+                                 if any(c[0] for c in conv) else None),
+            "mean_iterations": float(np.mean([c[2] for c in conv]))}
+        extra["residual_splash_1000x1000_h2"] = rs_row
+        _log(f"bench: residual splash {rs_row}")
+        # variables with their own numbers of states (2..81, a contact graph):
+        # the stand-in for the paper's side-chain models
+        for n_pl in (2000, 50000):
+            pr = inputs.protein_like_graph(n_pl, 8.0, 0)
+            nb = ragged_iteration_bytes(pr)
+            with bp.Graph(pr) as gg:
+                t0 = time.perf_counter()
+                rc = gg.run("rnbp", eps=args.eps, p=0.4, high_p=0.9, seed=1, max_iters=2000,
+                            check_every=16)
+                t_conv = time.perf_counter() - t0
+                rl = gg.run("lbp", eps=0.0, max_iters=50, check_every=args.check_every,
+                            profile=args.profile_every)
+                us = rl["eval_kernel_ms"] * 1e3 / max(rl["eval_kernel_launches"], 1)
+            extra[f"protein_like_{n_pl}_deg8_K2-81"] = {
+                "messages": 2 * len(pr["edges"]), "bytes_per_iteration": nb,
+                "rnbp_low0.4_high0.9_converged": rc["converged"],
+                "rnbp_iterations": rc["iterations"], "rnbp_solve_s": t_conv,
+                "lbp_eval_kernel_us": us,
+                "lbp_message_updates_per_s": rl["evaluated"] / (rl["device_ms"] / 1e3),
+                "hbm_frac": nb / (us * 1e-6) / HBM_PEAK if us > 0 else None}
+            _log(f"bench: protein-like {n_pl} {extra[f'protein_like_{n_pl}_deg8_K2-81']}")
+        from paper_1909_11469_amd import srbp
+        extra["paper_ratios_vs_srbp"] = paper_ratios(bp, inputs, srbp, torch, args.eps)
         extra["serving"] = serving_bench(bp, inputs, np, torch, args)
         _log(f"bench: serving {extra['serving']}")
         out["extra"] = extra
