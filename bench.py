@@ -146,17 +146,18 @@ def serving_mix(inputs, np, n, seed=0):
     return mix
 
 
-def serving_bench(bp, inputs, np, torch, args, n=48, max_iters=2000, p=0.5,
-                  rates=(25.0, 50.0, 100.0, 200.0)):
-    """Batched serving (one launch per iteration for every resident graph) vs one
-    graph per bp_run, on the same requests: RnBP, eps = 1e-4, at most 2000
-    iterations per request.  Arrival patterns: a burst (all at time 0) and
-    Poisson processes at each of `rates` requests/s.  Latency = completion -
+def serving_bench(bp, inputs, np, torch, args, n=1000, max_iters=2000, p=0.5,
+                  rates=(100.0,), launches=16):
+    """Batched serving (one launch per iteration for every resident graph,
+    recorded HIP graphs, autotuned grid) against one graph per bp_run, on the
+    same n requests (RnBP, eps = 1e-4, at most 2000 iterations each) and the same
+    arrival times, both legs replayed on the wall clock: a burst (all at time 0)
+    and Poisson processes at each of `rates` requests/s.  Latency = completion -
     arrival; submission (the host builds and validates the layout) is inside it."""
     mix = serving_mix(inputs, np, n)
     msgs = sum(2 * len(pr["edges"]) for pr in mix)
     out = {"requests": n, "messages_total": msgs, "max_iters": max_iters,
-           "poisson_rates": list(rates)}
+           "poisson_rates": list(rates), "launches_per_step": launches}
     rng = np.random.default_rng(7)
     gaps = rng.exponential(1.0, n)  # one unit-rate draw, scaled per rate
     arrivals = {"burst": np.zeros(n)}
@@ -168,26 +169,23 @@ def serving_bench(bp, inputs, np, torch, args, n=48, max_iters=2000, p=0.5,
         return {"graphs_per_s": n / makespan, "p50_ms": float(np.percentile(lat, 50) * 1e3),
                 "p99_ms": float(np.percentile(lat, 99) * 1e3), "makespan_s": makespan}
 
-    # one graph per run, in arrival order: execution times once, then each
-    # arrival pattern by queueing on one worker
-    torch.cuda.synchronize()
-    dur = []
-    for i, pr in enumerate(mix):
-        a = time.perf_counter()
-        with bp.Graph(pr) as g:
-            g.run("rnbp", eps=args.eps, p=p, seed=i, max_iters=max_iters, check_every=64)
-            g.marginals()
-        dur.append(time.perf_counter() - a)
     for name, arr in arrivals.items():
-        free, lat = 0.0, []
-        for i in range(n):
-            free = max(free, arr[i]) + dur[i]
-            lat.append(free - arr[i])
-        out.setdefault(name, {})["one_graph_per_run"] = stats(lat, free)
-
-    # batched serving, arrivals replayed in wall-clock time
-    for name, arr in arrivals.items():
-        with bp.Server(2 << 30, max_graphs=64) as srv:
+        # one graph per run: a single worker takes requests in arrival order
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat = []
+        for i, pr in enumerate(mix):
+            now = time.perf_counter() - t0
+            if arr[i] > now:
+                time.sleep(arr[i] - now)
+            with bp.Graph(pr) as g:
+                g.run("rnbp", eps=args.eps, p=p, seed=i, max_iters=max_iters, check_every=64)
+                g.marginals()
+            lat.append(time.perf_counter() - t0 - arr[i])
+        out.setdefault(name, {})["one_graph_per_run"] = stats(lat, time.perf_counter() - t0)
+        _log(f"bench: serving {name} one graph per run {out[name]['one_graph_per_run']}")
+        # batched serving
+        with bp.Server(4 << 30, max_graphs=128, graphs=True, autotune=True) as srv:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             ids, done, nxt = {}, {}, 0
@@ -197,16 +195,19 @@ def serving_bench(bp, inputs, np, torch, args, n=48, max_iters=2000, p=0.5,
                     ids[srv.submit(mix[nxt], "rnbp", eps=args.eps, p=p, seed=nxt,
                                    max_iters=max_iters)] = nxt
                     nxt += 1
-                if len(ids) > len(done):
-                    srv.step(8)
+                if ids:
+                    srv.step(launches)
                     now = time.perf_counter() - t0
-                    for rid, k in ids.items():
-                        if k not in done and srv.result(rid) is not None:
+                    for rid, k in list(ids.items()):
+                        if srv.result(rid) is not None:
                             done[k] = now
+                            del ids[rid]
                 else:
                     time.sleep(max(0.0, min(arr[nxt] - now, 0.001)))
             makespan = time.perf_counter() - t0
-        out[name]["batched"] = stats([done[k] - arr[k] for k in range(n)], makespan)
+            out[name]["batched"] = stats([done[k] - arr[k] for k in range(n)], makespan)
+            out[name]["batched"]["autotuner"] = srv.config()
+        _log(f"bench: serving {name} batched {out[name]['batched']}")
     return out
 
 
@@ -237,6 +238,10 @@ def main():
     ap.add_argument("--er-seeds", type=int, default=0,
                     help="time to convergence on this many 200k-node ER graphs (RnBP p = 0.3 "
                          "vs LBP, C = 2.5); 0 = skip")
+    ap.add_argument("--extras", default="rbp,er,potts,ising4000,splash,protein,paper_ratios,serving",
+                    help="comma-separated extras to run (unless --no-extra)")
+    ap.add_argument("--serving-requests", type=int, default=1000,
+                    help="requests of the serving mix")
     ap.add_argument("--ttc-check-every", type=int, default=16,
                     help="convergence poll interval of the time-to-convergence runs")
     args = ap.parse_args()
@@ -405,9 +410,10 @@ def main():
 
     if not args.no_extra:
         extra = {}
+        wanted = set(x.strip() for x in args.extras.split(",") if x.strip())
         # frontier residual BP on the same graph: share of the iteration spent
         # outside the evaluation kernel (top-k selection and commit)
-        for p_rbp in (1 / 256, 1 / 16):
+        for p_rbp in ((1 / 256, 1 / 16) if "rbp" in wanted else ()):
             r = g.run("rbp", eps=args.eps, p=p_rbp, max_iters=200, check_every=args.check_every,
                       profile=1)
             it_us = r["device_ms"] * 1e3 / (r["iterations"] + 1)
@@ -421,14 +427,17 @@ def main():
         # taken over launches that all evaluate (eps = 0: no launch is a no-op
         # after convergence); convergence at eps is reported from its own run.
         for name, pr, p_, iters in (
-                ("er_200k_deg6_C2.5", inputs.er_graph(200000, 6.0, 2.5, 0), 0.3, 1000),
-                ("potts_500x500_K32", inputs.potts_grid(500, 500, 32, 1.0, 0), 0.5, 100)):
+                (("er_200k_deg6_C2.5", inputs.er_graph(200000, 6.0, 2.5, 0), 0.3, 1000),)
+                if "er" in wanted else ()) + (
+                (("potts_500x500_K32", inputs.potts_grid(500, 500, 32, 1.0, 0), 0.5, 100),)
+                if "potts" in wanted else ()):
             E_, N_, K_ = 2 * len(pr["edges"]), pr["N"], pr["K"]
             # the workload's algorithmic bytes per iteration (iteration_bytes)
             nb = iteration_bytes(N_, E_, K_, 1 if K_ == 2 else K_)
             row = {"schedule": "rnbp", "p": p_, "messages": E_, "bytes_per_launch": nb}
             # Potts: the matrix-core product and the FP32 vector path (flag 2)
-            variants = (("", 0),) if K_ == 2 else (("", 0), ("vector_path_", 2))
+            # and BF16 operands on the matrix cores (flag 16)
+            variants = (("", 0),) if K_ == 2 else (("", 0), ("vector_path_", 2), ("bf16_", 16))
             margs = []
             for tag, flags in variants:
                 with bp.Graph(pr, flags=flags) as gg:
@@ -457,60 +466,64 @@ def main():
                                     profile=args.profile_every)
                         row["lbp_eval_kernel_us"] = (rl["eval_kernel_ms"] * 1e3 /
                                                      max(rl["eval_kernel_launches"], 1))
-            if len(margs) == 2:
+            if len(margs) == 3:
                 row["max_abs_marginal_diff_matrix_vs_vector"] = float(
                     np.max(np.abs(margs[0] - margs[1])))
+                row["max_abs_marginal_diff_bf16_vs_fp32_matrix"] = float(
+                    np.max(np.abs(margs[2] - margs[0])))
             extra[name] = row
             _log(f"bench: {name} {extra[name]}")
         # a working set far beyond the 256 MB Infinity Cache: every byte of a
         # sweep comes from HBM (16M variables, 64M messages)
-        pr = inputs.ising_grid(4000, 4000, args.C, 0)
-        N4, E4 = pr["N"], 2 * len(pr["edges"])
-        with bp.Graph(pr) as gg:
-            del pr
-            row = {"messages": E4}
-            for sched in ("lbp", "rnbp"):
-                rr = gg.run(sched, eps=args.eps, p=args.p, seed=1, max_iters=60,
-                            check_every=args.check_every, profile=args.profile_every)
-                us = rr["eval_kernel_ms"] * 1e3 / max(rr["eval_kernel_launches"], 1)
-                nb = iteration_bytes(N4, E4)
-                row[sched] = {"eval_kernel_us": us, "bytes_per_launch": nb,
-                              "hbm_frac": nb / (us * 1e-6) / HBM_PEAK if us > 0 else None,
-                              "message_updates_per_s": rr["evaluated"] / (rr["device_ms"] / 1e3)}
-        extra["ising_4000x4000_C%g" % args.C] = row
-        _log(f"bench: ising 4000x4000 {row}")
-        # residual splash (the paper's strongest prior GPU baseline, h = 2) on
-        # the 1000 x 1000 grid: iteration time at C = 2.5, convergence at C = 1
-        rs_row = {}
-        for p_rs in (1 / 256, 1 / 16):
-            r = g.run("rs", eps=args.eps, p=p_rs, max_iters=100, check_every=args.check_every,
-                      profile=1)
-            it_us = r["device_ms"] * 1e3 / (r["iterations"] + 1)
-            ev_us = r["eval_kernel_ms"] * 1e3 / max(r["eval_kernel_launches"], 1)
-            rs_row[f"p={p_rs:.6g}"] = {
-                "iteration_us": it_us, "eval_kernel_us": ev_us,
-                "share_outside_evaluation": max(0.0, 1.0 - ev_us / it_us),
-                "committed_per_iteration": r["committed"] / max(r["iterations"], 1)}
-        conv = []
-        for sd in range(3):
-            pr = inputs.ising_grid(S, S, 1.0, 100 + sd)
+        if "ising4000" in wanted:
+            pr = inputs.ising_grid(4000, 4000, args.C, 0)
+            N4, E4 = pr["N"], 2 * len(pr["edges"])
             with bp.Graph(pr) as gg:
-                torch.cuda.synchronize()
-                a = time.perf_counter()
-                rr = gg.run("rs", eps=args.eps, p=1 / 256, max_iters=args.max_iters,
-                            check_every=args.ttc_check_every)
-                torch.cuda.synchronize()
-                conv.append((rr["converged"], time.perf_counter() - a, rr["iterations"]))
-        rs_row["ttc_C=1_p=1/256"] = {
-            "converged": sum(c[0] for c in conv), "graphs": len(conv),
-            "mean_s_converged": (float(np.mean([c[1] for c in conv if c[0]]))
-                                 if any(c[0] for c in conv) else None),
-            "mean_iterations": float(np.mean([c[2] for c in conv]))}
-        extra["residual_splash_1000x1000_h2"] = rs_row
-        _log(f"bench: residual splash {rs_row}")
+                del pr
+                row = {"messages": E4}
+                for sched in ("lbp", "rnbp"):
+                    rr = gg.run(sched, eps=args.eps, p=args.p, seed=1, max_iters=60,
+                                check_every=args.check_every, profile=args.profile_every)
+                    us = rr["eval_kernel_ms"] * 1e3 / max(rr["eval_kernel_launches"], 1)
+                    nb = iteration_bytes(N4, E4)
+                    row[sched] = {"eval_kernel_us": us, "bytes_per_launch": nb,
+                                  "hbm_frac": nb / (us * 1e-6) / HBM_PEAK if us > 0 else None,
+                                  "message_updates_per_s": rr["evaluated"] / (rr["device_ms"] / 1e3)}
+            extra["ising_4000x4000_C%g" % args.C] = row
+            _log(f"bench: ising 4000x4000 {row}")
+        if "splash" in wanted:
+            # residual splash (the paper's strongest prior GPU baseline, h = 2) on
+            # the 1000 x 1000 grid: iteration time at C = 2.5, convergence at C = 1
+            rs_row = {}
+            for p_rs in (1 / 256, 1 / 16):
+                r = g.run("rs", eps=args.eps, p=p_rs, max_iters=100, check_every=args.check_every,
+                          profile=1)
+                it_us = r["device_ms"] * 1e3 / (r["iterations"] + 1)
+                ev_us = r["eval_kernel_ms"] * 1e3 / max(r["eval_kernel_launches"], 1)
+                rs_row[f"p={p_rs:.6g}"] = {
+                    "iteration_us": it_us, "eval_kernel_us": ev_us,
+                    "share_outside_evaluation": max(0.0, 1.0 - ev_us / it_us),
+                    "committed_per_iteration": r["committed"] / max(r["iterations"], 1)}
+            conv = []
+            for sd in range(3):
+                pr = inputs.ising_grid(S, S, 1.0, 100 + sd)
+                with bp.Graph(pr) as gg:
+                    torch.cuda.synchronize()
+                    a = time.perf_counter()
+                    rr = gg.run("rs", eps=args.eps, p=1 / 256, max_iters=args.max_iters,
+                                check_every=args.ttc_check_every)
+                    torch.cuda.synchronize()
+                    conv.append((rr["converged"], time.perf_counter() - a, rr["iterations"]))
+            rs_row["ttc_C=1_p=1/256"] = {
+                "converged": sum(c[0] for c in conv), "graphs": len(conv),
+                "mean_s_converged": (float(np.mean([c[1] for c in conv if c[0]]))
+                                     if any(c[0] for c in conv) else None),
+                "mean_iterations": float(np.mean([c[2] for c in conv]))}
+            extra["residual_splash_1000x1000_h2"] = rs_row
+            _log(f"bench: residual splash {rs_row}")
         # variables with their own numbers of states (2..81, a contact graph):
         # the stand-in for the paper's side-chain models
-        for n_pl in (2000, 50000):
+        for n_pl in ((2000, 50000) if "protein" in wanted else ()):
             pr = inputs.protein_like_graph(n_pl, 8.0, 0)
             nb = ragged_iteration_bytes(pr)
             with bp.Graph(pr) as gg:
@@ -529,9 +542,11 @@ def main():
                 "lbp_message_updates_per_s": rl["evaluated"] / (rl["device_ms"] / 1e3),
                 "hbm_frac": nb / (us * 1e-6) / HBM_PEAK if us > 0 else None}
             _log(f"bench: protein-like {n_pl} {extra[f'protein_like_{n_pl}_deg8_K2-81']}")
-        from paper_1909_11469_amd import srbp
-        extra["paper_ratios_vs_srbp"] = paper_ratios(bp, inputs, srbp, torch, args.eps)
-        extra["serving"] = serving_bench(bp, inputs, np, torch, args)
+        if "paper_ratios" in wanted:
+            from paper_1909_11469_amd import srbp
+            extra["paper_ratios_vs_srbp"] = paper_ratios(bp, inputs, srbp, torch, args.eps)
+        if "serving" in wanted:
+            extra["serving"] = serving_bench(bp, inputs, np, torch, args, n=args.serving_requests)
         _log(f"bench: serving {extra['serving']}")
         out["extra"] = extra
 

@@ -100,6 +100,12 @@ typedef enum bp_schedule { BP_LBP = 0, BP_RBP = 1, BP_RNBP = 2, BP_RS = 3 } bp_s
                                      Eq. (2) product on the FP32 vector units instead of
                                      the matrix cores (FP32 MFMA); same results within
                                      FP32 rounding */
+#define BP_FLAG_BF16_MATRIX_CORES 16u /* K = 32 with one symmetric shared table: BF16
+                                     operands on the matrix cores (FP32 accumulation):
+                                     the cavity distribution and the table are rounded
+                                     to 8-bit mantissas, so messages carry relative
+                                     errors of order 2^-8 (not within the FP32 sweep
+                                     tolerance); ignored with BP_FLAG_NO_MATRIX_CORES */
 #define BP_FLAG_SPARSE_BUFFERS 4u  /* one-log-odds-per-message graphs: hold the buffers of
                                      sparse re-evaluation (bp_run_opts.sparse) in the
                                      graph's memory (counted by bp_workspace_bytes) instead
@@ -167,6 +173,12 @@ typedef struct bp_run_opts {
                                  1: sparse from the first iteration;
                                  2: full evaluation until n_t <= E / 16 at a host poll,
                                     sparse from then on.
+                                 A sparse iteration costs about as much as a full one
+                                 when n_t is near E / 16 and more when it is larger
+                                 (its work is per variable, not tiled), so mode 1 is
+                                 slower than the full evaluation while most messages
+                                 stay active (strong coupling); mode 2 is the
+                                 adaptive choice.
                                  Messages, iteration counts and residuals are bitwise those
                                  of the full evaluation; only `evaluated` differs.  The
                                  buffers (2 bytes per node and 4 per message) are in the
@@ -217,6 +229,13 @@ typedef struct bp_graph_info {
                                  2 = K_j probabilities per message (var_states) */
     int32_t num_tiles;        /* node tiles of the evaluation kernel */
     uint64_t device_bytes;    /* device memory held by the graph */
+    int32_t eval_blocks;      /* one-log-odds-per-message graphs: the persistent grid of
+                                 the evaluation kernel chosen by launch-shape tuning (the
+                                 first run of at least 32 iterations times 8 launches at
+                                 each of 1, 2, 4 blocks per compute unit and every
+                                 resident block, and keeps the fastest; results do not
+                                 depend on it); 0 until tuned */
+    int32_t reserved;
 } bp_graph_info;
 
 /* Fill *opts with the defaults listed in bp_run_opts. */
@@ -303,9 +322,10 @@ const char* bp_last_error(void);
  * Serving: many independent graphs solved together.
  *
  * A server keeps up to max_graphs graphs resident in one device arena and
- * evaluates one iteration of every resident graph per kernel launch (each
- * block takes one tile of one graph), so small graphs share the GPU instead
- * of each paying for whole-GPU launches.  Requests wait in FIFO order until
+ * evaluates one iteration of every resident graph per kernel launch (a
+ * persistent grid; each block runs a contiguous range of the graphs' tiles
+ * through the same pipelined tile loop as bp_run), so small graphs share the
+ * GPU instead of each paying for whole-GPU launches.  Requests wait in FIFO order until
  * the arena has room, join the batch at the next step, and leave it when
  * they converge or reach max_iters.  Every graph advances exactly as bp_run
  * would advance it alone (same tiles, arithmetic, counters and random keys),
@@ -317,13 +337,21 @@ const char* bp_last_error(void);
  * ------------------------------------------------------------------------ */
 typedef struct bp_server bp_server;
 
+/* bp_server_desc.options */
+#define BP_SERVER_GRAPHS 1u    /* record the launches of a step once as a HIP graph of
+                                  kernel nodes and replay it (re-recorded when the set of
+                                  resident graphs or the launch shape changes) */
+#define BP_SERVER_AUTOTUNE 2u  /* choose the persistent grid of the batched kernel (blocks
+                                  per compute unit) from HIP-event timings of live steps;
+                                  results do not depend on the choice */
+
 typedef struct bp_server_desc {
     uint64_t arena_bytes;   /* device memory for resident graphs (> 0) */
     void* arena;            /* optional caller-owned device memory, 256-byte aligned,
                                at least arena_bytes; NULL = library allocates */
     void* stream;           /* hipStream_t for all device work, NULL = null stream */
     int32_t max_graphs;     /* most graphs resident at once, 1 ... 65536 */
-    int32_t reserved;
+    uint32_t options;       /* BP_SERVER_* */
 } bp_server_desc;
 
 typedef struct bp_request {
@@ -365,6 +393,15 @@ int bp_server_result(bp_server* s, int64_t id, float* marginals, bp_run_stats* s
 /* Requests waiting for room, resident in the batch, and retired but not yet
  * fetched (any pointer may be NULL). */
 int bp_server_counts(const bp_server* s, int64_t* queued, int64_t* resident, int64_t* retired);
+
+/* The batched kernel's launch shape: *grid_blocks (persistent blocks per
+ * launch), *tuned (1 once the autotuner has chosen), and the autotuner's
+ * measurements: for up to max_entries candidates, blocks per launch and
+ * device nanoseconds per resident message per launch of the last tuning round
+ * (*entries receives the count).  Any pointer may be NULL. */
+int bp_server_config(const bp_server* s, int32_t* grid_blocks, int32_t* tuned,
+                     int32_t* cand_blocks, double* cand_ns_per_msg, int32_t max_entries,
+                     int32_t* entries);
 
 /* Release the server's device memory (not a caller arena) and every request.
  * NULL is ignored. */

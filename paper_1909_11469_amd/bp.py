@@ -23,7 +23,10 @@ BP_LBP, BP_RBP, BP_RNBP, BP_RS = 0, 1, 2, 3
 BP_FLAG_GENERIC_LAYOUT = 1
 BP_FLAG_NO_MATRIX_CORES = 2
 BP_FLAG_SPARSE_BUFFERS = 4
+BP_FLAG_BF16_MATRIX_CORES = 16
 BP_FLAG_SPLASH_BUFFERS = 8
+BP_SERVER_GRAPHS = 1
+BP_SERVER_AUTOTUNE = 2
 
 SCHEDULES = {"lbp": BP_LBP, "rbp": BP_RBP, "rnbp": BP_RNBP, "rs": BP_RS}
 
@@ -32,7 +35,8 @@ EXPORTED = ["bp_default_opts", "bp_workspace_bytes", "bp_create_graph", "bp_run"
             "bp_run_noalloc", "bp_marginals", "bp_marginals_device", "bp_get_state", "bp_set_state",
             "bp_graph_info_get", "bp_destroy_graph", "bp_last_error",
             "bp_server_create", "bp_server_submit", "bp_server_step", "bp_server_result",
-            "bp_server_counts", "bp_server_destroy", "bp_server_inject_failures"]
+            "bp_server_counts", "bp_server_config", "bp_server_destroy",
+            "bp_server_inject_failures"]
 
 
 class BpError(RuntimeError):
@@ -77,13 +81,14 @@ class bp_graph_info(ctypes.Structure):
     _fields_ = [("num_vars", ctypes.c_int32), ("num_states", ctypes.c_int32),
                 ("num_edges", ctypes.c_int64), ("num_messages", ctypes.c_int64),
                 ("layout", ctypes.c_int32), ("num_tiles", ctypes.c_int32),
-                ("device_bytes", ctypes.c_uint64)]
+                ("device_bytes", ctypes.c_uint64), ("eval_blocks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class bp_server_desc(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_uint64), ("arena", ctypes.c_void_p),
                 ("stream", ctypes.c_void_p), ("max_graphs", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("options", ctypes.c_uint32)]
 
 
 class bp_request(ctypes.Structure):
@@ -138,6 +143,10 @@ def _load():
     lib.bp_server_counts.restype = ctypes.c_int
     lib.bp_server_destroy.argtypes = [P]
     lib.bp_server_destroy.restype = None
+    I32P = ctypes.POINTER(ctypes.c_int32)
+    lib.bp_server_config.argtypes = [P, I32P, I32P, I32P, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.c_int32, I32P]
+    lib.bp_server_config.restype = ctypes.c_int
     lib.bp_server_inject_failures.argtypes = [P, ctypes.c_int32]
     lib.bp_server_inject_failures.restype = ctypes.c_int
     return lib
@@ -367,9 +376,13 @@ class Server:
     runs n batched iterations and retires finished graphs; result(id) returns
     (marginals, stats) once the request is retired, else None."""
 
-    def __init__(self, arena_bytes, max_graphs=256, use_torch=True):
+    def __init__(self, arena_bytes, max_graphs=256, use_torch=True, graphs=False,
+                 autotune=False):
+        """graphs: replay each step's launches as a recorded HIP graph;
+        autotune: choose the batched kernel's grid from timed live steps."""
         d = bp_server_desc()
         d.arena_bytes, d.max_graphs = int(arena_bytes), int(max_graphs)
+        d.options = (BP_SERVER_GRAPHS if graphs else 0) | (BP_SERVER_AUTOTUNE if autotune else 0)
         self._arena = None
         torch = _torch_cuda() if use_torch else None
         if torch is not None:
@@ -430,6 +443,16 @@ class Server:
         out = {f: getattr(s, f) for f, _ in s._fields_ if f != "reserved0"}
         out["converged"] = bool(out["converged"])
         return m, out
+
+    def config(self):
+        """{"grid_blocks", "tuned", "candidates": [(blocks, ns per message per launch)]}"""
+        g, t, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        cb = (ctypes.c_int32 * 16)()
+        cn = (ctypes.c_double * 16)()
+        _check(lib.bp_server_config(self.handle, ctypes.byref(g), ctypes.byref(t), cb, cn, 16,
+                                    ctypes.byref(n)))
+        return {"grid_blocks": g.value, "tuned": bool(t.value),
+                "candidates": [(cb[i], cn[i]) for i in range(n.value)]}
 
     def inject_failures(self, admissions):
         """Test hook: the next `admissions` admissions fail (bp_server_inject_failures)."""

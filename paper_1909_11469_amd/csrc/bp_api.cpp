@@ -78,6 +78,7 @@ struct HostLayout {
     int tile_nodes_max = 1;           // most nodes in one regular tile
     int tile_big = 0;                 // 1 if some node's slots exceed the tile limit
     int no_mfma = 0;                  // BP_FLAG_NO_MATRIX_CORES
+    int mfma_bf16 = 0;                // BP_FLAG_BF16_MATRIX_CORES
     int sparse_reserved = 0;          // BP_FLAG_SPARSE_BUFFERS on a log-odds graph
     int splash_reserved = 0;          // BP_FLAG_SPLASH_BUFFERS on a log-odds graph
     std::vector<int> tiles4;          // log-odds layout: regular tiles {n0, n1, s0, s1}
@@ -225,9 +226,11 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
         return fail(BP_EINVAL, "unknown pair_kind %d", kind);
     }
     if (d->flags & ~(uint32_t)(BP_FLAG_GENERIC_LAYOUT | BP_FLAG_NO_MATRIX_CORES |
-                               BP_FLAG_SPARSE_BUFFERS | BP_FLAG_SPLASH_BUFFERS))
+                               BP_FLAG_SPARSE_BUFFERS | BP_FLAG_SPLASH_BUFFERS |
+                               BP_FLAG_BF16_MATRIX_CORES))
         return fail(BP_EINVAL, "unknown flags");
     L.no_mfma = (d->flags & BP_FLAG_NO_MATRIX_CORES) ? 1 : 0;
+    L.mfma_bf16 = (d->flags & BP_FLAG_BF16_MATRIX_CORES) ? 1 : 0;
     {
         std::unordered_set<unsigned long long> seen;
         seen.reserve((size_t)M * 2 + 1);
@@ -459,6 +462,7 @@ struct bp_graph {
     DevState* host_state = nullptr;  // pinned mirror
     int num_cus = 0;                 // compute units of the device
     int resident[4] = {0, 0, 0, 0};  // log-odds eval blocks resident per CU, by mode
+    int lo_grid = 0;                 // tuned persistent grid of the K = 2 kernel (0: not yet)
     // sparse re-evaluation buffers: dirty u8 [N], active-node flag u8 [N],
     // target node int32 [E]; in the graph's memory (BP_FLAG_SPARSE_BUFFERS) or
     // allocated by the first sparse run (sparse_owned); the target index is
@@ -631,6 +635,7 @@ int bp_graph_info_get(const bp_graph* g, bp_graph_info* info) {
     info->layout = g->L.layout;
     info->num_tiles = (int)g->L.tile_start.size() - 1;
     info->device_bytes = g->off.total;
+    info->eval_blocks = g->lo_grid;
     return BP_OK;
 }
 
@@ -677,6 +682,7 @@ static EvalArgs run_args(const bp_graph* g, int schedule, double eps, double p, 
         cap = std::max<long long>(8, cap / 8 * 8);
         a.pipe_grid = (int)std::min<long long>(cap, std::max(8, 8 * a.tiles_per_xcd));
     }
+    if (L.layout == kLayoutLogOdds && g->lo_grid > 0) a.pipe_grid = g->lo_grid;
     a.node_ptr = g->at<int>(g->off.node_ptr);
     a.rev = g->at<int>(g->off.rev);
     a.coupling = g->at<float>(g->off.coupling);
@@ -715,6 +721,7 @@ static EvalArgs run_args(const bp_graph* g, int schedule, double eps, double p, 
     a.tile_nodes_max = L.tile_nodes_max;
     a.tile_big = L.tile_big;
     a.no_mfma = L.no_mfma;
+    a.mfma_bf16 = L.mfma_bf16;
     a.rbp_k = (unsigned long long)rbp_k;
     a.sel0 = g->cur_sel;
     if (mode == kModeRnBP && o.dynamic_p) {
@@ -868,6 +875,12 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
     EvalArgs a = run_args(g, schedule, eps, p, seed, o, rbp_k);
     a.st = rs.st;
     a.ctr = rs.ctr;
+    // frontier RBP on the K = 2 kernel: the evaluation also counts the top-k's
+    // first radix digit (not for oversized nodes, the sparse phase, or k = E)
+    a.hist0 = (mode == kModeRBP && !splash && L.layout == kLayoutLogOdds && a.num_big == 0 &&
+               rbp_k < L.E && o.sparse != 1)
+                  ? 1
+                  : 0;
     a.dirty = g->sp_dirty;
     a.hasact = g->sp_hasact;
     a.dst = g->sp_dst;
@@ -923,6 +936,30 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
     }
     double kernel_ms = 0.0;
     long long kernel_launches = 0;
+    // Launch-shape tuning of the K = 2 kernel's persistent grid: the first
+    // run of a graph that is long enough times kTuneLaunches launches at each
+    // candidate grid (1, 2, 4 blocks per compute unit and every resident
+    // block) and keeps the fastest for this run and later ones.  The grid only
+    // decides which block evaluates which tile, so no result depends on it.
+    constexpr int kTuneLaunches = 8;
+    std::vector<int> tcand;
+    std::vector<hipEvent_t> tev;
+    bool tune = L.layout == kLayoutLogOdds && !rs.noalloc && g->lo_grid == 0 &&
+                mode != kModeRBP && a.num_big == 0 && !sparse_now && o.sparse == 0;
+    if (tune) {
+        const long long most = std::max(8, 8 * a.tiles_per_xcd);
+        for (int c : {1, 2, 4, 0}) {
+            long long v = c ? (long long)c * std::max(g->num_cus, 1) : a.pipe_grid;
+            v = std::max<long long>(8, std::min(most, v / 8 * 8));
+            if (std::find(tcand.begin(), tcand.end(), (int)v) == tcand.end()) tcand.push_back((int)v);
+        }
+        tune = tcand.size() > 1 && o.max_iters >= (long long)tcand.size() * kTuneLaunches;
+    }
+    if (tune) {
+        tev.assign(2 * tcand.size(), nullptr);
+        for (auto& x : tev) HIP_OK(hipEventCreate(&x), "event");
+    }
+    const long long tune_end = tune ? (long long)tcand.size() * kTuneLaunches : 0;
     if (ev0) HIP_OK(hipEventRecord(ev0, s), "event record");
 
     const int kp = kpad(L.K);
@@ -950,7 +987,7 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
                     const int all = rbp_k >= L.E;
                     if (!all)
                         HIP_OK(launch_rbp_select(rs.st, a.keys, a.rev, (int)L.E,
-                                                 (unsigned int)rbp_k, (int)(t & 3), ties, s),
+                                                 (unsigned int)rbp_k, nullptr, 0, ties, s),
                                "top-k select");
                     const RbpSparse sp{a.dirty, a.dst, a.ctr, a.eps, (int)((t + 1) & 3), 1};
                     HIP_OK(launch_rbp_commit(rs.st, a.keys, a.rev, a.cand, sp_buf, (int)L.E, L.row,
@@ -991,10 +1028,17 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
         a.after_final = 0;
         const int emode = final_launched ? kModeEvalOnly : mode;
         const bool timed = prof_every && !prof_window && (it % prof_every) == 0;
+        const bool tuning = tune && it < tune_end;
+        if (tuning && it % kTuneLaunches == 0) {
+            a.pipe_grid = tcand[(size_t)(it / kTuneLaunches)];
+            HIP_OK(hipEventRecord(tev[2 * (it / kTuneLaunches)], s), "event record");
+        }
         if (prof_window && in_chunk == 0) HIP_OK(hipEventRecord(kev[0], s), "event record");
         if (timed) HIP_OK(hipEventRecord(kev[2 * in_chunk], s), "event record");
         HIP_OK(launch_eval(L.layout, kp, emode, a, s), "evaluation kernel");
         if (timed) HIP_OK(hipEventRecord(kev[2 * in_chunk + 1], s), "event record");
+        if (tuning && it % kTuneLaunches == kTuneLaunches - 1)
+            HIP_OK(hipEventRecord(tev[2 * (it / kTuneLaunches) + 1], s), "event record");
         if (prof_every && !prof_window) kev_used[in_chunk] = timed ? 1 : 0;
         if (splash && !final_launched) {
             if (g->rs_tag == 0xFFFFFFFFu) {
@@ -1012,10 +1056,13 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
             }
         } else if (mode == kModeRBP && !final_launched) {
             const int all = rbp_k >= L.E;
-            HIP_OK(launch_rbp_gate(rs.st, rs.ctr, (int)(t & 3), s), "top-k gate");
-            if (!all)
+            // the first scan of the select is also the gate (IsConverged)
+            if (all)
+                HIP_OK(launch_rbp_gate(rs.st, rs.ctr, (int)(t & 3), s), "top-k gate");
+            else
                 HIP_OK(launch_rbp_select(rs.st, a.keys, a.rev, (int)L.E, (unsigned int)rbp_k,
-                                         (int)(t & 3), ties, s),
+                                         rs.ctr + (size_t)(t & 3) * kCounterCopies, a.hist0,
+                                         ties, s),
                        "top-k select");
             HIP_OK(launch_rbp_commit(rs.st, a.keys, a.rev, a.cand, start_buf, (int)L.E, L.row, all,
                                      (int)(t & 3), ties, RbpSparse{},
@@ -1043,6 +1090,22 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
                 }
             }
             in_chunk = 0;
+            if (tune && it + 1 >= tune_end) {
+                // every candidate has run: keep the fastest
+                int best = -1;
+                float best_ms = 0.0f;
+                for (size_t c = 0; c < tcand.size(); ++c) {
+                    float ms = 0.0f;
+                    HIP_OK(hipEventElapsedTime(&ms, tev[2 * c], tev[2 * c + 1]), "event time");
+                    if (best < 0 || ms < best_ms) {
+                        best = (int)c;
+                        best_ms = ms;
+                    }
+                }
+                g->lo_grid = tcand[(size_t)best];
+                a.pipe_grid = g->lo_grid;
+                tune = false;
+            }
             if (g->host_state->done || final_launched) break;
             if (o.sparse == 2 && (unsigned long long)g->host_state->last_active * kSparseSwitch <=
                                      (unsigned long long)L.E) {
@@ -1067,6 +1130,7 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
                 }
                 HIP_OK(launch_sparse_setup(a, 0, s), "dirty flags");
                 sparse_now = true;
+                a.hist0 = 0;
                 sp_it0 = it + 1;
                 prof_window = false;
             }
@@ -1092,6 +1156,7 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
         (void)hipEventDestroy(ev1);
     }
     for (auto& x : kev) (void)hipEventDestroy(x);
+    for (auto& x : tev) (void)hipEventDestroy(x);
 
     const DevState& h = *g->host_state;
     const bool converged = h.done != 0;
@@ -1350,6 +1415,23 @@ struct bp_server {
     uint64_t done_off = 0;                 // unsigned [max_graphs]: gathered done flags
     unsigned int* h_done = nullptr;        // pinned mirror
     int inject_failures = 0;               // admissions still to fail (test hook)
+    uint64_t ctl_off = 0;                  // BatchCtl: launch counter, list length
+    uint32_t options = 0;                  // BP_SERVER_*
+    int num_cus = 1;
+    int grid = 0;                          // persistent blocks of the batched kernel
+    long long resident_msgs = 0;           // messages of the resident graphs
+    // recorded step (BP_SERVER_GRAPHS)
+    hipGraphExec_t gexec = nullptr;
+    int g_launches = 0, g_grid = 0;
+    uint64_t g_list_off = ~0ull;
+    // autotuner (BP_SERVER_AUTOTUNE): candidates of blocks per CU, timed on
+    // live steps; a new round starts when the resident messages change 2x
+    std::vector<int> cand;                 // blocks per launch
+    std::vector<double> cand_ns;           // ns per resident message per launch
+    int tune_next = -1;                    // candidate of the next step, -1 = not tuning
+    int tuned = 0;
+    long long tuned_msgs = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
 namespace {
@@ -1405,6 +1487,7 @@ int server_admit(bp_server* s) {
                               sizeof(BatchGraph), hipMemcpyHostToDevice, s->stream),
                "batch record upload");
         const HostLayout& L = g->L;
+        s->resident_msgs += L.E;
         for (int t = 0; t < (int)(L.tiles4.size() / 4); ++t)
             s->h_list.insert(s->h_list.end(), {slot, t, 0, 0});
         for (int t = 0; t < (int)(L.big4.size() / 4); ++t)
@@ -1433,6 +1516,12 @@ int server_upload_list(bp_server* s) {
         HIP_OK(hipMemcpyAsync(s->base + s->list_off, s->h_list.data(), entries * 16,
                               hipMemcpyHostToDevice, s->stream),
                "tile list upload");
+    // the length lives in device memory, so a recorded step stays valid
+    const int n_entries = (int)entries;
+    HIP_OK(hipMemcpyAsync(s->base + s->ctl_off + offsetof(BatchCtl, entries), &n_entries,
+                          sizeof(int), hipMemcpyHostToDevice, s->stream),
+           "tile list length");
+    HIP_OK(hipStreamSynchronize(s->stream), "synchronize");
     s->list_dirty = false;
     return BP_OK;
 }
@@ -1469,6 +1558,7 @@ int server_retire(bp_server* s, Request* r) {
     r->stats.evaluated = (long long)st.evaluated;
     r->stats.committed = (long long)st.committed;
     r->stats.final_t = final_t;
+    s->resident_msgs -= g->L.E;
     bp_destroy_graph(g);
     r->g = nullptr;
     s->alloc.give(r->off, r->bytes);
@@ -1499,9 +1589,14 @@ int bp_server_create(const bp_server_desc* d, bp_server** out) {
         delete s;
         return hip_fail(e, "hipGetDevice");
     }
+    if (d->options & ~(uint32_t)(BP_SERVER_GRAPHS | BP_SERVER_AUTOTUNE)) {
+        delete s;
+        return fail(BP_EINVAL, "unknown server options");
+    }
     s->stream = (hipStream_t)d->stream;
     s->bytes = d->arena_bytes;
     s->max_graphs = d->max_graphs;
+    s->options = d->options;
     if (d->arena) {
         s->base = (char*)d->arena;
     } else {
@@ -1516,9 +1611,22 @@ int bp_server_create(const bp_server_desc* d, bp_server** out) {
     }
     s->alloc.init(s->bytes);
     s->alloc.take(rec_bytes, &s->graphs_off);
-    if (!s->alloc.take(sizeof(unsigned int) * (uint64_t)s->max_graphs, &s->done_off)) {
+    if (!s->alloc.take(sizeof(unsigned int) * (uint64_t)s->max_graphs, &s->done_off) ||
+        !s->alloc.take(sizeof(BatchCtl), &s->ctl_off)) {
         bp_server_destroy(s);
         return fail(BP_EINVAL, "arena_bytes too small");
+    }
+    e = hipDeviceGetAttribute(&s->num_cus, hipDeviceAttributeMultiprocessorCount, s->device);
+    if (e != hipSuccess || s->num_cus < 1) s->num_cus = 1;
+    // persistent grid: 4 blocks per compute unit unless the autotuner chooses
+    s->grid = 4 * s->num_cus;
+    for (int c : {1, 2, 4, 8}) s->cand.push_back(c * s->num_cus);
+    s->cand_ns.assign(s->cand.size(), 0.0);
+    if (s->options & BP_SERVER_AUTOTUNE) {
+        if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess) {
+            bp_server_destroy(s);
+            return fail(BP_EDEVICE, "hipEventCreate");
+        }
     }
     e = hipHostMalloc((void**)&s->h_done, sizeof(unsigned int) * (size_t)s->max_graphs,
                       hipHostMallocDefault);
@@ -1526,8 +1634,10 @@ int bp_server_create(const bp_server_desc* d, bp_server** out) {
         bp_server_destroy(s);
         return hip_fail(e, "hipHostMalloc");
     }
-    // empty slots: null state pointers (the status kernel reads every slot)
+    // empty slots: null state pointers (the status kernel reads every slot);
+    // launch counter 0, empty list
     e = hipMemsetAsync(s->base + s->graphs_off, 0, rec_bytes, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->base + s->ctl_off, 0, sizeof(BatchCtl), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
         bp_server_destroy(s);
@@ -1585,10 +1695,44 @@ int bp_server_step(bp_server* s, int32_t launches, int32_t* finished) {
     const int blocks = (int)(s->h_list.size() / 4);
     BatchGraph* graphs = (BatchGraph*)(s->base + s->graphs_off);
     const int* list = (const int*)(s->base + s->list_off);
-    for (int k = 0; k < launches; ++k) {
-        HIP_OK(launch_eval_batch(graphs, s->max_graphs, list, blocks, s->launch, s->stream),
-               "batch evaluation");
-        ++s->launch;
+    BatchCtl* ctl = (BatchCtl*)(s->base + s->ctl_off);
+    // autotuner: a new round when the resident work changed by 2x
+    const bool tune = (s->options & BP_SERVER_AUTOTUNE) && blocks > 0 && launches > 0;
+    if (tune && s->tune_next < 0 &&
+        (!s->tuned || s->resident_msgs > 2 * s->tuned_msgs || 2 * s->resident_msgs < s->tuned_msgs))
+        s->tune_next = 0;
+    const int tuning = tune ? s->tune_next : -1;
+    const int grid = tuning >= 0 ? s->cand[tuning] : s->grid;
+    if (blocks > 0 && launches > 0) {
+        if (tuning >= 0) HIP_OK(hipEventRecord(s->ev0, s->stream), "event record");
+        if (s->options & BP_SERVER_GRAPHS) {
+            if (!s->gexec || s->g_launches != launches || s->g_grid != grid ||
+                s->g_list_off != s->list_off) {
+                if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+                s->gexec = nullptr;
+                hipGraph_t gr = nullptr;
+                HIP_OK(batch_graph_nodes(graphs, s->max_graphs, list, ctl, grid, launches, &gr),
+                       "record batched launches");
+                hipError_t e = hipGraphInstantiate(&s->gexec, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                if (e != hipSuccess) {
+                    s->gexec = nullptr;
+                    return hip_fail(e, "hipGraphInstantiate");
+                }
+                s->g_launches = launches;
+                s->g_grid = grid;
+                s->g_list_off = s->list_off;
+            }
+            HIP_OK(hipGraphLaunch(s->gexec, s->stream), "replay batched launches");
+        } else {
+            for (int k = 0; k < launches; ++k)
+                HIP_OK(launch_eval_batch(graphs, s->max_graphs, list, ctl, grid, s->stream),
+                       "batch evaluation");
+        }
+        if (tuning >= 0) HIP_OK(hipEventRecord(s->ev1, s->stream), "event record");
+        // the device counter advanced once per launch; with nothing resident
+        // neither moves
+        s->launch += launches;
     }
     // poll every resident graph (one gathered readback of the done flags),
     // retire the finished ones
@@ -1599,6 +1743,21 @@ int bp_server_step(bp_server* s, int32_t launches, int32_t* finished) {
                           hipMemcpyDeviceToHost, s->stream),
            "status readback");
     HIP_OK(hipStreamSynchronize(s->stream), "synchronize");
+    if (tuning >= 0) {
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, s->ev0, s->ev1), "event time");
+        s->cand_ns[tuning] = (double)ms * 1e6 / ((double)std::max(1ll, s->resident_msgs) * launches);
+        s->tune_next = tuning + 1;
+        if (s->tune_next == (int)s->cand.size()) {
+            int best = 0;
+            for (int i = 1; i < (int)s->cand.size(); ++i)
+                if (s->cand_ns[i] < s->cand_ns[best]) best = i;
+            s->grid = s->cand[best];
+            s->tuned = 1;
+            s->tuned_msgs = s->resident_msgs;
+            s->tune_next = -1;
+        }
+    }
     bool removed = false;
     for (Request* r : s->slots) {
         if (!r || !r->g) continue;
@@ -1674,10 +1833,28 @@ void bp_server_destroy(bp_server* s) {
             if (kv.second->g) bp_destroy_graph(kv.second->g);
             delete kv.second;
         }
+        if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+        if (s->ev0) (void)hipEventDestroy(s->ev0);
+        if (s->ev1) (void)hipEventDestroy(s->ev1);
         if (s->owns && s->base) (void)hipFree(s->base);
         if (s->h_done) (void)hipHostFree(s->h_done);
     }
     delete s;
+}
+
+int bp_server_config(const bp_server* s, int32_t* grid_blocks, int32_t* tuned,
+                     int32_t* cand_blocks, double* cand_ns_per_msg, int32_t max_entries,
+                     int32_t* entries) {
+    if (!s) return fail(BP_EINVAL, "server is NULL");
+    if (grid_blocks) *grid_blocks = s->grid;
+    if (tuned) *tuned = s->tuned;
+    const int n = std::min<int>((int)s->cand.size(), std::max(0, max_entries));
+    for (int i = 0; i < n; ++i) {
+        if (cand_blocks) cand_blocks[i] = s->cand[i];
+        if (cand_ns_per_msg) cand_ns_per_msg[i] = s->cand_ns[i];
+    }
+    if (entries) *entries = n;
+    return BP_OK;
 }
 
 }  // extern "C"

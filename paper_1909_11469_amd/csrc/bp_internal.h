@@ -133,6 +133,9 @@ struct EvalArgs {
     int tile_nodes_max;         // [E][K] layout: most nodes in one regular tile
     int tile_big;               // [E][K] layout: 1 if some node's slots exceed a tile
     int no_mfma;                // K = 32 shared table on the vector units (not the matrix cores)
+    int mfma_bf16;              // K = 32 shared table: BF16 operands on the matrix cores
+    int hist0;                  // frontier RBP, K = 2 kernel: also count the first radix
+                                // digit of every residual key into st->hist
     unsigned long long rbp_k;   // RBP frontier size
     // sparse re-evaluation (K = 2 log-odds layout, RnBP)
     unsigned char* dirty;       // [N] 1 if a message into the node was committed
@@ -156,9 +159,23 @@ struct BatchGraph {
     int pad;
 };
 
+// Control block of a server's batched launches (device memory): the index of
+// the next launch (read by k_batch_advance, advanced by the evaluation kernel,
+// so that recorded launch sequences can be replayed) and the tile-list length.
+struct BatchCtl {
+    long long launch;
+    int entries;
+    int pad[13];
+};
+
 // Launch wrappers (bp_kernels.hip).  All return the hipError_t of the launch.
-hipError_t launch_eval_batch(BatchGraph* graphs, int num_graphs, const int* list, int num_blocks,
-                             long long launch, hipStream_t s);
+// One batched iteration: k_batch_advance, then the persistent evaluation
+// kernel on `grid` blocks.
+hipError_t launch_eval_batch(BatchGraph* graphs, int num_graphs, const int* list, BatchCtl* ctl,
+                             int grid, hipStream_t s);
+// The same `launches` iterations as a HIP graph of kernel nodes only.
+hipError_t batch_graph_nodes(BatchGraph* graphs, int num_graphs, const int* list, BatchCtl* ctl,
+                             int grid, int launches, hipGraph_t* out);
 hipError_t launch_batch_status(const BatchGraph* graphs, int num_graphs, unsigned int* done,
                                hipStream_t s);
 hipError_t launch_init_state(DevState* st, CounterLine* ctr, hipStream_t s);
@@ -180,9 +197,12 @@ hipError_t launch_sparse_setup(const EvalArgs& a, int build_dst, hipStream_t s);
 hipError_t launch_sparse_rmax(const EvalArgs& a, hipStream_t s);  // R_t after a sparse run
 // frontier residual BP selection
 hipError_t launch_rbp_gate(DevState* st, const CounterLine* ctr, int slot_idx, hipStream_t s);
+// gate_ctr: the counter set of the evaluation (the first scan sets rbp_skip
+// from it), or null when rbp_skip is already set; hist0_done: the evaluation
+// kernel already counted the first digit.
 hipError_t launch_rbp_select(DevState* st, const unsigned int* keys, const int* rev, int E,
-                             unsigned int k, int slot_idx, unsigned int* block_ties,
-                             hipStream_t s);
+                             unsigned int k, const CounterLine* gate_ctr, int hist0_done,
+                             unsigned int* block_ties, hipStream_t s);
 // Extra work of the top-k commit under sparse re-evaluation (on = 0: none):
 // committed slots get residual key 0 and their targets are marked dirty, and
 // the committed slots with residual > eps leave the running count of set `set`.

@@ -442,19 +442,144 @@ __device__ __forceinline__ int block_tile(const EvalArgs& a, int j) {
     return t < a.num_tiles ? t : -1;
 }
 
+// Add 1 to LDS bin `bin` for every lane with `on`.  Residual keys share
+// their leading digits, so most lanes of a wave hit one bin: the lanes whose
+// bin equals the first active lane's are counted by a ballot and one atomic,
+// the rest add individually.
+__device__ __forceinline__ void lds_count(unsigned int* h, unsigned int bin, bool on) {
+    const unsigned long long act = __ballot(on);
+    if (!act) return;
+    const int lead = __ffsll((long long)act) - 1;
+    const unsigned int lb = (unsigned int)__shfl((int)bin, lead, 64);
+    const bool same = on && bin == lb;
+    const unsigned long long sm = __ballot(same);
+    if ((int)(threadIdx.x & 63) == lead) atomicAdd(&h[lb], (unsigned int)__popcll(sm));
+    if (on && !same) atomicAdd(&h[bin], 1u);
+}
+
+// LDS of the K = 2 tile loop.
+struct LogoddsLds {
+    float lam[kTileSlotsLogOdds];
+    unsigned short owner[kTileSlotsLogOdds];
+    unsigned int u[kTileSlotsLogOdds];  // 24-bit uniforms of the slots (RnBP)
+    unsigned short ptr[kTileNodesLogOdds + 1];
+    float L[kTileNodesLogOdds];
+    unsigned int hist[256];             // frontier RBP: first radix digit of the keys
+};
+
+// The software-pipelined tile loop of the K = 2 kernel over a sequence of
+// tiles (seq.valid(j), seq.bounds(j)): while tile j is computed, the loads of
+// tile j + 1 are in flight, so the math of Eq. (2), the residual and the random
+// filter overlap the memory traffic instead of following it.  `cur` holds the
+// graph constants of tile 0 (issued by the caller); iteration j issues the
+// loads of tile j + 1, aggregates tile j (LDS), issues the gathers of tile
+// j + 1, computes and stores tile j, then stages tile j + 1 into LDS, so every
+// wait falls on loads that had a whole phase to complete.
+template <int MODE, class Seq>
+__device__ __forceinline__ void logodds_tile_loop(const EvalArgs& a, const float* __restrict__ m_in,
+                                                  const Seq& seq, TileRegs& cur, int4 bnext,
+                                                  LogoddsLds& l, float& rmax, unsigned int& act,
+                                                  unsigned int& sa, unsigned int& sb) {
+    const OutOff out{a.out_buf[0], a.out_buf[1], a.cand, a.keys};
+    const int tid = threadIdx.x;
+    TileRegs nxt;
+    float lin[kPP];
+    tile_load_msgs(cur, m_in);
+#pragma unroll
+    for (int k = 0; k < kPP; ++k) lin[k] = ld32(m_in, cur.rev[k]);
+    // stage tile 0
+#pragma unroll
+    for (int jj = 0; jj < kPJ; ++jj) {
+        const int v = tid + jj * kBlock;
+        if (v <= cur.nn) l.ptr[v] = (unsigned short)(cur.ptr[jj] - cur.s0);
+        if (v < cur.nn) l.L[v] = cur.u[jj];
+    }
+#pragma unroll
+    for (int k = 0; k < kPP; ++k) {
+        const int q = tid + k * kBlock;
+        if (q < cur.ns) l.lam[q] = lin[k];
+    }
+    for (int j = 0;; ++j) {
+        const bool has_next = seq.valid(j + 1);
+        const int4 bnext2 = seq.valid(j + 2) ? seq.bounds(j + 2) : make_int4(0, 0, 0, 0);
+        if (has_next) tile_load<MODE>(nxt, a, m_in, bnext);
+        lds_barrier();
+        // node aggregates of tile j, incoming messages in slot order; for
+        // RnBP also the draws of the node's messages, four per Philox call
+        for (int v = tid; v < cur.nn; v += kBlock) {
+            const int q0 = l.ptr[v], q1 = l.ptr[v + 1];
+            float L = l.L[v];
+            for (int q = q0; q < q1; ++q) {
+                L += l.lam[q];
+                l.owner[q] = (unsigned short)v;
+            }
+            l.L[v] = L;
+            if (MODE == kModeRnBP) {
+                for (int q = q0; q < q1; q += 4) {
+                    const uint4 w = philox4((unsigned int)(cur.n0 + v), (unsigned int)(q - q0) >> 2,
+                                            a.t, a.key0, a.key1);
+                    l.u[q] = w.x >> 8;
+                    if (q + 1 < q1) l.u[q + 1] = w.y >> 8;
+                    if (q + 2 < q1) l.u[q + 2] = w.z >> 8;
+                    if (q + 3 < q1) l.u[q + 3] = w.w >> 8;
+                }
+            }
+        }
+        lds_barrier();
+        float lin_n[kPP];
+        if (has_next) {
+#pragma unroll
+            for (int k = 0; k < kPP; ++k) lin_n[k] = ld32(m_in, nxt.rev[k]);
+        }
+        // outgoing messages of tile j, written at their own slots
+#pragma unroll
+        for (int k = 0; k < kPP; ++k) {
+            const int q = tid + k * kBlock;
+            float r = 0.0f;
+            if (q < cur.ns) {
+                const int v = l.owner[q];
+                const unsigned int u24 = MODE == kModeRnBP ? l.u[q] : 0u;
+                r = logodds_slot<MODE>(a, out, l.L[v], lin[k], cur.J[k], cur.old[k],
+                                       cur.s0 + q, u24, act, sa, sb);
+                rmax = fmaxf(rmax, r);
+            }
+            // frontier RBP: the first radix digit of the key (top 8 bits)
+            if (MODE == kModeRBP && a.hist0) lds_count(l.hist, __float_as_uint(r) >> 24, q < cur.ns);
+        }
+        if (!has_next) break;
+        lds_barrier();  // tile j's LDS reads are done
+        cur = nxt;
+#pragma unroll
+        for (int k = 0; k < kPP; ++k) lin[k] = lin_n[k];
+#pragma unroll
+        for (int jj = 0; jj < kPJ; ++jj) {
+            const int v = tid + jj * kBlock;
+            if (v <= cur.nn) l.ptr[v] = (unsigned short)(cur.ptr[jj] - cur.s0);
+            if (v < cur.nn) l.L[v] = cur.u[jj];
+        }
+#pragma unroll
+        for (int k = 0; k < kPP; ++k) {
+            const int q = tid + k * kBlock;
+            if (q < cur.ns) l.lam[q] = lin[k];
+        }
+        bnext = bnext2;
+    }
+}
+
+// The tiles of this block's XCD range (tiles are dealt to XCDs in contiguous
+// ranges so that neighbouring tiles share an L2).
+struct XcdTiles {
+    const EvalArgs& a;
+    const int4* tiles;
+    __device__ bool valid(int j) const { return block_tile(a, j) >= 0; }
+    __device__ int4 bounds(int j) const { return tiles[block_tile(a, j)]; }
+};
+
 // K = 2 evaluation kernel.  A persistent grid (as many blocks as are resident)
-// walks the tiles; while a block computes tile j, the loads of tile j + 1 are
-// in flight, so the math of Eq. (2), the residual and the random filter
-// overlaps the memory traffic instead of following it.
+// walks the tiles with the pipelined tile loop.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
-    constexpr int TS = kTileSlotsLogOdds;
-    constexpr int TN = kTileNodesLogOdds;
-    __shared__ float s_lam[TS];
-    __shared__ unsigned short s_owner[TS];
-    __shared__ unsigned int s_u[MODE == kModeRnBP ? TS : 1];  // 24-bit uniforms of the slots
-    __shared__ unsigned short s_ptr[TN + 1];
-    __shared__ float s_L[TN];
+    __shared__ LogoddsLds l;
     __shared__ RedScratch red;
     __shared__ unsigned long long s_red[2];
 
@@ -468,101 +593,24 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
     // so that the two latencies overlap (loads complete in issue order)
     CtrLoad cl;
     prologue_issue(a, cl, blockIdx.x == 0);
-    TileRegs cur, nxt;
+    TileRegs cur;
     tile_load_const<MODE>(cur, a, bcur);
     __builtin_amdgcn_sched_barrier(0);
     const float* m_sel = prologue_finish(a, cl, s_red, blockIdx.x == 0);
     if (!m_sel) return;
     const float* __restrict__ m_in = uniform_ptr(m_sel);
-    const OutOff out{a.out_buf[0], a.out_buf[1], a.cand, a.keys};
-    const int tid = threadIdx.x;
     float rmax = 0.0f;
     unsigned int act = 0, sa = 0, sb = 0;
-
-    if (t0 >= 0) {
-        // Software pipeline over this block's tiles.  Iteration j: issue the
-        // loads of tile j+1, aggregate tile j (LDS), issue the gathers of tile
-        // j+1, compute and store tile j, then stage tile j+1 into LDS.  Every
-        // wait therefore falls on loads that had a whole phase to complete.
-        float lin[kPP];
-        tile_load_msgs(cur, m_in);
-#pragma unroll
-        for (int k = 0; k < kPP; ++k) lin[k] = ld32(m_in, cur.rev[k]);
-        // stage tile 0
-#pragma unroll
-        for (int jj = 0; jj < kPJ; ++jj) {
-            const int v = tid + jj * kBlock;
-            if (v <= cur.nn) s_ptr[v] = (unsigned short)(cur.ptr[jj] - cur.s0);
-            if (v < cur.nn) s_L[v] = cur.u[jj];
-        }
-#pragma unroll
-        for (int k = 0; k < kPP; ++k) {
-            const int q = tid + k * kBlock;
-            if (q < cur.ns) s_lam[q] = lin[k];
-        }
-        for (int j = 0;; ++j) {
-            const bool has_next = block_tile(a, j + 1) >= 0;
-            const int t2 = block_tile(a, j + 2);
-            const int4 bnext2 = t2 >= 0 ? tiles[t2] : make_int4(0, 0, 0, 0);
-            if (has_next) tile_load<MODE>(nxt, a, m_in, bnext);
-            lds_barrier();
-            // node aggregates of tile j, incoming messages in slot order; for
-            // RnBP also the draws of the node's messages, four per Philox call
-            for (int v = tid; v < cur.nn; v += kBlock) {
-                const int q0 = s_ptr[v], q1 = s_ptr[v + 1];
-                float L = s_L[v];
-                for (int q = q0; q < q1; ++q) {
-                    L += s_lam[q];
-                    s_owner[q] = (unsigned short)v;
-                }
-                s_L[v] = L;
-                if (MODE == kModeRnBP) {
-                    for (int q = q0; q < q1; q += 4) {
-                        const uint4 w = philox4((unsigned int)(cur.n0 + v), (unsigned int)(q - q0) >> 2,
-                                                a.t, a.key0, a.key1);
-                        s_u[q] = w.x >> 8;
-                        if (q + 1 < q1) s_u[q + 1] = w.y >> 8;
-                        if (q + 2 < q1) s_u[q + 2] = w.z >> 8;
-                        if (q + 3 < q1) s_u[q + 3] = w.w >> 8;
-                    }
-                }
-            }
-            lds_barrier();
-            float lin_n[kPP];
-            if (has_next) {
-#pragma unroll
-                for (int k = 0; k < kPP; ++k) lin_n[k] = ld32(m_in, nxt.rev[k]);
-            }
-            // outgoing messages of tile j, written at their own slots
-#pragma unroll
-            for (int k = 0; k < kPP; ++k) {
-                const int q = tid + k * kBlock;
-                if (q < cur.ns) {
-                    const int v = s_owner[q];
-                    const unsigned int u24 = MODE == kModeRnBP ? s_u[q] : 0u;
-                    const float r = logodds_slot<MODE>(a, out, s_L[v], lin[k], cur.J[k], cur.old[k],
-                                                       cur.s0 + q, u24, act, sa, sb);
-                    rmax = fmaxf(rmax, r);
-                }
-            }
-            if (!has_next) break;
-            lds_barrier();  // tile j's LDS reads are done
-            cur = nxt;
-#pragma unroll
-            for (int k = 0; k < kPP; ++k) lin[k] = lin_n[k];
-#pragma unroll
-            for (int jj = 0; jj < kPJ; ++jj) {
-                const int v = tid + jj * kBlock;
-                if (v <= cur.nn) s_ptr[v] = (unsigned short)(cur.ptr[jj] - cur.s0);
-                if (v < cur.nn) s_L[v] = cur.u[jj];
-            }
-#pragma unroll
-            for (int k = 0; k < kPP; ++k) {
-                const int q = tid + k * kBlock;
-                if (q < cur.ns) s_lam[q] = lin[k];
-            }
-            bnext = bnext2;
-        }
+    const bool hist = MODE == kModeRBP && a.hist0;
+    if (hist)
+        for (int i = threadIdx.x; i < 256; i += kBlock) l.hist[i] = 0u;  // seen after the loop's barriers
+    if (t0 >= 0) logodds_tile_loop<MODE>(a, m_in, XcdTiles{a, tiles}, cur, bnext, l, rmax, act, sa, sb);
+    if (hist) {
+        // the block's digit counts into one of the copies of the global histogram
+        lds_barrier();
+        unsigned int* gh = &a.st->hist[blockIdx.x & 15][0];
+        for (int i = threadIdx.x; i < 256; i += kBlock)
+            if (l.hist[i]) atomicAdd(&gh[i], l.hist[i]);
     }
     block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
 }
@@ -612,76 +660,26 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds_big(EvalArgs a) {
 
 // ---------------------------------------------------------------------------
 // Batched evaluation for serving: one launch evaluates one iteration of every
-// graph of a batch.  Each block takes one tile (or one oversized node) of one
-// graph; the graph's arguments live in device memory and its iteration number
-// is the launch index minus the launch of its first evaluation, so graphs
-// admitted at different times advance independently, each exactly as bp_run
-// would advance it alone (same tiles, same per-slot arithmetic, per-graph
-// counters and random keys).
+// graph of a batch.  The graph's arguments live in device memory and its
+// iteration number is the launch index minus the launch of its first
+// evaluation, so graphs admitted at different times advance independently,
+// each exactly as bp_run would advance it alone (same tiles, same per-slot
+// arithmetic, per-graph counters and random keys).  The launch index is a
+// device counter (BatchCtl), so a sequence of launches can be recorded once in
+// a HIP graph and replayed.
+//
+// The grid is persistent: block b takes a contiguous range of the tile list
+// (entries of one graph are contiguous, regular tiles first), splits it into
+// runs of one graph, and runs each graph's regular tiles through the same
+// software-pipelined tile loop as bp_run's kernel, then its oversized nodes.
 // ---------------------------------------------------------------------------
-template <int MODE>
-__device__ __forceinline__ void logodds_tile_once(const EvalArgs& a, const float* __restrict__ m_in,
-                                                  int4 b, float* s_lam, unsigned short* s_owner,
-                                                  unsigned int* s_u, unsigned short* s_ptr,
-                                                  float* s_L, float& rmax, unsigned int& act,
-                                                  unsigned int& sa, unsigned int& sb) {
-    const int tid = threadIdx.x;
-    const OutOff out{a.out_buf[0], a.out_buf[1], a.cand, a.keys};
-    TileRegs cur;
-    tile_load<MODE>(cur, a, m_in, b);
-    float lin[kPP];
-#pragma unroll
-    for (int k = 0; k < kPP; ++k) lin[k] = ld32(m_in, cur.rev[k]);
-#pragma unroll
-    for (int jj = 0; jj < kPJ; ++jj) {
-        const int v = tid + jj * kBlock;
-        if (v <= cur.nn) s_ptr[v] = (unsigned short)(cur.ptr[jj] - cur.s0);
-        if (v < cur.nn) s_L[v] = cur.u[jj];
-    }
-#pragma unroll
-    for (int k = 0; k < kPP; ++k) {
-        const int q = tid + k * kBlock;
-        if (q < cur.ns) s_lam[q] = lin[k];
-    }
-    lds_barrier();
-    for (int v = tid; v < cur.nn; v += kBlock) {
-        const int q0 = s_ptr[v], q1 = s_ptr[v + 1];
-        float L = s_L[v];
-        for (int q = q0; q < q1; ++q) {
-            L += s_lam[q];
-            s_owner[q] = (unsigned short)v;
-        }
-        s_L[v] = L;
-        if (MODE == kModeRnBP) {
-            for (int q = q0; q < q1; q += 4) {
-                const uint4 w = philox4((unsigned int)(cur.n0 + v), (unsigned int)(q - q0) >> 2, a.t,
-                                        a.key0, a.key1);
-                s_u[q] = w.x >> 8;
-                if (q + 1 < q1) s_u[q + 1] = w.y >> 8;
-                if (q + 2 < q1) s_u[q + 2] = w.z >> 8;
-                if (q + 3 < q1) s_u[q + 3] = w.w >> 8;
-            }
-        }
-    }
-    lds_barrier();
-#pragma unroll
-    for (int k = 0; k < kPP; ++k) {
-        const int q = tid + k * kBlock;
-        if (q < cur.ns) {
-            const int v = s_owner[q];
-            const unsigned int u24 = MODE == kModeRnBP ? s_u[q] : 0u;
-            const float r = logodds_slot<MODE>(a, out, s_L[v], lin[k], cur.J[k], cur.old[k],
-                                               cur.s0 + q, u24, act, sa, sb);
-            rmax = fmaxf(rmax, r);
-        }
-    }
-}
 
 // Before each batched launch: the per-launch fields of every graph's
 // arguments, as bp_run sets them for its iteration `it`.
-__global__ void k_batch_advance(BatchGraph* graphs, int num_graphs, long long launch) {
+__global__ void k_batch_advance(BatchGraph* graphs, int num_graphs, const BatchCtl* ctl) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= num_graphs) return;
+    const long long launch = ctl->launch;
     BatchGraph& G = graphs[g];
     const long long it = launch - G.first;
     G.skip = (it < 0 || it > G.max_iters) ? 1 : 0;
@@ -698,47 +696,75 @@ __global__ void k_batch_advance(BatchGraph* graphs, int num_graphs, long long la
     G.mode_now = it == G.max_iters ? kModeEvalOnly : G.mode;
 }
 
+// The regular tiles of one graph's run of list entries.
+struct ListTiles {
+    const int4* tiles;
+    const int4* list;
+    int e0, n;
+    __device__ bool valid(int j) const { return j < n; }
+    __device__ int4 bounds(int j) const { return tiles[list[e0 + j].y]; }
+};
+
+template <int MODE>
+__device__ __forceinline__ void batch_run(const EvalArgs& a, const float* __restrict__ m_in,
+                                          const int4* __restrict__ list, int e0, int nreg, int e1,
+                                          LogoddsLds& l, float* s_part, float& rmax,
+                                          unsigned int& act, unsigned int& sa, unsigned int& sb) {
+    if (nreg > 0) {
+        const ListTiles seq{(const int4*)a.tiles4, list, e0, nreg};
+        TileRegs cur;
+        tile_load_const<MODE>(cur, a, seq.bounds(0));
+        const int4 bnext = nreg > 1 ? seq.bounds(1) : make_int4(0, 0, 0, 0);
+        logodds_tile_loop<MODE>(a, m_in, seq, cur, bnext, l, rmax, act, sa, sb);
+    }
+    for (int e = e0 + nreg; e < e1; ++e) {
+        const int4 b = ((const int4*)a.big4)[list[e].y];
+        logodds_big_node<MODE>(a, m_in, b, s_part, rmax, act, sa, sb);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_eval_batch(const BatchGraph* __restrict__ graphs,
-                                                       const int4* __restrict__ list) {
-    constexpr int TS = kTileSlotsLogOdds;
-    constexpr int TN = kTileNodesLogOdds;
-    __shared__ float s_lam[TS];
-    __shared__ unsigned short s_owner[TS];
-    __shared__ unsigned int s_u[TS];
-    __shared__ unsigned short s_ptr[TN + 1];
-    __shared__ float s_L[TN];
+                                                       const int4* __restrict__ list,
+                                                       BatchCtl* ctl) {
+    __shared__ LogoddsLds l;
     __shared__ float s_part[kBlock / 64];
     __shared__ RedScratch red;
     __shared__ unsigned long long s_red[2];
-    const int4 ent = list[blockIdx.x];  // {graph, tile, oversized node?, 0}
-    const BatchGraph& G = graphs[ent.x];
-    if (G.skip) return;  // not admitted yet, or finished
-    const EvalArgs& a = G.a;
-    const int mode = G.mode_now;
-    const float* m_sel = iteration_prologue(a, s_red, ent.z == 0 && ent.y == 0);
-    if (!m_sel) return;
-    const float* __restrict__ m_in = uniform_ptr(m_sel);
-    float rmax = 0.0f;
-    unsigned int act = 0, sa = 0, sb = 0;
-    const int4 b = ent.z ? ((const int4*)a.big4)[ent.y] : ((const int4*)a.tiles4)[ent.y];
-    if (ent.z) {
-        if (mode == kModeLBP)
-            logodds_big_node<kModeLBP>(a, m_in, b, s_part, rmax, act, sa, sb);
-        else if (mode == kModeRnBP)
-            logodds_big_node<kModeRnBP>(a, m_in, b, s_part, rmax, act, sa, sb);
-        else
-            logodds_big_node<kModeEvalOnly>(a, m_in, b, s_part, rmax, act, sa, sb);
-    } else {
-        if (mode == kModeLBP)
-            logodds_tile_once<kModeLBP>(a, m_in, b, s_lam, s_owner, s_u, s_ptr, s_L, rmax, act, sa, sb);
-        else if (mode == kModeRnBP)
-            logodds_tile_once<kModeRnBP>(a, m_in, b, s_lam, s_owner, s_u, s_ptr, s_L, rmax, act, sa,
-                                         sb);
-        else
-            logodds_tile_once<kModeEvalOnly>(a, m_in, b, s_lam, s_owner, s_u, s_ptr, s_L, rmax, act,
-                                             sa, sb);
+    // the next launch's index (k_batch_advance of this launch has read it)
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->launch += 1;
+    const int n = ctl->entries;
+    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+    int e = (int)blockIdx.x * per;
+    const int e_end = min(n, e + per);
+    while (e < e_end) {
+        const int4 ent = list[e];  // {graph slot, tile, oversized node?, 0}
+        int f = e + 1;
+        while (f < e_end && list[f].x == ent.x) ++f;
+        int r1 = e;
+        while (r1 < f && list[r1].z == 0) ++r1;
+        const BatchGraph& G = graphs[ent.x];
+        if (!G.skip) {  // not admitted yet, or finished
+            const EvalArgs& a = G.a;
+            // the block holding the graph's first tile closes its previous iteration
+            const float* m_sel = iteration_prologue(a, s_red, ent.z == 0 && ent.y == 0);
+            if (m_sel) {
+                const float* __restrict__ m_in = uniform_ptr(m_sel);
+                float rmax = 0.0f;
+                unsigned int act = 0, sa = 0, sb = 0;
+                const int mode = G.mode_now;
+                if (mode == kModeLBP)
+                    batch_run<kModeLBP>(a, m_in, list, e, r1 - e, f, l, s_part, rmax, act, sa, sb);
+                else if (mode == kModeRnBP)
+                    batch_run<kModeRnBP>(a, m_in, list, e, r1 - e, f, l, s_part, rmax, act, sa, sb);
+                else
+                    batch_run<kModeEvalOnly>(a, m_in, list, e, r1 - e, f, l, s_part, rmax, act, sa,
+                                             sb);
+                block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
+            }
+        }
+        lds_barrier();  // the run's LDS (and s_red) is free for the next run
+        e = f;
     }
-    block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
 }
 
 // ---------------------------------------------------------------------------
@@ -912,6 +938,13 @@ __device__ __forceinline__ void slot_update_split(const EvalArgs& a, const float
 }
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bit pattern, round to nearest even (finite inputs).
+__device__ __forceinline__ short bf16_rne(float f) {
+    const unsigned int b = __float_as_uint(f);
+    return (short)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
 
 // Eq. (2) for K = 32 with one symmetric shared table on the matrix cores.  Each
 // wave takes 32 slots of the tile; the products c = g P of its slots are one
@@ -923,9 +956,28 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // for the states x = 2 s + h, holds column m of the table for those states,
 // and after the product the tile goes through LDS (rows of 33 floats) back to
 // one slot per lane pair, each lane with 16 consecutive states of its slot.
-template <int MODE>
-__device__ __forceinline__ void slot_update_mfma32(const EvalArgs& a, const float* __restrict__ m_in,
-                                                   float* s_logm, const float* s_A,
+// BF16: the same product with BF16 operands (v_mfma_f32_32x32x8_bf16, FP32
+// accumulation): 4 steps of 8 states, lane (m, h) supplying the states
+// 8 s + 4 h .. 8 s + 4 h + 3; g and the table are rounded to 8-bit mantissas.
+// The lane's operand entry st of the product covers state mfma32_state(st).
+template <bool BF16>
+__device__ __forceinline__ int mfma32_state(int st, int h) {
+    return BF16 ? 8 * (st >> 2) + 4 * h + (st & 3) : 2 * st + h;
+}
+
+// B operand of the lane: P[x][m] for its 16 states (loaded once per block).
+template <bool BF16>
+__device__ __forceinline__ void mfma32_table(const EvalArgs& a, float* pb) {
+    const int lane = threadIdx.x & 63, m = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int st = 0; st < 16; ++st) pb[st] = a.pair[mfma32_state<BF16>(st, h) * 32 + m];
+}
+
+// old: the lane's 16 states of its slot's current row (issued by the caller).
+template <int MODE, bool BF16 = false>
+__device__ __forceinline__ void slot_update_mfma32(const EvalArgs& a, const float* pb,
+                                                   const float* old, float* s_logm,
+                                                   const float* s_A,
                                                    const unsigned short* s_owner, int s0,
                                                    int n0, int ns, float& rmax,
                                                    unsigned int& act, unsigned int& sa,
@@ -935,17 +987,14 @@ __device__ __forceinline__ void slot_update_mfma32(const EvalArgs& a, const floa
     const int m = lane & 31, h = lane >> 5;
     const int q = 32 * w + m;  // slot of the tile
     const bool valid = q < ns;
-    // B operand: P[2 s + h][m]
-    float pb[16];
-#pragma unroll
-    for (int st = 0; st < 16; ++st) pb[st] = a.pair[(2 * st + h) * K + m];
-    // A operand: the cavity distribution of slot q at the states 2 s + h
+    auto state = [&](int st) { return mfma32_state<BF16>(st, h); };
+    // A operand: the cavity distribution of slot q at the lane's states
     const int v = valid ? s_owner[q] : 0;
     float gv[16];
     float mx = -3.402823466e38f;
 #pragma unroll
     for (int st = 0; st < 16; ++st) {
-        const int x = 2 * st + h;
+        const int x = state(st);
         gv[st] = valid ? s_A[v * KS + x] - s_logm[q * KS + x] : 0.0f;
         mx = fmaxf(mx, gv[st]);
     }
@@ -955,8 +1004,20 @@ __device__ __forceinline__ void slot_update_mfma32(const EvalArgs& a, const floa
     floatx16 d;
 #pragma unroll
     for (int r = 0; r < 16; ++r) d[r] = 0.0f;
+    if (BF16) {
 #pragma unroll
-    for (int st = 0; st < 16; ++st) d = __builtin_amdgcn_mfma_f32_32x32x2f32(gv[st], pb[st], d, 0, 0, 0);
+        for (int st = 0; st < 4; ++st) {
+            const shortx4 ga = {bf16_rne(gv[4 * st]), bf16_rne(gv[4 * st + 1]), bf16_rne(gv[4 * st + 2]),
+                                bf16_rne(gv[4 * st + 3])};
+            const shortx4 pbb = {bf16_rne(pb[4 * st]), bf16_rne(pb[4 * st + 1]), bf16_rne(pb[4 * st + 2]),
+                                 bf16_rne(pb[4 * st + 3])};
+            d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ga, pbb, d, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int st = 0; st < 16; ++st)
+            d = __builtin_amdgcn_mfma_f32_32x32x2f32(gv[st], pb[st], d, 0, 0, 0);
+    }
     // D[i][m] -> LDS row 32 w + i (the wave's own rows of the log buffer, which
     // its lanes have finished reading: LDS operations of a wave run in order)
     float* rows = s_logm + (32 * w) * KS;
@@ -975,15 +1036,6 @@ __device__ __forceinline__ void slot_update_mfma32(const EvalArgs& a, const floa
     const float inv = 1.0f / z;
     const int sl = s0 + q;
     const long long eo = (long long)sl * K + 16 * h;
-    float old[16];
-#pragma unroll
-    for (int t4 = 0; t4 < 4; ++t4) {
-        const float4 o4 = *(const float4*)(m_in + eo + 4 * t4);
-        old[4 * t4] = o4.x;
-        old[4 * t4 + 1] = o4.y;
-        old[4 * t4 + 2] = o4.z;
-        old[4 * t4 + 3] = o4.w;
-    }
     float r = 0.0f;
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
@@ -1132,7 +1184,11 @@ __device__ __forceinline__ void generic_phase1(const EvalArgs& a, const float* _
 // K = 32 with a symmetric shared table and no oversized node: Eq. (2) on the
 // matrix cores (slot_update_mfma32).  A kernel of its own, so that its register
 // count (and hence its occupancy) is not set by the paths it does not take.
-template <int MODE>
+// A block per tile; the table columns and the lane's own row are loaded at the
+// start, so that they arrive while the incoming rows are gathered and
+// aggregated.  (A persistent variant that pipelined several tiles per block
+// ran slower: its register and LDS footprint halved the resident blocks.)
+template <int MODE, bool BF16>
 __global__ __launch_bounds__(kBlock) void k_eval_mfma32(EvalArgs a) {
     extern __shared__ float smem[];
     __shared__ RedScratch red;
@@ -1146,10 +1202,28 @@ __global__ __launch_bounds__(kBlock) void k_eval_mfma32(EvalArgs a) {
     const GenericLds l = generic_lds(smem, K, TS, a.tile_nodes_max, false);
     const int n0 = a.tile_start[tile], n1 = a.tile_start[tile + 1];
     const int s0 = a.tile_slot[tile], s1 = a.tile_slot[tile + 1];
-    generic_phase1(a, m_in, l, K, n0, n1 - n0, s0, s1 - s0);
+    const int ns = s1 - s0;
+    float pb[16];
+    mfma32_table<BF16>(a, pb);
+    float old[16];
+    {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int q = 32 * w + (lane & 31);
+        const long long eo = (long long)(s0 + min(q, max(ns - 1, 0))) * K + 16 * (lane >> 5);
+#pragma unroll
+        for (int t4 = 0; t4 < 4; ++t4) {
+            const float4 o4 = *(const float4*)(m_in + eo + 4 * t4);
+            old[4 * t4] = o4.x;
+            old[4 * t4 + 1] = o4.y;
+            old[4 * t4 + 2] = o4.z;
+            old[4 * t4 + 3] = o4.w;
+        }
+    }
+    generic_phase1(a, m_in, l, K, n0, n1 - n0, s0, ns);
     float rmax = 0.0f;
     unsigned int act = 0, sa = 0, sb = 0;
-    slot_update_mfma32<MODE>(a, m_in, l.logm, l.A, l.owner, s0, n0, s1 - s0, rmax, act, sa, sb);
+    slot_update_mfma32<MODE, BF16>(a, pb, old, l.logm, l.A, l.owner, s0, n0, ns, rmax, act, sa,
+                                   sb);
     block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
 }
 
@@ -1397,11 +1471,15 @@ __global__ void k_marginals_generic(const int* node_ptr, const int* rev, const f
 // the vector units take it and the kernel is bound by the table traffic.
 //
 // One wave per source variable (grid-stride): lane x holds the aggregate of
-// states x and x + 64 (K_i <= 128); then, per outgoing slot, the cavity
-// g(x_i) = exp(A(x_i) - log m_{j->i}(x_i) - max), the product with the table
-// (lane y computes states y and y + 64 of the target, reading one table row
-// per source state, contiguous across lanes), normalisation, the L-infinity
-// residual and the frontier rule, all as wave-wide shuffles and reductions.
+// states x and x + 64 (K_i <= 128); the cavity of each outgoing slot,
+// g(x_i) = exp(A(x_i) - log m_{j->i}(x_i) - max), goes to LDS.  Then every
+// (slot, target state) pair of the variable gets a lane, which takes the
+// product with its slot's table as a chain of fused multiply-adds over the
+// source states (the table entries of consecutive lanes are contiguous; a lane
+// runs four pairs together, 32 loads in flight); a lane per slot forms the normalisation, the
+// L-infinity residual and the frontier decision, and the pair lanes store the
+// committed values.  A variable whose slots do not fit the wave's LDS goes slot
+// by slot, lanes over states, with wave-wide shuffles and reductions.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float wave_max_f(float v) {
 #pragma unroll
@@ -1414,24 +1492,189 @@ __device__ __forceinline__ float wave_sum_f(float v) {
     return v;
 }
 
+// Wave-local LDS hand-off: this wave's LDS stores are complete and visible to
+// its other lanes (a wave executes its LDS operations in order).
+__device__ __forceinline__ void wave_lds_sync() { __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// LDS per wave of the flat path: the cavity vectors of one variable's slots,
+// and its slots' outputs (entries), each at most kRaggedFlat floats.
+constexpr int kRaggedFlat = 1024;
+constexpr int kRaggedMaxDeg = 64;
+
+template <int MODE>
+__device__ __forceinline__ void ragged_commit(const EvalArgs& a, int q, float v, float old, bool ka,
+                                              bool kb) {
+    if (MODE == kModeLBP) {
+        a.out_buf[0][q] = v;
+    } else if (MODE == kModeRnBP) {
+        a.out_buf[0][q] = ka ? v : old;
+        if (a.two_outputs) a.out_buf[1][q] = kb ? v : old;
+    } else if (MODE == kModeRBP) {
+        a.cand[q] = v;
+    }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_eval_ragged(EvalArgs a) {
     __shared__ RedScratch red;
     __shared__ unsigned long long s_red[2];
+    __shared__ float s_g[kBlock / 64][kRaggedFlat];    // cavity vectors, slot-major
+    __shared__ float s_c[kBlock / 64][kRaggedFlat];    // outputs of the variable's slots
+    __shared__ int s_off[kBlock / 64][kRaggedMaxDeg + 1];
+    __shared__ int s_rin[kBlock / 64][kRaggedMaxDeg];    // row of the message into the variable
+    __shared__ int s_toff[kBlock / 64][kRaggedMaxDeg];   // table of the slot
+    __shared__ float s_inv[kBlock / 64][kRaggedMaxDeg];
+    __shared__ unsigned int s_keep[kBlock / 64][kRaggedMaxDeg];
     const float* __restrict__ m_in = iteration_prologue(a, s_red, blockIdx.x == 0);
     if (!m_in) return;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    float* G = s_g[w];
+    float* Cv = s_c[w];
+    int* off = s_off[w];
     const int waves = (int)(gridDim.x * (blockDim.x >> 6));
     float rmax = 0.0f;
     unsigned int act = 0, sa = 0, sb = 0;
-    for (int i = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); i < a.num_nodes;
-         i += waves) {
+    for (int i = (int)(blockIdx.x * (blockDim.x >> 6) + w); i < a.num_nodes; i += waves) {
         const int Ki = a.kv[i];
         const int s0 = a.node_ptr[i], s1 = a.node_ptr[i + 1];
+        const int deg = s1 - s0;
         const float* U = a.unary + a.uoff[i];
         const float fK = (float)Ki;  // log(K_i m) keeps the aggregate near zero
         const bool x0 = lane < Ki, x1 = lane + 64 < Ki;
         float A0 = x0 ? U[lane] : 0.0f, A1 = x1 ? U[lane + 64] : 0.0f;
+        const int mo0 = a.moff[s0];
+        const int P = a.moff[s1] - mo0;  // outputs of all slots of the variable
+        if (deg <= kRaggedMaxDeg && deg * Ki <= kRaggedFlat && P <= kRaggedFlat) {
+            // Flat path.  A lane per slot fetches the slot's offsets (all in
+            // flight at once); the incoming rows are loaded eight slots at a
+            // time and their logs kept in LDS for the cavities; then the
+            // outputs of all slots at once (a lane per (slot, target state)
+            // pair), the per-slot sums, residuals and frontier decisions (a
+            // lane per slot), and the stores.
+            for (int k = lane; k < deg; k += 64) {
+                s_rin[w][k] = a.moff[a.rev[s0 + k]];
+                s_toff[w][k] = a.toff[s0 + k];
+                off[k] = a.moff[s0 + k] - mo0;
+            }
+            if (lane == 0) off[deg] = P;
+            wave_lds_sync();
+            for (int k0 = 0; k0 < deg; k0 += 8) {
+                float v0[8], v1[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int k = min(k0 + j, deg - 1);
+                    const int rin = s_rin[w][k];
+                    v0[j] = x0 ? m_in[rin + lane] : 1.0f;
+                    v1[j] = x1 ? m_in[rin + lane + 64] : 1.0f;
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (k0 + j >= deg) break;
+                    const float l0 = logf(fK * v0[j]), l1 = logf(fK * v1[j]);
+                    if (x0) {
+                        A0 += l0;
+                        G[(k0 + j) * Ki + lane] = l0;
+                    }
+                    if (x1) {
+                        A1 += l1;
+                        G[(k0 + j) * Ki + lane + 64] = l1;
+                    }
+                }
+            }
+            wave_lds_sync();
+            for (int k = 0; k < deg; ++k) {
+                const float c0 = x0 ? A0 - G[k * Ki + lane] : -INFINITY;
+                const float c1 = x1 ? A1 - G[k * Ki + lane + 64] : -INFINITY;
+                const float mx = wave_max_f(fmaxf(c0, c1));
+                if (x0) G[k * Ki + lane] = expf(c0 - mx);
+                if (x1) G[k * Ki + lane + 64] = expf(c1 - mx);
+            }
+            wave_lds_sync();
+            // up to four pairs per lane at once (p, p + 64, p + 128, p + 192):
+            // their table loads are independent, so 4 x 8 are in flight
+            for (int pb = 0; pb < P; pb += 256) {
+                const float* T[4];
+                const float* g[4];
+                int Kj[4];
+                bool on[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int p = pb + lane + 64 * j;
+                    on[j] = p < P;
+                    const int pp = on[j] ? p : P - 1;
+                    int k = 0;
+                    while (off[k + 1] <= pp) ++k;
+                    Kj[j] = off[k + 1] - off[k];
+                    T[j] = a.pair + s_toff[w][k] + (pp - off[k]);
+                    g[j] = G + k * Ki;
+                }
+                float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                int x = 0;
+                for (; x + 8 <= Ki; x += 8) {
+                    float tv[4][8];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) tv[j][u] = T[j][(x + u) * Kj[j]];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) acc[j] = fmaf(tv[j][u], g[j][x + u], acc[j]);
+                }
+                for (; x < Ki; ++x)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[j] = fmaf(T[j][x * Kj[j]], g[j][x], acc[j]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (on[j]) Cv[pb + lane + 64 * j] = acc[j];
+            }
+            wave_lds_sync();
+            for (int k = lane; k < deg; k += 64) {
+                float z = 0.0f;
+                for (int q = off[k]; q < off[k + 1]; ++q) z += Cv[q];
+                s_inv[w][k] = 1.0f / z;
+            }
+            wave_lds_sync();
+            // normalised outputs back into Cv, |change| into G (cavities are done)
+            for (int p = lane; p < P; p += 64) {
+                int k = 0;
+                while (off[k + 1] <= p) ++k;
+                const float v = Cv[p] * s_inv[w][k];
+                Cv[p] = v;
+                G[p] = fabsf(v - m_in[mo0 + p]);
+            }
+            wave_lds_sync();
+            for (int k = lane; k < deg; k += 64) {
+                float r = 0.0f;
+                for (int q = off[k]; q < off[k + 1]; ++q) r = fmaxf(r, G[q]);
+                const bool active = r > a.eps;
+                bool ka = false, kb = false;
+                if (MODE == kModeRnBP && active) {
+                    const unsigned int u24 = draw24(a, i, k);
+                    ka = u24 < a.thr_a;
+                    kb = u24 < a.thr_b;
+                }
+                if (MODE == kModeRBP) a.keys[s0 + k] = __float_as_uint(r);
+                s_keep[w][k] = (ka ? 1u : 0u) | (kb ? 2u : 0u);
+                act += active;
+                sa += ka;
+                sb += kb;
+                rmax = fmaxf(rmax, r);
+            }
+            wave_lds_sync();
+            for (int p = lane; p < P; p += 64) {
+                int k = 0;
+                while (off[k + 1] <= p) ++k;
+                const unsigned int kp = s_keep[w][k];
+                const float old = MODE == kModeRnBP ? m_in[mo0 + p] : 0.0f;
+                ragged_commit<MODE>(a, mo0 + p, Cv[p], old, kp & 1u, kp & 2u);
+            }
+            wave_lds_sync();  // the wave's LDS is free for its next variable
+            continue;
+        }
+        // Slot by slot (a variable whose slots do not fit the flat path): lanes
+        // over source states for the aggregate and the cavity, over target
+        // states for the output.
         for (int s = s0; s < s1; ++s) {
             const int rin = a.moff[a.rev[s]];
             if (x0) A0 += logf(fK * m_in[rin + lane]);
@@ -1461,33 +1704,19 @@ __global__ __launch_bounds__(kBlock) void k_eval_ragged(EvalArgs a) {
             const float r = wave_max_f(fmaxf(y0 ? fabsf(o0 - old0) : 0.0f,
                                              y1 ? fabsf(o1 - old1) : 0.0f));
             const bool active = r > a.eps;
-            if (MODE == kModeLBP) {
-                if (y0) a.out_buf[0][mo + lane] = o0;
-                if (y1) a.out_buf[0][mo + lane + 64] = o1;
-            } else if (MODE == kModeRnBP) {
-                bool ka = false, kb = false;
-                if (active) {
-                    const unsigned int u24 = draw24(a, i, s - s0);
-                    ka = u24 < a.thr_a;
-                    kb = u24 < a.thr_b;
-                }
-                if (y0) a.out_buf[0][mo + lane] = ka ? o0 : old0;
-                if (y1) a.out_buf[0][mo + lane + 64] = ka ? o1 : old1;
-                if (a.two_outputs) {
-                    if (y0) a.out_buf[1][mo + lane] = kb ? o0 : old0;
-                    if (y1) a.out_buf[1][mo + lane + 64] = kb ? o1 : old1;
-                }
-                if (lane == 0) {
-                    sa += ka;
-                    sb += kb;
-                }
-            } else if (MODE == kModeRBP) {
-                if (y0) a.cand[mo + lane] = o0;
-                if (y1) a.cand[mo + lane + 64] = o1;
-                if (lane == 0) a.keys[s] = __float_as_uint(r);
+            bool ka = false, kb = false;
+            if (MODE == kModeRnBP && active) {
+                const unsigned int u24 = draw24(a, i, s - s0);
+                ka = u24 < a.thr_a;
+                kb = u24 < a.thr_b;
             }
+            if (y0) ragged_commit<MODE>(a, mo + lane, o0, old0, ka, kb);
+            if (y1) ragged_commit<MODE>(a, mo + lane + 64, o1, old1, ka, kb);
             if (lane == 0) {
+                if (MODE == kModeRBP) a.keys[s] = __float_as_uint(r);
                 act += active;
+                sa += ka;
+                sb += kb;
                 rmax = fmaxf(rmax, r);
             }
         }
@@ -1861,52 +2090,40 @@ __device__ __forceinline__ void sel_load16(const T* base, long long q0, long lon
     }
 }
 
-// Add 1 to LDS bin `bin` for every lane with `on`.  Residual keys share
-// their leading digits, so most lanes of a wave hit one bin: the lanes whose
-// bin equals the first active lane's are counted by a ballot and one atomic,
-// the rest add individually.
-__device__ __forceinline__ void lds_count(unsigned int* h, unsigned int bin, bool on) {
-    const unsigned long long act = __ballot(on);
-    if (!act) return;
-    const int lead = __ffsll((long long)act) - 1;
-    const unsigned int lb = (unsigned int)__shfl((int)bin, lead, 64);
-    const bool same = on && bin == lb;
-    const unsigned long long sm = __ballot(same);
-    if ((int)(threadIdx.x & 63) == lead) atomicAdd(&h[lb], (unsigned int)__popcll(sm));
-    if (on && !same) atomicAdd(&h[bin], 1u);
-}
-
 // One pass of the radix select: histogram of digit `pass` (8 bits, from the
 // top) of the keys that match the prefix fixed so far, added into one of
 // kHistCopies copies of the global histogram (by block index) so that blocks
 // do not queue on one address.
-__global__ __launch_bounds__(kSelBlock) void k_rbp_hist(DevState* st, const unsigned int* keys,
-                                                        int E, int pass, unsigned int* ghist) {
-    __shared__ unsigned int h[256];
-    if (st->rbp_skip) return;
+// Digit histogram of pass `pass` (8 bits from the top) of the keys matching
+// the prefix fixed so far, over the chunks of kCommitChunk keys this block
+// takes (grid-stride), added into one of kHistCopies copies of the global
+// histogram (by block index) so that blocks do not queue on one address.
+__device__ __forceinline__ void rbp_hist_block(const DevState* st, const unsigned int* keys, int E,
+                                               int pass, unsigned int* ghist, unsigned int* h) {
     h[threadIdx.x] = 0u;
     __syncthreads();
     const unsigned int prefix = pass ? st->sel_prefix : 0u;
     const unsigned int mask = pass ? st->sel_mask : 0u;
     const int shift = 24 - 8 * pass;
-    const long long q0 = ((long long)blockIdx.x * kSelBlock + threadIdx.x) * kSelPer;
-    unsigned int v[kSelPer];
-    sel_load16(keys, q0, (long long)E, v);
+    const int chunks = (E + kCommitChunk - 1) / kCommitChunk;
+    for (int c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const long long q0 = (long long)c * kCommitChunk + (long long)threadIdx.x * kSelPer;
+        unsigned int v[kSelPer];
+        sel_load16(keys, q0, (long long)E, v);
 #pragma unroll
-    for (int j = 0; j < kSelPer; ++j)
-        lds_count(h, (v[j] >> shift) & 255u, q0 + j < E && (v[j] & mask) == prefix);
+        for (int j = 0; j < kSelPer; ++j)
+            lds_count(h, (v[j] >> shift) & 255u, q0 + j < E && (v[j] & mask) == prefix);
+    }
     __syncthreads();
     if (h[threadIdx.x])
         atomicAdd(&ghist[(blockIdx.x & (kHistCopies - 1)) * 256 + threadIdx.x], h[threadIdx.x]);
 }
 
-// Pick the digit of pass `pass`: the largest b whose suffix count S(b) (keys
-// with digit >= b) reaches the number still to take, digit 0 if none; clear
-// the histogram copies for the next pass.
-__global__ __launch_bounds__(kSelBlock) void k_rbp_scan(DevState* st, int pass, unsigned int k,
-                                                        unsigned int* ghist) {
-    __shared__ unsigned int h[256];
-    if (st->rbp_skip) return;
+// Pick the digit of pass `pass` (one block): the largest b whose suffix count
+// S(b) (keys with digit >= b) reaches the number still to take, digit 0 if
+// none; clear the histogram copies for the next pass.
+__device__ __forceinline__ void rbp_scan_block(DevState* st, int pass, unsigned int k,
+                                               unsigned int* ghist, unsigned int* h) {
     const int b = threadIdx.x;
     unsigned int hb = 0;
 #pragma unroll
@@ -1939,6 +2156,38 @@ __global__ __launch_bounds__(kSelBlock) void k_rbp_scan(DevState* st, int pass, 
             st->sel_rank_ties = (hb != left) ? 1u : 0u;
         }
     }
+}
+
+// One histogram pass (a block per chunk of kCommitChunk keys).
+__global__ __launch_bounds__(kSelBlock) void k_rbp_hist(DevState* st, const unsigned int* keys,
+                                                        int E, int pass) {
+    __shared__ unsigned int h[256];
+    if (st->rbp_skip) return;
+    rbp_hist_block(st, keys, E, pass, &st->hist[0][0], h);
+}
+
+// The digit pick of pass `pass`.  With gate_ctr (first pass only) it is also
+// IsConverged for the top-k: nothing is selected or committed when the
+// evaluation found no residual above eps (the copies that evaluation filled
+// are then left for the next run's reset).
+__global__ __launch_bounds__(kSelBlock) void k_rbp_scan(DevState* st, int pass, unsigned int k,
+                                                        const CounterLine* gate_ctr) {
+    __shared__ unsigned int h[256];
+    __shared__ unsigned int s_skip;
+    if (gate_ctr) {
+        if (threadIdx.x < 64) {
+            const unsigned long long n = wave_sum64(gate_ctr[threadIdx.x].active);
+            if (threadIdx.x == 0) {
+                s_skip = (st->done || n == 0ull) ? 1u : 0u;
+                st->rbp_skip = s_skip;
+            }
+        }
+    } else if (threadIdx.x == 0) {
+        s_skip = st->rbp_skip;
+    }
+    __syncthreads();
+    if (s_skip) return;
+    rbp_scan_block(st, pass, k, &st->hist[0][0], h);
 }
 
 // Ties at the threshold key are taken in (target, source) order.  Slots are
@@ -2520,11 +2769,20 @@ hipError_t launch_eval(int layout, int kp, int mode, const EvalArgs& a, hipStrea
         // no shared table in LDS
         const size_t shm = sizeof(float) * (size_t)(TS * (K + 1) + ((TN * (K + 1) + 3) & ~3)) +
                            sizeof(int) * (size_t)(TS + TN + 1) + sizeof(unsigned short) * (size_t)TS;
-        switch (mode) {
-        case kModeLBP: k_eval_mfma32<kModeLBP><<<grid, kBlock, shm, s>>>(a); break;
-        case kModeRnBP: k_eval_mfma32<kModeRnBP><<<grid, kBlock, shm, s>>>(a); break;
-        case kModeRBP: k_eval_mfma32<kModeRBP><<<grid, kBlock, shm, s>>>(a); break;
-        default: k_eval_mfma32<kModeEvalOnly><<<grid, kBlock, shm, s>>>(a); break;
+        if (a.mfma_bf16) {
+            switch (mode) {
+            case kModeLBP: k_eval_mfma32<kModeLBP, true><<<grid, kBlock, shm, s>>>(a); break;
+            case kModeRnBP: k_eval_mfma32<kModeRnBP, true><<<grid, kBlock, shm, s>>>(a); break;
+            case kModeRBP: k_eval_mfma32<kModeRBP, true><<<grid, kBlock, shm, s>>>(a); break;
+            default: k_eval_mfma32<kModeEvalOnly, true><<<grid, kBlock, shm, s>>>(a); break;
+            }
+        } else {
+            switch (mode) {
+            case kModeLBP: k_eval_mfma32<kModeLBP, false><<<grid, kBlock, shm, s>>>(a); break;
+            case kModeRnBP: k_eval_mfma32<kModeRnBP, false><<<grid, kBlock, shm, s>>>(a); break;
+            case kModeRBP: k_eval_mfma32<kModeRBP, false><<<grid, kBlock, shm, s>>>(a); break;
+            default: k_eval_mfma32<kModeEvalOnly, false><<<grid, kBlock, shm, s>>>(a); break;
+            }
         }
         return hipGetLastError();
     }
@@ -2575,12 +2833,44 @@ hipError_t launch_batch_status(const BatchGraph* graphs, int num_graphs, unsigne
     return hipGetLastError();
 }
 
-hipError_t launch_eval_batch(BatchGraph* graphs, int num_graphs, const int* list, int num_blocks,
-                             long long launch, hipStream_t s) {
-    if (num_blocks <= 0) return hipSuccess;
-    k_batch_advance<<<(num_graphs + 255) / 256, 256, 0, s>>>(graphs, num_graphs, launch);
-    k_eval_batch<<<num_blocks, kBlock, 0, s>>>(graphs, (const int4*)list);
+hipError_t launch_eval_batch(BatchGraph* graphs, int num_graphs, const int* list, BatchCtl* ctl,
+                             int grid, hipStream_t s) {
+    k_batch_advance<<<(num_graphs + 255) / 256, 256, 0, s>>>(graphs, num_graphs, ctl);
+    k_eval_batch<<<grid, kBlock, 0, s>>>(graphs, (const int4*)list, ctl);
     return hipGetLastError();
+}
+
+hipError_t batch_graph_nodes(BatchGraph* graphs, int num_graphs, const int* list, BatchCtl* ctl,
+                             int grid, int launches, hipGraph_t* out) {
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipGraphCreate(&gr, 0);
+    if (e != hipSuccess) return e;
+    void* adv_args[3] = {(void*)&graphs, (void*)&num_graphs, (void*)&ctl};
+    const int4* lst = (const int4*)list;
+    void* ev_args[3] = {(void*)&graphs, (void*)&lst, (void*)&ctl};
+    hipKernelNodeParams pa{};
+    pa.func = (void*)k_batch_advance;
+    pa.gridDim = dim3((unsigned)((num_graphs + 255) / 256));
+    pa.blockDim = dim3(256);
+    pa.kernelParams = adv_args;
+    hipKernelNodeParams pe{};
+    pe.func = (void*)k_eval_batch;
+    pe.gridDim = dim3((unsigned)grid);
+    pe.blockDim = dim3(kBlock);
+    pe.kernelParams = ev_args;
+    hipGraphNode_t prev = nullptr;
+    for (int k = 0; k < launches && e == hipSuccess; ++k) {
+        hipGraphNode_t na = nullptr, ne = nullptr;
+        e = hipGraphAddKernelNode(&na, gr, prev ? &prev : nullptr, prev ? 1 : 0, &pa);
+        if (e == hipSuccess) e = hipGraphAddKernelNode(&ne, gr, &na, 1, &pe);
+        prev = ne;
+    }
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        return e;
+    }
+    *out = gr;
+    return hipSuccess;
 }
 
 hipError_t launch_close_run(const EvalArgs& a, hipStream_t s) {
@@ -2654,15 +2944,13 @@ hipError_t launch_rbp_gate(DevState* st, const CounterLine* ctr, int slot_idx, h
 }
 
 hipError_t launch_rbp_select(DevState* st, const unsigned int* keys, const int* rev, int E,
-                             unsigned int k, int slot_idx, unsigned int* block_ties,
-                             hipStream_t s) {
-    (void)slot_idx;
+                             unsigned int k, const CounterLine* gate_ctr, int hist0_done,
+                             unsigned int* block_ties, hipStream_t s) {
     const int nb = (E + kCommitChunk - 1) / kCommitChunk;
     const int grid = nb > 0 ? nb : 1;
-    unsigned int* ghist = &st->hist[0][0];
     for (int pass = 0; pass < 4; ++pass) {
-        k_rbp_hist<<<grid, kSelBlock, 0, s>>>(st, keys, E, pass, ghist);
-        k_rbp_scan<<<1, kSelBlock, 0, s>>>(st, pass, k, ghist);
+        if (pass > 0 || !hist0_done) k_rbp_hist<<<grid, kSelBlock, 0, s>>>(st, keys, E, pass);
+        k_rbp_scan<<<1, kSelBlock, 0, s>>>(st, pass, k, pass == 0 ? gate_ctr : nullptr);
     }
     k_rbp_tiecount<<<grid, kSelBlock, 0, s>>>(st, keys, rev, E, block_ties);
     k_rbp_tiescan<<<1, kSelBlock, 0, s>>>(st, block_ties, nb);
@@ -2704,7 +2992,7 @@ hipError_t launch_rs_select(const RsArgs& r, unsigned int k, int all, unsigned i
     if (N <= 0) return hipSuccess;
     k_rs_vkeys<<<rs_grid(N), kBlock, 0, s>>>(r);
     if (!all) {
-        hipError_t e = launch_rbp_select(r.st, r.vkey, nullptr, N, k, 0, block_ties, s);
+        hipError_t e = launch_rbp_select(r.st, r.vkey, nullptr, N, k, nullptr, 0, block_ties, s);
         if (e != hipSuccess) return e;
     }
     k_rs_roots<<<(N + kCommitChunk - 1) / kCommitChunk, kSelBlock, 0, s>>>(r, all, block_ties);

@@ -136,7 +136,7 @@ def test_rejects_bad_problems(bp):
     J[0] = np.inf
     _expect_einval(bp, mod(coupling=J), match="coupling")
     _expect_einval(bp, mod(pair_kind=7), match="pair_kind")
-    _expect_einval(bp, base, flags=0x10, match="flags")
+    _expect_einval(bp, base, flags=0x100, match="flags")
     # Ising needs K = 2
     _expect_einval(bp, mod(K=3, log_unary=np.zeros((9, 3))), match="num_states")
 

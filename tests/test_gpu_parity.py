@@ -394,6 +394,27 @@ def test_bitwise_determinism(bp):
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
 
 
+@pytest.mark.parametrize("schedule,p", [("rnbp", 0.3), ("lbp", 1.0)])
+def test_launch_shape_tuning_changes_no_result(bp, schedule, p):
+    # the first long run of a graph times its first 32 launches at several
+    # persistent grid sizes and keeps the fastest; the second run uses only the
+    # chosen grid: both must give the same bits (here on a grid large enough
+    # for the candidates to differ)
+    prob = inputs.ising_grid(300, 300, 2.5, 4)
+    with bp.Graph(prob) as g:
+        assert g.info()["eval_blocks"] == 0
+        r1 = g.run(schedule, eps=1e-4, p=p, seed=5, max_iters=120, check_every=7)
+        m1 = g.get_state()[0]
+        chosen = g.info()["eval_blocks"]
+        assert chosen > 0 and chosen % 8 == 0
+        r2 = g.run(schedule, eps=1e-4, p=p, seed=5, max_iters=120, check_every=7)
+        m2 = g.get_state()[0]
+        assert g.info()["eval_blocks"] == chosen
+    assert np.array_equal(m1, m2)
+    for k in ("iterations", "committed", "last_active", "last_max_residual", "final_t"):
+        assert r1[k] == r2[k], k
+
+
 @pytest.mark.parametrize("schedule", ["lbp", "rnbp", "rbp"])
 def test_resume_from_exported_state(bp, schedule):
     # checkpoint through bp_get_state / bp_set_state (FP32 probabilities) and

@@ -49,11 +49,18 @@ def _alone(bp, prob, sched, eps, p, seed, max_iters):
         return g.marginals(), r
 
 
-@pytest.mark.parametrize("arena_mb,max_graphs,launches", [(256, 16, 9), (2, 3, 4)])
-def test_serving_bitwise_equals_bp_run(bp, arena_mb, max_graphs, launches):
+@pytest.mark.parametrize("arena_mb,max_graphs,launches,graphs,autotune", [
+    (256, 16, 9, False, False), (2, 3, 4, False, False),
+    # recorded HIP graphs replayed every step (re-recorded as graphs join and
+    # leave), with the server's own uploads, status kernels and readbacks
+    # between the replays; and the autotuner switching the grid between steps
+    (256, 16, 9, True, False), (256, 16, 5, True, True), (2, 3, 4, True, True),
+    (256, 16, 7, False, True)])
+def test_serving_bitwise_equals_bp_run(bp, arena_mb, max_graphs, launches, graphs, autotune):
     # the small arena holds a few graphs at a time: requests queue and join late
     mix = _mix()
-    with bp.Server(arena_mb << 20, max_graphs=max_graphs) as srv:
+    with bp.Server(arena_mb << 20, max_graphs=max_graphs, graphs=graphs,
+                   autotune=autotune) as srv:
         ids = [srv.submit(pr, sched, eps=eps, p=p, seed=seed, max_iters=mi)
                for pr, sched, eps, p, seed, mi in mix]
         got = {}
@@ -67,6 +74,10 @@ def test_serving_bitwise_equals_bp_run(bp, arena_mb, max_graphs, launches):
             if len(got) == len(ids):
                 break
         assert srv.counts() == (0, 0, 0)
+        cfg = srv.config()
+        if autotune:
+            assert cfg["tuned"] and cfg["grid_blocks"] in [c for c, _ in cfg["candidates"]]
+            assert all(ns > 0 for _, ns in cfg["candidates"])
     assert len(got) == len(ids)
     for i, (pr, sched, eps, p, seed, mi) in zip(ids, mix):
         m_ref, r_ref = _alone(bp, pr, sched, eps, p, seed, mi)
