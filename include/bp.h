@@ -235,7 +235,10 @@ typedef struct bp_graph_info {
                                  each of 1, 2, 4 blocks per compute unit and every
                                  resident block, and keeps the fastest; results do not
                                  depend on it); 0 until tuned */
-    int32_t reserved;
+    int32_t heavy_slots;      /* layout 2: messages whose source variable has many
+                                 states, neighbours or table entries, each evaluated
+                                 by a wave of its own (the others share one wave per
+                                 variable); 0 for the other layouts */
 } bp_graph_info;
 
 /* Fill *opts with the defaults listed in bp_run_opts. */

@@ -82,7 +82,7 @@ class bp_graph_info(ctypes.Structure):
                 ("num_edges", ctypes.c_int64), ("num_messages", ctypes.c_int64),
                 ("layout", ctypes.c_int32), ("num_tiles", ctypes.c_int32),
                 ("device_bytes", ctypes.c_uint64), ("eval_blocks", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("heavy_slots", ctypes.c_int32)]
 
 
 class bp_server_desc(ctypes.Structure):

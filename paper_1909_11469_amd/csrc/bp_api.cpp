@@ -92,6 +92,7 @@ struct HostLayout {
     std::vector<int> uoff;            // [N+1] unary / belief row of each variable
     std::vector<int> moff;            // [E+1] message row of each slot (K_target entries)
     std::vector<int> toff;            // [E+1] table of each slot (K_source x K_target)
+    std::vector<int> heavy;           // {slot, source} of the slots of heavy variables
     std::vector<long long> coff;      // [E+1] row of each canonical message in host arrays
     long long msg_floats = 0;         // entries of one message buffer
     long long belief_floats = 0;      // entries of the beliefs (N K, or sum K_i)
@@ -108,7 +109,7 @@ struct Arena {
 
 struct Offsets {
     size_t node_ptr, rev, tile, tile_slot, tiles4, big4, coupling, unary, pair, orient, msg[4], cand, keys, ties, state,
-        ctr, marg, kv, uoff, moff, toff, sparse, splash, total;
+        ctr, marg, kv, uoff, moff, toff, heavy, sparse, splash, total;
 };
 
 // Device bytes of the sparse re-evaluation buffers of a log-odds graph: dirty
@@ -144,6 +145,7 @@ Offsets plan(const HostLayout& L) {
     o.uoff = a.take(sizeof(int) * L.uoff.size());
     o.moff = a.take(sizeof(int) * L.moff.size());
     o.toff = a.take(sizeof(int) * L.toff.size());
+    o.heavy = a.take(sizeof(int) * L.heavy.size());
     o.sparse = L.sparse_reserved ? a.take(sparse_bytes(L)) : 0;
     o.splash = L.splash_reserved ? a.take(splash_bytes(L.N)) : 0;
     o.total = a.off;
@@ -304,6 +306,15 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
             L.toff[s + 1] = L.toff[s] + ki * kj;
         }
         L.msg_floats = L.moff[E];
+        // slots of heavy variables: each is evaluated by a wave of its own
+        for (long long i = 0; i < N; ++i) {
+            const int s0 = L.node_ptr[i], s1 = L.node_ptr[i + 1];
+            if (ragged_flat(s1 - s0, L.kv[i], L.moff[s1] - L.moff[s0])) continue;
+            for (int s = s0; s < s1; ++s) {
+                L.heavy.push_back(s);
+                L.heavy.push_back((int)i);
+            }
+        }
         L.coff.assign((size_t)E + 1, 0);
         for (long long c = 0; c < E; ++c) L.coff[c + 1] = L.coff[c] + L.kv[cdst(c)];
         L.unary.resize((size_t)L.belief_floats);
@@ -578,11 +589,12 @@ int create_graph_from_layout(HostLayout& layout, const bp_graph_desc* desc, bp_g
         if (n == 0) return hipSuccess;
         return hipMemcpyAsync(g->base + o, p, n, hipMemcpyHostToDevice, s);
     };
-    hipError_t errs[15] = {
+    hipError_t errs[16] = {
         up(g->off.kv, L.kv.data(), sizeof(int) * L.kv.size()),
         up(g->off.uoff, L.uoff.data(), sizeof(int) * L.uoff.size()),
         up(g->off.moff, L.moff.data(), sizeof(int) * L.moff.size()),
         up(g->off.toff, L.toff.data(), sizeof(int) * L.toff.size()),
+        up(g->off.heavy, L.heavy.data(), sizeof(int) * L.heavy.size()),
         up(g->off.tile_slot, L.tile_slot.data(), sizeof(int) * L.tile_slot.size()),
         up(g->off.tiles4, L.tiles4.data(), sizeof(int) * L.tiles4.size()),
         up(g->off.big4, L.big4.data(), sizeof(int) * L.big4.size()),
@@ -636,6 +648,7 @@ int bp_graph_info_get(const bp_graph* g, bp_graph_info* info) {
     info->num_tiles = (int)g->L.tile_start.size() - 1;
     info->device_bytes = g->off.total;
     info->eval_blocks = g->lo_grid;
+    info->heavy_slots = (int)(g->L.heavy.size() / 2);
     return BP_OK;
 }
 
@@ -693,9 +706,12 @@ static EvalArgs run_args(const bp_graph* g, int schedule, double eps, double p, 
     a.uoff = g->at<int>(g->off.uoff);
     a.moff = g->at<int>(g->off.moff);
     a.toff = g->at<int>(g->off.toff);
+    a.heavy = g->at<int>(g->off.heavy);
+    a.num_heavy = (int)(L.heavy.size() / 2);
     if (L.layout == kLayoutRagged) {
-        // a wave per variable, grid-stride: at most 8 blocks per CU
-        const long long waves = (long long)L.N;
+        // a wave per heavy slot and per variable, grid-stride: at most 8
+        // blocks per CU
+        const long long waves = (long long)L.N + a.num_heavy;
         const long long blocks = (waves + kBlock / 64 - 1) / (kBlock / 64);
         a.pipe_grid = (int)std::max<long long>(
             1, std::min<long long>(blocks, 8ll * std::max(g->num_cus, 1)));

@@ -17,6 +17,11 @@ namespace bp {
 #define BP_BLOCK 256
 #endif
 constexpr int kBlock = BP_BLOCK;
+#ifndef BP_BLOCK_LOGODDS
+#define BP_BLOCK_LOGODDS 256
+#endif
+constexpr int kBlockLO = BP_BLOCK_LOGODDS;  // threads of the K = 2 tile kernels
+static_assert(kBlockLO % 64 == 0 && kBlockLO <= kBlock, "K = 2 tile kernel block size");
 #ifndef BP_TILE_SLOTS_LOGODDS
 #define BP_TILE_SLOTS_LOGODDS 512
 #endif
@@ -29,6 +34,26 @@ constexpr int kTileFloatsGeneric = BP_TILE_FLOATS_GENERIC;  // [E][K] layout: ti
 constexpr int kTileNodesMax = 2048;      // nodes per tile (owner index fits in u16)
 constexpr int kMaxK = 64;
 constexpr int kMaxKRagged = 128;  // largest K_i of a graph with per-variable state counts
+// Ragged layout: a variable's slots are evaluated by one wave together (its
+// aggregate shared, the outputs of all its slots at once) when its cavity
+// vectors (deg K_i floats) and its outputs (P = sum of K_j over its slots)
+// each fit kRaggedFlat floats of the wave's LDS and its product work P K_i is
+// at most kRaggedHeavyWork; every other variable ("heavy") gives each of its
+// slots a wave of its own, so that no wave carries a long chain of table
+// loads.  Host (heavy slot list) and kernel decide with the same function.
+#ifndef BP_RAGGED_FLAT
+#define BP_RAGGED_FLAT 1024
+#endif
+constexpr int kRaggedFlat = BP_RAGGED_FLAT;
+constexpr int kRaggedMaxDeg = 64;
+#ifndef BP_RAGGED_HEAVY_WORK
+#define BP_RAGGED_HEAVY_WORK 16384
+#endif
+constexpr int kRaggedHeavyWork = BP_RAGGED_HEAVY_WORK;
+__host__ __device__ inline bool ragged_flat(int deg, int ki, int p) {
+    return deg <= kRaggedMaxDeg && deg * ki <= kRaggedFlat && p <= kRaggedFlat &&
+           p * ki <= kRaggedHeavyWork;
+}
 
 // 0: one log-odds value per message (K = 2 Ising); 1: K floats per message;
 // 2: K_j floats per message i -> j (per-variable state counts)
@@ -106,6 +131,8 @@ struct EvalArgs {
     const int* uoff;            // [N+1] first unary (and belief) entry of each variable
     const int* moff;            // [E+1] first message entry of each slot (K_j entries)
     const int* toff;            // [E+1] first table entry of each slot (K_i x K_j, x_i major)
+    const int* heavy;           // [num_heavy][2] {slot, source} of the slots of heavy variables
+    int num_heavy;
     const float* in_buf[2];     // m^t: candidates chosen by p_{t-1} (both equal on a run's first launch)
     float* out_buf[2];          // m^{t+1} under the larger [0] and smaller [1] keep threshold
     float* cand;                // RBP candidates, same layout as m

@@ -125,8 +125,7 @@ __device__ __forceinline__ void block_accumulate(RedScratch* red, CounterLine* c
     if (threadIdx.x == 0) {
         float r = red->rmax[0];
         unsigned int A = red->act[0], SA = red->sa[0], SB = red->sb[0];
-#pragma unroll
-        for (int i = 1; i < kBlock / 64; ++i) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
             r = fmaxf(r, red->rmax[i]);
             A += red->act[i];
             SA += red->sa[i];
@@ -380,8 +379,8 @@ __device__ __forceinline__ float logodds_slot(const EvalArgs& a, const Out& out,
     return r;
 }
 
-constexpr int kPP = kTileSlotsLogOdds / kBlock;              // slots per thread per tile
-constexpr int kPJ = (kTileNodesLogOdds + kBlock) / kBlock;    // node entries (TN + 1) per thread
+constexpr int kPP = kTileSlotsLogOdds / kBlockLO;              // slots per thread per tile
+constexpr int kPJ = (kTileNodesLogOdds + kBlockLO) / kBlockLO;    // node entries (TN + 1) per thread
 
 // The per-thread share of one tile: node bounds and unaries, and the slots'
 // own old values, reverse indices and couplings.
@@ -406,7 +405,7 @@ __device__ __forceinline__ void tile_load_const(TileRegs& d, const EvalArgs& a, 
     d.ns = b.w - b.z;
 #pragma unroll
     for (int j = 0; j < kPJ; ++j) {
-        const int v = tid + j * kBlock;
+        const int v = tid + j * kBlockLO;
         d.ptr[j] = ld32(a.node_ptr, d.n0 + min(v, d.nn));
         d.u[j] = ld32(a.unary, d.n0 + min(v, max(d.nn - 1, 0)));
     }
@@ -414,7 +413,7 @@ __device__ __forceinline__ void tile_load_const(TileRegs& d, const EvalArgs& a, 
     // device arena (the arrays are carved from one allocation in sequence)
 #pragma unroll
     for (int k = 0; k < kPP; ++k) {
-        const int s = d.s0 + min(tid + k * kBlock, max(d.ns - 1, 0));
+        const int s = d.s0 + min(tid + k * kBlockLO, max(d.ns - 1, 0));
         d.rev[k] = ld32(a.rev, s);
         d.J[k] = ld32(a.coupling, s);
     }
@@ -423,7 +422,7 @@ __device__ __forceinline__ void tile_load_const(TileRegs& d, const EvalArgs& a, 
 __device__ __forceinline__ void tile_load_msgs(TileRegs& d, const float* m_in) {
 #pragma unroll
     for (int k = 0; k < kPP; ++k)
-        d.old[k] = ld32(m_in, d.s0 + min((int)threadIdx.x + k * kBlock, max(d.ns - 1, 0)));
+        d.old[k] = ld32(m_in, d.s0 + min((int)threadIdx.x + k * kBlockLO, max(d.ns - 1, 0)));
 }
 
 template <int MODE>
@@ -490,13 +489,13 @@ __device__ __forceinline__ void logodds_tile_loop(const EvalArgs& a, const float
     // stage tile 0
 #pragma unroll
     for (int jj = 0; jj < kPJ; ++jj) {
-        const int v = tid + jj * kBlock;
+        const int v = tid + jj * kBlockLO;
         if (v <= cur.nn) l.ptr[v] = (unsigned short)(cur.ptr[jj] - cur.s0);
         if (v < cur.nn) l.L[v] = cur.u[jj];
     }
 #pragma unroll
     for (int k = 0; k < kPP; ++k) {
-        const int q = tid + k * kBlock;
+        const int q = tid + k * kBlockLO;
         if (q < cur.ns) l.lam[q] = lin[k];
     }
     for (int j = 0;; ++j) {
@@ -506,7 +505,7 @@ __device__ __forceinline__ void logodds_tile_loop(const EvalArgs& a, const float
         lds_barrier();
         // node aggregates of tile j, incoming messages in slot order; for
         // RnBP also the draws of the node's messages, four per Philox call
-        for (int v = tid; v < cur.nn; v += kBlock) {
+        for (int v = tid; v < cur.nn; v += kBlockLO) {
             const int q0 = l.ptr[v], q1 = l.ptr[v + 1];
             float L = l.L[v];
             for (int q = q0; q < q1; ++q) {
@@ -534,7 +533,7 @@ __device__ __forceinline__ void logodds_tile_loop(const EvalArgs& a, const float
         // outgoing messages of tile j, written at their own slots
 #pragma unroll
         for (int k = 0; k < kPP; ++k) {
-            const int q = tid + k * kBlock;
+            const int q = tid + k * kBlockLO;
             float r = 0.0f;
             if (q < cur.ns) {
                 const int v = l.owner[q];
@@ -553,13 +552,13 @@ __device__ __forceinline__ void logodds_tile_loop(const EvalArgs& a, const float
         for (int k = 0; k < kPP; ++k) lin[k] = lin_n[k];
 #pragma unroll
         for (int jj = 0; jj < kPJ; ++jj) {
-            const int v = tid + jj * kBlock;
+            const int v = tid + jj * kBlockLO;
             if (v <= cur.nn) l.ptr[v] = (unsigned short)(cur.ptr[jj] - cur.s0);
             if (v < cur.nn) l.L[v] = cur.u[jj];
         }
 #pragma unroll
         for (int k = 0; k < kPP; ++k) {
-            const int q = tid + k * kBlock;
+            const int q = tid + k * kBlockLO;
             if (q < cur.ns) l.lam[q] = lin[k];
         }
         bnext = bnext2;
@@ -578,7 +577,7 @@ struct XcdTiles {
 // K = 2 evaluation kernel.  A persistent grid (as many blocks as are resident)
 // walks the tiles with the pipelined tile loop.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
+__global__ __launch_bounds__(kBlockLO) void k_eval_logodds(EvalArgs a) {
     __shared__ LogoddsLds l;
     __shared__ RedScratch red;
     __shared__ unsigned long long s_red[2];
@@ -603,13 +602,13 @@ __global__ __launch_bounds__(kBlock) void k_eval_logodds(EvalArgs a) {
     unsigned int act = 0, sa = 0, sb = 0;
     const bool hist = MODE == kModeRBP && a.hist0;
     if (hist)
-        for (int i = threadIdx.x; i < 256; i += kBlock) l.hist[i] = 0u;  // seen after the loop's barriers
+        for (int i = threadIdx.x; i < 256; i += kBlockLO) l.hist[i] = 0u;  // seen after the loop's barriers
     if (t0 >= 0) logodds_tile_loop<MODE>(a, m_in, XcdTiles{a, tiles}, cur, bnext, l, rmax, act, sa, sb);
     if (hist) {
         // the block's digit counts into one of the copies of the global histogram
         lds_barrier();
         unsigned int* gh = &a.st->hist[blockIdx.x & 15][0];
-        for (int i = threadIdx.x; i < 256; i += kBlock)
+        for (int i = threadIdx.x; i < 256; i += kBlockLO)
             if (l.hist[i]) atomicAdd(&gh[i], l.hist[i]);
     }
     block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
@@ -625,15 +624,16 @@ __device__ __forceinline__ void logodds_big_node(const EvalArgs& a, const float*
     const int tid = threadIdx.x;
     const int n0 = b.x, s0 = b.z, ns = b.w - b.z;
     float part = 0.0f;
-    for (int q = tid; q < ns; q += kBlock) part += m_in[a.rev[s0 + q]];
+    const int nt = (int)blockDim.x;
+    for (int q = tid; q < ns; q += nt) part += m_in[a.rev[s0 + q]];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
     if ((tid & 63) == 0) s_part[tid >> 6] = part;
     __syncthreads();
     float L = a.unary[n0];
 #pragma unroll
-    for (int i = 0; i < kBlock / 64; ++i) L += s_part[i];
-    for (int q = tid; q < ns; q += kBlock) {
+    for (int i = 0; i < nt / 64; ++i) L += s_part[i];
+    for (int q = tid; q < ns; q += nt) {
         const int s = s0 + q;
         const unsigned int u24 = MODE == kModeRnBP ? draw24(a, n0, q) : 0u;
         const float r = logodds_slot<MODE>(a, OutPtr{a}, L, m_in[a.rev[s]], a.coupling[s], m_in[s], s,
@@ -723,7 +723,7 @@ __device__ __forceinline__ void batch_run(const EvalArgs& a, const float* __rest
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_eval_batch(const BatchGraph* __restrict__ graphs,
+__global__ __launch_bounds__(kBlockLO) void k_eval_batch(const BatchGraph* __restrict__ graphs,
                                                        const int4* __restrict__ list,
                                                        BatchCtl* ctl) {
     __shared__ LogoddsLds l;
@@ -1478,8 +1478,10 @@ __global__ void k_marginals_generic(const int* node_ptr, const int* rev, const f
 // source states (the table entries of consecutive lanes are contiguous; a lane
 // runs four pairs together, 32 loads in flight); a lane per slot forms the normalisation, the
 // L-infinity residual and the frontier decision, and the pair lanes store the
-// committed values.  A variable whose slots do not fit the wave's LDS goes slot
-// by slot, lanes over states, with wave-wide shuffles and reductions.
+// committed values.  A heavy variable (slots over the wave's LDS, or much
+// product work: ragged_flat) gives each of its slots a wave of its own
+// (ragged_slot), taken before the other variables, so the launch is not held
+// up by one wave that runs a long chain of table loads.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float wave_max_f(float v) {
 #pragma unroll
@@ -1498,8 +1500,6 @@ __device__ __forceinline__ void wave_lds_sync() { __asm__ volatile("s_waitcnt lg
 
 // LDS per wave of the flat path: the cavity vectors of one variable's slots,
 // and its slots' outputs (entries), each at most kRaggedFlat floats.
-constexpr int kRaggedFlat = 1024;
-constexpr int kRaggedMaxDeg = 64;
 
 template <int MODE>
 __device__ __forceinline__ void ragged_commit(const EvalArgs& a, int q, float v, float old, bool ka,
@@ -1512,6 +1512,129 @@ __device__ __forceinline__ void ragged_commit(const EvalArgs& a, int q, float v,
     } else if (MODE == kModeRBP) {
         a.cand[q] = v;
     }
+}
+
+// One slot i -> j of a heavy variable on one wave: the aggregate of i over all
+// its incoming rows (lanes over source states, rows eight at a time, summed in
+// slot order as the flat path sums them), the cavity of j's row, then the
+// product with the slot's table.  For K_j <= 64 the wave covers R = 64 / K_j
+// table rows per step: lane r K_j + y reads entry (step R + r) K_j + y, so each
+// load is one contiguous run of the table, eight steps in flight, and the R
+// partial sums of each target state are added through LDS.  For larger K_j,
+// lanes take target states y and y + 64 over all source states.
+template <int MODE>
+__device__ __forceinline__ void ragged_slot(const EvalArgs& a, const float* __restrict__ m_in, int s,
+                                            int i, float* G, float* Cv, float& rmax,
+                                            unsigned int& act, unsigned int& sa, unsigned int& sb) {
+    const int lane = threadIdx.x & 63;
+    const int Ki = a.kv[i];
+    const int s0 = a.node_ptr[i], s1 = a.node_ptr[i + 1];
+    const float fK = (float)Ki;
+    const bool x0 = lane < Ki, x1 = lane + 64 < Ki;
+    const float* U = a.unary + a.uoff[i];
+    const int mo = a.moff[s], Kj = a.moff[s + 1] - mo;
+    const float* __restrict__ T = a.pair + a.toff[s];
+    const int rj = a.moff[a.rev[s]];
+    const bool y0 = lane < Kj, y1 = lane + 64 < Kj;
+    const float old0 = y0 ? m_in[mo + lane] : 0.0f;
+    const float old1 = y1 ? m_in[mo + lane + 64] : 0.0f;
+    float A0 = x0 ? U[lane] : 0.0f, A1 = x1 ? U[lane + 64] : 0.0f;
+    for (int b = s0; b < s1; b += 64) {
+        const int nb = min(64, s1 - b);
+        const int my_rin = lane < nb ? a.moff[a.rev[b + lane]] : 0;
+        for (int k0 = 0; k0 < nb; k0 += 8) {
+            float v0[8], v1[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int rin = __shfl(my_rin, min(k0 + j, nb - 1), 64);
+                v0[j] = x0 ? m_in[rin + lane] : 1.0f;
+                v1[j] = x1 ? m_in[rin + lane + 64] : 1.0f;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (k0 + j >= nb) break;
+                if (x0) A0 += logf(fK * v0[j]);
+                if (x1) A1 += logf(fK * v1[j]);
+            }
+        }
+    }
+    const float c0 = x0 ? A0 - logf(fK * m_in[rj + lane]) : -INFINITY;
+    const float c1 = x1 ? A1 - logf(fK * m_in[rj + lane + 64]) : -INFINITY;
+    const float mx = wave_max_f(fmaxf(c0, c1));
+    if (x0) G[lane] = expf(c0 - mx);
+    if (x1) G[lane + 64] = expf(c1 - mx);
+    wave_lds_sync();
+    float o0 = 0.0f, o1 = 0.0f;
+    if (Kj <= 64) {
+        const int R = 64 / Kj;
+        const int r = lane / Kj;
+        const int RK = R * Kj;
+        const int steps = (Ki + R - 1) / R;
+        float acc = 0.0f;
+        int st = 0;
+        for (; st + 8 <= steps; st += 8) {
+            float tv[8], gv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int x = (st + u) * R + r;
+                const bool ok = lane < RK && x < Ki;
+                tv[u] = ok ? T[(st + u) * RK + lane] : 0.0f;
+                gv[u] = ok ? G[x] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = fmaf(tv[u], gv[u], acc);
+        }
+        for (; st < steps; ++st) {
+            const int x = st * R + r;
+            if (lane < RK && x < Ki) acc = fmaf(T[st * RK + lane], G[x], acc);
+        }
+        Cv[lane] = acc;
+        wave_lds_sync();
+        if (y0)
+            for (int q = 0; q < R; ++q) o0 += Cv[q * Kj + lane];
+    } else {
+        int x = 0;
+        for (; x + 8 <= Ki; x += 8) {
+            float t0[8], t1[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                t0[u] = T[(x + u) * Kj + lane];
+                t1[u] = y1 ? T[(x + u) * Kj + lane + 64] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float gx = G[x + u];
+                o0 = fmaf(t0[u], gx, o0);
+                o1 = fmaf(t1[u], gx, o1);
+            }
+        }
+        for (; x < Ki; ++x) {
+            const float gx = G[x];
+            o0 = fmaf(T[x * Kj + lane], gx, o0);
+            if (y1) o1 = fmaf(T[x * Kj + lane + 64], gx, o1);
+        }
+    }
+    const float z = wave_sum_f(o0 + o1);
+    o0 /= z;
+    o1 /= z;
+    const float res = wave_max_f(fmaxf(y0 ? fabsf(o0 - old0) : 0.0f, y1 ? fabsf(o1 - old1) : 0.0f));
+    const bool active = res > a.eps;
+    bool ka = false, kb = false;
+    if (MODE == kModeRnBP && active) {
+        const unsigned int u24 = draw24(a, i, s - s0);
+        ka = u24 < a.thr_a;
+        kb = u24 < a.thr_b;
+    }
+    if (y0) ragged_commit<MODE>(a, mo + lane, o0, old0, ka, kb);
+    if (y1) ragged_commit<MODE>(a, mo + lane + 64, o1, old1, ka, kb);
+    if (lane == 0) {
+        if (MODE == kModeRBP) a.keys[s] = __float_as_uint(res);
+        act += active;
+        sa += ka;
+        sb += kb;
+        rmax = fmaxf(rmax, res);
+    }
+    wave_lds_sync();  // G and Cv are free for the wave's next slot
 }
 
 template <int MODE>
@@ -1534,7 +1657,10 @@ __global__ __launch_bounds__(kBlock) void k_eval_ragged(EvalArgs a) {
     const int waves = (int)(gridDim.x * (blockDim.x >> 6));
     float rmax = 0.0f;
     unsigned int act = 0, sa = 0, sb = 0;
-    for (int i = (int)(blockIdx.x * (blockDim.x >> 6) + w); i < a.num_nodes; i += waves) {
+    const int gw = (int)(blockIdx.x * (blockDim.x >> 6) + w);
+    for (int h = gw; h < a.num_heavy; h += waves)
+        ragged_slot<MODE>(a, m_in, a.heavy[2 * h], a.heavy[2 * h + 1], G, Cv, rmax, act, sa, sb);
+    for (int i = gw; i < a.num_nodes; i += waves) {
         const int Ki = a.kv[i];
         const int s0 = a.node_ptr[i], s1 = a.node_ptr[i + 1];
         const int deg = s1 - s0;
@@ -1544,7 +1670,8 @@ __global__ __launch_bounds__(kBlock) void k_eval_ragged(EvalArgs a) {
         float A0 = x0 ? U[lane] : 0.0f, A1 = x1 ? U[lane + 64] : 0.0f;
         const int mo0 = a.moff[s0];
         const int P = a.moff[s1] - mo0;  // outputs of all slots of the variable
-        if (deg <= kRaggedMaxDeg && deg * Ki <= kRaggedFlat && P <= kRaggedFlat) {
+        if (!ragged_flat(deg, Ki, P)) continue;  // a heavy variable: its slots are done
+        {
             // Flat path.  A lane per slot fetches the slot's offsets (all in
             // flight at once); the incoming rows are loaded eight slots at a
             // time and their logs kept in LDS for the cavities; then the
@@ -1670,55 +1797,6 @@ __global__ __launch_bounds__(kBlock) void k_eval_ragged(EvalArgs a) {
                 ragged_commit<MODE>(a, mo0 + p, Cv[p], old, kp & 1u, kp & 2u);
             }
             wave_lds_sync();  // the wave's LDS is free for its next variable
-            continue;
-        }
-        // Slot by slot (a variable whose slots do not fit the flat path): lanes
-        // over source states for the aggregate and the cavity, over target
-        // states for the output.
-        for (int s = s0; s < s1; ++s) {
-            const int rin = a.moff[a.rev[s]];
-            if (x0) A0 += logf(fK * m_in[rin + lane]);
-            if (x1) A1 += logf(fK * m_in[rin + lane + 64]);
-        }
-        for (int s = s0; s < s1; ++s) {
-            const int rin = a.moff[a.rev[s]];
-            const int mo = a.moff[s], Kj = a.moff[s + 1] - mo;
-            const float* T = a.pair + a.toff[s];
-            const float c0 = x0 ? A0 - logf(fK * m_in[rin + lane]) : -INFINITY;
-            const float c1 = x1 ? A1 - logf(fK * m_in[rin + lane + 64]) : -INFINITY;
-            const float mx = wave_max_f(fmaxf(c0, c1));
-            const float g0 = x0 ? expf(c0 - mx) : 0.0f;
-            const float g1 = x1 ? expf(c1 - mx) : 0.0f;
-            const bool y0 = lane < Kj, y1 = lane + 64 < Kj;
-            float o0 = 0.0f, o1 = 0.0f;
-            for (int x = 0; x < Ki; ++x) {
-                const float gx = x < 64 ? __shfl(g0, x, 64) : __shfl(g1, x - 64, 64);
-                if (y0) o0 = fmaf(T[x * Kj + lane], gx, o0);
-                if (y1) o1 = fmaf(T[x * Kj + lane + 64], gx, o1);
-            }
-            const float z = wave_sum_f(o0 + o1);
-            o0 /= z;
-            o1 /= z;
-            const float old0 = y0 ? m_in[mo + lane] : 0.0f;
-            const float old1 = y1 ? m_in[mo + lane + 64] : 0.0f;
-            const float r = wave_max_f(fmaxf(y0 ? fabsf(o0 - old0) : 0.0f,
-                                             y1 ? fabsf(o1 - old1) : 0.0f));
-            const bool active = r > a.eps;
-            bool ka = false, kb = false;
-            if (MODE == kModeRnBP && active) {
-                const unsigned int u24 = draw24(a, i, s - s0);
-                ka = u24 < a.thr_a;
-                kb = u24 < a.thr_b;
-            }
-            if (y0) ragged_commit<MODE>(a, mo + lane, o0, old0, ka, kb);
-            if (y1) ragged_commit<MODE>(a, mo + lane + 64, o1, old1, ka, kb);
-            if (lane == 0) {
-                if (MODE == kModeRBP) a.keys[s] = __float_as_uint(r);
-                act += active;
-                sa += ka;
-                sb += kb;
-                rmax = fmaxf(rmax, r);
-            }
         }
     }
     block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
@@ -2737,10 +2815,10 @@ hipError_t launch_eval(int layout, int kp, int mode, const EvalArgs& a, hipStrea
     if (layout == kLayoutLogOdds) {
         const int g = a.pipe_grid;
         switch (mode) {
-        case kModeLBP: k_eval_logodds<kModeLBP><<<g, kBlock, 0, s>>>(a); break;
-        case kModeRnBP: k_eval_logodds<kModeRnBP><<<g, kBlock, 0, s>>>(a); break;
-        case kModeRBP: k_eval_logodds<kModeRBP><<<g, kBlock, 0, s>>>(a); break;
-        default: k_eval_logodds<kModeEvalOnly><<<g, kBlock, 0, s>>>(a); break;
+        case kModeLBP: k_eval_logodds<kModeLBP><<<g, kBlockLO, 0, s>>>(a); break;
+        case kModeRnBP: k_eval_logodds<kModeRnBP><<<g, kBlockLO, 0, s>>>(a); break;
+        case kModeRBP: k_eval_logodds<kModeRBP><<<g, kBlockLO, 0, s>>>(a); break;
+        default: k_eval_logodds<kModeEvalOnly><<<g, kBlockLO, 0, s>>>(a); break;
         }
         if (a.num_big > 0) {
             switch (mode) {
@@ -2804,16 +2882,16 @@ int logodds_blocks_per_cu(int mode) {
     hipError_t e;
     switch (mode) {
     case kModeLBP:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeLBP>, kBlock, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeLBP>, kBlockLO, 0);
         break;
     case kModeRnBP:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeRnBP>, kBlock, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeRnBP>, kBlockLO, 0);
         break;
     case kModeRBP:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeRBP>, kBlock, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeRBP>, kBlockLO, 0);
         break;
     default:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeEvalOnly>, kBlock, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeEvalOnly>, kBlockLO, 0);
         break;
     }
     return e == hipSuccess ? n : 0;
@@ -2836,7 +2914,7 @@ hipError_t launch_batch_status(const BatchGraph* graphs, int num_graphs, unsigne
 hipError_t launch_eval_batch(BatchGraph* graphs, int num_graphs, const int* list, BatchCtl* ctl,
                              int grid, hipStream_t s) {
     k_batch_advance<<<(num_graphs + 255) / 256, 256, 0, s>>>(graphs, num_graphs, ctl);
-    k_eval_batch<<<grid, kBlock, 0, s>>>(graphs, (const int4*)list, ctl);
+    k_eval_batch<<<grid, kBlockLO, 0, s>>>(graphs, (const int4*)list, ctl);
     return hipGetLastError();
 }
 

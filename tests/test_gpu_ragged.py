@@ -61,7 +61,23 @@ PROBLEMS = {
     "vark_tree_k128": lambda: inputs.vark_graph(40, 0, 128, 2, tree=True),
     "protein300": lambda: inputs.protein_like_graph(300, 8.0, 3),
     "vark_dense_deg": lambda: inputs.vark_graph(30, 300, 6, 4),
+    # most variables heavy: up to 128 states and about 14 neighbours
+    "vark_heavy_k128": lambda: inputs.vark_graph(30, 200, 128, 7),
 }
+
+
+def _heavy_slots(prob):
+    """Messages out of variables that the evaluation kernel gives a wave per
+    slot: more than 64 neighbours, more than 1024 cavity or output entries, or
+    more than 16384 multiply-adds (output entries times K_i)."""
+    K = np.asarray(prob["var_states"], dtype=np.int64)
+    e = np.asarray(prob["edges"], dtype=np.int64).reshape(-1, 2)
+    deg = np.bincount(e.ravel(), minlength=len(K))
+    P = np.zeros(len(K), np.int64)
+    np.add.at(P, e[:, 0], K[e[:, 1]])
+    np.add.at(P, e[:, 1], K[e[:, 0]])
+    flat = (deg <= 64) & (deg * K <= 1024) & (P <= 1024) & (P * K <= 16384)
+    return int(deg[~flat].sum())
 
 
 @pytest.mark.parametrize("name", list(PROBLEMS))
@@ -70,14 +86,25 @@ def test_ragged_single_lbp_sweep(bp, name):
     S = _random_state(prob, 7)
     with bp.Graph(prob) as g:
         assert g.info()["layout"] == 2
+        assert g.info()["heavy_slots"] == _heavy_slots(prob)
         g.set_state(S, t=0)
         S, _ = g.get_state()
         g.run("lbp", eps=0.0, max_iters=1, warm_start=True)
         m, _ = g.get_state()
     cand, _ = oracle.evaluate(prob, S.astype(np.float64))
     err = _row_rel_err(m, cand, prob)
-    print(f"{name}: {len(err)} messages, max rel err {err.max():.2e}")
+    print(f"{name}: {len(err)} messages ({_heavy_slots(prob)} heavy), max rel err {err.max():.2e}")
     assert err.max() <= SWEEP_TOL
+
+
+def test_ragged_heavy_slots_cover_both_product_forms():
+    # the sweep problems reach the per-slot path with K_j <= 64 (rows of the
+    # table several at a time) and K_j > 64 (two target states per lane)
+    for name in ("vark_tree_k128", "protein300", "vark_heavy_k128"):
+        assert _heavy_slots(PROBLEMS[name]()) > 0, name
+    prob = PROBLEMS["vark_heavy_k128"]()
+    K = np.asarray(prob["var_states"])
+    assert K.max() > 64 and K.min() <= 64
 
 
 @pytest.mark.parametrize("schedule,p", [("lbp", 1.0), ("rnbp", 0.5), ("rbp", 0.1)])
