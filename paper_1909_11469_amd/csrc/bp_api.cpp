@@ -750,6 +750,12 @@ static EvalArgs run_args(const bp_graph* g, int schedule, double eps, double p, 
         a.low_is_a = 1;
         a.two_outputs = 0;
     }
+    // the K = 32 matrix-core kernel writes one whole row per message and the
+    // other outcome only where the two differ
+    a.row_flags = (a.two_outputs && L.layout == kLayoutGeneric && L.K == 32 &&
+                   L.pair == kPairShared && !L.tile_big && !L.no_mfma)
+                      ? 1
+                      : 0;
 
     rbp_k_out = rbp_k;
     return a;
@@ -1180,6 +1186,15 @@ static int run_impl(bp_graph* g, int schedule, double eps, double p, uint64_t se
     if (mode != kModeRBP && !sparse_now) {
         g->cur_pair = (int)((pair0 + (final_t - t_start)) & 1);
         g->cur_sel = (int)h.in_sel[final_t & 3];
+        if (a.row_flags && final_t > t_start) {
+            // m^final_t: whole rows of the outcome launch final_t - 1 wrote whole,
+            // flagged rows of the other where the choice was the other
+            const int prim = (int)h.in_sel[(final_t - 1) & 3];
+            float* bufs[2] = {g->msg(g->cur_pair, 0), g->msg(g->cur_pair, 1)};
+            HIP_OK(launch_resolve_rows(bufs, prim, g->cur_sel, L.E, L.K, s), "resolve rows");
+            HIP_OK(hipStreamSynchronize(s), "synchronize");
+            g->cur_sel = prim;
+        }
     }
     g->t_next = final_t;
     g->prev_active = h.last_prev;

@@ -150,6 +150,10 @@ struct EvalArgs {
     unsigned int thr_b;         // smaller keep threshold
     unsigned int key0, key1;    // Philox key
     int two_outputs;            // RnBP with differing thresholds: write out_buf[1] too
+    int row_flags;              // K = 32 matrix-core kernel with two_outputs: one full row
+                                // per message (the outcome the last iteration chose), the
+                                // other outcome only where they differ, flagged by the
+                                // sign bit of the full row's first entry
     int dynamic_p;
     int low_is_a;               // 1 if p (low) has the larger threshold
     int sel0;                   // buffer index of the start state (recorded, first launch)
@@ -222,6 +226,11 @@ hipError_t launch_fill_ragged(float* m, const int* moff, int E, hipStream_t s);
 hipError_t launch_sparse_iteration(const EvalArgs& a, hipStream_t s);
 hipError_t launch_sparse_setup(const EvalArgs& a, int build_dst, hipStream_t s);
 hipError_t launch_sparse_rmax(const EvalArgs& a, hipStream_t s);  // R_t after a sparse run
+// After a run with row_flags: the state m^t (rows of buffer `prim` of pair
+// msg, flagged rows taken from the other buffer when `sel` differs) made
+// whole in buffer `prim`.
+hipError_t launch_resolve_rows(float* const* pair_bufs, int prim, int sel, long long E, int K,
+                               hipStream_t s);
 // frontier residual BP selection
 hipError_t launch_rbp_gate(DevState* st, const CounterLine* ctr, int slot_idx, hipStream_t s);
 // gate_ctr: the counter set of the evaluation (the first scan sets rbp_skip

@@ -974,6 +974,7 @@ __device__ __forceinline__ void mfma32_table(const EvalArgs& a, float* pb) {
 }
 
 // old: the lane's 16 states of its slot's current row (issued by the caller).
+// p_out (row_flags): the outcome whose rows are written whole.
 template <int MODE, bool BF16 = false>
 __device__ __forceinline__ void slot_update_mfma32(const EvalArgs& a, const float* pb,
                                                    const float* old, float* s_logm,
@@ -981,7 +982,7 @@ __device__ __forceinline__ void slot_update_mfma32(const EvalArgs& a, const floa
                                                    const unsigned short* s_owner, int s0,
                                                    int n0, int ns, float& rmax,
                                                    unsigned int& act, unsigned int& sa,
-                                                   unsigned int& sb) {
+                                                   unsigned int& sb, int p_out = 0) {
     constexpr int K = 32, KS = 33;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = lane & 31, h = lane >> 5;
@@ -1062,6 +1063,30 @@ __device__ __forceinline__ void slot_update_mfma32(const EvalArgs& a, const floa
         }
         sa += ka && lead;
         sb += kb && lead;
+        if (a.row_flags) {
+            // the whole row of outcome p_out, its first entry's sign bit set where
+            // the outcomes differ; the other outcome's row only there
+            const bool kp = p_out == 0 ? ka : kb, ko = p_out == 0 ? kb : ka;
+            const bool diff = ka != kb;
+            float4* op = (float4*)(a.out_buf[p_out] + eo);
+#pragma unroll
+            for (int t4 = 0; t4 < 4; ++t4) {
+                float4 v = kp ? make_float4(c[4 * t4], c[4 * t4 + 1], c[4 * t4 + 2], c[4 * t4 + 3])
+                              : make_float4(old[4 * t4], old[4 * t4 + 1], old[4 * t4 + 2],
+                                            old[4 * t4 + 3]);
+                if (t4 == 0 && h == 0 && diff) v.x = __uint_as_float(__float_as_uint(v.x) | 0x80000000u);
+                op[t4] = v;
+            }
+            if (diff) {
+                float4* os = (float4*)(a.out_buf[p_out ^ 1] + eo);
+#pragma unroll
+                for (int t4 = 0; t4 < 4; ++t4)
+                    os[t4] = ko ? make_float4(c[4 * t4], c[4 * t4 + 1], c[4 * t4 + 2], c[4 * t4 + 3])
+                                : make_float4(old[4 * t4], old[4 * t4 + 1], old[4 * t4 + 2],
+                                              old[4 * t4 + 3]);
+            }
+            return;
+        }
 #pragma unroll
         for (int t4 = 0; t4 < 4; ++t4)
             o0[t4] = ka ? make_float4(c[4 * t4], c[4 * t4 + 1], c[4 * t4 + 2], c[4 * t4 + 3])
@@ -1134,9 +1159,13 @@ __device__ __forceinline__ GenericLds generic_lds(float* smem, int K, int TS, in
 // for messages near uniform, where FP32 rounding of a large aggregate would
 // dominate), and sum them per node with the unary: A_i(x) of Eq. (2)/(3).
 // Ends with a barrier.
+// Rows written with outcome flags (EvalArgs.row_flags): m_in is the buffer of
+// full rows; the sign bit of a row's first entry marks a message whose other
+// outcome is in m_alt.  m_alt == nullptr: the full rows hold the chosen
+// outcome, and only the flag bit is cleared (a no-op on unflagged rows).
 __device__ __forceinline__ void generic_phase1(const EvalArgs& a, const float* __restrict__ m_in,
                                                const GenericLds& l, int K, int n0, int nn,
-                                               int s0, int ns) {
+                                               int s0, int ns, const float* m_alt = nullptr) {
     const int tid = threadIdx.x;
     const int KS = K + 1;
     const float fK = (float)K;
@@ -1151,11 +1180,27 @@ __device__ __forceinline__ void generic_phase1(const EvalArgs& a, const float* _
         const int q = i / K, x = i - q * K;
         gat[j] = q < ns ? m_in[(long long)l.rev[q] * K + x] : 1.0f;
     }
+    if (m_alt) {
+        // the other outcome was chosen: flagged rows come from m_alt
+        unsigned int f[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int i = tid + j * kBlock;
+            const int q = i / K;
+            f[j] = q < ns ? __float_as_uint(m_in[(long long)l.rev[q] * K]) >> 31 : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int i = tid + j * kBlock;
+            const int q = i / K, x = i - q * K;
+            if (f[j]) gat[j] = m_alt[(long long)l.rev[q] * K + x];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int i = tid + j * kBlock;
         const int q = i / K, x = i - q * K;
-        if (q < ns) l.logm[q * KS + x] = logf(fK * gat[j]);
+        if (q < ns) l.logm[q * KS + x] = logf(fK * (x == 0 ? fabsf(gat[j]) : gat[j]));
     }
     // the nodes' unaries (loads first), then the aggregates
 #pragma unroll
@@ -1193,13 +1238,22 @@ __global__ __launch_bounds__(kBlock) void k_eval_mfma32(EvalArgs a) {
     extern __shared__ float smem[];
     __shared__ RedScratch red;
     __shared__ unsigned long long s_red[2];
-    const float* __restrict__ m_in = iteration_prologue(a, s_red, blockIdx.x == 0);
-    if (!m_in) return;
+    const float* m_sel = iteration_prologue(a, s_red, blockIdx.x == 0);
+    if (!m_sel) return;
     const int tile = tile_of_block(a);
     if (tile >= a.num_tiles) return;
     constexpr int K = 32;
     constexpr int TS = kTileFloatsGeneric / K;
     const GenericLds l = generic_lds(smem, K, TS, a.tile_nodes_max, false);
+    // Outcome flags: the previous launch wrote whole rows of outcome p_in (its
+    // own choice, recorded in in_sel) and the other outcome where they differ.
+    // This launch chose sel; it writes whole rows of sel.
+    const int sel = (a.it >= 1 && m_sel == a.in_buf[1]) ? 1 : 0;
+    const bool flagged_in = a.row_flags && a.it >= 1;
+    const int p_in = flagged_in ? (int)a.st->in_sel[(a.t - 1u) & 3u] : sel;
+    const int p_out = a.it == 0 ? a.sel0 : sel;
+    const float* __restrict__ m_in = flagged_in ? a.in_buf[p_in] : m_sel;
+    const float* m_alt = (flagged_in && p_in != sel) ? a.in_buf[p_in ^ 1] : nullptr;
     const int n0 = a.tile_start[tile], n1 = a.tile_start[tile + 1];
     const int s0 = a.tile_slot[tile], s1 = a.tile_slot[tile + 1];
     const int ns = s1 - s0;
@@ -1218,12 +1272,28 @@ __global__ __launch_bounds__(kBlock) void k_eval_mfma32(EvalArgs a) {
             old[4 * t4 + 2] = o4.z;
             old[4 * t4 + 3] = o4.w;
         }
+        if (flagged_in) {
+            // the flag is the sign of entry 0, held by the lane with h = 0
+            const unsigned int f0 = __float_as_uint(old[0]) >> 31;
+            const unsigned int f = (unsigned int)__shfl((int)f0, lane & 31, 64);
+            if (m_alt && f) {
+#pragma unroll
+                for (int t4 = 0; t4 < 4; ++t4) {
+                    const float4 o4 = *(const float4*)(m_alt + eo + 4 * t4);
+                    old[4 * t4] = o4.x;
+                    old[4 * t4 + 1] = o4.y;
+                    old[4 * t4 + 2] = o4.z;
+                    old[4 * t4 + 3] = o4.w;
+                }
+            }
+            if ((lane >> 5) == 0) old[0] = fabsf(old[0]);
+        }
     }
-    generic_phase1(a, m_in, l, K, n0, n1 - n0, s0, ns);
+    generic_phase1(a, m_in, l, K, n0, n1 - n0, s0, ns, m_alt);
     float rmax = 0.0f;
     unsigned int act = 0, sa = 0, sb = 0;
     slot_update_mfma32<MODE, BF16>(a, pb, old, l.logm, l.A, l.owner, s0, n0, ns, rmax, act, sa,
-                                   sb);
+                                   sb, p_out);
     block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
 }
 
@@ -2999,6 +3069,34 @@ hipError_t launch_sparse_rbp_eval(const EvalArgs& a, hipStream_t s) {
     const int grid = a.num_nodes > 0 ? (a.num_nodes + kBlock - 1) / kBlock : 1;
     k_sparse_eval<<<grid, kBlock, 0, s>>>(a);
     k_sparse_rbp_close<<<1, 64, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+// After a run with outcome flags: rows of `prim` whose first entry carries the
+// flag take the other outcome's row (when the last choice was the other
+// outcome) or just lose the flag.
+__global__ void k_resolve_rows(float* prim, const float* other, int take_other, long long E,
+                               int K) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < E;
+         e += (long long)gridDim.x * blockDim.x) {
+        float* r = prim + e * K;
+        const float v0 = r[0];
+        if (!(__float_as_uint(v0) >> 31)) continue;
+        if (take_other) {
+            for (int x = 0; x < K; ++x) r[x] = other[e * K + x];
+        } else {
+            r[0] = fabsf(v0);
+        }
+    }
+}
+
+hipError_t launch_resolve_rows(float* const* pair_bufs, int prim, int sel, long long E, int K,
+                               hipStream_t s) {
+    if (E <= 0) return hipSuccess;
+    long long g = (E + 255) / 256;
+    if (g > 4096) g = 4096;
+    k_resolve_rows<<<(int)g, 256, 0, s>>>(pair_bufs[prim], pair_bufs[prim ^ 1], sel != prim ? 1 : 0,
+                                          E, K);
     return hipGetLastError();
 }
 

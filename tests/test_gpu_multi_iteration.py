@@ -167,3 +167,63 @@ def test_ising_1000_dynamic_p_three_iterations_full_size(bp):
         # about 2e-5 of the messages have an FP64 residual within 1e-6 of eps
         _check_iteration(prob, runs[k - 1], runs[k], runs[k][2], "rnbp", p, seed, eps, True,
                          max_band=E // 10000)
+
+
+def _random_rows(E, K, seed, lo):
+    m = np.random.default_rng(seed).uniform(lo, 1.0, size=(E, K))
+    m /= m.sum(1, keepdims=True)
+    return m.astype(np.float32)
+
+
+def test_potts_k32_dynamic_p_iterations_against_oracle(bp):
+    # the K = 32 matrix-core kernel under dynamic p writes one whole row per
+    # message (the outcome the last iteration chose) and the other outcome only
+    # where the two differ; every iteration of a run reads such rows, with the
+    # choice predicted right or wrong (p switches five times in these ten
+    # iterations), and the run's end resolves them
+    prob = inputs.potts_grid(12, 12, 32, 2.0, 3)
+    E = 2 * len(prob["edges"])
+    S0 = _random_rows(E, 32, 7, 0.3)
+    p, seed, t0, kmax, eps = 0.5, 5, 2, 10, 3e-4
+    runs = []
+    with bp.Graph(prob) as g:
+        for k in range(kmax + 1):
+            g.set_state(S0, t=t0, prev_active=-1)
+            r = g.run("rnbp", eps=eps, p=p, seed=seed, max_iters=k, warm_start=True,
+                      check_every=3)
+            m, st = g.get_state()
+            runs.append((m, st, r))
+    ps = []
+    for k in range(1, kmax + 1):
+        assert runs[k][2]["iterations"] == k
+        pt, _ = _check_iteration(prob, runs[k - 1], runs[k], runs[k][2], "rnbp", p, seed, eps,
+                                 True)
+        ps.append(pt)
+    assert sum(ps[i] != ps[i - 1] for i in range(1, len(ps))) >= 2, ps
+    # every message holds a normalised row: no flag bit is left behind
+    for m, _, _ in runs:
+        assert np.all(m >= 0.0) and np.allclose(m.sum(1), 1.0, atol=1e-5)
+
+
+@pytest.mark.parametrize("flags", [0, 16])
+def test_potts_k32_dynamic_p_chained_runs_bitwise(bp, flags):
+    # one run against the same iterations split over several warm-started runs
+    # (rows resolved at every run's end): bitwise equal
+    prob = inputs.potts_grid(24, 24, 32, 2.0, 4)
+    kw = dict(eps=1e-6, p=0.5, seed=8, check_every=4)
+    with bp.Graph(prob, flags=flags) as g:
+        r = g.run("rnbp", max_iters=60, **kw)
+        full, st_full = g.get_state()
+        marg_full = g.marginals()
+    with bp.Graph(prob, flags=flags) as g:
+        done, its = 0, 0
+        for k in (1, 2, 9, 13, 35):
+            its += g.run("rnbp", max_iters=k, warm_start=done > 0, **kw)["iterations"]
+            done += k
+        part, st_part = g.get_state()
+        marg_part = g.marginals()
+    print(f"potts 24x24 K=32 flags={flags}: {r['iterations']} iterations, "
+          f"converged {r['converged']}, committed {r['committed']}")
+    assert r["iterations"] == its and st_full == st_part
+    assert np.array_equal(full.view(np.uint32), part.view(np.uint32))
+    assert np.array_equal(marg_full.view(np.uint32), marg_part.view(np.uint32))
