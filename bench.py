@@ -547,7 +547,7 @@ def main():
             extra["paper_ratios_vs_srbp"] = paper_ratios(bp, inputs, srbp, torch, args.eps)
         if "serving" in wanted:
             extra["serving"] = serving_bench(bp, inputs, np, torch, args, n=args.serving_requests)
-        _log(f"bench: serving {extra['serving']}")
+            _log(f"bench: serving {extra['serving']}")
         out["extra"] = extra
 
     if not args.no_cpu_baseline:
