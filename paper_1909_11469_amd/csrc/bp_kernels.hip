@@ -1509,25 +1509,37 @@ __global__ void k_marginals_logodds(const int* node_ptr, const int* rev, const f
     out[2 * (long long)n + 0] = 1.0f / (1.0f + expf(L));
 }
 
+// Wave-wide max and sum (every lane gets the result).
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Eq. (3) for the [E][K] layout: one wave per variable, lane x holding state x
+// (K <= 64), so each incoming row is one coalesced read; the logs of K m are
+// summed in slot order, as the evaluation kernels sum them.
 __global__ void k_marginals_generic(const int* node_ptr, const int* rev, const float* unary,
                                     const float* m, float* out, int N, int K) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    float A[kMaxK];
-    float mx = -3.402823466e38f;
-    for (int x = 0; x < K; ++x) {
-        float acc = unary[(long long)n * K + x];
-        for (int s = node_ptr[n]; s < node_ptr[n + 1]; ++s)
-            acc += logf((float)K * m[(long long)rev[s] * K + x]);
-        A[x] = acc;
-        mx = fmaxf(mx, acc);
+    const int lane = threadIdx.x & 63;
+    const int waves = (int)(gridDim.x * (blockDim.x >> 6));
+    const bool on = lane < K;
+    const float fK = (float)K;
+    for (int n = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); n < N; n += waves) {
+        float acc = on ? unary[(long long)n * K + lane] : -INFINITY;
+        const int s0 = node_ptr[n], s1 = node_ptr[n + 1];
+        for (int s = s0; s < s1; ++s)
+            if (on) acc += logf(fK * m[(long long)rev[s] * K + lane]);
+        const float mx = wave_max_f(acc);
+        const float e = on ? expf(acc - mx) : 0.0f;
+        const float z = wave_sum_f(e);
+        if (on) out[(long long)n * K + lane] = e / z;
     }
-    float z = 0.0f;
-    for (int x = 0; x < K; ++x) {
-        A[x] = expf(A[x] - mx);
-        z += A[x];
-    }
-    for (int x = 0; x < K; ++x) out[(long long)n * K + x] = A[x] / z;
 }
 
 // ---------------------------------------------------------------------------
@@ -1553,16 +1565,6 @@ __global__ void k_marginals_generic(const int* node_ptr, const int* rev, const f
 // (ragged_slot), taken before the other variables, so the launch is not held
 // up by one wave that runs a long chain of table loads.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float wave_max_f(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ float wave_sum_f(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 // Wave-local LDS hand-off: this wave's LDS stores are complete and visible to
 // its other lanes (a wave executes its LDS operations in order).
@@ -2636,31 +2638,6 @@ __device__ __forceinline__ unsigned int block_append(unsigned int c, unsigned in
     return pos;
 }
 
-// The same for one item per flagged thread: the wave's ballot, the lane's
-// position among the flagged lanes of its wave (mbcnt), the wave offsets from a
-// prefix sum in LDS, one atomic per block.
-__device__ __forceinline__ unsigned int block_append_flag(bool f, unsigned int* count,
-                                                          unsigned int* s_w) {
-    const unsigned long long b = __ballot(f);
-    const unsigned int before = __builtin_amdgcn_mbcnt_hi(
-        (unsigned int)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned int)b, 0u));
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) s_w[w] = (unsigned int)__popcll(b);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned int tot = 0;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
-            const unsigned int v = s_w[i];
-            s_w[i] = tot;
-            tot += v;
-        }
-        s_w[kBlock / 64] = tot ? atomicAdd(count, tot) : 0u;
-    }
-    __syncthreads();
-    const unsigned int pos = s_w[kBlock / 64] + s_w[w] + before;
-    __syncthreads();
-    return pos;
-}
 
 // 1. Variable residual keys (FP32 bit patterns of non-negative residuals order
 // as unsigned integers).
@@ -2777,18 +2754,56 @@ __global__ __launch_bounds__(kBlock) void k_rs_bfs(RsArgs r) {
     }
 }
 
-// 4. The lists of levels 1 .. h.
+// 4. The lists of levels 1 .. h.  Each block takes a contiguous range of the
+// variables: it counts its marked variables of a level (block sum), reserves
+// their places with one atomic, then writes them in order, a chunk of 256 at a
+// time (wave ballot, the lane's rank among the flagged lanes of its wave
+// (mbcnt), the wave offsets from a prefix sum in LDS).  A small grid keeps the
+// atomics on the level counters few (one per block and level).
+constexpr int kRsListGrid = 128;
 __global__ __launch_bounds__(kBlock) void k_rs_lists(RsArgs r) {
-    __shared__ unsigned int s_w[kBlock / 64 + 1];
+    __shared__ unsigned int s_w[kBlock / 64];
+    __shared__ unsigned int s_base;
     if (r.st->rbp_skip) return;
     const int N = r.num_nodes;
-    for (int base = blockIdx.x * kBlock; base < N; base += gridDim.x * kBlock) {
-        const int v = base + (int)threadIdx.x;
-        for (int d = 1; d <= r.depth; ++d) {
-            const bool f = v < N && r.mark[(size_t)d * N + v] == r.tag;
-            const unsigned int pos = block_append_flag(f, &r.st->rs_count[d], s_w);
-            if (f) r.list[(size_t)d * N + pos] = v;
+    const int tid = (int)threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int per = ((N + (int)gridDim.x - 1) / (int)gridDim.x + kBlock - 1) / kBlock * kBlock;
+    const int v0 = (int)blockIdx.x * per, v1 = min(N, v0 + per);
+    for (int d = 1; d <= r.depth; ++d) {
+        const unsigned int* mk = r.mark + (size_t)d * N;
+        int* L = r.list + (size_t)d * N;
+        unsigned int c = 0;
+        for (int v = v0 + tid; v < v1; v += kBlock) c += mk[v] == r.tag ? 1u : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) c += (unsigned int)__shfl_xor((int)c, o, 64);
+        if (lane == 0) s_w[w] = c;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned int tot = 0;
+            for (int i = 0; i < kBlock / 64; ++i) tot += s_w[i];
+            s_base = tot ? atomicAdd(&r.st->rs_count[d], tot) : 0u;
         }
+        __syncthreads();
+        unsigned int off = s_base;
+        for (int vb = v0; vb < v1; vb += kBlock) {
+            const int v = vb + tid;
+            const bool f = v < v1 && mk[v] == r.tag;
+            const unsigned long long b = __ballot(f);
+            const unsigned int before = __builtin_amdgcn_mbcnt_hi(
+                (unsigned int)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned int)b, 0u));
+            __syncthreads();  // s_w of the previous chunk has been read
+            if (lane == 0) s_w[w] = (unsigned int)__popcll(b);
+            __syncthreads();
+            unsigned int wpre = 0, tot = 0;
+            for (int i = 0; i < kBlock / 64; ++i) {
+                const unsigned int x = s_w[i];
+                if (i < w) wpre += x;
+                tot += x;
+            }
+            if (f) L[off + wpre + before] = v;
+            off += tot;
+        }
+        __syncthreads();  // s_w and s_base are reused by the next level
     }
 }
 
@@ -3035,7 +3050,8 @@ hipError_t launch_marginals(int layout, int kp, const int* node_ptr, const int* 
     if (layout == kLayoutLogOdds)
         k_marginals_logodds<<<grid, 256, 0, s>>>(node_ptr, rev, unary, m, out, N);
     else
-        k_marginals_generic<<<grid, 256, 0, s>>>(node_ptr, rev, unary, m, out, N, K);
+        k_marginals_generic<<<(int)std::min<long long>(((long long)N + 3) / 4, 65536), 256, 0, s>>>(
+            node_ptr, rev, unary, m, out, N, K);
     return hipGetLastError();
 }
 
@@ -3174,7 +3190,7 @@ hipError_t launch_rs_select(const RsArgs& r, unsigned int k, int all, unsigned i
     k_rs_roots<<<(N + kCommitChunk - 1) / kCommitChunk, kSelBlock, 0, s>>>(r, all, block_ties);
     if (r.depth >= 1) {
         k_rs_bfs<<<rs_grid(N), kBlock, 0, s>>>(r);
-        k_rs_lists<<<rs_grid(N), kBlock, 0, s>>>(r);
+        k_rs_lists<<<kRsListGrid, kBlock, 0, s>>>(r);
     }
     return hipGetLastError();
 }
