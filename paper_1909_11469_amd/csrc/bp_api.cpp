@@ -750,12 +750,9 @@ static EvalArgs run_args(const bp_graph* g, int schedule, double eps, double p, 
         a.low_is_a = 1;
         a.two_outputs = 0;
     }
-    // the K = 32 matrix-core kernel writes one whole row per message and the
-    // other outcome only where the two differ
-    a.row_flags = (a.two_outputs && L.layout == kLayoutGeneric && L.K == 32 &&
-                   L.pair == kPairShared && !L.tile_big && !L.no_mfma)
-                      ? 1
-                      : 0;
+    // [E][K] rows: one whole row per message and the other outcome only where
+    // the two keep decisions differ
+    a.row_flags = (a.two_outputs && L.layout == kLayoutGeneric) ? 1 : 0;
 
     rbp_k_out = rbp_k;
     return a;

@@ -804,18 +804,65 @@ __device__ __forceinline__ float group_sum(float v, int h) {
     return (p[0] + p[1]) + (p[2] + p[3]);
 }
 
+// Outcome flags of [E][K] rows (EvalArgs.row_flags).  A launch under dynamic p
+// writes whole rows of one outcome (the one its prologue chose for the previous
+// iteration: a prediction) and the other outcome's row only where the two keep
+// decisions differ, marked by the sign bit of the whole row's first entry
+// (messages are non-negative).  The next launch reads whole rows from `p` (the
+// buffer of the predicted outcome); if it chose the other outcome, flagged rows
+// come from `alt`.  `on` is 0 for rows written without flags.
+struct FlagRows {
+    const float* p;
+    const float* alt;   // nullptr: the prediction held
+    int on;
+};
+
+// Entry x of the row starting at `row` (x == 0 loses the flag bit).
+__device__ __forceinline__ float flag_entry(const FlagRows& f, long long row, int x) {
+    float v = f.p[row + x];
+    if (f.on) {
+        if (f.alt && (__float_as_uint(f.p[row]) >> 31)) v = f.alt[row + x];
+        if (x == 0) v = fabsf(v);
+    }
+    return v;
+}
+
+// Where a launch writes: whole rows of outcome `prim`, the other outcome's
+// rows where the decisions differ.
+__device__ __forceinline__ float flag_first(float v, bool diff) {
+    return diff ? __uint_as_float(__float_as_uint(v) | 0x80000000u) : v;
+}
+
+// The input rows of a launch and the outcome its own rows are written for:
+// sel = the outcome its prologue chose (m_sel = in_buf[sel]); with flags the
+// previous launch wrote whole rows of outcome in_sel[t - 1].
+__device__ __forceinline__ FlagRows flag_inputs(const EvalArgs& a, const float* m_sel,
+                                                int& p_out) {
+    const int sel = (a.it >= 1 && m_sel == a.in_buf[1]) ? 1 : 0;
+    p_out = a.it == 0 ? a.sel0 : sel;
+    FlagRows f{m_sel, nullptr, 0};
+    if (a.row_flags && a.it >= 1) {
+        const int p_in = (int)a.st->in_sel[(a.t - 1u) & 3u];
+        f.p = a.in_buf[p_in];
+        f.alt = p_in != sel ? a.in_buf[p_in ^ 1] : nullptr;
+        f.on = 1;
+    }
+    return f;
+}
+
 // Eq. (2) for one slot split over a group of R lanes (KP = K states, each lane
 // owns KR = K / R of them): the lane computes its part of the cavity
 // distribution g, the group exchanges the parts, and each lane forms its KR
 // outputs c(y) = sum_x psi(x, y) g(x) from the shared table in LDS.  The
 // normalisation and the residual are reduced over the group.
 template <int KP, int R, int MODE>
-__device__ __forceinline__ void slot_update_split(const EvalArgs& a, const float* __restrict__ m_in,
+__device__ __forceinline__ void slot_update_split(const EvalArgs& a, const FlagRows& fr,
                                                   const float* s_logm, const float* s_A,
                                                   const float* s_psi,
                                                   const unsigned short* s_owner, int s0, int n0,
                                                   int ns, float& rmax, unsigned int& act,
-                                                  unsigned int& sa, unsigned int& sb) {
+                                                  unsigned int& sa, unsigned int& sb, int p_out) {
+    const float* __restrict__ m_in = fr.p;
     constexpr int KR = KP / R;
     constexpr int KS = KP + 1;
     const int tid = threadIdx.x;
@@ -901,6 +948,21 @@ __device__ __forceinline__ void slot_update_split(const EvalArgs& a, const float
         old[4 * j4 + 2] = o4.z;
         old[4 * j4 + 3] = o4.w;
     }
+    if (fr.on) {
+        // the flag is the sign of the row's first entry (lane h = 0 holds it)
+        const long long row = (long long)s * KP;
+        if (fr.alt && (__float_as_uint(m_in[row]) >> 31)) {
+#pragma unroll
+            for (int j4 = 0; j4 < KR / 4; ++j4) {
+                const float4 o4 = *(const float4*)(fr.alt + eo + 4 * j4);
+                old[4 * j4] = o4.x;
+                old[4 * j4 + 1] = o4.y;
+                old[4 * j4 + 2] = o4.z;
+                old[4 * j4 + 3] = o4.w;
+            }
+        }
+        if (h == 0) old[0] = fabsf(old[0]);
+    }
 #pragma unroll
     for (int j = 0; j < KR; ++j) {
         c[j] *= inv;
@@ -924,6 +986,20 @@ __device__ __forceinline__ void slot_update_split(const EvalArgs& a, const float
         }
         sa += ka && lead;
         sb += kb && lead;
+        if (a.row_flags) {
+            const bool kp = p_out == 0 ? ka : kb, ko = p_out == 0 ? kb : ka;
+            const bool diff = ka != kb;
+            float* op = a.out_buf[p_out] + eo;
+#pragma unroll
+            for (int j = 0; j < KR; ++j)
+                op[j] = (j == 0 && h == 0) ? flag_first(kp ? c[0] : old[0], diff) : (kp ? c[j] : old[j]);
+            if (diff) {
+                float* os = a.out_buf[p_out ^ 1] + eo;
+#pragma unroll
+                for (int j = 0; j < KR; ++j) os[j] = ko ? c[j] : old[j];
+            }
+            return;
+        }
 #pragma unroll
         for (int j = 0; j < KR; ++j) a.out_buf[0][eo + j] = ka ? c[j] : old[j];
         if (a.two_outputs) {
@@ -1245,15 +1321,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_mfma32(EvalArgs a) {
     constexpr int K = 32;
     constexpr int TS = kTileFloatsGeneric / K;
     const GenericLds l = generic_lds(smem, K, TS, a.tile_nodes_max, false);
-    // Outcome flags: the previous launch wrote whole rows of outcome p_in (its
-    // own choice, recorded in in_sel) and the other outcome where they differ.
-    // This launch chose sel; it writes whole rows of sel.
-    const int sel = (a.it >= 1 && m_sel == a.in_buf[1]) ? 1 : 0;
-    const bool flagged_in = a.row_flags && a.it >= 1;
-    const int p_in = flagged_in ? (int)a.st->in_sel[(a.t - 1u) & 3u] : sel;
-    const int p_out = a.it == 0 ? a.sel0 : sel;
-    const float* __restrict__ m_in = flagged_in ? a.in_buf[p_in] : m_sel;
-    const float* m_alt = (flagged_in && p_in != sel) ? a.in_buf[p_in ^ 1] : nullptr;
+    int p_out;
+    const FlagRows fr = flag_inputs(a, m_sel, p_out);
+    const bool flagged_in = fr.on != 0;
+    const float* __restrict__ m_in = fr.p;
+    const float* m_alt = fr.alt;
     const int n0 = a.tile_start[tile], n1 = a.tile_start[tile + 1];
     const int s0 = a.tile_slot[tile], s1 = a.tile_slot[tile + 1];
     const int ns = s1 - s0;
@@ -1302,8 +1374,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
     extern __shared__ float smem[];
     __shared__ RedScratch red;
     __shared__ unsigned long long s_red[2];
-    const float* __restrict__ m_in = iteration_prologue(a, s_red, blockIdx.x == 0);
-    if (!m_in) return;
+    const float* m_sel = iteration_prologue(a, s_red, blockIdx.x == 0);
+    if (!m_sel) return;
+    int p_out;
+    const FlagRows fr = flag_inputs(a, m_sel, p_out);
+    const float* __restrict__ m_in = fr.p;
     const int tile = tile_of_block(a);
     if (tile >= a.num_tiles) return;
     const int K = EXACT ? KP : a.num_states;
@@ -1329,13 +1404,13 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
     if (shared && (!EXACT || R > 1))
         for (int i = tid; i < K * K; i += kBlock) s_psi[i] = a.pair[i];
     if (!big) {
-        generic_phase1(a, m_in, l, K, n0, nn, s0, ns);
+        generic_phase1(a, m_in, l, K, n0, nn, s0, ns, fr.alt);
     } else {
         // single node with degree > TS: aggregate each state with a strided sum
         for (int x = 0; x < K; ++x) {
             float part = 0.0f;
             for (int q = tid; q < ns; q += kBlock)
-                part += logf(fK * m_in[(long long)a.rev[s0 + q] * K + x]);
+                part += logf(fK * flag_entry(fr, (long long)a.rev[s0 + q] * K, x));
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
             if ((tid & 63) == 0) red.rmax[tid >> 6] = part;
@@ -1353,8 +1428,8 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
     float rmax = 0.0f;
     unsigned int act = 0, sa = 0, sb = 0;
     if (R > 1 && shared && !big) {
-        slot_update_split<KP, R, MODE>(a, m_in, s_logm, s_A, s_psi, s_owner, s0, n0, ns, rmax, act,
-                                       sa, sb);
+        slot_update_split<KP, R, MODE>(a, fr, s_logm, s_A, s_psi, s_owner, s0, n0, ns, rmax, act,
+                                       sa, sb, p_out);
         block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
         return;
     }
@@ -1368,7 +1443,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
 #pragma unroll
         for (int x = 0; x < KP; ++x) {
             if (x < K) {
-                const float lm = big ? logf(fK * m_in[rin + x]) : s_logm[q * KS + x];
+                const float lm = big ? logf(fK * flag_entry(fr, rin, x)) : s_logm[q * KS + x];
                 g[x] = s_A[v * KS + x] - lm;
                 mx = fmaxf(mx, g[x]);
             }
@@ -1427,7 +1502,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
         for (int y = 0; y < KP; ++y) {
             if (y < K) {
                 c[y] *= inv;
-                old[y] = m_in[eo + y];
+                old[y] = flag_entry(fr, eo, y);
                 r = fmaxf(r, fabsf(c[y] - old[y]));
             }
         }
@@ -1447,13 +1522,29 @@ __global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
             }
             sa += ka;
             sb += kb;
-#pragma unroll
-            for (int y = 0; y < KP; ++y)
-                if (y < K) a.out_buf[0][eo + y] = ka ? c[y] : old[y];
-            if (a.two_outputs) {
+            if (a.row_flags) {
+                // the whole row of outcome p_out, the other where they differ
+                const bool kp = p_out == 0 ? ka : kb, ko = p_out == 0 ? kb : ka;
+                const bool diff = ka != kb;
+                float* op = a.out_buf[p_out] + eo;
 #pragma unroll
                 for (int y = 0; y < KP; ++y)
-                    if (y < K) a.out_buf[1][eo + y] = kb ? c[y] : old[y];
+                    if (y < K) op[y] = y == 0 ? flag_first(kp ? c[0] : old[0], diff) : (kp ? c[y] : old[y]);
+                if (diff) {
+                    float* os = a.out_buf[p_out ^ 1] + eo;
+#pragma unroll
+                    for (int y = 0; y < KP; ++y)
+                        if (y < K) os[y] = ko ? c[y] : old[y];
+                }
+            } else {
+#pragma unroll
+                for (int y = 0; y < KP; ++y)
+                    if (y < K) a.out_buf[0][eo + y] = ka ? c[y] : old[y];
+                if (a.two_outputs) {
+#pragma unroll
+                    for (int y = 0; y < KP; ++y)
+                        if (y < K) a.out_buf[1][eo + y] = kb ? c[y] : old[y];
+                }
             }
         } else if (MODE == kModeRBP) {
 #pragma unroll

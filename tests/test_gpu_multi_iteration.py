@@ -175,18 +175,43 @@ def _random_rows(E, K, seed, lo):
     return m.astype(np.float32)
 
 
-def test_potts_k32_dynamic_p_iterations_against_oracle(bp):
-    # the K = 32 matrix-core kernel under dynamic p writes one whole row per
-    # message (the outcome the last iteration chose) and the other outcome only
-    # where the two differ; every iteration of a run reads such rows, with the
-    # choice predicted right or wrong (p switches five times in these ten
-    # iterations), and the run's end resolves them
-    prob = inputs.potts_grid(12, 12, 32, 2.0, 3)
-    E = 2 * len(prob["edges"])
-    S0 = _random_rows(E, 32, 7, 0.3)
-    p, seed, t0, kmax, eps = 0.5, 5, 2, 10, 3e-4
+def _star_dense(n, K, seed):
+    # a centre whose messages exceed one [E][K] tile, plus a ring of leaves
+    star = [(0, i) for i in range(1, n)]
+    ring = [(i, i + 1) for i in range(1, n - 1)]
+    edges = np.array(star + ring, dtype=np.int32)
+    rng = np.random.default_rng(seed)
+    return dict(N=n, K=K, edges=edges, log_unary=rng.standard_normal((n, K)),
+                pair_kind=inputs.PAIR_DENSE,
+                pair=np.exp(1.5 * rng.standard_normal((len(edges), K, K))))
+
+
+# [E][K] kernels whose rows carry outcome flags under dynamic p: the K = 32
+# matrix cores, the FP32 vector path split over 2 lanes per message (K = 32)
+# and 4 lanes (K = 64), a thread per message (K = 8), and a node over one tile
+# (dense K = 3)
+FLAG_CASES = {
+    "potts32_mfma": (lambda: inputs.potts_grid(12, 12, 32, 2.0, 3), 0, 3e-4),
+    "potts32_vector": (lambda: inputs.potts_grid(12, 12, 32, 2.0, 3), 2, 3e-4),
+    "potts64": (lambda: inputs.potts_grid(10, 10, 64, 2.0, 3), 0, 3e-4),
+    "potts8": (lambda: inputs.potts_grid(12, 12, 8, 2.0, 3), 0, 3e-4),
+    "dense3_star": (lambda: _star_dense(2001, 3, 4), 0, 3e-4),
+}
+
+
+@pytest.mark.parametrize("name", list(FLAG_CASES))
+def test_ek_dynamic_p_iterations_against_oracle(bp, name):
+    # under dynamic p an [E][K] launch writes one whole row per message (the
+    # outcome the last iteration chose) and the other outcome only where the
+    # two keep decisions differ; every iteration of a run reads such rows, with
+    # the choice predicted right or wrong, and the run's end resolves them
+    make, flags, eps = FLAG_CASES[name]
+    prob = make()
+    E, K = 2 * len(prob["edges"]), prob["K"]
+    S0 = _random_rows(E, K, 7, 0.3)
+    p, seed, t0, kmax = 0.5, 5, 2, 10
     runs = []
-    with bp.Graph(prob) as g:
+    with bp.Graph(prob, flags=flags) as g:
         for k in range(kmax + 1):
             g.set_state(S0, t=t0, prev_active=-1)
             r = g.run("rnbp", eps=eps, p=p, seed=seed, max_iters=k, warm_start=True,
@@ -195,21 +220,25 @@ def test_potts_k32_dynamic_p_iterations_against_oracle(bp):
             runs.append((m, st, r))
     ps = []
     for k in range(1, kmax + 1):
-        assert runs[k][2]["iterations"] == k
+        if runs[k][2]["iterations"] < k:
+            break  # converged
         pt, _ = _check_iteration(prob, runs[k - 1], runs[k], runs[k][2], "rnbp", p, seed, eps,
-                                 True)
+                                 True, max_band=3 + E // 1000)
         ps.append(pt)
-    assert sum(ps[i] != ps[i - 1] for i in range(1, len(ps))) >= 2, ps
+    print(f"{name}: {len(ps)} iterations checked, p_t {ps}")
+    assert len(ps) >= 4
+    if name == "potts32_mfma":
+        assert sum(ps[i] != ps[i - 1] for i in range(1, len(ps))) >= 2, ps
     # every message holds a normalised row: no flag bit is left behind
     for m, _, _ in runs:
         assert np.all(m >= 0.0) and np.allclose(m.sum(1), 1.0, atol=1e-5)
 
 
-@pytest.mark.parametrize("flags", [0, 16])
-def test_potts_k32_dynamic_p_chained_runs_bitwise(bp, flags):
+@pytest.mark.parametrize("K,flags", [(32, 0), (32, 16), (32, 2), (8, 0), (64, 0)])
+def test_ek_dynamic_p_chained_runs_bitwise(bp, K, flags):
     # one run against the same iterations split over several warm-started runs
     # (rows resolved at every run's end): bitwise equal
-    prob = inputs.potts_grid(24, 24, 32, 2.0, 4)
+    prob = inputs.potts_grid(24, 24, K, 2.0, 4)
     kw = dict(eps=1e-6, p=0.5, seed=8, check_every=4)
     with bp.Graph(prob, flags=flags) as g:
         r = g.run("rnbp", max_iters=60, **kw)
@@ -222,7 +251,7 @@ def test_potts_k32_dynamic_p_chained_runs_bitwise(bp, flags):
             done += k
         part, st_part = g.get_state()
         marg_part = g.marginals()
-    print(f"potts 24x24 K=32 flags={flags}: {r['iterations']} iterations, "
+    print(f"potts 24x24 K={K} flags={flags}: {r['iterations']} iterations, "
           f"converged {r['converged']}, committed {r['committed']}")
     assert r["iterations"] == its and st_full == st_part
     assert np.array_equal(full.view(np.uint32), part.view(np.uint32))
