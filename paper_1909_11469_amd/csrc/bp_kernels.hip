@@ -1747,9 +1747,18 @@ __device__ __forceinline__ void ragged_slot(const EvalArgs& a, const float* __re
 #pragma unroll
             for (int u = 0; u < 8; ++u) acc = fmaf(tv[u], gv[u], acc);
         }
-        for (; st < steps; ++st) {
-            const int x = st * R + r;
-            if (lane < RK && x < Ki) acc = fmaf(T[st * RK + lane], G[x], acc);
+        if (st < steps) {
+            // the remaining steps (fewer than eight), predicated, loads together
+            float tv[8], gv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int x = (st + u) * R + r;
+                const bool ok = st + u < steps && lane < RK && x < Ki;
+                tv[u] = ok ? T[(st + u) * RK + lane] : 0.0f;
+                gv[u] = ok ? G[x] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = fmaf(tv[u], gv[u], acc);
         }
         Cv[lane] = acc;
         wave_lds_sync();
@@ -1771,10 +1780,21 @@ __device__ __forceinline__ void ragged_slot(const EvalArgs& a, const float* __re
                 o1 = fmaf(t1[u], gx, o1);
             }
         }
-        for (; x < Ki; ++x) {
-            const float gx = G[x];
-            o0 = fmaf(T[x * Kj + lane], gx, o0);
-            if (y1) o1 = fmaf(T[x * Kj + lane + 64], gx, o1);
+        if (x < Ki) {
+            float t0[8], t1[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const bool ok = x + u < Ki;
+                t0[u] = ok ? T[(x + u) * Kj + lane] : 0.0f;
+                t1[u] = ok && y1 ? T[(x + u) * Kj + lane + 64] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (x + u >= Ki) break;
+                const float gx = G[x + u];
+                o0 = fmaf(t0[u], gx, o0);
+                o1 = fmaf(t1[u], gx, o1);
+            }
         }
     }
     const float z = wave_sum_f(o0 + o1);
@@ -1899,21 +1919,20 @@ __global__ __launch_bounds__(kBlock) void k_eval_ragged(EvalArgs a) {
                     g[j] = G + k * Ki;
                 }
                 float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                int x = 0;
-                for (; x + 8 <= Ki; x += 8) {
+                // eight source states per step, the last step predicated (a
+                // variable with few states takes one step, not one per state)
+                for (int x = 0; x < Ki; x += 8) {
                     float tv[4][8];
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) tv[j][u] = T[j][(x + u) * Kj[j]];
+                        for (int u = 0; u < 8; ++u) tv[j][u] = x + u < Ki ? T[j][(x + u) * Kj[j]] : 0.0f;
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) acc[j] = fmaf(tv[j][u], g[j][x + u], acc[j]);
+                        for (int u = 0; u < 8; ++u)
+                            if (x + u < Ki) acc[j] = fmaf(tv[j][u], g[j][x + u], acc[j]);
                 }
-                for (; x < Ki; ++x)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[j] = fmaf(T[j][x * Kj[j]], g[j][x], acc[j]);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     if (on[j]) Cv[pb + lane + 64 * j] = acc[j];
