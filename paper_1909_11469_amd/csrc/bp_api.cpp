@@ -72,6 +72,7 @@ struct HostLayout {
     long long M = 0, E = 0;
     std::vector<int> node_ptr;        // [N+1] slot range of each source node
     std::vector<int> rev;             // [E]
+    std::vector<short> rev16;         // [E] rev[e] - e (K = 2 log-odds layout, when all fit)
     std::vector<int> slot_of_canon;   // [E]
     std::vector<int> tile_start;      // [T+1]
     std::vector<int> tile_slot;       // [T+1] node_ptr[tile_start]
@@ -109,7 +110,7 @@ struct Arena {
 
 struct Offsets {
     size_t node_ptr, rev, tile, tile_slot, tiles4, big4, coupling, unary, pair, orient, msg[4], cand, keys, ties, state,
-        ctr, marg, kv, uoff, moff, toff, heavy, sparse, splash, total;
+        ctr, marg, kv, uoff, moff, toff, heavy, rev16, sparse, splash, total;
 };
 
 // Device bytes of the sparse re-evaluation buffers of a log-odds graph: dirty
@@ -146,6 +147,7 @@ Offsets plan(const HostLayout& L) {
     o.moff = a.take(sizeof(int) * L.moff.size());
     o.toff = a.take(sizeof(int) * L.toff.size());
     o.heavy = a.take(sizeof(int) * L.heavy.size());
+    o.rev16 = a.take(sizeof(short) * L.rev16.size());
     o.sparse = L.sparse_reserved ? a.take(sparse_bytes(L)) : 0;
     o.splash = L.splash_reserved ? a.take(splash_bytes(L.N)) : 0;
     o.total = a.off;
@@ -287,6 +289,20 @@ int build_layout(const bp_graph_desc* d, HostLayout& L) {
     for (long long s = 0; s < E; ++s) L.rev[s] = L.slot_of_canon[canon_of_slot[s] ^ 1];
     // the K = 2 kernel reads slot 0 of a tile without slots: keep one valid entry
     if (E == 0) L.rev.assign(1, 0);
+    // K = 2 log-odds layout: the reverse slot as a 16-bit offset when every
+    // one fits (grids: the reverse message is a few rows of slots away), two
+    // bytes per message instead of four for the evaluation kernel
+    if (L.layout == kLayoutLogOdds && E > 0) {
+        bool fits = true;
+        for (long long s = 0; s < E && fits; ++s) {
+            const long long d = (long long)L.rev[s] - s;
+            fits = d >= -32768 && d <= 32767;
+        }
+        if (fits) {
+            L.rev16.resize((size_t)E);
+            for (long long s = 0; s < E; ++s) L.rev16[s] = (short)((long long)L.rev[s] - s);
+        }
+    }
 
     L.msg_floats = E * L.row;
     L.belief_floats = N * K;
@@ -589,12 +605,13 @@ int create_graph_from_layout(HostLayout& layout, const bp_graph_desc* desc, bp_g
         if (n == 0) return hipSuccess;
         return hipMemcpyAsync(g->base + o, p, n, hipMemcpyHostToDevice, s);
     };
-    hipError_t errs[16] = {
+    hipError_t errs[17] = {
         up(g->off.kv, L.kv.data(), sizeof(int) * L.kv.size()),
         up(g->off.uoff, L.uoff.data(), sizeof(int) * L.uoff.size()),
         up(g->off.moff, L.moff.data(), sizeof(int) * L.moff.size()),
         up(g->off.toff, L.toff.data(), sizeof(int) * L.toff.size()),
         up(g->off.heavy, L.heavy.data(), sizeof(int) * L.heavy.size()),
+        up(g->off.rev16, L.rev16.data(), sizeof(short) * L.rev16.size()),
         up(g->off.tile_slot, L.tile_slot.data(), sizeof(int) * L.tile_slot.size()),
         up(g->off.tiles4, L.tiles4.data(), sizeof(int) * L.tiles4.size()),
         up(g->off.big4, L.big4.data(), sizeof(int) * L.big4.size()),
@@ -698,6 +715,7 @@ static EvalArgs run_args(const bp_graph* g, int schedule, double eps, double p, 
     if (L.layout == kLayoutLogOdds && g->lo_grid > 0) a.pipe_grid = g->lo_grid;
     a.node_ptr = g->at<int>(g->off.node_ptr);
     a.rev = g->at<int>(g->off.rev);
+    a.rev16 = L.rev16.empty() ? nullptr : g->at<short>(g->off.rev16);
     a.coupling = g->at<float>(g->off.coupling);
     a.unary = g->at<float>(g->off.unary);
     a.pair = g->at<float>(g->off.pair);

@@ -122,6 +122,7 @@ struct EvalArgs {
     int pipe_grid;              // blocks of the persistent log-odds kernel (multiple of 8)
     const int* node_ptr;        // [N+1] slot range of each source node
     const int* rev;             // [E] slot of the reverse message
+    const short* rev16;         // K = 2 log-odds layout: rev[e] - e as 16 bits, or nullptr
     const float* coupling;      // [E] Ising J per slot
     const float* unary;         // log-odds [N] (K = 2 log-odds layout) or log psi [N][K]
     const float* pair;          // shared [K][K] or dense [E][K][K]

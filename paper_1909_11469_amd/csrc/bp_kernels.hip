@@ -395,8 +395,13 @@ struct TileRegs {
 
 // Issue every load of a tile (indices clamped into the tile, so there is no
 // per-lane branch and the loads are not ordered behind one another): the graph
-// constants, then the tile's own old messages.
-template <int MODE>
+// constants, then the tile's own old messages.  R16: the reverse slots are
+// read as 16-bit offsets from the slot (EvalArgs.rev16).
+template <class T>
+__device__ __forceinline__ T ld16(const T* base, int i) {
+    return *(const T*)((const char*)base + (unsigned int)i * 2u);
+}
+template <int MODE, bool R16 = false>
 __device__ __forceinline__ void tile_load_const(TileRegs& d, const EvalArgs& a, int4 b) {
     const int tid = threadIdx.x;
     d.n0 = b.x;
@@ -414,7 +419,7 @@ __device__ __forceinline__ void tile_load_const(TileRegs& d, const EvalArgs& a, 
 #pragma unroll
     for (int k = 0; k < kPP; ++k) {
         const int s = d.s0 + min(tid + k * kBlockLO, max(d.ns - 1, 0));
-        d.rev[k] = ld32(a.rev, s);
+        d.rev[k] = R16 ? s + (int)ld16(a.rev16, s) : ld32(a.rev, s);
         d.J[k] = ld32(a.coupling, s);
     }
 }
@@ -425,10 +430,10 @@ __device__ __forceinline__ void tile_load_msgs(TileRegs& d, const float* m_in) {
         d.old[k] = ld32(m_in, d.s0 + min((int)threadIdx.x + k * kBlockLO, max(d.ns - 1, 0)));
 }
 
-template <int MODE>
+template <int MODE, bool R16 = false>
 __device__ __forceinline__ void tile_load(TileRegs& d, const EvalArgs& a, const float* m_in,
                                           int4 b) {
-    tile_load_const<MODE>(d, a, b);
+    tile_load_const<MODE, R16>(d, a, b);
     tile_load_msgs(d, m_in);
 }
 
@@ -474,7 +479,7 @@ struct LogoddsLds {
 // loads of tile j + 1, aggregates tile j (LDS), issues the gathers of tile
 // j + 1, computes and stores tile j, then stages tile j + 1 into LDS, so every
 // wait falls on loads that had a whole phase to complete.
-template <int MODE, class Seq>
+template <int MODE, class Seq, bool R16 = false>
 __device__ __forceinline__ void logodds_tile_loop(const EvalArgs& a, const float* __restrict__ m_in,
                                                   const Seq& seq, TileRegs& cur, int4 bnext,
                                                   LogoddsLds& l, float& rmax, unsigned int& act,
@@ -501,7 +506,7 @@ __device__ __forceinline__ void logodds_tile_loop(const EvalArgs& a, const float
     for (int j = 0;; ++j) {
         const bool has_next = seq.valid(j + 1);
         const int4 bnext2 = seq.valid(j + 2) ? seq.bounds(j + 2) : make_int4(0, 0, 0, 0);
-        if (has_next) tile_load<MODE>(nxt, a, m_in, bnext);
+        if (has_next) tile_load<MODE, R16>(nxt, a, m_in, bnext);
         lds_barrier();
         // node aggregates of tile j, incoming messages in slot order; for
         // RnBP also the draws of the node's messages, four per Philox call
@@ -576,7 +581,7 @@ struct XcdTiles {
 
 // K = 2 evaluation kernel.  A persistent grid (as many blocks as are resident)
 // walks the tiles with the pipelined tile loop.
-template <int MODE>
+template <int MODE, bool R16>
 __global__ __launch_bounds__(kBlockLO) void k_eval_logodds(EvalArgs a) {
     __shared__ LogoddsLds l;
     __shared__ RedScratch red;
@@ -593,7 +598,7 @@ __global__ __launch_bounds__(kBlockLO) void k_eval_logodds(EvalArgs a) {
     CtrLoad cl;
     prologue_issue(a, cl, blockIdx.x == 0);
     TileRegs cur;
-    tile_load_const<MODE>(cur, a, bcur);
+    tile_load_const<MODE, R16>(cur, a, bcur);
     __builtin_amdgcn_sched_barrier(0);
     const float* m_sel = prologue_finish(a, cl, s_red, blockIdx.x == 0);
     if (!m_sel) return;
@@ -603,7 +608,9 @@ __global__ __launch_bounds__(kBlockLO) void k_eval_logodds(EvalArgs a) {
     const bool hist = MODE == kModeRBP && a.hist0;
     if (hist)
         for (int i = threadIdx.x; i < 256; i += kBlockLO) l.hist[i] = 0u;  // seen after the loop's barriers
-    if (t0 >= 0) logodds_tile_loop<MODE>(a, m_in, XcdTiles{a, tiles}, cur, bnext, l, rmax, act, sa, sb);
+    if (t0 >= 0)
+        logodds_tile_loop<MODE, XcdTiles, R16>(a, m_in, XcdTiles{a, tiles}, cur, bnext, l, rmax, act,
+                                              sa, sb);
     if (hist) {
         // the block's digit counts into one of the copies of the global histogram
         lds_barrier();
@@ -3009,11 +3016,20 @@ hipError_t launch_eval(int layout, int kp, int mode, const EvalArgs& a, hipStrea
     if (grid <= 0) return hipSuccess;
     if (layout == kLayoutLogOdds) {
         const int g = a.pipe_grid;
-        switch (mode) {
-        case kModeLBP: k_eval_logodds<kModeLBP><<<g, kBlockLO, 0, s>>>(a); break;
-        case kModeRnBP: k_eval_logodds<kModeRnBP><<<g, kBlockLO, 0, s>>>(a); break;
-        case kModeRBP: k_eval_logodds<kModeRBP><<<g, kBlockLO, 0, s>>>(a); break;
-        default: k_eval_logodds<kModeEvalOnly><<<g, kBlockLO, 0, s>>>(a); break;
+        if (a.rev16) {
+            switch (mode) {
+            case kModeLBP: k_eval_logodds<kModeLBP, true><<<g, kBlockLO, 0, s>>>(a); break;
+            case kModeRnBP: k_eval_logodds<kModeRnBP, true><<<g, kBlockLO, 0, s>>>(a); break;
+            case kModeRBP: k_eval_logodds<kModeRBP, true><<<g, kBlockLO, 0, s>>>(a); break;
+            default: k_eval_logodds<kModeEvalOnly, true><<<g, kBlockLO, 0, s>>>(a); break;
+            }
+        } else {
+            switch (mode) {
+            case kModeLBP: k_eval_logodds<kModeLBP, false><<<g, kBlockLO, 0, s>>>(a); break;
+            case kModeRnBP: k_eval_logodds<kModeRnBP, false><<<g, kBlockLO, 0, s>>>(a); break;
+            case kModeRBP: k_eval_logodds<kModeRBP, false><<<g, kBlockLO, 0, s>>>(a); break;
+            default: k_eval_logodds<kModeEvalOnly, false><<<g, kBlockLO, 0, s>>>(a); break;
+            }
         }
         if (a.num_big > 0) {
             switch (mode) {
@@ -3077,16 +3093,16 @@ int logodds_blocks_per_cu(int mode) {
     hipError_t e;
     switch (mode) {
     case kModeLBP:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeLBP>, kBlockLO, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeLBP, true>, kBlockLO, 0);
         break;
     case kModeRnBP:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeRnBP>, kBlockLO, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeRnBP, true>, kBlockLO, 0);
         break;
     case kModeRBP:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeRBP>, kBlockLO, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeRBP, true>, kBlockLO, 0);
         break;
     default:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeEvalOnly>, kBlockLO, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_eval_logodds<kModeEvalOnly, true>, kBlockLO, 0);
         break;
     }
     return e == hipSuccess ? n : 0;
