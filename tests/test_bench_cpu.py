@@ -15,9 +15,12 @@ COUNTERS = os.path.join(ROOT, "profiles", "k_eval_logodds_rnbp_ising1000_counter
 
 def test_eval_kernel_bytes_1000x1000():
     # 1000 x 1000 grid: N = 10^6, E = 2 * 1,998,000 directed messages
+    # (the grid's reverse slots are read as 16-bit offsets: 18 B per message)
     N, E = 1000 * 1000, 2 * 2 * 1000 * 999
-    assert bench.eval_kernel_bytes(N, E) == 20 * 3996000 + 8 * 1000000 == 87920000
-    assert bench.eval_kernel_bytes(N, E, two_outputs=False) == 16 * 3996000 + 8 * 1000000
+    assert bench.eval_kernel_bytes(N, E) == 18 * 3996000 + 8 * 1000000 == 79928000
+    assert bench.eval_kernel_bytes(N, E, two_outputs=False) == 14 * 3996000 + 8 * 1000000
+    # with 4-byte reverse indices (graphs whose offsets do not fit 16 bits)
+    assert bench.eval_kernel_bytes(N, E, rev_bytes=4) == 20 * 3996000 + 8 * 1000000
 
 
 def test_iteration_bytes_matches_workload_definition():
