@@ -1316,8 +1316,12 @@ __device__ __forceinline__ void generic_phase1(const EvalArgs& a, const float* _
 // start, so that they arrive while the incoming rows are gathered and
 // aggregated.  (A persistent variant that pipelined several tiles per block
 // ran slower: its register and LDS footprint halved the resident blocks.)
+// Five waves per SIMD (96 registers, one spilled) instead of the four that the
+// unconstrained allocation (115 with the accumulators) leaves: the kernel is
+// bound by memory latency, so more resident waves hide more of it.
 template <int MODE, bool BF16>
-__global__ __launch_bounds__(kBlock) void k_eval_mfma32(EvalArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_eval_mfma32(
+    EvalArgs a) {
     extern __shared__ float smem[];
     __shared__ RedScratch red;
     __shared__ unsigned long long s_red[2];
@@ -1376,8 +1380,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_mfma32(EvalArgs a) {
     block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
 }
 
+// K = 32 exactly: five waves per SIMD fit in 96 registers (114 unconstrained);
+// the other widths keep the compiler's allocation, where a cap would spill.
 template <int KP, int MODE, bool EXACT>
-__global__ __launch_bounds__(kBlock) void k_eval_generic(EvalArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KP == 32 && EXACT ? 5 : 1)))
+void k_eval_generic(EvalArgs a) {
     extern __shared__ float smem[];
     __shared__ RedScratch red;
     __shared__ unsigned long long s_red[2];
