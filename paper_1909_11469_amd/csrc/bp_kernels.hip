@@ -1380,10 +1380,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
 }
 
-// K = 32 exactly: five waves per SIMD fit in 96 registers (114 unconstrained);
-// the other widths keep the compiler's allocation, where a cap would spill.
+// Waves per SIMD asked of the register allocator for k_eval_generic<KP, MODE,
+// EXACT> (1 leaves it unconstrained).  The kernel waits on memory, so more
+// resident waves pay for a spilled register or two: K = 8 and 32 take five
+// (96 registers; 99 and 114 unconstrained), K = 64 takes three (168; 170) and
+// under RnBP, whose second outcome needs more live values, or with K below the
+// width, two (256; unconstrained the allocator spills into the accumulation
+// registers and leaves one).  The other widths fit without a cap.
 template <int KP, int MODE, bool EXACT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KP == 32 && EXACT ? 5 : 1)))
+constexpr int generic_waves() {
+    if (KP == 64) return EXACT && MODE != 1 ? 3 : 2;
+    return (KP == 8 || KP == 32) && EXACT ? 5 : 1;
+}
+
+template <int KP, int MODE, bool EXACT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(generic_waves<KP, MODE, EXACT>())))
 void k_eval_generic(EvalArgs a) {
     extern __shared__ float smem[];
     __shared__ RedScratch red;
@@ -1834,8 +1845,11 @@ __device__ __forceinline__ void ragged_slot(const EvalArgs& a, const float* __re
     wave_lds_sync();  // G and Cv are free for the wave's next slot
 }
 
+// Four waves per SIMD: 124 to 127 registers, none spilled (three waves and up
+// to 141 registers unconstrained).
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_eval_ragged(EvalArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_ragged(
+    EvalArgs a) {
     __shared__ RedScratch red;
     __shared__ unsigned long long s_red[2];
     __shared__ float s_g[kBlock / 64][kRaggedFlat];    // cavity vectors, slot-major
