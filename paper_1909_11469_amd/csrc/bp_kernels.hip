@@ -810,6 +810,19 @@ __device__ __forceinline__ float group_sum(float v, int h) {
     p[3] = h == 3 ? v : h == 2 ? o1 : h == 1 ? o2 : o3;
     return (p[0] + p[1]) + (p[2] + p[3]);
 }
+// Lane pp of each group, read by every lane of the group (DPP quad_perm
+// broadcast; for R = 2 the quad holds two groups).
+template <int R, int PP>
+__device__ __forceinline__ float group_bcast(float v) {
+    constexpr int sel = R == 4 ? PP * 0x55 : (PP | PP << 2 | (2 + PP) << 4 | (2 + PP) << 6);
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), sel, 0xF, 0xF, false));
+}
+template <int R>
+__device__ __forceinline__ float group_bcast(float v, int pp) {
+    return pp == 0 ? group_bcast<R, 0>(v)
+                   : pp == 1 ? group_bcast<R, 1>(v)
+                             : pp == 2 ? group_bcast<R, 2 % R>(v) : group_bcast<R, 3 % R>(v);
+}
 
 // Outcome flags of [E][K] rows (EvalArgs.row_flags).  A launch under dynamic p
 // writes whole rows of one outcome (the one its prologue chose for the previous
@@ -859,13 +872,16 @@ __device__ __forceinline__ FlagRows flag_inputs(const EvalArgs& a, const float* 
 
 // Eq. (2) for one slot split over a group of R lanes (KP = K states, each lane
 // owns KR = K / R of them): the lane computes its part of the cavity
-// distribution g, the group exchanges the parts, and each lane forms its KR
-// outputs c(y) = sum_x psi(x, y) g(x) from the shared table in LDS.  The
-// normalisation and the residual are reduced over the group.
+// distribution g, and each lane forms its KR outputs c(y) = sum_x psi(x, y) g(x)
+// from the shared table in LDS, taking g(x) of the other parts from their lanes
+// one value at a time (a lane never holds all of g).  Messages that use the
+// transposed table read psi^T, staged beside psi, so that both sum over x in
+// ascending order with the same row reads.  The normalisation and the residual
+// are reduced over the group.
 template <int KP, int R, int MODE>
 __device__ __forceinline__ void slot_update_split(const EvalArgs& a, const FlagRows& fr,
                                                   const float* s_logm, const float* s_A,
-                                                  const float* s_psi,
+                                                  const float* s_psi, const float* s_psiT,
                                                   const unsigned short* s_owner, int s0, int n0,
                                                   int ns, float& rmax, unsigned int& act,
                                                   unsigned int& sa, unsigned int& sb, int p_out) {
@@ -888,47 +904,17 @@ __device__ __forceinline__ void slot_update_split(const EvalArgs& a, const FlagR
     mx = group_max<R>(mx);
 #pragma unroll
     for (int i = 0; i < KR; ++i) gp[i] = expf(gp[i] - mx);
-    // g(x) for all x: part p comes from the lane with h' = p, i.e. partner h ^ p
-    float g[KP];
-#pragma unroll
-    for (int i = 0; i < KR; ++i) {
-        const float o1 = dpp_xor1(gp[i]);
-        if (R == 2) {
-            g[i] = h == 0 ? gp[i] : o1;
-            g[KR + i] = h == 0 ? o1 : gp[i];
-        } else {
-            const float o2 = dpp_xor2(gp[i]), o3 = dpp_xor3(gp[i]);
-#pragma unroll
-            for (int pp = 0; pp < R; ++pp) {
-                const int k = pp ^ h;
-                g[pp * KR + i] = k == 0 ? gp[i] : k == 1 ? o1 : k == 2 ? o2 : o3;
-            }
-        }
-    }
+    const float* tab =
+        a.pair_kind == kPairSharedAsym && a.orient[s] ? s_psiT : s_psi;
     float c[KR];
 #pragma unroll
     for (int j = 0; j < KR; ++j) c[j] = 0.0f;
-    if (a.pair_kind == kPairSharedAsym && a.orient[s]) {
-        // transposed table: c(y) = sum_x psi(y, x) g(x)
 #pragma unroll
-        for (int j = 0; j < KR; ++j) {
-            const float4* row = (const float4*)(s_psi + (h * KR + j) * KP);
-            float acc = 0.0f;
+    for (int pp = 0; pp < R; ++pp) {
 #pragma unroll
-            for (int x4 = 0; x4 < KP / 4; ++x4) {
-                const float4 p4 = row[x4];
-                acc = fmaf(p4.x, g[4 * x4], acc);
-                acc = fmaf(p4.y, g[4 * x4 + 1], acc);
-                acc = fmaf(p4.z, g[4 * x4 + 2], acc);
-                acc = fmaf(p4.w, g[4 * x4 + 3], acc);
-            }
-            c[j] = acc;
-        }
-    } else {
-#pragma unroll
-        for (int x = 0; x < KP; ++x) {
-            const float4* row = (const float4*)(s_psi + x * KP + h * KR);
-            const float gx = g[x];
+        for (int i = 0; i < KR; ++i) {
+            const float gx = group_bcast<R>(gp[i], pp);  // g(x), x = pp KR + i
+            const float4* row = (const float4*)(tab + (pp * KR + i) * KP + h * KR);
 #pragma unroll
             for (int j4 = 0; j4 < KR / 4; ++j4) {
                 const float4 p4 = row[j4];
@@ -1215,20 +1201,23 @@ struct GenericLds {
     float* logm;             // [TS][KS] logs of the incoming messages
     float* A;                // [TN][KS] node aggregates
     float* psi;              // [K][K] shared table (paths that read it from LDS)
+    float* psiT;             // [K][K] its transpose (asymmetric tables), else psi
     int* rev;                // [TS]
     int* ptr;                // [TN + 1] local slot offsets of the nodes
     unsigned short* owner;   // [TS]
 };
 
-// with_psi: reserve the K x K table (the launch sizes the LDS the same way)
+// tables: the number of K x K tables reserved (0; 1, psi; 2, psi and psi^T);
+// the launch sizes the LDS the same way
 __device__ __forceinline__ GenericLds generic_lds(float* smem, int K, int TS, int TN,
-                                                  bool with_psi) {
+                                                  int tables) {
     GenericLds l;
     const int KS = K + 1;
     l.logm = smem;
     l.A = l.logm + TS * KS;
     l.psi = l.A + ((TN * KS + 3) & ~3);  // 16-byte aligned: read as float4 rows
-    l.rev = (int*)(l.psi + (with_psi ? K * K : 0));
+    l.psiT = tables == 2 ? l.psi + K * K : l.psi;
+    l.rev = (int*)(l.psi + tables * K * K);
     l.ptr = l.rev + TS;
     l.owner = (unsigned short*)(l.ptr + TN + 1);
     return l;
@@ -1331,7 +1320,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     if (tile >= a.num_tiles) return;
     constexpr int K = 32;
     constexpr int TS = kTileFloatsGeneric / K;
-    const GenericLds l = generic_lds(smem, K, TS, a.tile_nodes_max, false);
+    const GenericLds l = generic_lds(smem, K, TS, a.tile_nodes_max, 0);
     int p_out;
     const FlagRows fr = flag_inputs(a, m_sel, p_out);
     const bool flagged_in = fr.on != 0;
@@ -1387,14 +1376,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
 // under RnBP, whose second outcome needs more live values, or with K below the
 // width, two (256; unconstrained the allocator spills into the accumulation
 // registers and leaves one).  The other widths fit without a cap.
-template <int KP, int MODE, bool EXACT>
+template <int KP, int MODE, bool EXACT, bool SPLIT>
 constexpr int generic_waves() {
+    if (SPLIT) return 1;
     if (KP == 64) return EXACT && MODE != 1 ? 3 : 2;
     return (KP == 8 || KP == 32) && EXACT ? 5 : 1;
 }
 
-template <int KP, int MODE, bool EXACT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(generic_waves<KP, MODE, EXACT>())))
+// SPLIT: the launch guarantees a shared table, K == KP with R > 1 and no tile
+// holding a node over its slot limit, so only the lane-group path is compiled
+// (its registers are then not those of the per-slot path).
+template <int KP, int MODE, bool EXACT, bool SPLIT = false>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(generic_waves<KP, MODE, EXACT, SPLIT>())))
 void k_eval_generic(EvalArgs a) {
     extern __shared__ float smem[];
     __shared__ RedScratch red;
@@ -1409,7 +1402,8 @@ void k_eval_generic(EvalArgs a) {
     const int K = EXACT ? KP : a.num_states;
     const int TS = kTileFloatsGeneric / K;  // slots per tile
     const int KS = K + 1;
-    const GenericLds l = generic_lds(smem, K, TS, a.tile_nodes_max, true);
+    const GenericLds l =
+        generic_lds(smem, K, TS, a.tile_nodes_max, a.pair_kind == kPairSharedAsym ? 2 : 1);
     float* s_logm = l.logm;
     float* s_A = l.A;
     float* s_psi = l.psi;
@@ -1419,15 +1413,18 @@ void k_eval_generic(EvalArgs a) {
     const int s0 = a.tile_slot[tile], s1 = a.tile_slot[tile + 1];
     const int ns = s1 - s0, nn = n1 - n0;
     const int tid = threadIdx.x;
-    const bool big = ns > TS;
+    const bool big = !SPLIT && ns > TS;
     const float fK = (float)K;
 
     // K > 16 with a shared table: each slot is split over R lanes, which read
     // the table from LDS (the lanes of a wave need different columns)
     constexpr int R = (EXACT && KP * kBlock > kTileFloatsGeneric) ? KP * kBlock / kTileFloatsGeneric : 1;
-    const bool shared = a.pair_kind == kPairShared || a.pair_kind == kPairSharedAsym;
+    static_assert(!SPLIT || R > 1, "the lane-group path needs K = KP > 16");
+    const bool shared = SPLIT || a.pair_kind == kPairShared || a.pair_kind == kPairSharedAsym;
     if (shared && (!EXACT || R > 1))
         for (int i = tid; i < K * K; i += kBlock) s_psi[i] = a.pair[i];
+    if (R > 1 && a.pair_kind == kPairSharedAsym)
+        for (int i = tid; i < K * K; i += kBlock) l.psiT[i] = a.pair[(i % K) * K + i / K];
     if (!big) {
         generic_phase1(a, m_in, l, K, n0, nn, s0, ns, fr.alt);
     } else {
@@ -1453,7 +1450,7 @@ void k_eval_generic(EvalArgs a) {
     float rmax = 0.0f;
     unsigned int act = 0, sa = 0, sb = 0;
     if (R > 1 && shared && !big) {
-        slot_update_split<KP, R, MODE>(a, fr, s_logm, s_A, s_psi, s_owner, s0, n0, ns, rmax, act,
+        slot_update_split<KP, R, MODE>(a, fr, s_logm, s_A, s_psi, l.psiT, s_owner, s0, n0, ns, rmax, act,
                                        sa, sb, p_out);
         block_accumulate(&red, a.ctr, a.t, rmax, act, sa, sb);
         return;
@@ -3013,14 +3010,14 @@ hipError_t launch_fill(float* p, float v, long long n, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int KP, bool EXACT>
+template <int KP, bool EXACT, bool SPLIT = false>
 static hipError_t launch_generic_kp(int mode, const EvalArgs& a, int grid, size_t shm,
                                     hipStream_t s) {
     switch (mode) {
-    case kModeLBP: k_eval_generic<KP, kModeLBP, EXACT><<<grid, kBlock, shm, s>>>(a); break;
-    case kModeRnBP: k_eval_generic<KP, kModeRnBP, EXACT><<<grid, kBlock, shm, s>>>(a); break;
-    case kModeRBP: k_eval_generic<KP, kModeRBP, EXACT><<<grid, kBlock, shm, s>>>(a); break;
-    default: k_eval_generic<KP, kModeEvalOnly, EXACT><<<grid, kBlock, shm, s>>>(a); break;
+    case kModeLBP: k_eval_generic<KP, kModeLBP, EXACT, SPLIT><<<grid, kBlock, shm, s>>>(a); break;
+    case kModeRnBP: k_eval_generic<KP, kModeRnBP, EXACT, SPLIT><<<grid, kBlock, shm, s>>>(a); break;
+    case kModeRBP: k_eval_generic<KP, kModeRBP, EXACT, SPLIT><<<grid, kBlock, shm, s>>>(a); break;
+    default: k_eval_generic<KP, kModeEvalOnly, EXACT, SPLIT><<<grid, kBlock, shm, s>>>(a); break;
     }
     return hipGetLastError();
 }
@@ -3028,8 +3025,13 @@ static hipError_t launch_generic_kp(int mode, const EvalArgs& a, int grid, size_
 template <int KP>
 static hipError_t launch_generic_k(int mode, const EvalArgs& a, int grid, size_t shm,
                                    hipStream_t s) {
-    return a.num_states == KP ? launch_generic_kp<KP, true>(mode, a, grid, shm, s)
-                              : launch_generic_kp<KP, false>(mode, a, grid, shm, s);
+    if (a.num_states != KP) return launch_generic_kp<KP, false>(mode, a, grid, shm, s);
+    if constexpr (KP * kBlock > kTileFloatsGeneric) {
+        // every tile on the lane-group path
+        if ((a.pair_kind == kPairShared || a.pair_kind == kPairSharedAsym) && !a.tile_big)
+            return launch_generic_kp<KP, true, true>(mode, a, grid, shm, s);
+    }
+    return launch_generic_kp<KP, true>(mode, a, grid, shm, s);
 }
 
 hipError_t launch_eval(int layout, int kp, int mode, const EvalArgs& a, hipStream_t s) {
@@ -3096,8 +3098,10 @@ hipError_t launch_eval(int layout, int kp, int mode, const EvalArgs& a, hipStrea
         }
         return hipGetLastError();
     }
-    const size_t shm = sizeof(float) * (size_t)(TS * (K + 1) + ((TN * (K + 1) + 3) & ~3) + K * K) +
-                       sizeof(int) * (size_t)(TS + TN + 1) + sizeof(unsigned short) * (size_t)TS;
+    const int tables = a.pair_kind == kPairSharedAsym ? 2 : 1;
+    const size_t shm =
+        sizeof(float) * (size_t)(TS * (K + 1) + ((TN * (K + 1) + 3) & ~3) + tables * K * K) +
+        sizeof(int) * (size_t)(TS + TN + 1) + sizeof(unsigned short) * (size_t)TS;
     switch (kp) {
     case 2: return launch_generic_k<2>(mode, a, grid, shm, s);
     case 4: return launch_generic_k<4>(mode, a, grid, shm, s);
