@@ -144,6 +144,28 @@ def test_high_degree_node_single_sweep(bp):
         assert err.max() <= SWEEP_TOL, (K, err.max())
 
 
+@pytest.mark.parametrize("K,sym", [(32, True), (32, False), (64, True), (64, False)])
+def test_lane_groups_beside_oversized_node_single_sweep(bp, K, sym):
+    # a star centre over the tile limit (128 slots at K = 32, 64 at K = 64)
+    # keeps the graph on the kernel that holds both the lane-group branch (the
+    # other tiles) and the per-slot path (the centre's tile); graphs without
+    # such a node run an instantiation with the lane-group branch alone
+    n = 301
+    star = [(0, i) for i in range(1, n)]
+    ring = [(i, i + 1) for i in range(1, n - 1)]
+    edges = np.array(star + ring, dtype=np.int32)
+    rng = np.random.default_rng(K + sym)
+    table = np.exp(0.5 * rng.standard_normal((K, K)))
+    if sym:
+        table = 0.5 * (table + table.T)
+    prob = dict(N=n, K=K, edges=edges, log_unary=rng.standard_normal((n, K)),
+                pair_kind=inputs.PAIR_SHARED, shared=table,
+                edge_scale=rng.uniform(0.5, 1.5, len(edges)))
+    state = _random_state(2 * len(edges), K, 11, lo=0.3)
+    err, _ = _one_sweep_parity(bp, prob, state)
+    assert err.max() <= SWEEP_TOL, err.max()
+
+
 def test_every_node_oversized(bp):
     # complete graph on 530 nodes: every degree (529) exceeds a K = 2 tile, so
     # all nodes go to the single-node kernel and the regular kernel only keeps
