@@ -1375,7 +1375,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
 // (96 registers; 99 and 114 unconstrained), K = 64 takes three (168; 170) and
 // under RnBP, whose second outcome needs more live values, or with K below the
 // width, two (256; unconstrained the allocator spills into the accumulation
-// registers and leaves one).  The other widths fit without a cap.
+// registers and leaves one).  The other widths fit without a cap, and so does
+// the lane-group instantiation (SPLIT: about 60 registers, LDS sets its
+// occupancy).
 template <int KP, int MODE, bool EXACT, bool SPLIT>
 constexpr int generic_waves() {
     if (SPLIT) return 1;
@@ -2375,10 +2377,6 @@ __device__ __forceinline__ void sel_load16(const T* base, long long q0, long lon
     }
 }
 
-// One pass of the radix select: histogram of digit `pass` (8 bits, from the
-// top) of the keys that match the prefix fixed so far, added into one of
-// kHistCopies copies of the global histogram (by block index) so that blocks
-// do not queue on one address.
 // Digit histogram of pass `pass` (8 bits from the top) of the keys matching
 // the prefix fixed so far, over the chunks of kCommitChunk keys this block
 // takes (grid-stride), added into one of kHistCopies copies of the global
