@@ -186,14 +186,24 @@ def _star_dense(n, K, seed):
                 pair=np.exp(1.5 * rng.standard_normal((len(edges), K, K))))
 
 
+def _asym_potts(side, K, seed):
+    # a Potts grid whose shared table is not symmetric: half of the messages
+    # use its transpose
+    prob = inputs.potts_grid(side, side, K, 2.0, seed)
+    prob["shared"] = np.exp(0.8 * np.random.default_rng(seed).standard_normal((K, K)))
+    return prob
+
+
 # [E][K] kernels whose rows carry outcome flags under dynamic p: the K = 32
 # matrix cores, the FP32 vector path split over 2 lanes per message (K = 32)
-# and 4 lanes (K = 64), a thread per message (K = 8), and a node over one tile
-# (dense K = 3)
+# and 4 lanes (K = 64), with symmetric and asymmetric tables, a thread per
+# message (K = 8), and a node over one tile (dense K = 3)
 FLAG_CASES = {
     "potts32_mfma": (lambda: inputs.potts_grid(12, 12, 32, 2.0, 3), 0, 3e-4),
     "potts32_vector": (lambda: inputs.potts_grid(12, 12, 32, 2.0, 3), 2, 3e-4),
     "potts64": (lambda: inputs.potts_grid(10, 10, 64, 2.0, 3), 0, 3e-4),
+    "asym32": (lambda: _asym_potts(12, 32, 5), 0, 3e-4),
+    "asym64": (lambda: _asym_potts(10, 64, 6), 0, 3e-4),
     "potts8": (lambda: inputs.potts_grid(12, 12, 8, 2.0, 3), 0, 3e-4),
     "dense3_star": (lambda: _star_dense(2001, 3, 4), 0, 3e-4),
 }
