@@ -1636,24 +1636,53 @@ __device__ __forceinline__ float wave_sum_f(float v) {
     return v;
 }
 
-// Eq. (3) for the [E][K] layout: one wave per variable, lane x holding state x
-// (K <= 64), so each incoming row is one coalesced read; the logs of K m are
-// summed in slot order, as the evaluation kernels sum them.
+// Eq. (3) for the [E][K] layout: a group of W lanes per variable (W = K
+// rounded up to a power of two, 64 / W variables per wave), lane x holding
+// state x, so each incoming row is one coalesced read; the logs of K m are
+// summed in slot order, as the evaluation kernels sum them.  The reverse slots
+// of up to W incoming messages come in one load (a lane each) and eight rows
+// are in flight at a time, so a variable costs a few round trips, not two per
+// neighbour.  Shuffles and reductions stay inside the group, whose lanes run
+// the same loop trips.
 __global__ void k_marginals_generic(const int* node_ptr, const int* rev, const float* unary,
                                     const float* m, float* out, int N, int K) {
+    constexpr int kRows = 8;
     const int lane = threadIdx.x & 63;
-    const int waves = (int)(gridDim.x * (blockDim.x >> 6));
-    const bool on = lane < K;
+    int W = 1;
+    while (W < K) W <<= 1;
+    const int G = 64 / W;  // variables per wave
+    const int sub = lane / W, x = lane % W, base = sub * W;
+    const bool on = x < K;
     const float fK = (float)K;
-    for (int n = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); n < N; n += waves) {
-        float acc = on ? unary[(long long)n * K + lane] : -INFINITY;
-        const int s0 = node_ptr[n], s1 = node_ptr[n + 1];
-        for (int s = s0; s < s1; ++s)
-            if (on) acc += logf(fK * m[(long long)rev[s] * K + lane]);
-        const float mx = wave_max_f(acc);
-        const float e = on ? expf(acc - mx) : 0.0f;
-        const float z = wave_sum_f(e);
-        if (on) out[(long long)n * K + lane] = e / z;
+    const long long waves = (long long)gridDim.x * (blockDim.x >> 6);
+    const long long w0 = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    for (long long n0 = w0 * G; n0 < N; n0 += waves * G) {
+        const int n = (int)(n0 + sub);
+        if (n < N) {
+            float acc = on ? unary[(long long)n * K + x] : -INFINITY;
+            const int s0 = node_ptr[n], s1 = node_ptr[n + 1];
+            for (int c = s0; c < s1; c += W) {
+                const int cnt = min(W, s1 - c);
+                const int r = x < cnt ? rev[c + x] : 0;
+                for (int j = 0; j < cnt; j += kRows) {
+                    float v[kRows];
+#pragma unroll
+                    for (int u = 0; u < kRows; ++u) {
+                        const int ru = __shfl(r, base + (j + u) % W, 64);
+                        v[u] = on && j + u < cnt ? m[(long long)ru * K + x] : 1.0f;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kRows; ++u)
+                        if (on && j + u < cnt) acc += logf(fK * v[u]);
+                }
+            }
+            float mx = acc;
+            for (int o = W >> 1; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+            const float e = on ? expf(acc - mx) : 0.0f;
+            float z = e;
+            for (int o = W >> 1; o > 0; o >>= 1) z += __shfl_xor(z, o, 64);
+            if (on) out[(long long)n * K + x] = e / z;
+        }
     }
 }
 
@@ -3198,9 +3227,13 @@ hipError_t launch_marginals(int layout, int kp, const int* node_ptr, const int* 
     const int grid = (N + 255) / 256;
     if (layout == kLayoutLogOdds)
         k_marginals_logodds<<<grid, 256, 0, s>>>(node_ptr, rev, unary, m, out, N);
-    else
-        k_marginals_generic<<<(int)std::min<long long>(((long long)N + 3) / 4, 65536), 256, 0, s>>>(
-            node_ptr, rev, unary, m, out, N, K);
+    else {
+        int W = 1;
+        while (W < K) W <<= 1;
+        const long long per_block = 4ll * (64 / W);  // four waves of 64 / W variables
+        k_marginals_generic<<<(int)std::min<long long>((N + per_block - 1) / per_block, 65536), 256,
+                              0, s>>>(node_ptr, rev, unary, m, out, N, K);
+    }
     return hipGetLastError();
 }
 
